@@ -1,0 +1,353 @@
+"""Pins of the oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: an independent library
+implementation, a value the paper prints, a closed form, an algebraic identity
+or brute force on tiny inputs.
+"""
+
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+from sympy import isprime
+
+from oracle import fv, hers, philox
+from oracle.primes import ntt_primes, plain_modulus, psi
+from oracle.ring import center, negacyclic_mul, negacyclic_mul_schoolbook, negacyclic_sum_of_products
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper():
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        return json.load(f)
+
+
+# ----------------------------------------------------------------------------- Philox
+
+def _numpy_block(ctr, key):
+    """Philox4x64-10 block from numpy's independent implementation.  numpy
+    increments its 256-bit counter before producing a block."""
+    c = sum(int(x) << (64 * i) for i, x in enumerate(ctr))
+    c = (c - 1) % (1 << 256)
+    cw = np.array([(c >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=cw)
+    return [int(x) for x in g.random_raw(4)]
+
+
+@pytest.mark.parametrize("key,ctr", [
+    ((0, 0), (0, 0, 0, 0)),
+    ((1, 2), (0, 0, 0, 0)),
+    ((201, 1), (3, 7, 0, 0)),
+    ((2**64 - 1, 2**63), (2**64 - 1, 2**64 - 1, 5, 9)),
+    ((123456789, 3), (17, 0, 127, 2)),
+])
+def test_philox_matches_numpy(key, ctr):
+    assert list(philox.philox4x64_10(ctr, key)) == _numpy_block(ctr, key)
+
+
+def test_philox_stream_addressing():
+    key, obj = (5, 2), (3, 4, 1)
+    w = philox.words(key, obj, 10)
+    assert w[4:8] == list(philox.philox4x64_10((1, 3, 4, 1), key))
+    assert w[9] == philox.philox4x64_10((2, 3, 4, 1), key)[1]
+
+
+def test_samplers_ranges_and_moments():
+    n = 4096
+    key = (11, 1)
+    s = philox.sample_binary(key, (0, 0, 0), n)
+    assert set(s) <= {0, 1} and abs(sum(s) - n / 2) < 5 * (n / 4) ** 0.5
+    e = np.array(philox.sample_cbd(key, (1, 0, 0), 4 * n))
+    assert e.min() >= -20 and e.max() <= 20
+    assert abs(e.mean()) < 0.2 and abs(e.var() - 10.0) < 0.8       # CBD(20): variance eta/2
+    primes = [1032193, 0xffffee001]
+    r = philox.sample_uniform_residues(key, (2, 0, 0), n, primes)
+    for row, p in zip(r, primes):
+        row = np.array(row, dtype=np.float64)
+        assert row.min() >= 0 and row.max() < p
+        assert abs(row.mean() / p - 0.5) < 0.03
+
+
+def test_binary_sampler_bit_layout():
+    key, obj = (9, 9), (1, 2, 3)
+    w = philox.words(key, obj, 2)
+    s = philox.sample_binary(key, obj, 128)
+    assert s[0] == w[0] & 1 and s[63] == w[0] >> 63 and s[64] == w[1] & 1
+
+
+# ----------------------------------------------------------------------------- primes
+
+def test_paper_plain_modulus():
+    """Sec. 4.1 prints t = 1,032,193 for n = 4096; the selection rule reproduces it."""
+    pv = _paper()["encryption_parameters"]
+    assert plain_modulus(20, 2 * pv["n"]) == pv["t"]
+
+
+def test_prime_rule_is_largest():
+    """Brute force: every larger candidate p = 1 mod 2n below 2^b is composite."""
+    for bits, two_n in [(36, 8192), (20, 4096), (54, 4096), (44, 16384), (21, 16384)]:
+        p = ntt_primes([bits], two_n)[0]
+        assert isprime(p) and p % two_n == 1 and p < 2**bits
+        c = p + two_n
+        while c < 2**bits:
+            assert not isprime(c)
+            c += two_n
+
+
+def test_q_primes_distinct_and_sized():
+    qs = ntt_primes([36, 36, 36], 8192)
+    assert len(set(qs)) == 3 and all(p.bit_length() == 36 for p in qs)
+    assert qs == sorted(qs, reverse=True)
+    pv = _paper()["encryption_parameters"]
+    assert len(qs) == pv["q_prime_count"] and all(p.bit_length() == pv["q_prime_bits"] for p in qs)
+
+
+@pytest.mark.parametrize("p,n", [(1032193, 4096), (1032193, 2048), (1785857, 8192), (0xffffee001, 4096)])
+def test_psi_is_primitive_2n_root(p, n):
+    r = psi(p, 2 * n)
+    assert pow(r, n, p) == p - 1          # psi^n = -1: root of x^n + 1
+    assert pow(r, 2 * n, p) == 1
+
+
+# ----------------------------------------------------------------------------- ring
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 32, 64])
+def test_negacyclic_mul_vs_schoolbook(n):
+    rng = random.Random(n)
+    for bound in [1, 63, 2**36, 2**107]:
+        a = [rng.randint(-bound, bound) for _ in range(n)]
+        b = [rng.randint(-bound, bound) for _ in range(n)]
+        assert negacyclic_mul(a, b) == negacyclic_mul_schoolbook(a, b)
+
+
+def test_negacyclic_extremes_and_x_shift():
+    n, B = 16, 2**107
+    a = [B] * n
+    b = [-B] * n
+    assert negacyclic_mul(a, b) == negacyclic_mul_schoolbook(a, b)
+    # multiplying by x rotates and negates the wrapped coefficient (x^n = -1)
+    x = [0, 1] + [0] * (n - 2)
+    c = list(range(1, n + 1))
+    assert negacyclic_mul(c, x) == [-n] + c[:-1]
+
+
+def test_sum_of_products_matches_sum():
+    rng = random.Random(7)
+    n, B = 32, 2**60
+    pairs = [([rng.randint(-B, B) for _ in range(n)], [rng.randint(-B, B) for _ in range(n)]) for _ in range(5)]
+    want = [0] * n
+    for a, b in pairs:
+        want = [x + y for x, y in zip(want, negacyclic_mul_schoolbook(a, b))]
+    assert negacyclic_sum_of_products(pairs, n, B) == want
+
+
+# ----------------------------------------------------------------------------- slot encoding
+
+def _small_params(n=64, qbits=(36, 36), t_bits=20, w_bits=0):
+    return fv.Params(n=n, qbits=qbits, t_bits=t_bits, w_bits=w_bits)
+
+
+def test_encode_matches_interpolation_definition():
+    p = _small_params(n=128)
+    rng = np.random.default_rng(3)
+    z = rng.integers(-63, 64, size=p.n)
+    m = hers.encode_slots(p, z[None, :])[0]
+    assert [int(x) for x in m] == hers.encode_slots_direct(p, z)
+    for j in [0, 1, 77, 127]:
+        assert hers.evaluate_at_slot(p, m, j) == z[j] % p.t
+
+
+def test_encode_decode_roundtrip_large_n():
+    p = fv.Params(n=4096, qbits=(36,), t_bits=20)
+    rng = np.random.default_rng(4)
+    z = rng.integers(0, p.t, size=(2, p.n))
+    m = hers.encode_slots(p, z)
+    assert np.array_equal(hers.decode_slots(p, m), z)
+    for j in [0, 2047, 4095]:
+        assert hers.evaluate_at_slot(p, m[1], j) == z[1, j]
+
+
+def test_constant_polynomial_fills_every_slot():
+    """Eq. 2: the query's value replicated in all slots is the constant polynomial."""
+    p = _small_params(n=64)
+    m = hers.probe_plaintext(p, -17)
+    assert np.all(hers.decode_slots(p, m) == (-17) % p.t)
+
+
+def test_ring_product_is_slotwise_product():
+    """CRT batching: multiplication in R_t acts slot-wise (convolution theorem)."""
+    p = _small_params(n=32)
+    rng = np.random.default_rng(5)
+    z1, z2 = rng.integers(0, p.t, size=(2, p.n))
+    m1 = [int(x) for x in hers.encode_slots(p, z1[None])[0]]
+    m2 = [int(x) for x in hers.encode_slots(p, z2[None])[0]]
+    prod = [c % p.t for c in negacyclic_mul_schoolbook(m1, m2)]
+    assert np.array_equal(hers.decode_slots(p, prod), (z1 * z2) % p.t)
+
+
+# ----------------------------------------------------------------------------- FV identities
+
+@pytest.fixture(scope="module")
+def toy():
+    p = fv.Params(n=256, qbits=(36, 36, 36), t_bits=20, w_bits=0)
+    sk, pk, rlk = fv.keygen(p, 77)
+    return p, sk, pk, rlk
+
+
+def test_public_key_relation(toy):
+    """pk0 + pk1 s = -e with |e| <= eta (Alg. "Key Generation")."""
+    p, sk, pk, _ = toy
+    v = fv.poly_add(pk[0], fv.poly_mul_q(pk[1], sk, p.q), p.q)
+    assert max(abs(center(x, p.q)) for x in v) <= p.eta
+
+
+def test_relin_key_relation(toy):
+    """rlk_g0 + rlk_g1 s = g s^2 - e_g with |e_g| <= eta."""
+    p, sk, _, rlk = toy
+    s2 = fv.poly_mul_q(sk, sk, p.q)
+    for (rho, l, g), (b, a) in zip(p.gadget(), rlk):
+        v = fv.poly_add(b, fv.poly_mul_q(a, sk, p.q), p.q)
+        v = [(x - g * y) % p.q for x, y in zip(v, s2)]
+        assert max(abs(center(x, p.q)) for x in v) <= p.eta
+
+
+@pytest.mark.parametrize("w_bits", [0, 12])
+def test_gadget_identity(w_bits):
+    """sum_g y_g * g = c2 (mod q) for the digits of any c2."""
+    p = fv.Params(n=8, qbits=(36, 30), t_bits=12, w_bits=w_bits)
+    rng = random.Random(w_bits)
+    c2 = [rng.randrange(p.q) for _ in range(p.n)] + []
+    c2[0], c2[1] = 0, p.q - 1
+    digits = fv.relin_digits(p, c2)
+    gad = p.gadget()
+    assert len(digits) == len(gad)
+    for j in range(p.n):
+        assert sum(d[j] * g for d, (_, _, g) in zip(digits, gad)) % p.q == c2[j]
+        if w_bits:
+            assert all(d[j] < 2**w_bits for d in digits)
+
+
+def test_encrypt_decrypt_and_add(toy):
+    p, sk, pk, _ = toy
+    rng = np.random.default_rng(6)
+    z1, z2 = rng.integers(-500, 500, size=(2, p.n))
+    m1 = [int(x) for x in hers.encode_slots(p, z1[None])[0]]
+    m2 = [int(x) for x in hers.encode_slots(p, z2[None])[0]]
+    c1 = fv.encrypt(p, pk, m1, (1, 2), (0, 0))
+    c2 = fv.encrypt(p, pk, m2, (1, 2), (0, 1))
+    assert fv.decrypt(p, sk, c1) == m1
+    s = fv.add(p, c1, c2)
+    assert np.array_equal(hers.decode_slots(p, fv.decrypt(p, sk, s)), (z1 + z2) % p.t)
+    # fresh noise: |e1 + pk0 u ... | bounded by eta (1 + n) for binary u, s
+    assert fv.noise(p, sk, c1, m1) <= p.eta * (2 * p.n + 1)
+
+
+def test_multiply_relin_is_slotwise_product(toy):
+    p, sk, pk, rlk = toy
+    rng = np.random.default_rng(8)
+    z1, z2 = rng.integers(-63, 64, size=(2, p.n))
+    m1 = [int(x) for x in hers.encode_slots(p, z1[None])[0]]
+    m2 = [int(x) for x in hers.encode_slots(p, z2[None])[0]]
+    c1 = fv.encrypt(p, pk, m1, (3, 2), (0, 0))
+    c2 = fv.encrypt(p, pk, m2, (3, 2), (0, 1))
+    X = fv.tensor(p, [(c1, c2)])
+    deg2 = tuple(fv.scale_round(p, x) for x in X)
+    assert np.array_equal(hers.decode_slots(p, fv.decrypt(p, sk, deg2)), (z1 * z2) % p.t)
+    prod = fv.multiply(p, rlk, c1, c2)
+    assert np.array_equal(hers.decode_slots(p, fv.decrypt(p, sk, prod)), (z1 * z2) % p.t)
+
+
+def test_scale_round_brute_force():
+    """round(t X / q) against exact rational rounding, on values next to the
+    rounding boundaries (t X = (q +- 1)/2 mod q) and at the range ends."""
+    from fractions import Fraction
+    p = fv.Params(n=8, qbits=(36, 36), t_bits=20)
+    q, t = p.q, p.t
+    tinv = pow(t, -1, q)
+    xs = [0, 1, -1, q // 2, -(q // 2), 3 * q, -5 * q + 7]
+    for r in [(q - 1) // 2, (q + 1) // 2, 1, q - 1]:
+        base = (r * tinv) % q               # t * base = r (mod q)
+        xs += [base, base - q, base + 11 * q, base - 1000 * q]
+    got = fv.scale_round(p, xs)
+    for x, g in zip(xs, got):
+        f = Fraction(t * x, q)
+        fl = f.numerator // f.denominator
+        want = fl + (1 if f - fl > Fraction(1, 2) else 0)
+        assert f - fl != Fraction(1, 2)     # q odd: no ties
+        assert g == want % q
+
+
+# ----------------------------------------------------------------------------- HERS search
+
+def _features(rng, d, m):
+    return rng.integers(-63, 64, size=(d, m)), rng.integers(-63, 64, size=d)
+
+
+def test_search_scores_equal_plaintext_inner_products():
+    """Eq. 1 and Eq. 4: decrypted encrypted scores are exactly P^T q; ragged last block."""
+    p = fv.Params(n=256, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 5)
+    rng = np.random.default_rng(9)
+    d, m = 6, 2 * 256 + 37
+    P, qv = _features(rng, d, m)
+    G = hers.encrypt_gallery(p, pk, P, 31)
+    Q = hers.encrypt_probe(p, pk, qv, 41)
+    S = {b: hers.search_block(p, rlk, Q, G[b]) for b in G}
+    assert np.array_equal(hers.decrypt_scores(p, sk, S, m), hers.plaintext_scores(P, qv))
+
+
+def test_fused_and_literal_forms_decrypt_alike():
+    """Form F (sum, one rescale, one relin) and form L (Alg. "HERS Search" per
+    dimension) differ in ciphertext bits but not in decrypted scores."""
+    p = fv.Params(n=128, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 6)
+    rng = np.random.default_rng(10)
+    d, m = 4, 100
+    P, qv = _features(rng, d, m)
+    G = hers.encrypt_gallery(p, pk, P, 32)
+    Q = hers.encrypt_probe(p, pk, qv, 42)
+    F = {0: hers.search_block(p, rlk, Q, G[0])}
+    L = {0: hers.search_block_literal(p, rlk, Q, G[0])}
+    assert F[0] != L[0]
+    want = hers.plaintext_scores(P, qv)
+    assert np.array_equal(hers.decrypt_scores(p, sk, F, m), want)
+    assert np.array_equal(hers.decrypt_scores(p, sk, L, m), want)
+
+
+def test_search_with_digit_split_gadget():
+    p = fv.Params(n=128, qbits=(54, 54), t_bits=20, w_bits=18)
+    sk, pk, rlk = fv.keygen(p, 7)
+    assert len(rlk) == 6
+    rng = np.random.default_rng(11)
+    d, m = 5, 128
+    P, qv = _features(rng, d, m)
+    G = hers.encrypt_gallery(p, pk, P, 33)
+    Q = hers.encrypt_probe(p, pk, qv, 43)
+    S = {0: hers.search_block(p, rlk, Q, G[0])}
+    assert np.array_equal(hers.decrypt_scores(p, sk, S, m), hers.plaintext_scores(P, qv))
+
+
+def test_single_prime_toy_config_exceeds_noise_budget():
+    """With q one 54-bit prime (n = 2048, t ~ 2^20) the product noise exceeds
+    Delta/2 = 2^33: ciphertexts are still defined, decryption of the scores is not."""
+    p = fv.Params(n=2048, qbits=(54,), t_bits=20, w_bits=18)
+    assert (p.delta // 2).bit_length() == 34
+    sk, pk, rlk = fv.keygen(p, 201)
+    rng = np.random.default_rng(101)
+    P, qv = _features(rng, 4, 2048)
+    G = hers.encrypt_gallery(p, pk, P, 301)
+    Q = hers.encrypt_probe(p, pk, qv, 401)
+    c = hers.search_block_unrelinearized(p, Q, G[0])
+    want = [int(x) for x in hers.encode_slots(p, hers.plaintext_scores(P, qv)[None, :])[0]]
+    assert fv.noise(p, sk, c, want) > p.delta // 2
+
+
+def test_table2_operation_counts():
+    """Table 2, HERS row: ceil(m/n) d multiplications and ceil(m/n)(d-1) additions."""
+    for case in _paper()["table2_hers_counts"]["cases"]:
+        M = hers.blocks(case["m"], case["n"])
+        assert M * case["d"] == case["multiplications"]
+        assert M * (case["d"] - 1) == case["additions"]
