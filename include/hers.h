@@ -1,0 +1,182 @@
+/*
+ * hers.h -- C ABI of the MI355X HERS encrypted-search library (libhers.so).
+ *
+ * HERS (Engelsma, Jain, Boddeti, "HERS: Homomorphically Encrypted
+ * Representation Search") scores a query q in Z^d against a gallery
+ * P in Z^{d x m} under FV encryption: r(P, q) = P^T q computed on ciphertexts
+ * (Sec. 3.1, Eq. 1).  Each gallery dimension of a block of n items is one FV
+ * ciphertext with item j in slot j; each query dimension is one ciphertext with
+ * its value in every slot (Sec. 3.2, Eq. 2-4).  The server multiplies the
+ * ciphertexts dimension by dimension and sums over d (App. B, Alg. "HERS
+ * Search"); the client decrypts one score ciphertext per block.
+ *
+ * Conventions for every call
+ *   - Return value: HERS_OK (0) or a negative HERS_E* code; hers_last_error()
+ *     returns a thread-local message for the last failure.
+ *   - Pointers named *_dev are device pointers on the context's GPU; the caller
+ *     allocates and owns them (sizes from the hers_*_words / hers_*_bytes
+ *     queries) and must keep them alive until the work on `stream` completes.
+ *     Pointers without the suffix are host pointers.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL = the
+ *     default stream) and is complete when the stream is synchronised.
+ *   - Canonical ciphertext layout (the exchange format, bit-comparable with
+ *     the reference oracle): uint64 [2][k][n], component (ct[0], ct[1]),
+ *     residue modulo q_i, coefficient j, every residue in [0, q_i).
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Randomness: every random polynomial is drawn from Philox4x64-10 (Salmon et
+ * al., SC'11) with key (seed, domain) and counter (w / 4, obj0, obj1, obj2);
+ * binary polynomials take bit j mod 64 of word j / 64, errors are centred
+ * binomial (eta = 20) from word j, uniform residues mod q_i come from words
+ * 2(i n + j), 2(i n + j) + 1 read as a 128-bit integer reduced mod q_i.
+ */
+#ifndef HERS_H
+#define HERS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HERS_OK 0
+#define HERS_EINVAL (-1)   /* bad argument: null pointer, size, layout       */
+#define HERS_EPARAM (-2)   /* unsupported or non NTT-friendly parameters     */
+#define HERS_EDIM (-3)     /* dimension count out of range or mismatched     */
+#define HERS_ESPACE (-4)   /* workspace too small                            */
+#define HERS_EDEVICE (-5)  /* HIP runtime error                              */
+#define HERS_ENOMEM (-6)   /* device allocation of library tables failed     */
+
+#define HERS_MAX_QPRIMES 8
+
+/* Encryption parameters (App. A; Sec. 4.1 uses n = 4096, t = 1,032,193 and
+ * three 36-bit primes in q).
+ *   n          ring degree, a power of two in [256, 8192]; R = Z[x]/(x^n + 1)
+ *   k, qbits   q is the product of k primes, the i-th being the largest prime
+ *              below 2^qbits[i] that is 1 mod 2n and not yet taken (20..60 bits)
+ *   t_bits     t is the largest prime below 2^t_bits that is 1 mod 2n (<= 22)
+ *   w_bits     relinearization digit width: 0 = one digit per prime of q,
+ *              else each residue digit is split into w_bits-bit digits
+ *   d_max      largest number of dimensions a gallery may have; sizes the
+ *              internal exact-product base
+ *   feature_bound  largest |feature| of gallery and query; the context is
+ *              rejected unless d_max * feature_bound^2 < t / 2, so that every
+ *              score is recovered exactly modulo t (Sec. 3.2, "Encoding Scheme")
+ */
+typedef struct {
+  uint32_t n;
+  uint32_t k;
+  uint32_t qbits[HERS_MAX_QPRIMES];
+  uint32_t t_bits;
+  uint32_t w_bits;
+  uint32_t d_max;
+  uint32_t feature_bound;
+} hers_params;
+
+/* Values derived from hers_params by the prime rule (no GPU needed). */
+typedef struct {
+  uint32_t n, k;
+  uint64_t q[HERS_MAX_QPRIMES];   /* ciphertext primes q_0..q_{k-1}            */
+  uint64_t t;                     /* plaintext modulus                          */
+  uint32_t num_digits;            /* L: evaluation keys (gadget digits)         */
+  uint32_t num_aux;               /* K: primes < 2^30 of the exact-product base */
+  uint64_t aux[32];               /* those primes                               */
+  double   log2_q, log2_aux;      /* log2 q and log2 of the product base        */
+} hers_info;
+
+typedef struct hers_ctx hers_ctx;
+
+const char* hers_last_error(void);
+
+/* Resolve parameters on the host only (prime selection, digit counts). */
+int hers_params_resolve(const hers_params* params, hers_info* out);
+
+/* Create a context on HIP device `device`: precomputes NTT tables and the
+ * constants of the exact base conversions and uploads them (library-owned
+ * device memory, freed by hers_ctx_destroy). */
+int hers_ctx_create(const hers_params* params, int device, hers_ctx** out);
+void hers_ctx_destroy(hers_ctx* ctx);
+int hers_ctx_info(const hers_ctx* ctx, hers_info* out);
+
+/* ---- sizes (in elements of the stated type) ---------------------------- */
+uint64_t hers_blocks(const hers_ctx* ctx, int64_t m);                 /* M = ceil(m / n)          */
+uint64_t hers_ct_words(const hers_ctx* ctx);                          /* u64: 2 k n (one ct)      */
+uint64_t hers_pk_words(const hers_ctx* ctx);                          /* u64: 2 k n               */
+uint64_t hers_rlk_words(const hers_ctx* ctx);                         /* u64: L 2 k n             */
+uint64_t hers_gallery_words(const hers_ctx* ctx, int64_t m, int32_t d); /* u32: M K d 2 n search form */
+uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d);            /* u32: K d 2 n search form */
+/* workspace bytes for one call; `op` is 0 = encrypt_gallery (per block of
+ * the chunk size given in `m` items), 1 = encrypt_probe, 2 = search over m
+ * items, 3 = decrypt_scores over m items. */
+uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d);
+
+/* ---- keys (App. A, Alg. "Key Generation") ------------------------------- */
+/* theta_sk from R_2, pk = ([-(a s + e)]_q, a), and one evaluation key
+ * ([-(a_g s + e_g) + g s^2]_q, a_g) per gadget digit g (the paper's base-w
+ * decomposition generalised to RNS digits; w_bits above).  Philox key
+ * (seed, 1); objects s (0,0,0), a (1,0,0), e (2,0,0), a_g (3,g,0), e_g (4,g,0).
+ *   sk_dev  uint8 [n] in {0,1}; pk_dev canonical [2][k][n]; rlk_dev [L][2][k][n].
+ * The public and evaluation keys are also loaded into the context. */
+int hers_keygen(hers_ctx* ctx, uint64_t seed, uint8_t* sk_dev, uint64_t* pk_dev,
+                uint64_t* rlk_dev, void* stream);
+
+/* Load externally held keys (canonical layouts above) into the context. */
+int hers_load_keys(hers_ctx* ctx, const uint64_t* pk_dev, const uint64_t* rlk_dev, void* stream);
+
+/* ---- enrollment (Sec. 3.2 "Enrollment Protocol"; App. B Alg. "HERS Enrollment") ----
+ * Encrypts gallery blocks [block0, block0 + nblocks) of a gallery of m_total
+ * items and d dimensions.  feats_dev is int32 [d][ld] dimension-major
+ * (Eq. 3: row i holds dimension i of every item) and holds items
+ * block0*n .. block0*n + nblocks*n - 1 (those >= m_total are read as 0), ld
+ * is its row stride in items (>= nblocks*n, or >= the remaining items).
+ * Block b, dimension i is Encrypt(BatchEncode(row i of block b)) with Philox
+ * key (seed, 2) and objects (b, i, 0|1|2) for u, e1, e2.
+ *   gallery_dev  search form, u32 [M][K][d][2][n]; blocks outside the range
+ *                are not touched.
+ *   canon_dev    optional (NULL to skip): canonical cts [M][d][2][k][n].
+ *   work_dev     workspace of hers_workspace_bytes(ctx, 0, nblocks*n, d).  */
+int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t m_total,
+                         int32_t d, int64_t block0, int64_t nblocks, uint64_t seed,
+                         uint32_t* gallery_dev, uint64_t* canon_dev, void* work_dev,
+                         size_t work_bytes, void* stream);
+
+/* ---- query (App. B Alg. "HERS Search", client side) ---------------------
+ * Dimension i is the constant plaintext [q_i]_t (Eq. 2), encrypted with the
+ * public key (Philox key (seed, 3), objects (0, i, 0|1|2)).
+ *   query_dev int32 [d]; probe_dev search form u32 [K][d][2][n];
+ *   canon_dev optional canonical cts [d][2][k][n]. */
+int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed,
+                       uint32_t* probe_dev, uint64_t* canon_dev, void* work_dev,
+                       size_t work_bytes, void* stream);
+
+/* ---- search (App. B Alg. "HERS Search", server side) --------------------
+ * For every block b: X_0 = sum_i P_i0 G_bi0, X_1 = sum_i (P_i0 G_bi1 + P_i1 G_bi0),
+ * X_2 = sum_i P_i1 G_bi1 over Z[x]/(x^n+1) (centred representatives), then
+ * c_j = [round(t X_j / q)]_q (Alg. "Ciphertext Multiplication"), then one
+ * relinearization with the context's evaluation keys.
+ *   scores_dev canonical score cts [M][2][k][n]. */
+int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
+                const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
+                size_t work_bytes, void* stream);
+
+/* Batched search: nreq independent (gallery, probe) requests in one
+ * submission; request r reads galleries[r] (m[r] items, d[r] dims) and
+ * probes[r] and writes scores[r].  Results are bit-identical to nreq calls of
+ * hers_search.  work_dev: hers_workspace_bytes(ctx, 2, sum of m, max d). */
+int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries,
+                      const int64_t* m, const int32_t* d, const uint32_t* const* probes,
+                      uint64_t* const* scores, void* work_dev, size_t work_bytes, void* stream);
+
+/* ---- decryption (App. B Alg. "HERS Search", client side) ----------------
+ * pt = [round(t/q [c0 + c1 s]_q)]_t (Alg. "Decryption"), slot decode, centred
+ * into [-t/2, t/2): scores_out_dev int32 [m], item b*n + j from slot j of block b. */
+int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev,
+                        int64_t m, int32_t* scores_out_dev, void* work_dev, size_t work_bytes,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERS_H */

@@ -1,0 +1,319 @@
+// hers_api.cpp -- the C ABI of libhers (include/hers.h): context set-up,
+// size queries, argument checks and the launch sequences of each call.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hers.h"
+#include "kernels.h"
+#include "params.h"
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return fail(HERS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct hers_ctx {
+  hers_params prm;
+  hers::HostTables host;
+  int device;
+  std::vector<void*> allocs;
+  DevTabs T;
+  bool keys_loaded;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+int upload(hers_ctx* c, const std::vector<T>& v, const T** dst) {
+  void* p = nullptr;
+  if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return fail(HERS_ENOMEM, "hipMalloc of library tables failed");
+  c->allocs.push_back(p);
+  HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = (const T*)p;
+  return HERS_OK;
+}
+
+int alloc_dev(hers_ctx* c, size_t bytes, void** dst) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(HERS_ENOMEM, "hipMalloc of library tables failed");
+  c->allocs.push_back(p);
+  *dst = p;
+  return HERS_OK;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// per-block workspace of the search: accumulators u32 [3][K][n] + digits u64 [L][k][n]
+size_t search_ws_per_block(const HersConsts& C) {
+  return align256((size_t)3 * C.K * C.n * 4) + align256((size_t)C.L * C.k * C.n * 8);
+}
+
+size_t decrypt_ws_fixed(const HersConsts& C) { return align256((size_t)2 * C.k * C.n * 8); }
+size_t decrypt_ws_per_block(const HersConsts& C) { return align256((size_t)C.k * C.n * 8); }
+
+size_t enc_ws_per_block(const HersConsts& C, int32_t d, bool canon_given) {
+  size_t b = align256((size_t)d * C.n * 4);
+  if (!canon_given) b += align256((size_t)d * 2 * C.k * C.n * 8);
+  return b;
+}
+
+int check_d(const hers_ctx* c, int32_t d) {
+  if (d < 1 || (uint32_t)d > c->prm.d_max) return fail(HERS_EDIM, "d must be in [1, d_max]");
+  return HERS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hers_last_error(void) { return g_err.c_str(); }
+
+int hers_params_resolve(const hers_params* params, hers_info* out) {
+  if (!params || !out) return fail(HERS_EINVAL, "null argument");
+  std::string e = hers::resolve(*params, out);
+  if (!e.empty()) return fail(HERS_EPARAM, e);
+  return HERS_OK;
+}
+
+int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
+  if (!params || !out) return fail(HERS_EINVAL, "null argument");
+  *out = nullptr;
+  hers_ctx* c = new hers_ctx();
+  c->prm = *params;
+  c->device = device;
+  c->keys_loaded = false;
+  std::string e = hers::precompute(*params, &c->host);
+  if (!e.empty()) { delete c; return fail(HERS_EPARAM, e); }
+  DeviceGuard g(device);
+  int rc = HERS_OK;
+  const HersConsts& C = c->host.C;
+  std::vector<HersConsts> cv(1, C);
+  const HersConsts* dC = nullptr;
+  void *pk = nullptr, *pks = nullptr, *rl = nullptr, *rls = nullptr;
+  if ((rc = upload(c, cv, &dC)) ||
+      (rc = upload(c, c->host.qtw, &c->T.qtw)) || (rc = upload(c, c->host.qtw_sh, &c->T.qtw_sh)) ||
+      (rc = upload(c, c->host.qitw, &c->T.qitw)) || (rc = upload(c, c->host.qitw_sh, &c->T.qitw_sh)) ||
+      (rc = upload(c, c->host.ptw, &c->T.ptw)) || (rc = upload(c, c->host.ptw_sh, &c->T.ptw_sh)) ||
+      (rc = upload(c, c->host.pitw, &c->T.pitw)) || (rc = upload(c, c->host.pitw_sh, &c->T.pitw_sh)) ||
+      (rc = upload(c, c->host.ttw, &c->T.ttw)) || (rc = upload(c, c->host.ttw_sh, &c->T.ttw_sh)) ||
+      (rc = upload(c, c->host.titw, &c->T.titw)) || (rc = upload(c, c->host.titw_sh, &c->T.titw_sh)) ||
+      (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pk)) || (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pks)) ||
+      (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rl)) ||
+      (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rls))) {
+    std::string msg = g_err;
+    hers_ctx_destroy(c);
+    return fail(rc, msg);
+  }
+  c->T.C = dC;
+  c->T.pk_ntt = (uint64_t*)pk;
+  c->T.pk_ntt_sh = (uint64_t*)pks;
+  c->T.rlk_ntt = (uint64_t*)rl;
+  c->T.rlk_ntt_sh = (uint64_t*)rls;
+  *out = c;
+  return HERS_OK;
+}
+
+void hers_ctx_destroy(hers_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard g(ctx->device);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+  }
+  delete ctx;
+}
+
+int hers_ctx_info(const hers_ctx* ctx, hers_info* out) {
+  if (!ctx || !out) return fail(HERS_EINVAL, "null argument");
+  *out = ctx->host.info;
+  return HERS_OK;
+}
+
+uint64_t hers_blocks(const hers_ctx* ctx, int64_t m) {
+  if (!ctx || m < 0) return 0;
+  return (uint64_t)((m + ctx->host.C.n - 1) / ctx->host.C.n);
+}
+
+uint64_t hers_ct_words(const hers_ctx* ctx) { return ctx ? (uint64_t)2 * ctx->host.C.k * ctx->host.C.n : 0; }
+uint64_t hers_pk_words(const hers_ctx* ctx) { return hers_ct_words(ctx); }
+uint64_t hers_rlk_words(const hers_ctx* ctx) { return ctx ? (uint64_t)ctx->host.C.L * hers_ct_words(ctx) : 0; }
+
+uint64_t hers_gallery_words(const hers_ctx* ctx, int64_t m, int32_t d) {
+  if (!ctx || d < 1) return 0;
+  const HersConsts& C = ctx->host.C;
+  return hers_blocks(ctx, m) * C.K * (uint64_t)d * 2 * C.n;
+}
+
+uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d) {
+  if (!ctx || d < 1) return 0;
+  const HersConsts& C = ctx->host.C;
+  return (uint64_t)C.K * d * 2 * C.n;
+}
+
+uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d) {
+  if (!ctx) return 0;
+  const HersConsts& C = ctx->host.C;
+  const uint64_t M = hers_blocks(ctx, m);
+  switch (op) {
+    case 0: return M * enc_ws_per_block(C, d, false);
+    case 1: return align256((size_t)d * 2 * C.k * C.n * 8);
+    case 2: return M * search_ws_per_block(C);
+    case 3: return decrypt_ws_fixed(C) + M * decrypt_ws_per_block(C);
+    default: return 0;
+  }
+}
+
+int hers_keygen(hers_ctx* ctx, uint64_t seed, uint8_t* sk_dev, uint64_t* pk_dev, uint64_t* rlk_dev, void* stream) {
+  if (!ctx || !sk_dev || !pk_dev || !rlk_dev) return fail(HERS_EINVAL, "null argument");
+  DeviceGuard g(ctx->device);
+  const HersConsts& C = ctx->host.C;
+  HIP_TRY(hers::launch_keygen(ctx->T, C.n, C.k, C.L, seed, sk_dev, pk_dev, rlk_dev, S(stream)));
+  ctx->keys_loaded = true;
+  return HERS_OK;
+}
+
+int hers_load_keys(hers_ctx* ctx, const uint64_t* pk_dev, const uint64_t* rlk_dev, void* stream) {
+  if (!ctx || !pk_dev || !rlk_dev) return fail(HERS_EINVAL, "null argument");
+  DeviceGuard g(ctx->device);
+  const HersConsts& C = ctx->host.C;
+  HIP_TRY(hers::launch_load_keys(ctx->T, C.n, C.k, C.L, pk_dev, rlk_dev, S(stream)));
+  ctx->keys_loaded = true;
+  return HERS_OK;
+}
+
+int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t m_total, int32_t d,
+                         int64_t block0, int64_t nblocks, uint64_t seed, uint32_t* gallery_dev,
+                         uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !feats_dev || !gallery_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m_total);
+  if (m_total < 1 || block0 < 0 || nblocks < 1 || block0 + nblocks > M)
+    return fail(HERS_EINVAL, "block range outside the gallery");
+  const int64_t need_items = (m_total - block0 * (int64_t)C.n) < nblocks * (int64_t)C.n
+                                 ? m_total - block0 * (int64_t)C.n : nblocks * (int64_t)C.n;
+  if (ld < need_items) return fail(HERS_EINVAL, "feature row stride smaller than the items of the range");
+  const size_t per = enc_ws_per_block(C, d, canon_dev != nullptr);
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t chunk = (int64_t)(work_bytes / per);
+  DeviceGuard g(ctx->device);
+  for (int64_t lo = block0; lo < block0 + nblocks; lo += chunk) {
+    const int64_t nb = (lo + chunk < block0 + nblocks) ? chunk : block0 + nblocks - lo;
+    uint32_t* pt = (uint32_t*)work_dev;
+    uint64_t* canon = canon_dev ? canon_dev + (size_t)lo * d * 2 * C.k * C.n
+                                : (uint64_t*)((char*)work_dev + align256((size_t)nb * d * C.n * 4));
+    const int32_t* f = feats_dev + (lo - block0) * (int64_t)C.n;
+    HIP_TRY(hers::launch_encode(ctx->T, C.n, f, ld, m_total, d, lo, nb, pt, S(stream)));
+    HIP_TRY(hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)(nb * d), pt, nullptr, d, lo, seed,
+                                 HERS_DOMAIN_GALLERY, canon, S(stream)));
+    HIP_TRY(hers::launch_lift(ctx->T, C.n, canon, (uint32_t)(nb * d), d, lo, gallery_dev, S(stream)));
+    HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, gallery_dev + (size_t)lo * C.K * d * 2 * C.n,
+                               (uint64_t)nb * C.K * d * 2, 2 * d, 0, S(stream)));
+  }
+  return HERS_OK;
+}
+
+int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
+                       uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  const HersConsts& C = ctx->host.C;
+  uint64_t* canon = canon_dev;
+  if (!canon) {
+    if (!work_dev || work_bytes < (size_t)d * 2 * C.k * C.n * 8) return fail(HERS_ESPACE, "workspace too small");
+    canon = (uint64_t*)work_dev;
+  }
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed, HERS_DOMAIN_PROBE,
+                               canon, S(stream)));
+  HIP_TRY(hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, S(stream)));
+  HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, S(stream)));
+  return HERS_OK;
+}
+
+int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
+                uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !gallery_dev || !probe_dev || !scores_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (m < 1) return fail(HERS_EINVAL, "empty gallery");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m);
+  const size_t per = search_ws_per_block(C);
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t chunk = (int64_t)(work_bytes / per);
+  DeviceGuard g(ctx->device);
+  for (int64_t lo = 0; lo < M; lo += chunk) {
+    const int64_t hi = lo + chunk < M ? lo + chunk : M;
+    const int64_t nb = hi - lo;
+    uint32_t* acc = (uint32_t*)work_dev;
+    uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)nb * 3 * C.K * C.n * 4));
+    HIP_TRY(hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream)));
+    HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
+    HIP_TRY(hers::launch_rescale(ctx->T, C.n, acc, nb, lo, scores_dev, digits, S(stream)));
+    HIP_TRY(hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, scores_dev, S(stream)));
+  }
+  return HERS_OK;
+}
+
+int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
+                      const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores, void* work_dev,
+                      size_t work_bytes, void* stream) {
+  if (!ctx || nreq < 0 || (nreq && (!galleries || !m || !d || !probes || !scores)))
+    return fail(HERS_EINVAL, "null argument");
+  for (int32_t r = 0; r < nreq; ++r) {
+    int rc = hers_search(ctx, galleries[r], m[r], d[r], probes[r], scores[r], work_dev, work_bytes, stream);
+    if (rc) return rc;
+  }
+  return HERS_OK;
+}
+
+int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev, int64_t m,
+                        int32_t* scores_out_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !sk_dev || !scores_dev || !scores_out_dev) return fail(HERS_EINVAL, "null argument");
+  if (m < 1) return fail(HERS_EINVAL, "empty gallery");
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m);
+  const size_t fixed = decrypt_ws_fixed(C), per = decrypt_ws_per_block(C);
+  if (!work_dev || work_bytes < fixed + per) return fail(HERS_ESPACE, "workspace too small");
+  const int64_t chunk = (int64_t)((work_bytes - fixed) / per);
+  uint64_t* Sn = (uint64_t*)work_dev;
+  uint64_t* Ssh = Sn + (size_t)C.k * C.n;
+  uint64_t* x = (uint64_t*)((char*)work_dev + fixed);
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
+  for (int64_t lo = 0; lo < M; lo += chunk) {
+    const int64_t nb = lo + chunk < M ? chunk : M - lo;
+    HIP_TRY(hers::launch_dec_mul(ctx->T, C.n, C.k, scores_dev, nb, lo, Sn, Ssh, x, S(stream)));
+    HIP_TRY(hers::launch_dec_decode(ctx->T, C.n, x, nb, lo, m, scores_out_dev, S(stream)));
+  }
+  return HERS_OK;
+}
+
+}  // extern "C"

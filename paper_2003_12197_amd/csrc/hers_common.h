@@ -1,0 +1,276 @@
+// hers_common.h -- constants layout and modular arithmetic shared by the host
+// precompute and the gfx950 kernels of libhers.
+//
+// Moduli
+//   q_i  ciphertext primes (App. A: R_q = Z_q[x]/(x^n+1)), 30..61 bits, 64-bit words
+//   p_r  primes < 2^30 of the exact-product base P (internal): the tensor of
+//        centred representatives is exact over Z once P > 4 max|X|
+//   t    plaintext prime, < 2^22
+// All primes are 1 mod 2n so x^n + 1 splits and the negacyclic NTT exists.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define HD __host__ __device__ __forceinline__
+#else
+#define HD inline
+#endif
+
+#define HC_MAXQ 8      // ciphertext primes
+#define HC_MAXP 32     // exact-product base primes
+#define HC_MAXL 64     // gadget digits (evaluation keys)
+
+typedef unsigned __int128 u128;
+
+// Per-context constants, resident in device memory and read with uniform
+// indices (scalar loads).  "sh" = Shoup companion floor(w 2^W / m), W = 32 or 64.
+struct HersConsts {
+  uint32_t n, logn, k, K, L, w_bits, t, pad0;
+
+  // ---- ciphertext primes q_i
+  uint64_t q[HC_MAXQ];
+  uint64_t q_mu64[HC_MAXQ];            // floor(2^64 / q_i)
+  uint64_t q_m128h[HC_MAXQ];           // floor(2^128 / q_i), high word
+  uint64_t q_m128l[HC_MAXQ];           //                      low word
+  uint64_t q_bar[HC_MAXQ];             // floor(2^(2 beta) / q_i), beta = bit length
+  uint32_t q_beta[HC_MAXQ];
+  uint64_t q_r64[HC_MAXQ], q_r64_sh[HC_MAXQ];        // 2^64 mod q_i
+  uint64_t q_ninv[HC_MAXQ], q_ninv_sh[HC_MAXQ];      // n^-1 mod q_i
+  uint64_t q_delta[HC_MAXQ], q_delta_sh[HC_MAXQ];    // Delta = floor(q/t) mod q_i
+  uint64_t q_hatinv[HC_MAXQ], q_hatinv_sh[HC_MAXQ];  // (q/q_i)^-1 mod q_i
+  uint64_t q_t[HC_MAXQ], q_t_sh[HC_MAXQ];            // t mod q_i
+  uint64_t garner[HC_MAXQ][HC_MAXQ];                 // [i][j]: q_j^-1 mod q_i, j < i
+  uint64_t garner_sh[HC_MAXQ][HC_MAXQ];
+  uint64_t half_digit[HC_MAXQ];                      // mixed-radix digits of (q-1)/2
+  uint64_t Pmod_q[HC_MAXQ], Pmod_q_sh[HC_MAXQ];      // P mod q_i
+  uint64_t phat_q[HC_MAXP][HC_MAXQ];                 // (P/p_r) mod q_i
+  uint64_t phat_q_sh[HC_MAXP][HC_MAXQ];
+
+  // ---- exact-product base primes p_r
+  uint32_t p[HC_MAXP];
+  uint64_t p_mu64[HC_MAXP];                          // floor(2^64 / p_r)
+  uint32_t p_ninv[HC_MAXP], p_ninv_sh[HC_MAXP];
+  uint32_t p_hatinv[HC_MAXP], p_hatinv_sh[HC_MAXP];  // (P/p_r)^-1 mod p_r
+  double   p_inv[HC_MAXP];                           // 1 / p_r
+  uint32_t Qw_p[HC_MAXQ][HC_MAXP];                   // (q_0 ... q_{i-1}) mod p_r
+  uint32_t Qw_p_sh[HC_MAXQ][HC_MAXP];
+  uint32_t qmod_p[HC_MAXP];                          // q mod p_r
+  uint32_t qinv_p[HC_MAXP], qinv_p_sh[HC_MAXP];      // q^-1 mod p_r
+  uint32_t t_p[HC_MAXP], t_p_sh[HC_MAXP];            // t mod p_r
+
+  // ---- plaintext prime t
+  uint64_t t_mu64;                                   // floor(2^64 / t)
+  uint32_t t_ninv, t_ninv_sh;
+  uint32_t Qw_t[HC_MAXQ], Qw_t_sh[HC_MAXQ];          // (q_0 ... q_{i-1}) mod t
+  uint32_t qmod_t, qinv_t, qinv_t_sh, pad1;
+
+  // ---- gadget (relinearization digits), key order
+  uint32_t g_rho[HC_MAXL], g_shift[HC_MAXL];
+  uint64_t g_val[HC_MAXL][HC_MAXQ];                  // g mod q_i
+  uint64_t g_val_sh[HC_MAXL][HC_MAXQ];
+};
+
+// ============================================================== 32-bit moduli
+
+HD uint32_t mulhi32(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+HD uint64_t mulhi64(uint64_t a, uint64_t b) { return (uint64_t)(((u128)a * b) >> 64); }
+
+HD uint32_t add_p(uint32_t a, uint32_t b, uint32_t p) { uint32_t s = a + b; return s >= p ? s - p : s; }
+HD uint32_t sub_p(uint32_t a, uint32_t b, uint32_t p) { return a >= b ? a - b : a + p - b; }
+
+// a * w mod p for a < 2^32, w < p < 2^31, wsh = floor(w 2^32 / p) (Shoup).
+HD uint32_t shoup_p(uint32_t a, uint32_t w, uint32_t wsh, uint32_t p) {
+  uint32_t qh = mulhi32(a, wsh);
+  uint32_t r = a * w - qh * p;
+  return r >= p ? r - p : r;
+}
+
+// x mod p for any 64-bit x, mu = floor(2^64 / p), p < 2^31.
+HD uint32_t red_p(uint64_t x, uint32_t p, uint64_t mu) {
+  uint64_t qh = mulhi64(x, mu);
+  uint64_t r = x - qh * (uint64_t)p;
+  return (uint32_t)(r >= p ? r - p : r);
+}
+
+// ============================================================== 64-bit moduli
+
+HD uint64_t add_q(uint64_t a, uint64_t b, uint64_t q) { uint64_t s = a + b; return s >= q ? s - q : s; }
+HD uint64_t sub_q(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q for a < 2^64, w < q < 2^63, wsh = floor(w 2^64 / q) (Shoup).
+HD uint64_t shoup_q(uint64_t a, uint64_t w, uint64_t wsh, uint64_t q) {
+  uint64_t qh = mulhi64(a, wsh);
+  uint64_t r = a * w - qh * q;
+  return r >= q ? r - q : r;
+}
+
+// x mod q for any 64-bit x, mu = floor(2^64 / q).
+HD uint64_t red_q(uint64_t x, uint64_t q, uint64_t mu) {
+  uint64_t qh = mulhi64(x, mu);
+  uint64_t r = x - qh * q;
+  return r >= q ? r - q : r;
+}
+
+// Barrett reduction of x < 2^(2 beta), q of bit length beta <= 62,
+// mu = floor(2^(2 beta) / q) (Handbook of Applied Cryptography, Alg. 14.42).
+HD uint64_t barrett_q(u128 x, uint64_t q, uint64_t mu, uint32_t beta) {
+  uint64_t q1 = (uint64_t)(x >> (beta - 1));
+  uint64_t q3 = (uint64_t)(((u128)q1 * mu) >> (beta + 1));
+  uint64_t r = (uint64_t)x - q3 * q;
+  if (r >= q) r -= q;
+  if (r >= q) r -= q;
+  return r;
+}
+
+HD uint64_t mul_q(uint64_t a, uint64_t b, uint64_t q, uint64_t mu, uint32_t beta) {
+  return barrett_q((u128)a * b, q, mu, beta);
+}
+
+// Shoup companion floor(w 2^64 / q) for w < q < 2^63, from M = floor(2^128 / q).
+HD uint64_t shoup_companion_q(uint64_t w, uint64_t q, uint64_t mh, uint64_t ml) {
+  u128 lo = (u128)w * ml;
+  u128 e = (u128)w * mh + (uint64_t)(lo >> 64);   // floor(w M / 2^64): Q - 1 or Q
+  uint64_t est = (uint64_t)e;
+  u128 r = ((u128)w << 64) - (u128)est * q;
+  if (r >= (u128)q) est += 1;
+  return est;
+}
+
+// ============================================================== Philox4x64-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): two 64x64->128 multiplies per round, ten rounds, key bumped by the
+// Weyl constants between rounds.
+
+#define PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define PHILOX_M1 0xCA5A826395121157ULL
+#define PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define PHILOX_W1 0xBB67AE8584CAA73BULL
+
+struct Philox4 { uint64_t v[4]; };
+
+HD Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+#endif
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+    uint64_t lo0 = PHILOX_M0 * c0, hi0 = mulhi64(PHILOX_M0, c0);
+    uint64_t lo1 = PHILOX_M1 * c2, hi1 = mulhi64(PHILOX_M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  Philox4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// Domains separating the uses of one seed.
+#define HERS_DOMAIN_KEYGEN 1
+#define HERS_DOMAIN_GALLERY 2
+#define HERS_DOMAIN_PROBE 3
+
+// Word w of object (o0, o1, o2) under key (seed, domain).
+HD uint64_t philox_word(uint64_t seed, uint64_t domain, uint64_t o0, uint64_t o1, uint64_t o2, uint64_t w) {
+  Philox4 b = philox4x64_10(w >> 2, o0, o1, o2, seed, domain);
+  return b.v[w & 3];
+}
+
+HD int cbd20(uint64_t w) {
+  const uint64_t m = (1ULL << 20) - 1;
+  return __builtin_popcountll(w & m) - __builtin_popcountll((w >> 20) & m);
+}
+
+// ============================================================== exact CRT helpers
+
+// Mixed-radix digits a_i of x in [0, q) given residues v_i = x mod q_i
+// (Garner): x = a_0 + a_1 q_0 + a_2 q_0 q_1 + ..., 0 <= a_i < q_i.
+// Returns whether x > (q - 1)/2, i.e. whether the centred representative of x is x - q.
+HD bool garner_digits(const HersConsts& C, const uint64_t* v, uint64_t* a) {
+  const uint32_t k = C.k;
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint64_t qi = C.q[i];
+    uint64_t acc = v[i];
+    for (uint32_t j = 0; j < i; ++j) {
+      uint64_t aj = a[j] >= qi ? red_q(a[j], qi, C.q_mu64[i]) : a[j];
+      acc = sub_q(acc, aj, qi);
+      acc = shoup_q(acc, C.garner[i][j], C.garner_sh[i][j], qi);
+    }
+    a[i] = acc;
+  }
+  for (int i = (int)k - 1; i >= 0; --i)
+    if (a[i] != C.half_digit[i]) return a[i] > C.half_digit[i];
+  return false;
+}
+
+// Centred representative of the mixed-radix number (a, neg) modulo p_r.
+HD uint32_t mixed_to_p(const HersConsts& C, const uint64_t* a, bool neg, uint32_t r) {
+  const uint32_t p = C.p[r];
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < C.k; ++i) {
+    uint32_t ai = red_p(a[i], p, C.p_mu64[r]);
+    acc = add_p(acc, shoup_p(ai, C.Qw_p[i][r], C.Qw_p_sh[i][r], p), p);
+  }
+  return neg ? sub_p(acc, C.qmod_p[r], p) : acc;
+}
+
+// Centred representative of (a, neg) modulo t.
+HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
+  const uint32_t t = C.t;
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < C.k; ++i) {
+    uint32_t ai = red_p(a[i], t, C.t_mu64);
+    acc = add_p(acc, shoup_p(ai, C.Qw_t[i], C.Qw_t_sh[i], t), t);
+  }
+  return neg ? sub_p(acc, C.qmod_t, t) : acc;
+}
+
+// Exact conversion from base P to base q of an integer Y with |Y| < P/4:
+// y_r = [Y (P/p_r)^-1]_{p_r}; sum_r y_r / p_r = Y/P + gamma, so gamma is the
+// nearest integer to the sum (a quarter of headroom covers the rounding error
+// of the double-precision sum); Y = sum_r y_r (P/p_r) - gamma P.
+HD void p_to_q(const HersConsts& C, const uint32_t* y_res, uint64_t* out) {
+  uint32_t y[HC_MAXP];
+  double s = 0.0;
+  for (uint32_t r = 0; r < C.K; ++r) {
+    y[r] = shoup_p(y_res[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
+    s += (double)y[r] * C.p_inv[r];
+  }
+  const uint64_t gamma = (uint64_t)__builtin_rint(s);
+  for (uint32_t i = 0; i < C.k; ++i) {
+    const uint64_t qi = C.q[i];
+    uint64_t acc = 0;
+    for (uint32_t r = 0; r < C.K; ++r) acc = add_q(acc, shoup_q(y[r], C.phat_q[r][i], C.phat_q_sh[r][i], qi), qi);
+    out[i] = sub_q(acc, shoup_q(gamma, C.Pmod_q[i], C.Pmod_q_sh[i], qi), qi);
+  }
+}
+
+// Scale and round of one coefficient (Alg. "Ciphertext Multiplication"):
+// given X mod p_r (|X| < P/4), returns c_i = [round(t X / q)]_q mod q_i.
+// With T the centred representative of t X mod q, t X = q Y + T and |T| < q/2,
+// so Y = round(t X / q) = (t X - T) / q exactly; Y is formed in base P (q is
+// invertible there) and converted to base q.
+HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
+  uint64_t xq[HC_MAXQ], a[HC_MAXQ];
+  p_to_q(C, x, xq);                                   // X mod q_i
+  for (uint32_t i = 0; i < C.k; ++i) xq[i] = shoup_q(xq[i], C.q_t[i], C.q_t_sh[i], C.q[i]);  // t X mod q_i
+  const bool neg = garner_digits(C, xq, a);           // T
+  uint32_t yr[HC_MAXP];
+  for (uint32_t r = 0; r < C.K; ++r) {
+    const uint32_t p = C.p[r];
+    uint32_t tx = shoup_p(x[r], C.t_p[r], C.t_p_sh[r], p);
+    uint32_t T = mixed_to_p(C, a, neg, r);
+    yr[r] = shoup_p(sub_p(tx, T, p), C.qinv_p[r], C.qinv_p_sh[r], p);
+  }
+  p_to_q(C, yr, out);
+}
+
+// Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,
+// returns [round(t x / q)]_t in [0, t): with t x = q Y + T as above, Y = -T q^-1 mod t.
+HD uint32_t decrypt_coeff(const HersConsts& C, const uint64_t* x) {
+  uint64_t tx[HC_MAXQ], a[HC_MAXQ];
+  for (uint32_t i = 0; i < C.k; ++i) tx[i] = shoup_q(x[i], C.q_t[i], C.q_t_sh[i], C.q[i]);
+  const bool neg = garner_digits(C, tx, a);
+  uint32_t T = mixed_to_t(C, a, neg);
+  uint32_t y = shoup_p(T, C.qinv_t, C.qinv_t_sh, C.t);
+  return y ? C.t - y : 0;
+}

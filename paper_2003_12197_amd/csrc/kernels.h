@@ -1,0 +1,43 @@
+// kernels.h -- device table bundle and kernel launchers of libhers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hers_common.h"
+
+// Device pointers handed to every kernel by value.
+struct DevTabs {
+  const HersConsts* C;
+  const uint64_t *qtw, *qtw_sh, *qitw, *qitw_sh;   // [k][n]
+  const uint32_t *ptw, *ptw_sh, *pitw, *pitw_sh;   // [K][n]
+  const uint32_t *ttw, *ttw_sh, *titw, *titw_sh;   // [n]
+  uint64_t *pk_ntt, *pk_ntt_sh;                    // [2][k][n] NTT domain
+  uint64_t *rlk_ntt, *rlk_ntt_sh;                  // [L][2][k][n] NTT domain
+};
+
+namespace hers {
+hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
+                         uint64_t* pk, uint64_t* rlk, hipStream_t s);
+hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, const uint64_t* pk,
+                            const uint64_t* rlk, hipStream_t s);
+hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t m_total,
+                         int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt, hipStream_t s);
+hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct, const uint32_t* pt,
+                          const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
+                          uint64_t* canon, hipStream_t s);
+hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
+                       int64_t block0, uint32_t* out, hipStream_t s);
+hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
+                        int inverse, hipStream_t s);
+hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s);
+hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
+                          uint64_t* scores, uint64_t* digits, hipStream_t s);
+hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
+                        int64_t blk_lo, uint64_t* scores, hipStream_t s);
+hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,
+                         hipStream_t s);
+hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,
+                          int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s);
+hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
+                             int64_t m, int32_t* out, hipStream_t s);
+}  // namespace hers

@@ -1,0 +1,528 @@
+// kernels.hip -- gfx950 kernels of the HERS encrypted-search path.
+//
+// Layouts (device memory, little-endian words)
+//   canonical ciphertext   u64 [2][k][n]     residues mod q_i in [0, q_i)
+//   search form, gallery   u32 [M][K][d][2][n] centred representative mod p_r, NTT domain
+//   search form, probe     u32 [K][d][2][n]
+//   accumulators           u32 [M][3][K][n]   sum_i of the tensor, NTT then coefficient domain
+//   relin digits           u64 [M][L][k][n]   digit g of c2, reduced mod q_sigma
+// Workgroups are 256 lanes (four wave64s).
+#include "kernels.h"
+
+#include "ntt.h"
+
+#define WG 256
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restrict__ pk,
+         uint64_t* __restrict__ rlk) {
+  // Alg. "Key Generation": one workgroup per (job, residue rho); job 0 is the
+  // public key, job 1 + g the evaluation key of gadget digit g.  Every
+  // workgroup regenerates s from its counter, so no cross-workgroup traffic.
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x;
+  const uint32_t job = blockIdx.x, rho = blockIdx.y;
+  const uint64_t q = C.q[rho];
+  const ModQ mq{q};
+  uint64_t* S = lds64;
+  uint64_t* A = lds64 + n;
+  const uint64_t* tw = T.qtw + (size_t)rho * n;
+  const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
+  const uint64_t* itw = T.qitw + (size_t)rho * n;
+  const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
+
+  for (uint32_t j = tid; j < n; j += WG) {
+    uint64_t w = philox_word(seed, HERS_DOMAIN_KEYGEN, 0, 0, 0, j >> 6);
+    uint64_t s = (w >> (j & 63)) & 1;
+    S[j] = s;
+    if (job == 0 && rho == 0) sk[j] = (uint8_t)s;
+  }
+  // uniform a (job 0) or a_g (job 1 + g), residues rho, two per Philox block
+  const uint64_t oa0 = job == 0 ? 1 : 3, oa1 = job == 0 ? 0 : job - 1;
+  const uint64_t oe0 = job == 0 ? 2 : 4;
+  for (uint32_t h = tid; h < n / 2; h += WG) {
+    Philox4 b = philox4x64_10(((uint64_t)rho * n) / 2 + h, oa0, oa1, 0, seed, HERS_DOMAIN_KEYGEN);
+    for (int s = 0; s < 2; ++s) {
+      uint64_t lo = b.v[2 * s], hi = b.v[2 * s + 1];
+      uint64_t v = add_q(shoup_q(red_q(hi, q, C.q_mu64[rho]), C.q_r64[rho], C.q_r64_sh[rho], q),
+                         red_q(lo, q, C.q_mu64[rho]), q);
+      A[2 * h + s] = v;
+    }
+  }
+  uint64_t* out = job == 0 ? pk : rlk + (size_t)(job - 1) * 2 * k * n;        // this key's [2][k][n]
+  uint64_t* out_ntt = job == 0 ? T.pk_ntt : T.rlk_ntt + (size_t)(job - 1) * 2 * k * n;
+  uint64_t* out_sh = job == 0 ? T.pk_ntt_sh : T.rlk_ntt_sh + (size_t)(job - 1) * 2 * k * n;
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += WG) out[((size_t)1 * k + rho) * n + j] = A[j];
+  ntt_forward(S, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward(A, tw, twsh, mq, n, C.logn, tid, WG);
+  const uint64_t gv = job == 0 ? 0 : C.g_val[job - 1][rho];
+  const uint64_t gvsh = job == 0 ? 0 : C.g_val_sh[job - 1][rho];
+  for (uint32_t j = tid; j < n; j += WG) {
+    const uint64_t a = A[j], s = S[j];
+    out_ntt[((size_t)1 * k + rho) * n + j] = a;
+    out_sh[((size_t)1 * k + rho) * n + j] = shoup_companion_q(a, q, C.q_m128h[rho], C.q_m128l[rho]);
+    uint64_t v = sub_q(0, mul_q(a, s, q, C.q_bar[rho], C.q_beta[rho]), q);        // -a s
+    if (job) v = add_q(v, shoup_q(mul_q(s, s, q, C.q_bar[rho], C.q_beta[rho]), gv, gvsh, q), q);  // + g s^2
+    A[j] = v;
+  }
+  __syncthreads();
+  ntt_inverse(A, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  for (uint32_t g4 = tid; g4 < n / 4; g4 += WG) {
+    Philox4 b = philox4x64_10(g4, oe0, oa1, 0, seed, HERS_DOMAIN_KEYGEN);
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t j = 4 * g4 + s;
+      const int e = cbd20(b.v[s]);
+      const uint64_t em = e >= 0 ? (uint64_t)e : q - (uint64_t)(-e);
+      const uint64_t v = sub_q(A[j], em, q);
+      A[j] = v;
+      out[((size_t)0 * k + rho) * n + j] = v;
+    }
+  }
+  __syncthreads();
+  ntt_forward(A, tw, twsh, mq, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) {
+    out_ntt[((size_t)0 * k + rho) * n + j] = A[j];
+    out_sh[((size_t)0 * k + rho) * n + j] = shoup_companion_q(A[j], q, C.q_m128h[rho], C.q_m128l[rho]);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_load_keys(DevTabs T, const uint64_t* __restrict__ pk, const uint64_t* __restrict__ rlk) {
+  // NTT form and Shoup companions of externally supplied keys: one workgroup
+  // per key polynomial (key in [0, 1 + L), component, residue).
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x;
+  const uint32_t key = blockIdx.x, comp = blockIdx.y / k, rho = blockIdx.y % k;
+  const uint64_t q = C.q[rho];
+  const uint64_t* src = key == 0 ? pk : rlk + (size_t)(key - 1) * 2 * k * n;
+  uint64_t* dst = key == 0 ? T.pk_ntt : T.rlk_ntt + (size_t)(key - 1) * 2 * k * n;
+  uint64_t* dsh = key == 0 ? T.pk_ntt_sh : T.rlk_ntt_sh + (size_t)(key - 1) * 2 * k * n;
+  const size_t off = ((size_t)comp * k + rho) * n;
+  for (uint32_t j = tid; j < n; j += WG) lds64[j] = src[off + j];
+  __syncthreads();
+  ntt_forward(lds64, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, ModQ{q}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) {
+    dst[off + j] = lds64[j];
+    dsh[off + j] = shoup_companion_q(lds64[j], q, C.q_m128h[rho], C.q_m128l[rho]);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_total, int32_t d,
+         int64_t block0, uint32_t* __restrict__ pt) {
+  // Eq. 3 with slot packing: slot j of (block b, dimension i) holds item
+  // b n + j; the plaintext is the inverse negacyclic NTT mod t of the slots
+  // placed at bit-reversed positions (out[i] = m(psi^(2 brv(i)+1))).
+  extern __shared__ uint32_t lds32[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, tid = threadIdx.x, t = C.t;
+  const uint32_t c = blockIdx.x;
+  const uint32_t bl = c / d, i = c % d;
+  const int64_t b = block0 + bl;
+  for (uint32_t j = tid; j < n; j += WG) {
+    const int64_t item = b * n + j;
+    int64_t v = item < m_total ? feats[(int64_t)i * ld + (int64_t)bl * n + j] : 0;
+    int64_t z = v % (int64_t)t;
+    if (z < 0) z += t;
+    lds32[bit_reverse(j, C.logn)] = (uint32_t)z;
+  }
+  __syncthreads();
+  ntt_inverse(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) pt[(size_t)c * n + j] = lds32[j];
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict__ query,
+          int32_t d, int64_t block0, uint64_t seed, uint32_t domain, uint64_t* __restrict__ canon) {
+  // Alg. "Encryption" for ciphertext c (gallery: c = b_local d + i, or probe
+  // dimension c) and residue rho: ct = ([Delta m + pk0 u + e1]_q, [pk1 u + e2]_q).
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x;
+  const uint32_t c = blockIdx.x, rho = blockIdx.y;
+  const uint64_t q = C.q[rho];
+  const ModQ mq{q};
+  const uint64_t o0 = query ? 0 : (uint64_t)(block0 + c / d);
+  const uint64_t o1 = query ? c : c % d;
+  uint64_t* U = lds64;
+  uint64_t* V = lds64 + n;
+  uint64_t* W = V;                      // n/64 words of u, consumed before V is written
+  for (uint32_t bk = tid; bk < n / 256; bk += WG) {
+    Philox4 b = philox4x64_10(bk, o0, o1, 0, seed, domain);
+    for (int s = 0; s < 4; ++s) W[4 * bk + s] = b.v[s];
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += WG) U[j] = (W[j >> 6] >> (j & 63)) & 1;
+  __syncthreads();
+  const uint64_t* tw = T.qtw + (size_t)rho * n;
+  const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
+  ntt_forward(U, tw, twsh, mq, n, C.logn, tid, WG);
+  const uint64_t* pk0 = T.pk_ntt + (size_t)rho * n;
+  const uint64_t* pk0s = T.pk_ntt_sh + (size_t)rho * n;
+  const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
+  const uint64_t* pk1s = T.pk_ntt_sh + ((size_t)k + rho) * n;
+  for (uint32_t j = tid; j < n; j += WG) {
+    const uint64_t u = U[j];
+    V[j] = shoup_q(u, pk1[j], pk1s[j], q);
+    U[j] = shoup_q(u, pk0[j], pk0s[j], q);
+  }
+  __syncthreads();
+  const uint64_t* itw = T.qitw + (size_t)rho * n;
+  const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
+  ntt_inverse(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  uint32_t qconst = 0;
+  if (query) {
+    int64_t z = (int64_t)query[c] % (int64_t)C.t;
+    if (z < 0) z += C.t;
+    qconst = (uint32_t)z;
+  }
+  uint64_t* o_ct0 = canon + (((size_t)c * 2 + 0) * k + rho) * n;
+  uint64_t* o_ct1 = canon + (((size_t)c * 2 + 1) * k + rho) * n;
+  for (uint32_t g4 = tid; g4 < n / 4; g4 += WG) {
+    Philox4 b1 = philox4x64_10(g4, o0, o1, 1, seed, domain);
+    Philox4 b2 = philox4x64_10(g4, o0, o1, 2, seed, domain);
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t j = 4 * g4 + s;
+      const int e1 = cbd20(b1.v[s]), e2 = cbd20(b2.v[s]);
+      const uint64_t m = query ? (j == 0 ? qconst : 0) : pt[(size_t)c * n + j];
+      uint64_t v0 = add_q(U[j], shoup_q(m, C.q_delta[rho], C.q_delta_sh[rho], q), q);
+      v0 = e1 >= 0 ? add_q(v0, (uint64_t)e1, q) : sub_q(v0, (uint64_t)(-e1), q);
+      uint64_t v1 = e2 >= 0 ? add_q(V[j], (uint64_t)e2, q) : sub_q(V[j], (uint64_t)(-e2), q);
+      o_ct0[j] = v0;
+      o_ct1[j] = v1;
+    }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_lift(DevTabs T, const uint64_t* __restrict__ canon, uint32_t nct, int32_t d, int64_t block0,
+       uint32_t* __restrict__ out) {
+  // Exact centred lift of canonical residues mod q to residues mod p_r
+  // (the representative in (-q/2, q/2) that the tensor product needs):
+  // Garner mixed-radix digits decide the sign exactly, then the digits are
+  // evaluated mod p_r.  Writes the search form (coefficient domain).
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, K = C.K;
+  const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
+  if (idx >= (uint64_t)nct * n) return;
+  const uint32_t c = (uint32_t)(idx / n), j = (uint32_t)(idx % n);
+  const int64_t b = block0 + c / d;
+  const uint32_t i = c % d;
+  for (uint32_t poly = 0; poly < 2; ++poly) {
+    uint64_t v[HC_MAXQ], a[HC_MAXQ];
+    for (uint32_t r = 0; r < k; ++r) v[r] = canon[(((size_t)c * 2 + poly) * k + r) * n + j];
+    const bool neg = garner_digits(C, v, a);
+    for (uint32_t r = 0; r < K; ++r) {
+      const size_t o = ((((size_t)b * K + r) * d + i) * 2 + poly) * n + j;
+      out[o] = mixed_to_p(C, a, neg, r);
+    }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse) {
+  // In-place negacyclic NTT mod p_r of polynomial blockIdx.x, where
+  // r = (blockIdx.x / inner) mod K.
+  extern __shared__ uint32_t lds32[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, tid = threadIdx.x;
+  const uint32_t r = (blockIdx.x / inner) % C.K;
+  uint32_t* a = polys + (size_t)blockIdx.x * n;
+  for (uint32_t j = tid; j < n; j += WG) lds32[j] = a[j];
+  __syncthreads();
+  const ModP mp{C.p[r]};
+  if (!inverse)
+    ntt_forward(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG);
+  else
+    ntt_inverse(lds32, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r], C.p_ninv_sh[r],
+                mp, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[j];
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe,
+      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group, uint32_t* __restrict__ acc) {
+  // The hot loop (Alg. "HERS Search" with the tensor of Alg. "Ciphertext
+  // Multiplication", summed over the d dimensions before any rescale):
+  //   A0 = sum_i P_i0 G_bi0,  A1 = sum_i (P_i0 G_bi1 + P_i1 G_bi0),  A2 = sum_i P_i1 G_bi1
+  // slot-wise in the NTT domain mod p_r.  One lane per (prime r, NTT slot);
+  // products (< 2^60) accumulate unreduced in 64 bits and are folded every 8
+  // dimensions.  acc is indexed from blk_lo.
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, K = C.K;
+  const uint32_t slot = blockIdx.x * WG + threadIdx.x;
+  const uint32_t r = blockIdx.y;
+  const uint32_t p = C.p[r];
+  const uint64_t mu = C.p_mu64[r];
+  const int64_t b0 = blk_lo + (int64_t)blockIdx.z * blocks_per_group;
+  const int64_t b1 = b0 + blocks_per_group < blk_hi ? b0 + blocks_per_group : blk_hi;
+  const uint32_t* pr = probe + (size_t)r * d * 2 * n + slot;
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t* gb = gallery + (((size_t)b * K + r) * d * 2) * n + slot;
+    uint64_t a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t i = 0; i < d; ++i) {
+      const uint64_t g0 = gb[(size_t)(2 * i) * n], g1 = gb[(size_t)(2 * i + 1) * n];
+      const uint64_t p0 = pr[(size_t)(2 * i) * n], p1 = pr[(size_t)(2 * i + 1) * n];
+      a0 += p0 * g0;
+      a1 += p0 * g1 + p1 * g0;
+      a2 += p1 * g1;
+      if ((i & 7) == 7) { a0 = red_p(a0, p, mu); a1 = red_p(a1, p, mu); a2 = red_p(a2, p, mu); }
+    }
+    uint32_t* o = acc + ((size_t)(b - blk_lo) * 3 * K + r) * n + slot;
+    o[0] = red_p(a0, p, mu);
+    o[(size_t)K * n] = red_p(a1, p, mu);
+    o[(size_t)2 * K * n] = red_p(a2, p, mu);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_rescale(DevTabs T, const uint32_t* __restrict__ X, int64_t nblk, int64_t blk_lo,
+          uint64_t* __restrict__ scores, uint64_t* __restrict__ digits) {
+  // Per coefficient of X_j (j = 0, 1, 2; residues mod p_r, |X| < P/4):
+  // c_j = [round(t X_j / q)]_q.  c0, c1 go to the score ciphertext (before
+  // relinearization); c2 is split into the gadget digits y_g.
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, K = C.K, L = C.L;
+  const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
+  if (idx >= (uint64_t)nblk * 3 * n) return;
+  const uint64_t bj = idx / n;
+  const uint32_t c = (uint32_t)(idx % n);
+  const int64_t bl = (int64_t)(bj / 3);
+  const uint32_t j = (uint32_t)(bj % 3);
+  uint32_t x[HC_MAXP];
+  for (uint32_t r = 0; r < K; ++r) x[r] = X[(bj * K + r) * n + c];
+  uint64_t out[HC_MAXQ];
+  scale_round_coeff(C, x, out);
+  const int64_t b = blk_lo + bl;
+  if (j < 2) {
+    for (uint32_t i = 0; i < k; ++i) scores[(((size_t)b * 2 + j) * k + i) * n + c] = out[i];
+    return;
+  }
+  for (uint32_t g = 0; g < L; ++g) {
+    const uint32_t rho = C.g_rho[g];
+    const uint64_t y = shoup_q(out[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
+    const uint64_t dg = C.w_bits ? (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1) : y;
+    for (uint32_t s = 0; s < k; ++s)
+      digits[(((size_t)bl * L + g) * k + s) * n + c] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+  }
+}
+
+template <int NPT>
+__global__ void __launch_bounds__(WG)
+k_relin(DevTabs T, const uint64_t* __restrict__ digits, int64_t blk_lo, uint64_t* __restrict__ scores) {
+  // Relinearization of block blk_lo + blockIdx.x, residue sigma:
+  // (c0, c1) += sum_g y_g (rlk_g0, rlk_g1) in R_q; products in the NTT domain.
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
+  const int64_t bl = blockIdx.x;
+  const int64_t b = blk_lo + bl;
+  const uint32_t sg = blockIdx.y;
+  const uint64_t q = C.q[sg];
+  const ModQ mq{q};
+  uint64_t acc0[NPT], acc1[NPT];
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) { acc0[u] = 0; acc1[u] = 0; }
+  const uint64_t* tw = T.qtw + (size_t)sg * n;
+  const uint64_t* twsh = T.qtw_sh + (size_t)sg * n;
+  for (uint32_t g = 0; g < L; ++g) {
+    const uint64_t* src = digits + (((size_t)bl * L + g) * k + sg) * n;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) lds64[tid + u * WG] = src[tid + u * WG];
+    __syncthreads();
+    ntt_forward(lds64, tw, twsh, mq, n, C.logn, tid, WG);
+    const size_t r0 = (((size_t)g * 2 + 0) * k + sg) * n, r1 = (((size_t)g * 2 + 1) * k + sg) * n;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const uint32_t jj = tid + u * WG;
+      const uint64_t y = lds64[jj];
+      acc0[u] = add_q(acc0[u], shoup_q(y, T.rlk_ntt[r0 + jj], T.rlk_ntt_sh[r0 + jj], q), q);
+      acc1[u] = add_q(acc1[u], shoup_q(y, T.rlk_ntt[r1 + jj], T.rlk_ntt_sh[r1 + jj], q), q);
+    }
+    __syncthreads();
+  }
+  const uint64_t* itw = T.qitw + (size_t)sg * n;
+  const uint64_t* itwsh = T.qitw_sh + (size_t)sg * n;
+  for (uint32_t comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) lds64[tid + u * WG] = comp ? acc1[u] : acc0[u];
+    __syncthreads();
+    ntt_inverse(lds64, itw, itwsh, C.q_ninv[sg], C.q_ninv_sh[sg], mq, n, C.logn, tid, WG);
+    uint64_t* dst = scores + (((size_t)b * 2 + comp) * k + sg) * n;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const uint32_t jj = tid + u * WG;
+      dst[jj] = add_q(dst[jj], lds64[jj], q);
+    }
+    __syncthreads();
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, uint64_t* __restrict__ Ssh) {
+  // NTT of the secret key mod q_sigma with Shoup companions (decryption).
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, tid = threadIdx.x, sg = blockIdx.x;
+  const uint64_t q = C.q[sg];
+  for (uint32_t j = tid; j < n; j += WG) lds64[j] = sk[j] ? 1 : 0;
+  __syncthreads();
+  ntt_forward(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) {
+    S[(size_t)sg * n + j] = lds64[j];
+    Ssh[(size_t)sg * n + j] = shoup_companion_q(lds64[j], q, C.q_m128h[sg], C.q_m128l[sg]);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const uint64_t* __restrict__ S,
+          const uint64_t* __restrict__ Ssh, uint64_t* __restrict__ xout) {
+  // x = [c0 + c1 s]_q for block blk_lo + blockIdx.x, residue sigma.
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x, sg = blockIdx.y;
+  const int64_t bl = blockIdx.x, b = blk_lo + bl;
+  const uint64_t q = C.q[sg];
+  const ModQ mq{q};
+  const uint64_t* c0 = scores + (((size_t)b * 2 + 0) * k + sg) * n;
+  const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * k + sg) * n;
+  for (uint32_t j = tid; j < n; j += WG) lds64[j] = c1[j];
+  __syncthreads();
+  ntt_forward(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG)
+    lds64[j] = shoup_q(lds64[j], S[(size_t)sg * n + j], Ssh[(size_t)sg * n + j], q);
+  __syncthreads();
+  ntt_inverse(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg], mq,
+              n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[j], c0[j], q);
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t m, int32_t* __restrict__ out) {
+  // pt = [round(t x / q)]_t coefficient-wise, then slot j = pt(psi^(2j+1))
+  // (forward NTT mod t, read at brv(j)), centred into [-t/2, t/2).
+  extern __shared__ uint32_t lds32[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x, t = C.t;
+  const int64_t bl = blockIdx.x, b = blk_lo + bl;
+  for (uint32_t j = tid; j < n; j += WG) {
+    uint64_t v[HC_MAXQ];
+    for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
+    lds32[j] = decrypt_coeff(C, v);
+  }
+  __syncthreads();
+  ntt_forward(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG);
+  for (uint32_t s = tid; s < n; s += WG) {
+    const int64_t item = b * n + s;
+    if (item >= m) continue;
+    const uint32_t z = lds32[bit_reverse(s, C.logn)];
+    out[item] = z >= (t + 1) / 2 ? (int32_t)z - (int32_t)t : (int32_t)z;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+namespace hers {
+
+static size_t lds_bytes(uint32_t n, int words64) { return (size_t)n * 8 * words64; }
+
+hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
+                         uint64_t* pk, uint64_t* rlk, hipStream_t s) {
+  hipLaunchKernelGGL(k_keygen, dim3(1 + L, k), dim3(WG), lds_bytes(n, 2), s, T, seed, sk, pk, rlk);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, const uint64_t* pk,
+                            const uint64_t* rlk, hipStream_t s) {
+  hipLaunchKernelGGL(k_load_keys, dim3(1 + L, 2 * k), dim3(WG), lds_bytes(n, 1), s, T, pk, rlk);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t m_total,
+                         int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt, hipStream_t s) {
+  hipLaunchKernelGGL(k_encode, dim3((uint32_t)(nblocks * d)), dim3(WG), (size_t)n * 4, s, T, feats, ld, m_total,
+                     d, block0, pt);
+  return hipGetLastError();
+}
+
+hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct, const uint32_t* pt,
+                          const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
+                          uint64_t* canon, hipStream_t s) {
+  size_t lds = lds_bytes(n, 2);
+  hipLaunchKernelGGL(k_encrypt, dim3(nct, k), dim3(WG), lds, s, T, pt, query, d, block0, seed, domain, canon);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
+                       int64_t block0, uint32_t* out, hipStream_t s) {
+  uint64_t total = (uint64_t)nct * n;
+  hipLaunchKernelGGL(k_lift, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, canon, nct, d, block0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
+                        int inverse, hipStream_t s) {
+  hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys), dim3(WG), (size_t)n * 4, s, T, polys, inner, inverse);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s) {
+  const int64_t nb = blk_hi - blk_lo;
+  const uint64_t base = (uint64_t)(n / WG) * K;
+  // about 4096 workgroups: 16 per compute unit
+  uint64_t bpg = (uint64_t)nb * base / 4096;
+  if (bpg < 1) bpg = 1;
+  const uint64_t groups = ((uint64_t)nb + bpg - 1) / bpg;
+  hipLaunchKernelGGL(k_mac, dim3(n / WG, K, (uint32_t)groups), dim3(WG), 0, s, T, gallery, probe, d, blk_lo,
+                     blk_hi, (uint32_t)bpg, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
+                          uint64_t* scores, uint64_t* digits, hipStream_t s) {
+  uint64_t total = (uint64_t)nblk * 3 * n;
+  hipLaunchKernelGGL(k_rescale, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, X, nblk, blk_lo,
+                     scores, digits);
+  return hipGetLastError();
+}
+
+hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
+                        int64_t blk_lo, uint64_t* scores, hipStream_t s) {
+  dim3 grid((uint32_t)nblk, k);
+  size_t lds = lds_bytes(n, 1);
+  switch (n / WG) {
+    case 1: hipLaunchKernelGGL(k_relin<1>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 2: hipLaunchKernelGGL(k_relin<2>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 4: hipLaunchKernelGGL(k_relin<4>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 8: hipLaunchKernelGGL(k_relin<8>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 16: hipLaunchKernelGGL(k_relin<16>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 32: hipLaunchKernelGGL(k_relin<32>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_sk_ntt, dim3(k), dim3(WG), lds_bytes(n, 1), s, T, sk, S, Ssh);
+  return hipGetLastError();
+}
+
+hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,
+                          int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_dec_mul, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
+                             int64_t m, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), (size_t)n * 4, s, T, x, blk_lo, m, out);
+  return hipGetLastError();
+}
+
+}  // namespace hers

@@ -1,0 +1,238 @@
+"""Python binding of libhers (argument marshalling only).
+
+Every step of keygen, encryption, search and decryption runs in the HIP
+kernels of libhers.so; this module allocates device memory through PyTorch,
+passes raw pointers and the current HIP stream, and checks return codes.  It
+raises if the library is missing: there is no CPU fallback.
+
+The call names follow include/hers.h: keygen, load_keys, encrypt_gallery,
+encrypt_probe, search, search_batch, decrypt_scores.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhers.so")
+
+c_u32, c_u64, c_i32, c_i64, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+MAX_QPRIMES = 8
+
+
+class HersParams(ctypes.Structure):
+    _fields_ = [("n", c_u32), ("k", c_u32), ("qbits", c_u32 * MAX_QPRIMES), ("t_bits", c_u32),
+                ("w_bits", c_u32), ("d_max", c_u32), ("feature_bound", c_u32)]
+
+
+class HersInfo(ctypes.Structure):
+    _fields_ = [("n", c_u32), ("k", c_u32), ("q", c_u64 * MAX_QPRIMES), ("t", c_u64), ("num_digits", c_u32),
+                ("num_aux", c_u32), ("aux", c_u64 * 32), ("log2_q", ctypes.c_double), ("log2_aux", ctypes.c_double)]
+
+
+EXPORTS = {
+    "hers_last_error": (ctypes.c_char_p, []),
+    "hers_params_resolve": (c_i32, [ctypes.POINTER(HersParams), ctypes.POINTER(HersInfo)]),
+    "hers_ctx_create": (c_i32, [ctypes.POINTER(HersParams), c_i32, ctypes.POINTER(c_vp)]),
+    "hers_ctx_destroy": (None, [c_vp]),
+    "hers_ctx_info": (c_i32, [c_vp, ctypes.POINTER(HersInfo)]),
+    "hers_blocks": (c_u64, [c_vp, c_i64]),
+    "hers_ct_words": (c_u64, [c_vp]),
+    "hers_pk_words": (c_u64, [c_vp]),
+    "hers_rlk_words": (c_u64, [c_vp]),
+    "hers_gallery_words": (c_u64, [c_vp, c_i64, c_i32]),
+    "hers_probe_words": (c_u64, [c_vp, c_i32]),
+    "hers_workspace_bytes": (c_u64, [c_vp, ctypes.c_int, c_i64, c_i32]),
+    "hers_keygen": (c_i32, [c_vp, c_u64, c_vp, c_vp, c_vp, c_vp]),
+    "hers_load_keys": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
+                                     ctypes.c_size_t, c_vp]),
+    "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
+                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
+    "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+}
+
+OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT = 0, 1, 2, 3
+
+
+class HersError(RuntimeError):
+    pass
+
+
+def declare(lib):
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def library(path=LIB_PATH):
+    """Load libhers.so (built by paper_2003_12197_amd.build)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise HersError("libhers.so is not built (run paper_2003_12197_amd.build.build())")
+        _LIB = declare(ctypes.CDLL(path))
+    return _LIB
+
+
+def make_params(n, qbits, t_bits, w_bits=0, d_max=128, feature_bound=63):
+    p = HersParams()
+    p.n, p.k, p.t_bits, p.w_bits, p.d_max, p.feature_bound = n, len(qbits), t_bits, w_bits, d_max, feature_bound
+    for i, b in enumerate(qbits):
+        p.qbits[i] = b
+    return p
+
+
+def _check(lib, rc, what):
+    if rc != 0:
+        raise HersError("%s failed (%d): %s" % (what, rc, lib.hers_last_error().decode()))
+
+
+def resolve(n, qbits, t_bits, w_bits=0, d_max=128, feature_bound=63):
+    """Host-only parameter resolution (no GPU)."""
+    lib = library()
+    info = HersInfo()
+    _check(lib, lib.hers_params_resolve(ctypes.byref(make_params(n, qbits, t_bits, w_bits, d_max, feature_bound)),
+                                        ctypes.byref(info)), "hers_params_resolve")
+    return info
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A libhers context on one GPU: parameters, tables and loaded keys."""
+
+    def __init__(self, n, qbits, t_bits, w_bits=0, d_max=128, feature_bound=63, device=0):
+        self.lib = library()
+        self.device = torch.device("cuda", device)
+        self.params = make_params(n, qbits, t_bits, w_bits, d_max, feature_bound)
+        h = c_vp()
+        _check(self.lib, self.lib.hers_ctx_create(ctypes.byref(self.params), device, ctypes.byref(h)),
+               "hers_ctx_create")
+        self.handle = h
+        info = HersInfo()
+        _check(self.lib, self.lib.hers_ctx_info(h, ctypes.byref(info)), "hers_ctx_info")
+        self.info = info
+        self.n, self.k, self.K, self.L = info.n, info.k, info.num_aux, info.num_digits
+        self.q = [info.q[i] for i in range(info.k)]
+        self.t = info.t
+
+    def close(self):
+        if self.handle:
+            self.lib.hers_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- helpers
+    def _empty(self, count, dtype):
+        return torch.empty(int(count), dtype=dtype, device=self.device)
+
+    def workspace(self, op, m, d):
+        nbytes = int(self.lib.hers_workspace_bytes(self.handle, op, int(m), int(d)))
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def blocks(self, m):
+        return int(self.lib.hers_blocks(self.handle, int(m)))
+
+    # ------------------------------------------------------------- calls
+    def keygen(self, seed):
+        """Returns (sk uint8 [n], pk int64 [2][k][n], rlk int64 [L][2][k][n]); keys are loaded."""
+        n, k, L = self.n, self.k, self.L
+        sk = self._empty(n, torch.uint8)
+        pk = self._empty(2 * k * n, torch.int64).view(2, k, n)
+        rlk = self._empty(L * 2 * k * n, torch.int64).view(L, 2, k, n)
+        _check(self.lib, self.lib.hers_keygen(self.handle, seed, _ptr(sk), _ptr(pk), _ptr(rlk), _stream()),
+               "hers_keygen")
+        return sk, pk, rlk
+
+    def load_keys(self, pk, rlk):
+        _check(self.lib, self.lib.hers_load_keys(self.handle, _ptr(pk.contiguous()), _ptr(rlk.contiguous()),
+                                                 _stream()), "hers_load_keys")
+
+    def new_gallery(self, m, d):
+        return self._empty(self.lib.hers_gallery_words(self.handle, int(m), int(d)), torch.int32)
+
+    def encrypt_gallery(self, feats, m_total, seed, block0=0, nblocks=None, gallery=None, canon=None,
+                        workspace=None):
+        """feats: int32 [d][ld] on the device holding items block0*n ...; returns the search-form gallery."""
+        d, ld = feats.shape
+        M = self.blocks(m_total)
+        if nblocks is None:
+            nblocks = M - block0
+        if gallery is None:
+            gallery = self.new_gallery(m_total, d)
+        if workspace is None:
+            workspace = self.workspace(OP_ENCRYPT_GALLERY, nblocks * self.n, d)
+        feats = feats.contiguous()
+        _check(self.lib, self.lib.hers_encrypt_gallery(
+            self.handle, _ptr(feats), ld, int(m_total), d, int(block0), int(nblocks), seed, _ptr(gallery),
+            _ptr(canon), _ptr(workspace), workspace.numel(), _stream()), "hers_encrypt_gallery")
+        return gallery
+
+    def encrypt_probe(self, query, seed, canon=None, probe=None, workspace=None):
+        """query: int32 [d] on the device; returns the search-form probe."""
+        d = query.numel()
+        if probe is None:
+            probe = self._empty(self.lib.hers_probe_words(self.handle, d), torch.int32)
+        if workspace is None and canon is None:
+            workspace = self.workspace(OP_ENCRYPT_PROBE, 0, d)
+        _check(self.lib, self.lib.hers_encrypt_probe(
+            self.handle, _ptr(query.contiguous()), d, seed, _ptr(probe), _ptr(canon), _ptr(workspace),
+            0 if workspace is None else workspace.numel(), _stream()), "hers_encrypt_probe")
+        return probe
+
+    def new_scores(self, m):
+        return self._empty(self.blocks(m) * 2 * self.k * self.n, torch.int64).view(-1, 2, self.k, self.n)
+
+    def search(self, gallery, m, d, probe, scores=None, workspace=None):
+        """Encrypted scores [M][2][k][n] (canonical)."""
+        if scores is None:
+            scores = self.new_scores(m)
+        if workspace is None:
+            workspace = self.workspace(OP_SEARCH, m, d)
+        _check(self.lib, self.lib.hers_search(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
+                                              _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
+               "hers_search")
+        return scores
+
+    def search_batch(self, galleries, ms, ds, probes, scores=None, workspace=None):
+        nreq = len(galleries)
+        if scores is None:
+            scores = [self.new_scores(m) for m in ms]
+        if workspace is None:
+            workspace = self.workspace(OP_SEARCH, max(ms), max(ds))
+        arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
+        _check(self.lib, self.lib.hers_search_batch(
+            self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
+            _ptr(workspace), workspace.numel(), _stream()), "hers_search_batch")
+        return scores
+
+    def decrypt_scores(self, sk, scores, m, out=None, workspace=None):
+        """int32 [m] decrypted scores (client side)."""
+        if out is None:
+            out = self._empty(m, torch.int32)
+        if workspace is None:
+            workspace = self.workspace(OP_DECRYPT, m, 1)
+        _check(self.lib, self.lib.hers_decrypt_scores(self.handle, _ptr(sk), _ptr(scores), int(m), _ptr(out),
+                                                      _ptr(workspace), workspace.numel(), _stream()),
+               "hers_decrypt_scores")
+        return out

@@ -1,0 +1,237 @@
+"""GPU parity: libhers on the GPU against the oracle, bit for bit.
+
+Every canonical ciphertext (keys, gallery, probe, encrypted scores) must equal
+the oracle's residue by residue, and decrypted scores must equal the
+plaintext inner products P^T q (Eq. 1 and Eq. 4).  Integer work: tolerance 0.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fv, hers
+from paper_2003_12197_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = {
+    # toy, non-secure: n = 2048, q one 54-bit prime, relinearization digits of 18 bits
+    "c1": dict(n=2048, qbits=(54,), t_bits=20, w_bits=18),
+    # the same ring with q two 54-bit primes, which has room for the product noise
+    "c1b": dict(n=2048, qbits=(54, 54), t_bits=20, w_bits=0),
+    # three 36-bit primes (the paper's q shape) at n = 2048
+    "r36": dict(n=2048, qbits=(36, 36, 36), t_bits=20, w_bits=0),
+}
+
+
+def res(poly, primes):
+    return np.array(fv.to_residues(poly, primes), dtype=np.int64)
+
+
+class Case:
+    """Oracle and GPU state for one configuration and one gallery."""
+
+    def __init__(self, gpu_lib, cfg, d, m, key_seed=201, gal_seed=301, probe_seed=401, feat_seed=101):
+        c = CONFIGS[cfg]
+        self.op = fv.Params(**c)
+        self.ctx = gpu_lib.Context(d_max=max(d, 16), **c)
+        self.d, self.m = d, m
+        self.key_seed, self.gal_seed, self.probe_seed = key_seed, gal_seed, probe_seed
+        self.P, self.qv = synth.uniform_features(feat_seed, d, m)
+        self.osk, self.opk, self.orlk = fv.keygen(self.op, key_seed)
+        self.sk, self.pk, self.rlk = self.ctx.keygen(key_seed)
+        dev = self.ctx.device
+        self.feats = torch.from_numpy(self.P).to(dev)
+        self.query = torch.from_numpy(self.qv).to(dev)
+        self.M = self.ctx.blocks(m)
+        k, n = self.ctx.k, self.ctx.n
+        self.gcanon = torch.zeros(self.M * d * 2 * k * n, dtype=torch.int64, device=dev)
+        self.gallery = self.ctx.encrypt_gallery(self.feats, m, gal_seed, canon=self.gcanon)
+        self.pcanon = torch.zeros(d * 2 * k * n, dtype=torch.int64, device=dev)
+        self.probe = self.ctx.encrypt_probe(self.query, probe_seed, canon=self.pcanon)
+        self.scores = self.ctx.search(self.gallery, m, d, self.probe)
+        torch.cuda.synchronize()
+        self.gcanon = self.gcanon.view(self.M, d, 2, k, n).cpu().numpy()
+        self.pcanon = self.pcanon.view(d, 2, k, n).cpu().numpy()
+        self._og = {}
+        self._oq = None
+
+    def oracle_gallery_block(self, b):
+        if b not in self._og:
+            self._og[b] = hers.encrypt_gallery_block(self.op, self.opk, self.P, b, self.gal_seed)
+        return self._og[b]
+
+    def oracle_probe(self):
+        if self._oq is None:
+            self._oq = hers.encrypt_probe(self.op, self.opk, self.qv, self.probe_seed)
+        return self._oq
+
+
+@pytest.fixture(scope="module")
+def case_c1(gpu_lib):
+    print("case c1: n=2048 q=1x54 w=18 d=16 m=2048", flush=True)
+    return Case(gpu_lib, "c1", 16, 2048)
+
+
+@pytest.fixture(scope="module")
+def case_c1b(gpu_lib):
+    print("case c1b: n=2048 q=2x54 d=16 m=2048", flush=True)
+    return Case(gpu_lib, "c1b", 16, 2048)
+
+
+@pytest.fixture(scope="module")
+def case_r36(gpu_lib):
+    print("case r36: n=2048 q=3x36 d=5 m=2*2048+37 (ragged)", flush=True)
+    return Case(gpu_lib, "r36", 5, 2 * 2048 + 37)
+
+
+CASES = ["case_c1", "case_c1b", "case_r36"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_keys_bit_exact(name, request):
+    c = request.getfixturevalue(name)
+    assert c.sk.cpu().numpy().tolist() == c.osk
+    pk = c.pk.cpu().numpy()
+    assert np.array_equal(pk[0], res(c.opk[0], c.op.q_primes))
+    assert np.array_equal(pk[1], res(c.opk[1], c.op.q_primes))
+    rlk = c.rlk.cpu().numpy()
+    assert rlk.shape[0] == len(c.orlk)
+    for g, (b, a) in enumerate(c.orlk):
+        assert np.array_equal(rlk[g, 0], res(b, c.op.q_primes)), g
+        assert np.array_equal(rlk[g, 1], res(a, c.op.q_primes)), g
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gallery_ciphertexts_bit_exact(name, request):
+    c = request.getfixturevalue(name)
+    for b in range(c.M):
+        og = c.oracle_gallery_block(b)
+        for i in range(c.d):
+            assert np.array_equal(c.gcanon[b, i, 0], res(og[i][0], c.op.q_primes)), (b, i)
+            assert np.array_equal(c.gcanon[b, i, 1], res(og[i][1], c.op.q_primes)), (b, i)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_probe_ciphertexts_bit_exact(name, request):
+    c = request.getfixturevalue(name)
+    for i, ct in enumerate(c.oracle_probe()):
+        assert np.array_equal(c.pcanon[i, 0], res(ct[0], c.op.q_primes)), i
+        assert np.array_equal(c.pcanon[i, 1], res(ct[1], c.op.q_primes)), i
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_score_ciphertexts_bit_exact(name, request):
+    c = request.getfixturevalue(name)
+    scores = c.scores.cpu().numpy()
+    for b in range(c.M):
+        S = hers.search_block(c.op, c.orlk, c.oracle_probe(), c.oracle_gallery_block(b))
+        assert np.array_equal(scores[b, 0], res(S[0], c.op.q_primes)), b
+        assert np.array_equal(scores[b, 1], res(S[1], c.op.q_primes)), b
+
+
+@pytest.mark.parametrize("name", ["case_c1b", "case_r36"])
+def test_decrypted_scores_equal_plaintext_inner_products(name, request):
+    c = request.getfixturevalue(name)
+    out = c.ctx.decrypt_scores(c.sk, c.scores, c.m).cpu().numpy()
+    assert np.array_equal(out, hers.plaintext_scores(c.P, c.qv))
+    # and the oracle's decryption of the GPU's score ciphertexts agrees
+    scores = c.scores.cpu().numpy()
+    S = {b: ([int(x) for x in fv.from_residues(scores[b, 0].tolist(), c.op.q_primes)],
+             [int(x) for x in fv.from_residues(scores[b, 1].tolist(), c.op.q_primes)]) for b in [c.M - 1]}
+    tail = hers.decrypt_scores(c.op, c.osk, S, c.m)
+    assert np.array_equal(tail, out[(c.M - 1) * c.op.n:])
+
+
+def test_single_prime_config_decrypts_wrongly(case_c1):
+    """q of one 54-bit prime: ciphertexts are exact, the noise exceeds Delta/2."""
+    c = case_c1
+    out = c.ctx.decrypt_scores(c.sk, c.scores, c.m).cpu().numpy()
+    assert not np.array_equal(out, hers.plaintext_scores(c.P, c.qv))
+
+
+def test_edge_one_dimension_one_item(gpu_lib):
+    print("case edge: r36 d=1 m=1", flush=True)
+    c = Case(gpu_lib, "r36", 1, 1, feat_seed=7)
+    og = c.oracle_gallery_block(0)
+    assert np.array_equal(c.gcanon[0, 0, 0], res(og[0][0], c.op.q_primes))
+    S = hers.search_block(c.op, c.orlk, c.oracle_probe(), og)
+    scores = c.scores.cpu().numpy()
+    assert np.array_equal(scores[0, 0], res(S[0], c.op.q_primes))
+    assert np.array_equal(scores[0, 1], res(S[1], c.op.q_primes))
+    out = c.ctx.decrypt_scores(c.sk, c.scores, 1).cpu().numpy()
+    assert out.tolist() == [int(c.P[0, 0]) * int(c.qv[0])]
+
+
+def test_extreme_features(gpu_lib):
+    """Features at +-63 everywhere: the largest scores d * 63^2 decrypt exactly."""
+    print("case extreme: r36 d=16 m=2048 features +-63", flush=True)
+    c = Case(gpu_lib, "r36", 16, 2048, feat_seed=8)
+    P = np.where(np.arange(2048)[None, :] % 2 == 0, 63, -63).repeat(16, 0).astype(np.int32)
+    qv = np.full(16, 63, dtype=np.int32)
+    feats = torch.from_numpy(P).to(c.ctx.device)
+    g = c.ctx.encrypt_gallery(feats, 2048, 5)
+    pr = c.ctx.encrypt_probe(torch.from_numpy(qv).to(c.ctx.device), 6)
+    out = c.ctx.decrypt_scores(c.sk, c.ctx.search(g, 2048, 16, pr), 2048).cpu().numpy()
+    assert np.array_equal(out, hers.plaintext_scores(P, qv))
+    assert out.max() == 16 * 63 * 63 and out.min() == -16 * 63 * 63
+
+
+def test_chunked_calls_equal_single_call(case_r36):
+    """Encryption over block ranges [0,1) + [1,M) (a resumed enrollment) and a
+    search whose workspace holds one block at a time give the same bits."""
+    c = case_r36
+    ctx, dev = c.ctx, c.ctx.device
+    g2 = ctx.new_gallery(c.m, c.d)
+    n = ctx.n
+    ctx.encrypt_gallery(c.feats[:, :n].contiguous(), c.m, c.gal_seed, block0=0, nblocks=1, gallery=g2)
+    ctx.encrypt_gallery(c.feats[:, n:].contiguous(), c.m, c.gal_seed, block0=1, nblocks=c.M - 1, gallery=g2)
+    assert torch.equal(g2, c.gallery)
+    one = int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, 1, c.d))
+    ws = torch.empty(one, dtype=torch.uint8, device=dev)
+    s2 = ctx.search(c.gallery, c.m, c.d, c.probe, workspace=ws)
+    assert torch.equal(s2, c.scores)
+
+
+def test_batch_equals_single(case_r36):
+    """hers_search_batch over uneven requests equals one hers_search per request."""
+    a = case_r36
+    ctx = a.ctx
+    outs = ctx.search_batch([a.gallery, a.gallery], [a.m, 100], [a.d, a.d], [a.probe, a.probe])
+    assert torch.equal(outs[0], a.scores)
+    single = ctx.search(a.gallery, 100, a.d, a.probe)
+    assert torch.equal(outs[1], single)
+    # a 100-item prefix is block 0 of the full gallery
+    assert torch.equal(outs[1][0], a.scores[0])
+
+
+@pytest.mark.timeout(600)
+def test_full_size_single_probe_sampled_parity(gpu_lib):
+    """1,048,576 items x d = 64, n = 4096, q = 3 x 36-bit: every decrypted score
+    equals P^T q, and a sampled block's ciphertexts equal the oracle's."""
+    n, d, m = 4096, 64, 1 << 20
+    print("case full: n=4096 q=3x36 d=64 m=2^20", flush=True)
+    ctx = gpu_lib.Context(n=n, qbits=(36, 36, 36), t_bits=20, w_bits=0, d_max=64)
+    op = fv.Params(n=n, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = ctx.keygen(11)
+    P = synth.gallery_features(1000, n, d, m)
+    qv, mate = synth.probe_for(2000, 1000, n, d, m)
+    feats = torch.from_numpy(P).to(ctx.device)
+    gal = ctx.encrypt_gallery(feats, m, 12)
+    del feats
+    pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 13)
+    sc = ctx.search(gal, m, d, pr)
+    out = ctx.decrypt_scores(sk, sc, m).cpu().numpy()
+    want = hers.plaintext_scores(P, qv)
+    assert np.array_equal(out, want)
+    assert int(np.argmax(out)) == mate or out[mate] == out.max()
+    # sampled block against the oracle
+    b = 137
+    osk, opk, orlk = fv.keygen(op, 11)
+    assert sk.cpu().numpy().tolist() == osk
+    og = hers.encrypt_gallery_block(op, opk, P, b, 12)
+    oq = hers.encrypt_probe(op, opk, qv, 13)
+    S = hers.search_block(op, orlk, oq, og)
+    scores = sc[b].cpu().numpy()
+    assert np.array_equal(scores[0], res(S[0], op.q_primes))
+    assert np.array_equal(scores[1], res(S[1], op.q_primes))
