@@ -175,6 +175,16 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
                         int64_t m, int32_t* scores_out_dev, void* work_dev, size_t work_bytes,
                         void* stream);
 
+/* ---- per-stage timing ---------------------------------------------------
+ * While enabled, every kernel launch of the library is bracketed by HIP events
+ * recorded on the stream it is launched on.  hers_profile_enable clears the
+ * records.  hers_profile_read waits for the recorded events and returns the
+ * summed duration (ms) and launch count of one stage: "mac" (the fused
+ * multiply-accumulate), "intt_acc", "rescale", "relin", "encrypt", "lift",
+ * "ntt_fwd", "encode", "keygen", "sk_ntt", "dec_mul", "dec_decode". */
+int hers_profile_enable(hers_ctx* ctx, int on);
+int hers_profile_read(hers_ctx* ctx, const char* stage, double* total_ms, uint64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

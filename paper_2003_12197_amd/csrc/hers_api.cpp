@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,12 @@ struct hers_ctx {
   std::vector<void*> allocs;
   DevTabs T;
   bool keys_loaded;
+  // per-stage timing
+  struct Rec { std::string stage; hipEvent_t a, b; };
+  bool prof_on = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, uint64_t>> totals;
 };
 
 namespace {
@@ -63,6 +70,41 @@ int alloc_dev(hers_ctx* c, size_t bytes, void** dst) {
   *dst = p;
   return HERS_OK;
 }
+
+hipEvent_t take_event(hers_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events on its stream while profiling is enabled.
+struct StageTimer {
+  hers_ctx* c;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  const char* stage;
+  StageTimer(hers_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream), stage(name) {
+    if (c->prof_on && (a = take_event(c))) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) { c->pool.push_back(a); return; }
+    (void)hipEventRecord(b, s);
+    c->pending.push_back({stage, a, b});
+  }
+};
+
+#define TIMED(ctx, name, stream, expr) \
+  do {                                 \
+    StageTimer st_(ctx, name, stream); \
+    HIP_TRY(expr);                     \
+  } while (0)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -142,9 +184,49 @@ void hers_ctx_destroy(hers_ctx* ctx) {
   if (!ctx) return;
   {
     DeviceGuard g(ctx->device);
+    for (auto& r : ctx->pending) {
+      (void)hipEventSynchronize(r.b);
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     for (void* p : ctx->allocs) (void)hipFree(p);
   }
   delete ctx;
+}
+
+int hers_profile_enable(hers_ctx* ctx, int on) {
+  if (!ctx) return fail(HERS_EINVAL, "null argument");
+  DeviceGuard g(ctx->device);
+  for (auto& r : ctx->pending) {
+    (void)hipEventSynchronize(r.b);
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  ctx->totals.clear();
+  ctx->prof_on = on != 0;
+  return HERS_OK;
+}
+
+int hers_profile_read(hers_ctx* ctx, const char* stage, double* total_ms, uint64_t* launches) {
+  if (!ctx || !stage || !total_ms || !launches) return fail(HERS_EINVAL, "null argument");
+  DeviceGuard g(ctx->device);
+  for (auto& r : ctx->pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& t = ctx->totals[r.stage];
+    t.first += ms;
+    t.second += 1;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  auto it = ctx->totals.find(stage);
+  *total_ms = it == ctx->totals.end() ? 0.0 : it->second.first;
+  *launches = it == ctx->totals.end() ? 0 : it->second.second;
+  return HERS_OK;
 }
 
 int hers_ctx_info(const hers_ctx* ctx, hers_info* out) {
@@ -191,7 +273,7 @@ int hers_keygen(hers_ctx* ctx, uint64_t seed, uint8_t* sk_dev, uint64_t* pk_dev,
   if (!ctx || !sk_dev || !pk_dev || !rlk_dev) return fail(HERS_EINVAL, "null argument");
   DeviceGuard g(ctx->device);
   const HersConsts& C = ctx->host.C;
-  HIP_TRY(hers::launch_keygen(ctx->T, C.n, C.k, C.L, seed, sk_dev, pk_dev, rlk_dev, S(stream)));
+  TIMED(ctx, "keygen", S(stream), hers::launch_keygen(ctx->T, C.n, C.k, C.L, seed, sk_dev, pk_dev, rlk_dev, S(stream)));
   ctx->keys_loaded = true;
   return HERS_OK;
 }
@@ -200,7 +282,7 @@ int hers_load_keys(hers_ctx* ctx, const uint64_t* pk_dev, const uint64_t* rlk_de
   if (!ctx || !pk_dev || !rlk_dev) return fail(HERS_EINVAL, "null argument");
   DeviceGuard g(ctx->device);
   const HersConsts& C = ctx->host.C;
-  HIP_TRY(hers::launch_load_keys(ctx->T, C.n, C.k, C.L, pk_dev, rlk_dev, S(stream)));
+  TIMED(ctx, "load_keys", S(stream), hers::launch_load_keys(ctx->T, C.n, C.k, C.L, pk_dev, rlk_dev, S(stream)));
   ctx->keys_loaded = true;
   return HERS_OK;
 }
@@ -228,11 +310,11 @@ int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, in
     uint64_t* canon = canon_dev ? canon_dev + (size_t)lo * d * 2 * C.k * C.n
                                 : (uint64_t*)((char*)work_dev + align256((size_t)nb * d * C.n * 4));
     const int32_t* f = feats_dev + (lo - block0) * (int64_t)C.n;
-    HIP_TRY(hers::launch_encode(ctx->T, C.n, f, ld, m_total, d, lo, nb, pt, S(stream)));
-    HIP_TRY(hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)(nb * d), pt, nullptr, d, lo, seed,
+    TIMED(ctx, "encode", S(stream), hers::launch_encode(ctx->T, C.n, f, ld, m_total, d, lo, nb, pt, S(stream)));
+    TIMED(ctx, "encrypt", S(stream), hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)(nb * d), pt, nullptr, d, lo, seed,
                                  HERS_DOMAIN_GALLERY, canon, S(stream)));
-    HIP_TRY(hers::launch_lift(ctx->T, C.n, canon, (uint32_t)(nb * d), d, lo, gallery_dev, S(stream)));
-    HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, gallery_dev + (size_t)lo * C.K * d * 2 * C.n,
+    TIMED(ctx, "lift", S(stream), hers::launch_lift(ctx->T, C.n, canon, (uint32_t)(nb * d), d, lo, gallery_dev, S(stream)));
+    TIMED(ctx, "ntt_fwd", S(stream), hers::launch_ntt_p(ctx->T, C.n, gallery_dev + (size_t)lo * C.K * d * 2 * C.n,
                                (uint64_t)nb * C.K * d * 2, 2 * d, 0, S(stream)));
   }
   return HERS_OK;
@@ -250,10 +332,10 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
     canon = (uint64_t*)work_dev;
   }
   DeviceGuard g(ctx->device);
-  HIP_TRY(hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed, HERS_DOMAIN_PROBE,
+  TIMED(ctx, "encrypt", S(stream), hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed, HERS_DOMAIN_PROBE,
                                canon, S(stream)));
-  HIP_TRY(hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, S(stream)));
-  HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, S(stream)));
+  TIMED(ctx, "lift", S(stream), hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, S(stream)));
+  TIMED(ctx, "ntt_fwd", S(stream), hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, S(stream)));
   return HERS_OK;
 }
 
@@ -274,10 +356,10 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
     const int64_t nb = hi - lo;
     uint32_t* acc = (uint32_t*)work_dev;
     uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)nb * 3 * C.K * C.n * 4));
-    HIP_TRY(hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream)));
-    HIP_TRY(hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
-    HIP_TRY(hers::launch_rescale(ctx->T, C.n, acc, nb, lo, scores_dev, digits, S(stream)));
-    HIP_TRY(hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, scores_dev, S(stream)));
+    TIMED(ctx, "mac", S(stream), hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream)));
+    TIMED(ctx, "intt_acc", S(stream), hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
+    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, scores_dev, digits, S(stream)));
+    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, scores_dev, S(stream)));
   }
   return HERS_OK;
 }
@@ -307,11 +389,11 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
   uint64_t* Ssh = Sn + (size_t)C.k * C.n;
   uint64_t* x = (uint64_t*)((char*)work_dev + fixed);
   DeviceGuard g(ctx->device);
-  HIP_TRY(hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
+  TIMED(ctx, "sk_ntt", S(stream), hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
   for (int64_t lo = 0; lo < M; lo += chunk) {
     const int64_t nb = lo + chunk < M ? chunk : M - lo;
-    HIP_TRY(hers::launch_dec_mul(ctx->T, C.n, C.k, scores_dev, nb, lo, Sn, Ssh, x, S(stream)));
-    HIP_TRY(hers::launch_dec_decode(ctx->T, C.n, x, nb, lo, m, scores_out_dev, S(stream)));
+    TIMED(ctx, "dec_mul", S(stream), hers::launch_dec_mul(ctx->T, C.n, C.k, scores_dev, nb, lo, Sn, Ssh, x, S(stream)));
+    TIMED(ctx, "dec_decode", S(stream), hers::launch_dec_decode(ctx->T, C.n, x, nb, lo, m, scores_out_dev, S(stream)));
   }
   return HERS_OK;
 }

@@ -53,6 +53,8 @@ EXPORTS = {
     "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
                                   ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
     "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_profile_enable": (c_i32, [c_vp, c_i32]),
+    "hers_profile_read": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_u64)]),
 }
 
 OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT = 0, 1, 2, 3
@@ -225,6 +227,16 @@ class Context:
             self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
             _ptr(workspace), workspace.numel(), _stream()), "hers_search_batch")
         return scores
+
+    def profile_enable(self, on=True):
+        _check(self.lib, self.lib.hers_profile_enable(self.handle, 1 if on else 0), "hers_profile_enable")
+
+    def profile_read(self, stage):
+        """(total ms, launches) of one stage since profile_enable."""
+        ms, cnt = ctypes.c_double(), c_u64()
+        _check(self.lib, self.lib.hers_profile_read(self.handle, stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+               "hers_profile_read")
+        return ms.value, cnt.value
 
     def decrypt_scores(self, sk, scores, m, out=None, workspace=None):
         """int32 [m] decrypted scores (client side)."""
