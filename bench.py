@@ -154,6 +154,10 @@ def main():
     ws_s = ctx.workspace(hers_gpu.OP_SEARCH, m, d)
     ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, m, 1)
 
+    ctx.encrypt_probe(query, PROBE_SEED, probe=probe, workspace=ws_p)
+    mac_variant = ctx.autotune(gallery, m, d, probe, reps=3, workspace=ws_s)
+    print("autotuned k_mac schedule: %d" % mac_variant, file=sys.stderr, flush=True)
+
     def step(seed):
         ctx.encrypt_probe(query, seed, probe=probe, workspace=ws_p)
         ctx.search(gallery, m, d, probe, scores=scores, workspace=ws_s)
@@ -219,7 +223,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "items": m, "dims": d, "probes_per_step": 1, "blocks": M,
                    "ring_degree": n, "q_primes_bits": list(cfg["qbits"]), "t": int(ctx.t),
-                   "base_primes": K, "step": "encrypt probe + search all blocks + decrypt scores"},
+                   "base_primes": K, "step": "encrypt probe + search all blocks + decrypt scores",
+                   "mac_schedule": mac_variant},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},

@@ -175,6 +175,26 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
                         int64_t m, int32_t* scores_out_dev, void* work_dev, size_t work_bytes,
                         void* stream);
 
+/* ---- tuning --------------------------------------------------------------
+ * Kernel schedule knobs, normally chosen by hers_autotune.  Keys:
+ *   "mac_variant"  fused multiply-accumulate schedule, 0..11, as (gallery
+ *                  blocks per pass sharing one probe load, dimensions per
+ *                  double-buffered load batch, non-temporal gallery loads):
+ *                  0 (1,2,no) 1 (2,2,no) 2 (1,4,no) 3 (2,4,no) 4 (1,2,yes)
+ *                  5 (2,2,yes) 6 (1,4,yes) 7 (2,4,yes) 8 (4,1,yes)
+ *                  9 (4,2,yes) 10 (2,1,yes) 11 (1,1,yes).
+ * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
+ * key or value. */
+int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
+
+/* Autotuner: times every "mac_variant" schedule on the caller's gallery and
+ * probe (reps launches each, over as many leading blocks as the search
+ * workspace holds), keeps the fastest in the context and returns it in
+ * *chosen (may be NULL).  The workspace contents are overwritten. */
+int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
+                  void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen);
+int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
+
 /* ---- per-stage timing ---------------------------------------------------
  * While enabled, every kernel launch of the library is bracketed by HIP events
  * recorded on the stream it is launched on.  hers_profile_enable clears the

@@ -31,6 +31,7 @@ struct hers_ctx {
   std::vector<void*> allocs;
   DevTabs T;
   bool keys_loaded;
+  int mac_variant = 8;   // k_mac schedule (see hers_set_option)
   // per-stage timing
   struct Rec { std::string stage; hipEvent_t a, b; };
   bool prof_on = false;
@@ -195,6 +196,25 @@ void hers_ctx_destroy(hers_ctx* ctx) {
   delete ctx;
 }
 
+int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
+  if (!ctx || !key) return fail(HERS_EINVAL, "null argument");
+  if (!std::strcmp(key, "mac_variant")) {
+    if (value < 0 || value > 11) return fail(HERS_EINVAL, "mac_variant must be in [0, 11]");
+    ctx->mac_variant = (int)value;
+    return HERS_OK;
+  }
+  return fail(HERS_EINVAL, std::string("unknown option ") + key);
+}
+
+int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
+  if (!ctx || !key || !value) return fail(HERS_EINVAL, "null argument");
+  if (!std::strcmp(key, "mac_variant")) {
+    *value = ctx->mac_variant;
+    return HERS_OK;
+  }
+  return fail(HERS_EINVAL, std::string("unknown option ") + key);
+}
+
 int hers_profile_enable(hers_ctx* ctx, int on) {
   if (!ctx) return fail(HERS_EINVAL, "null argument");
   DeviceGuard g(ctx->device);
@@ -356,11 +376,48 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
     const int64_t nb = hi - lo;
     uint32_t* acc = (uint32_t*)work_dev;
     uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)nb * 3 * C.K * C.n * 4));
-    TIMED(ctx, "mac", S(stream), hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream)));
+    TIMED(ctx, "mac", S(stream), hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream),
+                                                       ctx->mac_variant));
     TIMED(ctx, "intt_acc", S(stream), hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
     TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, scores_dev, digits, S(stream)));
     TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, scores_dev, S(stream)));
   }
+  return HERS_OK;
+}
+
+int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
+                  void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen) {
+  if (!ctx || !gallery_dev || !probe_dev || reps < 1) return fail(HERS_EINVAL, "bad argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m);
+  const size_t per = search_ws_per_block(C);
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t hi = (int64_t)(work_bytes / per) < M ? (int64_t)(work_bytes / per) : M;
+  DeviceGuard g(ctx->device);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 0.f;
+  int best_v = ctx->mac_variant;
+  int rc = HERS_OK;
+  for (int v = 0; v < 12 && rc == HERS_OK; ++v) {
+    hipError_t e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, 0, hi, (uint32_t*)work_dev, S(stream), v);
+    if (e == hipSuccess) e = hipEventRecord(e0, S(stream));
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, 0, hi, (uint32_t*)work_dev, S(stream), v);
+    if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+    if (v == 0 || ms < best) { best = ms; best_v = v; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->mac_variant = best_v;
+  if (chosen) *chosen = best_v;
   return HERS_OK;
 }
 

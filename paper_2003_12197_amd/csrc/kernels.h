@@ -29,7 +29,7 @@ hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
                         int inverse, hipStream_t s);
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
-                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s);
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           uint64_t* scores, uint64_t* digits, hipStream_t s);
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,

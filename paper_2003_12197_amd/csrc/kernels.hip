@@ -243,39 +243,119 @@ k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse) {
   for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[j];
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
-k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe,
-      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group, uint32_t* __restrict__ acc) {
-  // The hot loop (Alg. "HERS Search" with the tensor of Alg. "Ciphertext
-  // Multiplication", summed over the d dimensions before any rescale):
-  //   A0 = sum_i P_i0 G_bi0,  A1 = sum_i (P_i0 G_bi1 + P_i1 G_bi0),  A2 = sum_i P_i1 G_bi1
-  // slot-wise in the NTT domain mod p_r.  One lane per (prime r, NTT slot);
-  // products (< 2^60) accumulate unreduced in 64 bits and are folded every 8
-  // dimensions.  acc is indexed from blk_lo.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+// The hot loop (Alg. "HERS Search" with the tensor of Alg. "Ciphertext
+// Multiplication", summed over the d dimensions before any rescale):
+//   A0 = sum_i P_i0 G_bi0,  A1 = sum_i (P_i0 G_bi1 + P_i1 G_bi0),  A2 = sum_i P_i1 G_bi1
+// slot-wise in the NTT domain mod p_r.  A lane owns 4 consecutive NTT slots of
+// one prime (16-byte loads, 1 KiB per wave instruction) and NB blocks at a
+// time, so one probe load serves NB gallery loads.  Dimensions go in batches
+// of U; the loads of batch j + 1 are issued before the products of batch j
+// (double buffering), so a wave's arithmetic overlaps its own memory traffic.
+// Gallery rows are read once, so NT streams them past the cache.  Products of
+// residues below 2^30 are < 2^60: A0 and A2 take one product per dimension and
+// fold every 16 dimensions, A1 takes two and folds every 8.  acc is indexed
+// from blk_lo.
+template <int NB, int U, bool NT>
+struct MacBatch {
+  u32x4 P0[U], P1[U], G0[U][NB], G1[U][NB];
+  __device__ __forceinline__ void load(const u32x4* pr, const u32x4* const (&gb)[NB], int32_t i, size_t row) {
+#pragma unroll
+    for (int v = 0; v < U; ++v) {
+      const size_t o0 = (size_t)(2 * (i + v)) * row, o1 = o0 + row;
+      P0[v] = pr[o0];
+      P1[v] = pr[o1];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        G0[v][u] = load_stream<NT>(gb[u] + o0);
+        G1[v][u] = load_stream<NT>(gb[u] + o1);
+      }
+    }
+  }
+};
+
+template <int NB, int U, bool NT>
+__global__ void __launch_bounds__(WG)
+k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe, int32_t d,
+      int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group, uint32_t* __restrict__ acc) {
+  static_assert(8 % U == 0, "U divides the fold period");
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
-  const uint32_t slot = blockIdx.x * WG + threadIdx.x;
+  const uint32_t slot = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
   const uint32_t r = blockIdx.y;
   const uint32_t p = C.p[r];
   const uint64_t mu = C.p_mu64[r];
   const int64_t b0 = blk_lo + (int64_t)blockIdx.z * blocks_per_group;
   const int64_t b1 = b0 + blocks_per_group < blk_hi ? b0 + blocks_per_group : blk_hi;
-  const uint32_t* pr = probe + (size_t)r * d * 2 * n + slot;
-  for (int64_t b = b0; b < b1; ++b) {
-    const uint32_t* gb = gallery + (((size_t)b * K + r) * d * 2) * n + slot;
-    uint64_t a0 = 0, a1 = 0, a2 = 0;
-    for (int32_t i = 0; i < d; ++i) {
-      const uint64_t g0 = gb[(size_t)(2 * i) * n], g1 = gb[(size_t)(2 * i + 1) * n];
-      const uint64_t p0 = pr[(size_t)(2 * i) * n], p1 = pr[(size_t)(2 * i + 1) * n];
-      a0 += p0 * g0;
-      a1 += p0 * g1 + p1 * g0;
-      a2 += p1 * g1;
-      if ((i & 7) == 7) { a0 = red_p(a0, p, mu); a1 = red_p(a1, p, mu); a2 = red_p(a2, p, mu); }
+  const size_t row = n / 4;                               // u32x4 between dimension rows
+  const u32x4* pr = (const u32x4*)(probe + (size_t)r * d * 2 * n + slot);
+  const int32_t dfull = d / U * U;
+  for (int64_t b = b0; b < b1; b += NB) {
+    const u32x4* gb[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int64_t bb = b + u < b1 ? b + u : b;          // a short tail recomputes block b, not stored
+      gb[u] = (const u32x4*)(gallery + (((size_t)bb * K + r) * d * 2) * n + slot);
     }
-    uint32_t* o = acc + ((size_t)(b - blk_lo) * 3 * K + r) * n + slot;
-    o[0] = red_p(a0, p, mu);
-    o[(size_t)K * n] = red_p(a1, p, mu);
-    o[(size_t)2 * K * n] = red_p(a2, p, mu);
+    uint64_t a0[NB][4], a1[NB][4], a2[NB][4];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { a0[u][s] = 0; a1[u][s] = 0; a2[u][s] = 0; }
+
+    auto mac = [&](const u32x4& P0, const u32x4& P1, const u32x4 (&G0)[NB], const u32x4 (&G1)[NB]) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a0[u][s] += (uint64_t)P0[s] * G0[u][s];
+          a1[u][s] += (uint64_t)P0[s] * G1[u][s];
+          a1[u][s] += (uint64_t)P1[s] * G0[u][s];
+          a2[u][s] += (uint64_t)P1[s] * G1[u][s];
+        }
+    };
+    auto fold = [&](bool all) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a1[u][s] = red_p(a1[u][s], p, mu);
+          if (all) { a0[u][s] = red_p(a0[u][s], p, mu); a2[u][s] = red_p(a2[u][s], p, mu); }
+        }
+    };
+
+    MacBatch<NB, U, NT> cur, nxt;
+    if (dfull) cur.load(pr, gb, 0, row);
+    for (int32_t i = 0; i < dfull; i += U) {
+      if (i + U < dfull) nxt.load(pr, gb, i + U, row);
+#pragma unroll
+      for (int v = 0; v < U; ++v) mac(cur.P0[v], cur.P1[v], cur.G0[v], cur.G1[v]);
+      const int32_t done = i + U;
+      if ((done & 7) == 0) fold((done & 15) == 0);
+      cur = nxt;
+    }
+    for (int32_t i = dfull; i < d; ++i) {                   // remainder, one dimension at a time
+      MacBatch<NB, 1, NT> one;
+      one.load(pr, gb, i, row);
+      mac(one.P0[0], one.P1[0], one.G0[0], one.G1[0]);
+    }
+    fold(true);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (b + u >= b1) break;
+      u32x4* o = (u32x4*)(acc + ((size_t)(b + u - blk_lo) * 3 * K + r) * n + slot);
+      const size_t comp = (size_t)K * n / 4;
+      o[0] = u32x4{(uint32_t)a0[u][0], (uint32_t)a0[u][1], (uint32_t)a0[u][2], (uint32_t)a0[u][3]};
+      o[comp] = u32x4{(uint32_t)a1[u][0], (uint32_t)a1[u][1], (uint32_t)a1[u][2], (uint32_t)a1[u][3]};
+      o[2 * comp] = u32x4{(uint32_t)a2[u][0], (uint32_t)a2[u][1], (uint32_t)a2[u][2], (uint32_t)a2[u][3]};
+    }
   }
 }
 
@@ -471,15 +551,39 @@ hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t 
 }
 
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
-                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s) {
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant) {
   const int64_t nb = blk_hi - blk_lo;
-  const uint64_t base = (uint64_t)(n / WG) * K;
-  // about 4096 workgroups: 16 per compute unit
-  uint64_t bpg = (uint64_t)nb * base / 4096;
-  if (bpg < 1) bpg = 1;
+  const uint32_t lanes = n / 4 < WG ? n / 4 : WG;          // 4 slots per lane
+  const uint64_t tiles = n / 4 / lanes;
+  static const int nb_of[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 4, 2, 1};
+  const int NB = variant >= 0 && variant < 12 ? nb_of[variant] : 1;
+  // about 2048 workgroups (8 per compute unit), groups a multiple of NB blocks
+  uint64_t bpg = (uint64_t)nb * tiles * K / 2048;
+  if (bpg < (uint64_t)NB) bpg = NB;
+  bpg = (bpg + NB - 1) / NB * NB;
   const uint64_t groups = ((uint64_t)nb + bpg - 1) / bpg;
-  hipLaunchKernelGGL(k_mac, dim3(n / WG, K, (uint32_t)groups), dim3(WG), 0, s, T, gallery, probe, d, blk_lo,
-                     blk_hi, (uint32_t)bpg, acc);
+  dim3 grid((uint32_t)tiles, K, (uint32_t)groups);
+#define MAC_CASE(V, NB_, U_, NT_)                                                                    \
+  case V:                                                                                            \
+    hipLaunchKernelGGL((k_mac<NB_, U_, NT_>), grid, dim3(lanes), 0, s, T, gallery, probe, d, blk_lo, \
+                       blk_hi, (uint32_t)bpg, acc);                                                  \
+    break;
+  switch (variant) {
+    MAC_CASE(0, 1, 2, false)
+    MAC_CASE(1, 2, 2, false)
+    MAC_CASE(2, 1, 4, false)
+    MAC_CASE(3, 2, 4, false)
+    MAC_CASE(4, 1, 2, true)
+    MAC_CASE(5, 2, 2, true)
+    MAC_CASE(6, 1, 4, true)
+    MAC_CASE(7, 2, 4, true)
+    MAC_CASE(8, 4, 1, true)
+    MAC_CASE(9, 4, 2, true)
+    MAC_CASE(10, 2, 1, true)
+    MAC_CASE(11, 1, 1, true)
+    default: return hipErrorInvalidValue;
+  }
+#undef MAC_CASE
   return hipGetLastError();
 }
 

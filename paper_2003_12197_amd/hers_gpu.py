@@ -53,6 +53,10 @@ EXPORTS = {
     "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
                                   ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
     "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_set_option": (c_i32, [c_vp, ctypes.c_char_p, c_i64]),
+    "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
+                              ctypes.POINTER(c_i64)]),
+    "hers_get_option": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(c_i64)]),
     "hers_profile_enable": (c_i32, [c_vp, c_i32]),
     "hers_profile_read": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_u64)]),
 }
@@ -227,6 +231,24 @@ class Context:
             self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
             _ptr(workspace), workspace.numel(), _stream()), "hers_search_batch")
         return scores
+
+    def set_option(self, key, value):
+        _check(self.lib, self.lib.hers_set_option(self.handle, key.encode(), int(value)), "hers_set_option")
+
+    def autotune(self, gallery, m, d, probe, reps=3, workspace=None):
+        """Pick the fastest multiply-accumulate schedule for this gallery; returns it."""
+        if workspace is None:
+            workspace = self.workspace(OP_SEARCH, m, d)
+        v = c_i64()
+        _check(self.lib, self.lib.hers_autotune(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
+                                                _ptr(workspace), workspace.numel(), int(reps), _stream(),
+                                                ctypes.byref(v)), "hers_autotune")
+        return v.value
+
+    def get_option(self, key):
+        v = c_i64()
+        _check(self.lib, self.lib.hers_get_option(self.handle, key.encode(), ctypes.byref(v)), "hers_get_option")
+        return v.value
 
     def profile_enable(self, on=True):
         _check(self.lib, self.lib.hers_profile_enable(self.handle, 1 if on else 0), "hers_profile_enable")
