@@ -162,11 +162,28 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
 
 /* Batched search: nreq independent (gallery, probe) requests in one
  * submission; request r reads galleries[r] (m[r] items, d[r] dims) and
- * probes[r] and writes scores[r].  Results are bit-identical to nreq calls of
- * hers_search.  work_dev: hers_workspace_bytes(ctx, 2, sum of m, max d). */
+ * probes[r] and writes scores[r].  Requests on the same gallery (same
+ * pointer, m and d) are grouped, up to 16 per group: one persistent
+ * multiply-accumulate launch streams each gallery block once for the whole
+ * group, then every request gets its own rescale and relinearization.
+ * Results are bit-identical to nreq calls of hers_search.  The workspace
+ * holds at least one block per request; with W bytes, rounds of
+ * floor(W / (nreq * hers_workspace_bytes(ctx, 2, n, 1))) blocks are used. */
 int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries,
                       const int64_t* m, const int32_t* d, const uint32_t* const* probes,
                       uint64_t* const* scores, void* work_dev, size_t work_bytes, void* stream);
+
+/* The same batch captured once as a HIP graph and replayed by
+ * hers_plan_launch: the pointers are fixed at capture, so callers refill the
+ * probe buffers (hers_encrypt_probe into the same probe_dev) and replay.
+ * The plan keeps the context, galleries, probes, scores and workspace
+ * pointers; they must stay valid until hers_plan_destroy. */
+typedef struct hers_plan hers_plan;
+int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
+                     const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores,
+                     void* work_dev, size_t work_bytes, hers_plan** out);
+int hers_plan_launch(hers_plan* plan, void* stream);
+void hers_plan_destroy(hers_plan* plan);
 
 /* ---- decryption (App. B Alg. "HERS Search", client side) ----------------
  * pt = [round(t/q [c0 + c1 s]_q)]_t (Alg. "Decryption"), slot decode, centred
@@ -200,7 +217,7 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
  * recorded on the stream it is launched on.  hers_profile_enable clears the
  * records.  hers_profile_read waits for the recorded events and returns the
  * summed duration (ms) and launch count of one stage: "mac" (the fused
- * multiply-accumulate), "intt_acc", "rescale", "relin", "encrypt", "lift",
+ * multiply-accumulate), "mac_multi" (its batched form), "intt_acc", "rescale", "relin", "encrypt", "lift",
  * "ntt_fwd", "encode", "keygen", "sk_ntt", "dec_mul", "dec_decode". */
 int hers_profile_enable(hers_ctx* ctx, int on);
 int hers_profile_read(hers_ctx* ctx, const char* stage, double* total_ms, uint64_t* launches);

@@ -25,6 +25,7 @@ static int fail(int code, const std::string& msg) {
   } while (0)
 
 struct hers_ctx {
+  int num_cus = 256;
   hers_params prm;
   hers::HostTables host;
   int device;
@@ -172,6 +173,9 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
     hers_ctx_destroy(c);
     return fail(rc, msg);
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->num_cus = cus;
   c->T.C = dC;
   c->T.pk_ntt = (uint64_t*)pk;
   c->T.pk_ntt_sh = (uint64_t*)pks;
@@ -421,16 +425,183 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   return HERS_OK;
 }
 
+namespace {
+
+struct BatchGroup {
+  const uint32_t* gallery;
+  int64_t m, M;
+  int32_t d;
+  std::vector<int32_t> reqs;
+};
+
+// Groups requests by (gallery, m, d), at most MB_PROBES per group.
+int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m, const int32_t* d,
+                const uint32_t* const* probes, uint64_t* const* scores, std::vector<BatchGroup>* out) {
+  out->clear();
+  for (int32_t r = 0; r < nreq; ++r) {
+    if (!galleries[r] || !probes[r] || !scores[r]) return fail(HERS_EINVAL, "null request pointer");
+    if (int rc = check_d(ctx, d[r])) return rc;
+    if (m[r] < 1) return fail(HERS_EINVAL, "empty gallery");
+    BatchGroup* g = nullptr;
+    for (auto& x : *out)
+      if (x.gallery == galleries[r] && x.m == m[r] && x.d == d[r] && x.reqs.size() < MB_PROBES) { g = &x; break; }
+    if (!g) {
+      out->push_back({galleries[r], m[r], (int64_t)hers_blocks(ctx, m[r]), d[r], {}});
+      g = &out->back();
+    }
+    g->reqs.push_back(r);
+  }
+  return HERS_OK;
+}
+
+// Enqueues a batch: rounds of at most CB blocks per group; per round one
+// persistent multiply-accumulate launch per MB_MAXG groups, then the
+// per-request epilogue (inverse NTT, rescale, relinearization).
+int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32_t* const* probes,
+              uint64_t* const* scores, void* work_dev, size_t work_bytes, hipStream_t s) {
+  const HersConsts& C = ctx->host.C;
+  size_t nprobe = 0;
+  int64_t maxM = 0;
+  for (auto& g : groups) { nprobe += g.reqs.size(); maxM = g.M > maxM ? g.M : maxM; }
+  if (!nprobe) return HERS_OK;
+  const size_t acc_pb = align256((size_t)3 * C.K * C.n * 4), dig_pb = align256((size_t)C.L * C.k * C.n * 8);
+  int64_t CB = (int64_t)(work_bytes / (nprobe * (acc_pb + dig_pb)));
+  if (!work_dev || CB < 1) return fail(HERS_ESPACE, "workspace smaller than one block per request");
+  if (CB > MB_BLOCKS) CB = CB / MB_BLOCKS * MB_BLOCKS;
+  char* base = (char*)work_dev;
+  const size_t acc_bytes = nprobe * CB * acc_pb;
+  const uint32_t tiles = C.n / 64;
+  for (int64_t lo = 0; lo < maxM; lo += CB) {
+    // accumulator slab per request, digits slab per request
+    std::vector<uint32_t*> acc_of(groups.size());
+    std::vector<uint64_t*> dig_of(groups.size());
+    {
+      size_t pi = 0;
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        acc_of[gi] = (uint32_t*)(base + pi * CB * acc_pb);
+        dig_of[gi] = (uint64_t*)(base + acc_bytes + pi * CB * dig_pb);
+        pi += groups[gi].reqs.size();
+      }
+    }
+    MacBatchArgs A;
+    std::memset(&A, 0, sizeof(A));
+    auto flush = [&]() -> int {
+      if (!A.ngroups) return HERS_OK;
+      uint64_t grid = (uint64_t)ctx->num_cus * 2;
+      if (grid > A.total_items) grid = A.total_items;
+      TIMED(ctx, "mac_multi", s, hers::launch_mac_multi(ctx->T, A, (uint32_t)grid, s));
+      std::memset(&A, 0, sizeof(A));
+      return HERS_OK;
+    };
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const BatchGroup& g = groups[gi];
+      const int64_t hi = lo + CB < g.M ? lo + CB : g.M;
+      if (lo >= hi) continue;
+      if (g.reqs.size() == 1) {
+        // a lone probe streams its gallery with the single-probe schedule
+        const int32_t r = g.reqs[0];
+        TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, g.gallery, probes[r], g.d, lo, hi, acc_of[gi], s,
+                                              ctx->mac_variant));
+        continue;
+      }
+      MacGroup& G = A.g[A.ngroups];
+      G.gallery = g.gallery;
+      for (size_t j = 0; j < g.reqs.size(); ++j) G.probe[j] = probes[g.reqs[j]];
+      G.acc = acc_of[gi];
+      G.acc_stride = CB * acc_pb / 4;
+      G.blk_lo = lo;
+      G.blk_hi = hi;
+      G.item_begin = A.total_items;
+      G.d = g.d;
+      G.nprobe = (int32_t)g.reqs.size();
+      A.total_items += (uint64_t)((hi - lo + MB_BLOCKS - 1) / MB_BLOCKS) * C.K * tiles;
+      if (++A.ngroups == MB_MAXG)
+        if (int rc = flush()) return rc;
+    }
+    if (int rc = flush()) return rc;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const BatchGroup& g = groups[gi];
+      const int64_t hi = lo + CB < g.M ? lo + CB : g.M;
+      if (lo >= hi) continue;
+      for (size_t j = 0; j < g.reqs.size(); ++j) {
+        uint32_t* acc = acc_of[gi] + j * (CB * acc_pb / 4);
+        uint64_t* dig = dig_of[gi] + j * (CB * dig_pb / 8);
+        uint64_t* sc = scores[g.reqs[j]];
+        TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s));
+        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sc, dig, s));
+        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, dig, hi - lo, lo, sc, s));
+      }
+    }
+  }
+  return HERS_OK;
+}
+
+}  // namespace
+
 int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
                       const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores, void* work_dev,
                       size_t work_bytes, void* stream) {
   if (!ctx || nreq < 0 || (nreq && (!galleries || !m || !d || !probes || !scores)))
     return fail(HERS_EINVAL, "null argument");
-  for (int32_t r = 0; r < nreq; ++r) {
-    int rc = hers_search(ctx, galleries[r], m[r], d[r], probes[r], scores[r], work_dev, work_bytes, stream);
-    if (rc) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  std::vector<BatchGroup> groups;
+  if (int rc = plan_groups(ctx, nreq, galleries, m, d, probes, scores, &groups)) return rc;
+  DeviceGuard g(ctx->device);
+  return run_batch(ctx, groups, probes, scores, work_dev, work_bytes, S(stream));
+}
+
+struct hers_plan {
+  hers_ctx* ctx;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
+                     const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores, void* work_dev,
+                     size_t work_bytes, hers_plan** out) {
+  if (!ctx || !out || nreq < 1 || !galleries || !m || !d || !probes || !scores)
+    return fail(HERS_EINVAL, "null argument");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  *out = nullptr;
+  std::vector<BatchGroup> groups;
+  if (int rc = plan_groups(ctx, nreq, galleries, m, d, probes, scores, &groups)) return rc;
+  DeviceGuard g(ctx->device);
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;   // no event nodes in the graph
+  hers_plan* p = new hers_plan{ctx};
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = e == hipSuccess ? run_batch(ctx, groups, probes, scores, work_dev, work_bytes, cs) : HERS_EDEVICE;
+  hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+  ctx->prof_on = prof;
+  if (rc == HERS_OK && e == hipSuccess && e2 == hipSuccess)
+    e2 = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (rc != HERS_OK || e != hipSuccess || e2 != hipSuccess) {
+    std::string msg = rc != HERS_OK ? g_err : std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return fail(rc != HERS_OK ? rc : HERS_EDEVICE, msg);
   }
+  *out = p;
   return HERS_OK;
+}
+
+int hers_plan_launch(hers_plan* plan, void* stream) {
+  if (!plan) return fail(HERS_EINVAL, "null plan");
+  DeviceGuard g(plan->ctx->device);
+  HIP_TRY(hipGraphLaunch(plan->exec, S(stream)));
+  return HERS_OK;
+}
+
+void hers_plan_destroy(hers_plan* plan) {
+  if (!plan) return;
+  DeviceGuard g(plan->ctx->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
 }
 
 int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev, int64_t m,

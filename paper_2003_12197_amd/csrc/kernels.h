@@ -14,7 +14,31 @@ struct DevTabs {
   uint64_t *rlk_ntt, *rlk_ntt_sh;                  // [L][2][k][n] NTT domain
 };
 
+// Batched multiply-accumulate: up to MB_PROBES probes of one gallery per group.
+#define MB_PROBES 16
+#define MB_WG (64 * MB_PROBES)
+#define MB_DC 16        // dimensions per register/LDS chunk
+#define MB_BLOCKS 8     // blocks per work item
+#define MB_MAXG 15      // groups per launch (kernel arguments stay below 4 KiB)
+
+struct MacGroup {
+  const uint32_t* gallery;            // search form [M][K][d][2][n]
+  const uint32_t* probe[MB_PROBES];   // search forms [K][d][2][n]
+  uint32_t* acc;                      // probe j's accumulators at acc + j * acc_stride: [blocks][3][K][n]
+  uint64_t acc_stride;                // u32 words
+  int64_t blk_lo, blk_hi;             // blocks of this round; accumulators indexed from blk_lo
+  uint64_t item_begin;                // first work item of the group
+  int32_t d, nprobe;
+};
+
+struct MacBatchArgs {
+  MacGroup g[MB_MAXG];
+  uint64_t total_items;
+  int32_t ngroups, pad;
+};
+
 namespace hers {
+hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s);
 hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
                          uint64_t* pk, uint64_t* rlk, hipStream_t s);
 hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, const uint64_t* pk,

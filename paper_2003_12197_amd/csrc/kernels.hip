@@ -359,6 +359,92 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
   }
 }
 
+// ---------------------------------------------------------------- batched multiply-accumulate
+// Many probes against galleries of uneven size and d, one persistent launch.
+// A work item is (group, block range of up to MB_BLOCKS blocks, prime r,
+// 64-slot tile); a group is up to MB_PROBES probes of one gallery.  The
+// workgroup's 16 waves are the group's probes: each lane keeps its probe's
+// values for a chunk of MB_DC dimensions in registers, the gallery tile of
+// the chunk is staged once in LDS and read by every wave, so one HBM read of
+// the gallery serves the whole group.  Folding as in k_mac.  Workgroups
+// stride over the items (static assignment, no atomics).
+__global__ void __launch_bounds__(MB_WG)
+k_mac_multi(DevTabs T, MacBatchArgs A) {
+  __shared__ uint32_t tileG[2][MB_DC][2][64];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, K = C.K;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tiles = n / 64;
+  uint32_t stage = 0;   // consecutive stagings alternate LDS buffers; each reuse is two barriers apart
+  for (uint64_t item = blockIdx.x; item < A.total_items; item += gridDim.x) {
+    int g = 0;
+    while (g + 1 < A.ngroups && item >= A.g[g + 1].item_begin) ++g;
+    const MacGroup& G = A.g[g];
+    const uint64_t local = item - G.item_begin;
+    const uint32_t tile = (uint32_t)(local % tiles);
+    const uint32_t r = (uint32_t)((local / tiles) % K);
+    const int64_t b0 = G.blk_lo + (int64_t)(local / ((uint64_t)tiles * K)) * MB_BLOCKS;
+    const int nblk = (int)(G.blk_hi - b0 < MB_BLOCKS ? G.blk_hi - b0 : MB_BLOCKS);
+    const int32_t d = G.d;
+    const uint32_t p = C.p[r];
+    const uint64_t mu = C.p_mu64[r];
+    const bool active = wave < (uint32_t)G.nprobe;
+    const uint32_t slot = tile * 64 + lane;
+    const uint32_t* pr = active ? G.probe[wave] + (size_t)r * d * 2 * n + slot : nullptr;
+    uint64_t a0[MB_BLOCKS], a1[MB_BLOCKS], a2[MB_BLOCKS];
+#pragma unroll
+    for (int u = 0; u < MB_BLOCKS; ++u) { a0[u] = 0; a1[u] = 0; a2[u] = 0; }
+    for (int32_t dc = 0; dc < d; dc += MB_DC) {
+      const int32_t dn = d - dc < MB_DC ? d - dc : MB_DC;
+      uint32_t P0[MB_DC], P1[MB_DC];
+#pragma unroll
+      for (int v = 0; v < MB_DC; ++v) {
+        P0[v] = active && v < dn ? pr[(size_t)(2 * (dc + v)) * n] : 0;
+        P1[v] = active && v < dn ? pr[(size_t)(2 * (dc + v) + 1) * n] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < MB_BLOCKS; ++u) {
+        if (u >= nblk) break;
+        const uint32_t* gb = G.gallery + (((size_t)(b0 + u) * K + r) * d * 2) * n + tile * 64;
+        uint32_t (*buf)[2][64] = tileG[stage++ & 1];
+        // stage rows (dc .. dc+dn) x 2 polys x 64 slots: 2 * MB_DC * 64 words, 2 per thread
+        for (uint32_t w = tid; w < (uint32_t)(2 * dn * 64); w += MB_WG) {
+          const uint32_t rowi = w >> 6, c = w & 63;
+          buf[rowi >> 1][rowi & 1][c] = __builtin_nontemporal_load(gb + (size_t)(2 * dc + rowi) * n + c);
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int v = 0; v < MB_DC; ++v) {
+            if (v < dn) {
+              const uint64_t g0 = buf[v][0][lane], g1 = buf[v][1][lane];
+              a0[u] += (uint64_t)P0[v] * g0;
+              a1[u] += (uint64_t)P0[v] * g1 + (uint64_t)P1[v] * g0;
+              a2[u] += (uint64_t)P1[v] * g1;
+            }
+            if ((v & 7) == 7) a1[u] = red_p(a1[u], p, mu);
+          }
+          a0[u] = red_p(a0[u], p, mu);
+          a1[u] = red_p(a1[u], p, mu);
+          a2[u] = red_p(a2[u], p, mu);
+        }
+      }
+    }
+    if (active) {
+      uint32_t* ob = G.acc + (size_t)wave * G.acc_stride;
+#pragma unroll
+      for (int u = 0; u < MB_BLOCKS; ++u) {
+        if (u >= nblk) break;
+        uint32_t* o = ob + ((size_t)(b0 + u - G.blk_lo) * 3 * K + r) * n + slot;
+        o[0] = (uint32_t)a0[u];
+        o[(size_t)K * n] = (uint32_t)a1[u];
+        o[(size_t)2 * K * n] = (uint32_t)a2[u];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 extern "C" __global__ void __launch_bounds__(WG)
 k_rescale(DevTabs T, const uint32_t* __restrict__ X, int64_t nblk, int64_t blk_lo,
           uint64_t* __restrict__ scores, uint64_t* __restrict__ digits) {
@@ -584,6 +670,11 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
     default: return hipErrorInvalidValue;
   }
 #undef MAC_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_mac_multi, dim3(grid), dim3(MB_WG), 0, s, T, A);
   return hipGetLastError();
 }
 

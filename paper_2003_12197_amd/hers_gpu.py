@@ -52,6 +52,11 @@ EXPORTS = {
     "hers_search": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
                                   ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
+    "hers_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
+                                 ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t,
+                                 ctypes.POINTER(c_vp)]),
+    "hers_plan_launch": (c_i32, [c_vp, c_vp]),
+    "hers_plan_destroy": (None, [c_vp]),
     "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_set_option": (c_i32, [c_vp, ctypes.c_char_p, c_i64]),
     "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
@@ -220,17 +225,33 @@ class Context:
                "hers_search")
         return scores
 
+    def batch_workspace(self, ms, blocks_per_round=None):
+        """Workspace for search_batch: every request's accumulators for a round of blocks."""
+        per = int(self.lib.hers_workspace_bytes(self.handle, OP_SEARCH, self.n, 1))
+        rounds = blocks_per_round or max(self.blocks(m) for m in ms)
+        return torch.empty(per * len(ms) * rounds, dtype=torch.uint8, device=self.device)
+
     def search_batch(self, galleries, ms, ds, probes, scores=None, workspace=None):
         nreq = len(galleries)
         if scores is None:
             scores = [self.new_scores(m) for m in ms]
         if workspace is None:
-            workspace = self.workspace(OP_SEARCH, max(ms), max(ds))
+            workspace = self.batch_workspace(ms)
         arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
         _check(self.lib, self.lib.hers_search_batch(
             self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
             _ptr(workspace), workspace.numel(), _stream()), "hers_search_batch")
         return scores
+
+    def plan(self, galleries, ms, ds, probes, scores, workspace):
+        """Capture a batch as a HIP graph; returns a Plan whose launch() replays it."""
+        nreq = len(galleries)
+        arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
+        h = c_vp()
+        _check(self.lib, self.lib.hers_plan_create(
+            self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
+            _ptr(workspace), workspace.numel(), ctypes.byref(h)), "hers_plan_create")
+        return Plan(self, h, (galleries, probes, scores, workspace))
 
     def set_option(self, key, value):
         _check(self.lib, self.lib.hers_set_option(self.handle, key.encode(), int(value)), "hers_set_option")
@@ -270,3 +291,24 @@ class Context:
                                                       _ptr(workspace), workspace.numel(), _stream()),
                "hers_decrypt_scores")
         return out
+
+
+class Plan:
+    """A captured batch (hers_plan); keeps its buffers alive."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+
+    def launch(self):
+        _check(self.ctx.lib, self.ctx.lib.hers_plan_launch(self.handle, _stream()), "hers_plan_launch")
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.hers_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -235,3 +235,63 @@ def test_full_size_single_probe_sampled_parity(gpu_lib):
     scores = sc[b].cpu().numpy()
     assert np.array_equal(scores[0], res(S[0], op.q_primes))
     assert np.array_equal(scores[1], res(S[1], op.q_primes))
+
+
+def _single_scores(ctx, gal, m, d, probe):
+    return ctx.search(gal, m, d, probe).clone()
+
+
+@pytest.fixture(scope="module")
+def batch_setup(case_r36):
+    """Two galleries of uneven size and d on one context, 23 probes."""
+    a = case_r36
+    ctx = a.ctx
+    P2, _ = synth.uniform_features(55, 16, 2048 + 900)
+    g2 = ctx.encrypt_gallery(torch.from_numpy(P2).to(ctx.device), P2.shape[1], 77)
+    rng = np.random.default_rng(66)
+    reqs = []
+    for j in range(20):
+        qv = rng.integers(-63, 64, size=a.d).astype(np.int32)
+        pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 1000 + j)
+        reqs.append((a.gallery, a.m, a.d, pr, a.P, qv))
+    for j in range(3):
+        qv = rng.integers(-63, 64, size=16).astype(np.int32)
+        pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 2000 + j)
+        reqs.append((g2, P2.shape[1], 16, pr, P2, qv))
+    return ctx, reqs
+
+
+def test_batch_multi_probe_equals_single(batch_setup, case_r36):
+    """Grouped requests (16 + 4 on one gallery, 3 on another) in one submission
+    give the same score ciphertexts as one hers_search per request."""
+    ctx, reqs = batch_setup
+    gals, ms, ds, prs = [r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
+    for ws in (ctx.batch_workspace(ms), ctx.batch_workspace(ms, blocks_per_round=1)):
+        outs = ctx.search_batch(gals, ms, ds, prs, workspace=ws)
+        for j, (g, m, d, pr, P, qv) in enumerate(reqs):
+            assert torch.equal(outs[j], _single_scores(ctx, g, m, d, pr)), j
+    dec = ctx.decrypt_scores(case_r36.sk, outs[5], ms[5]).cpu().numpy()
+    assert np.array_equal(dec, hers.plaintext_scores(reqs[5][4], reqs[5][5]))
+    dec = ctx.decrypt_scores(case_r36.sk, outs[21], ms[21]).cpu().numpy()
+    assert np.array_equal(dec, hers.plaintext_scores(reqs[21][4], reqs[21][5]))
+
+
+def test_plan_replays_match_eager(batch_setup, case_r36):
+    """A captured batch replayed three times, with the probes re-encrypted in
+    place and eager searches between replays, matches the eager result each time."""
+    ctx, reqs = batch_setup
+    reqs = reqs[:6] + reqs[20:22]
+    gals, ms, ds, prs = [r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
+    scores = [ctx.new_scores(m) for m in ms]
+    ws = ctx.batch_workspace(ms, blocks_per_round=2)
+    plan = ctx.plan(gals, ms, ds, prs, scores, ws)
+    rng = np.random.default_rng(99)
+    for rep in range(3):
+        for j, r in enumerate(reqs):
+            qv = rng.integers(-63, 64, size=r[2]).astype(np.int32)
+            ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 5000 + 10 * rep + j, probe=prs[j])
+        plan.launch()
+        torch.cuda.synchronize()
+        for j, r in enumerate(reqs):
+            assert torch.equal(scores[j], _single_scores(ctx, r[0], r[1], r[2], prs[j])), (rep, j)
+    plan.close()
