@@ -383,8 +383,10 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
     TIMED(ctx, "mac", S(stream), hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream),
                                                        ctx->mac_variant));
     TIMED(ctx, "intt_acc", S(stream), hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
-    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, scores_dev, digits, S(stream)));
-    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, scores_dev, S(stream)));
+    ScorePtrs sp;
+    sp.p[0] = scores_dev;
+    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, S(stream)));
+    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, sp, 1, 0, S(stream)));
   }
   return HERS_OK;
 }
@@ -519,17 +521,22 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         if (int rc = flush()) return rc;
     }
     if (int rc = flush()) return rc;
+    // epilogue: the requests of a group share a block range; their slabs are
+    // consecutive, so one launch per kernel covers up to EP_MAXR of them
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       const BatchGroup& g = groups[gi];
       const int64_t hi = lo + CB < g.M ? lo + CB : g.M;
       if (lo >= hi) continue;
-      for (size_t j = 0; j < g.reqs.size(); ++j) {
-        uint32_t* acc = acc_of[gi] + j * (CB * acc_pb / 4);
-        uint64_t* dig = dig_of[gi] + j * (CB * dig_pb / 8);
-        uint64_t* sc = scores[g.reqs[j]];
-        TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s));
-        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sc, dig, s));
-        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, dig, hi - lo, lo, sc, s));
+      const uint64_t as = CB * acc_pb / 4, ds = CB * dig_pb / 8;
+      for (size_t j0 = 0; j0 < g.reqs.size(); j0 += EP_MAXR) {
+        const uint32_t nr = (uint32_t)(g.reqs.size() - j0 < EP_MAXR ? g.reqs.size() - j0 : EP_MAXR);
+        uint32_t* acc = acc_of[gi] + j0 * as;
+        uint64_t* dig = dig_of[gi] + j0 * ds;
+        ScorePtrs sp;
+        for (uint32_t j = 0; j < nr; ++j) sp.p[j] = scores[g.reqs[j0 + j]];
+        TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
+        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s));
+        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, dig, hi - lo, lo, sp, nr, ds, s));
       }
     }
   }

@@ -31,6 +31,12 @@ struct MacGroup {
   int32_t d, nprobe;
 };
 
+// Score-ciphertext pointers of the requests of one epilogue launch.
+#define EP_MAXR 64
+struct ScorePtrs {
+  uint64_t* p[EP_MAXR];
+};
+
 struct MacBatchArgs {
   MacGroup g[MB_MAXG];
   uint64_t total_items;
@@ -51,13 +57,14 @@ hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct
 hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
                        int64_t block0, uint32_t* out, hipStream_t s);
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
-                        int inverse, hipStream_t s);
+                        int inverse, hipStream_t s, uint32_t nsets = 1, uint64_t set_stride = 0);
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
                       int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
-                          uint64_t* scores, uint64_t* digits, hipStream_t s);
+                          const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
+                          uint64_t dig_stride, hipStream_t s);
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
-                        int64_t blk_lo, uint64_t* scores, hipStream_t s);
+                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s);
 hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,
                          hipStream_t s);
 hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,

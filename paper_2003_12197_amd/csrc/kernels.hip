@@ -224,14 +224,15 @@ k_lift(DevTabs T, const uint64_t* __restrict__ canon, uint32_t nct, int32_t d, i
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
-k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse) {
-  // In-place negacyclic NTT mod p_r of polynomial blockIdx.x, where
+k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, uint64_t req_stride) {
+  // In-place negacyclic NTT mod p_r of polynomial blockIdx.x of set
+  // blockIdx.y (at polys + blockIdx.y * req_stride words), where
   // r = (blockIdx.x / inner) mod K.
   extern __shared__ uint32_t lds32[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, tid = threadIdx.x;
   const uint32_t r = (blockIdx.x / inner) % C.K;
-  uint32_t* a = polys + (size_t)blockIdx.x * n;
+  uint32_t* a = polys + (size_t)blockIdx.y * req_stride + (size_t)blockIdx.x * n;
   for (uint32_t j = tid; j < n; j += WG) lds32[j] = a[j];
   __syncthreads();
   const ModP mp{C.p[r]};
@@ -446,11 +447,16 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
-k_rescale(DevTabs T, const uint32_t* __restrict__ X, int64_t nblk, int64_t blk_lo,
-          uint64_t* __restrict__ scores, uint64_t* __restrict__ digits) {
+k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_lo, ScorePtrs SP,
+          uint64_t* __restrict__ digits_b, uint64_t acc_stride, uint64_t dig_stride) {
   // Per coefficient of X_j (j = 0, 1, 2; residues mod p_r, |X| < P/4):
   // c_j = [round(t X_j / q)]_q.  c0, c1 go to the score ciphertext (before
-  // relinearization); c2 is split into the gadget digits y_g.
+  // relinearization); c2 is split into the gadget digits y_g.  Request
+  // blockIdx.y of the round: accumulators at Xb + y acc_stride, digits at
+  // digits_b + y dig_stride, score ciphertexts SP.p[y].
+  const uint32_t* __restrict__ X = Xb + (size_t)blockIdx.y * acc_stride;
+  uint64_t* __restrict__ digits = digits_b + (size_t)blockIdx.y * dig_stride;
+  uint64_t* __restrict__ scores = SP.p[blockIdx.y];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, K = C.K, L = C.L;
   const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
@@ -479,10 +485,12 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ X, int64_t nblk, int64_t blk_l
 
 template <int NPT>
 __global__ void __launch_bounds__(WG)
-k_relin(DevTabs T, const uint64_t* __restrict__ digits, int64_t blk_lo, uint64_t* __restrict__ scores) {
-  // Relinearization of block blk_lo + blockIdx.x, residue sigma:
+k_relin(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride) {
+  // Relinearization of block blk_lo + blockIdx.x, residue sigma, request z:
   // (c0, c1) += sum_g y_g (rlk_g0, rlk_g1) in R_q; products in the NTT domain.
   extern __shared__ uint64_t lds64[];
+  const uint64_t* __restrict__ digits = digits_b + (size_t)blockIdx.z * dig_stride;
+  uint64_t* __restrict__ scores = SP.p[blockIdx.z];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
   const int64_t bl = blockIdx.x;
@@ -631,8 +639,9 @@ hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint
 }
 
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
-                        int inverse, hipStream_t s) {
-  hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys), dim3(WG), (size_t)n * 4, s, T, polys, inner, inverse);
+                        int inverse, hipStream_t s, uint32_t nsets, uint64_t set_stride) {
+  hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys, nsets), dim3(WG), (size_t)n * 4, s, T, polys, inner, inverse,
+                     set_stride);
   return hipGetLastError();
 }
 
@@ -679,24 +688,25 @@ hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t gr
 }
 
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
-                          uint64_t* scores, uint64_t* digits, hipStream_t s) {
+                          const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
+                          uint64_t dig_stride, hipStream_t s) {
   uint64_t total = (uint64_t)nblk * 3 * n;
-  hipLaunchKernelGGL(k_rescale, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, X, nblk, blk_lo,
-                     scores, digits);
+  hipLaunchKernelGGL(k_rescale, dim3((uint32_t)((total + WG - 1) / WG), nreq), dim3(WG), 0, s, T, X, nblk, blk_lo,
+                     SP, digits, acc_stride, dig_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
-                        int64_t blk_lo, uint64_t* scores, hipStream_t s) {
-  dim3 grid((uint32_t)nblk, k);
+                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s) {
+  dim3 grid((uint32_t)nblk, k, nreq);
   size_t lds = lds_bytes(n, 1);
   switch (n / WG) {
-    case 1: hipLaunchKernelGGL(k_relin<1>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
-    case 2: hipLaunchKernelGGL(k_relin<2>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
-    case 4: hipLaunchKernelGGL(k_relin<4>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
-    case 8: hipLaunchKernelGGL(k_relin<8>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
-    case 16: hipLaunchKernelGGL(k_relin<16>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
-    case 32: hipLaunchKernelGGL(k_relin<32>, grid, dim3(WG), lds, s, T, digits, blk_lo, scores); break;
+    case 1: hipLaunchKernelGGL(k_relin<1>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
+    case 2: hipLaunchKernelGGL(k_relin<2>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
+    case 4: hipLaunchKernelGGL(k_relin<4>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
+    case 8: hipLaunchKernelGGL(k_relin<8>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
+    case 16: hipLaunchKernelGGL(k_relin<16>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
+    case 32: hipLaunchKernelGGL(k_relin<32>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
