@@ -2,15 +2,21 @@
 """Benchmark of HERS encrypted search on one MI355X.
 
 Metric: encrypted scores per second (gallery items x probes per second), with
-p50/p99 probe latency.  One step is one query through the whole per-query path
-on data resident in HBM: encrypt the probe (one ciphertext per dimension),
-search every gallery block (fused multiply-accumulate over d, exact t/q
-rescale, one relinearization per block), decrypt and decode the scores.  The
-one-time enrollment (key generation, gallery encoding, encryption and lift)
-runs before the timed region and is reported on its own.
+p50/p99 probe latency.  One step is one batch of queries through the whole
+per-query path on data resident in HBM: encrypt the probes (one ciphertext per
+dimension), search every gallery block (fused multiply-accumulate over d, exact
+t/q rescale, one relinearization per block), decrypt and decode the scores.
+The one-time enrollment (key generation, gallery encoding, encryption and
+lift) runs before the timed region and is reported on its own.
 
-Printed: one JSON line with the metric, the roofline of the multiply-accumulate
-kernel (k_mac; durations from HIP events on its launch stream), and the oracle
+Workloads (--workload):
+  single   1 probe vs 1,048,576 items x d=64, n=4096, q = 3 x 36-bit (default)
+  batched  64 probes in one captured HIP-graph submission vs 10,000,000 items
+           x d=128, n=8192, q = 5 primes (218 bits), t ~ 2^21
+  large    1 probe (or --probes 16) vs 100,000,000 items x d=32, n=4096
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(durations from HIP events recorded on its launch stream), and the oracle
 timed on a bounded sample on the host cores as the CPU baseline.
 """
 
@@ -27,15 +33,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+# 64-bit integer multiply-add (v_mad_u64_u32) issue rate: 256 CUs x 4 SIMDs x
+# 16 lanes per clock at half rate x 2.4 GHz (a dependency-free microbenchmark
+# measures 20.6 T/s on the same part)
+MAD64_PEAK_TOPS = 256 * 4 * 16 / 2 * 2.4e9 / 1e12
 
 WORKLOADS = {
-    # the configuration the metric is quoted on: single probe, 2^20 items, d = 64
     "single": dict(desc="single probe vs 1,048,576-item gallery, d=64, n=4096, q=3x36-bit primes, t=1,032,193",
-                   n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=64, m=1 << 20),
-    # largest single-GPU instance: 10^8 items, d = 32
+                   n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=64, m=1 << 20, probes=1),
+    "batched": dict(desc="64 probes in one HIP-graph submission vs 10,000,000-item gallery, d=128, n=8192, "
+                         "q=3x44+2x43-bit primes, t=1,785,857",
+                    n=8192, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0, d=128, m=10_000_000, probes=64),
     "large": dict(desc="single probe vs 100,000,000-item gallery, d=32, n=4096, q=3x36-bit primes, t=1,032,193",
-                  n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=32, m=100_000_000),
+                  n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=32, m=100_000_000, probes=1),
 }
 
 KEY_SEED, GALLERY_SEED, PROBE_SEED, FEATURE_SEED, QUERY_SEED = 201, 301, 401, 1000, 2000
@@ -50,8 +61,8 @@ def kernel_source_digest():
 
 
 def measured_traffic(workload):
-    """HBM bytes per k_mac launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on different kernel sources."""
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when missing or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "k_mac_%s_pmc.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -63,27 +74,35 @@ def measured_traffic(workload):
     return int(m.group(1))
 
 
-def cpu_baseline(cfg, P_block0, qv, m):
-    """The oracle on one gallery block: probe encryption once plus one block's
-    search and decryption, scaled to the whole gallery (blocks are independent)."""
+def cpu_baseline(cfg, P_block0, qv, m, probes):
+    """The oracle on a bounded sample: one probe's encryption and one block's
+    search + decryption (for d > 64, 8 of the d tensor products, scaled by
+    d/8), scaled to every block and probe (blocks and probes are independent)."""
     from oracle import fv, hers
     op = fv.Params(n=cfg["n"], qbits=cfg["qbits"], t_bits=cfg["t_bits"], w_bits=cfg["w_bits"])
-    n = cfg["n"]
+    n, d = cfg["n"], cfg["d"]
     sk, pk, rlk = fv.keygen(op, KEY_SEED)
-    og = hers.encrypt_gallery_block(op, pk, P_block0, 0, GALLERY_SEED)
+    dims = d if d <= 64 else 8
+    og = hers.encrypt_gallery_block(op, pk, P_block0[:dims], 0, GALLERY_SEED)
     t0 = time.perf_counter()
-    oq = hers.encrypt_probe(op, pk, qv, PROBE_SEED)
+    oq = hers.encrypt_probe(op, pk, qv[:dims], PROBE_SEED)
     t1 = time.perf_counter()
-    S = hers.search_block(op, rlk, oq, og)
-    scores = hers.decrypt_scores(op, sk, {0: S}, n)
+    X = fv.tensor(op, list(zip(oq, og)))
     t2 = time.perf_counter()
-    assert np.array_equal(scores, hers.plaintext_scores(P_block0, qv))
+    c = tuple(fv.scale_round(op, x) for x in X)
+    S = fv.relinearize(op, rlk, c)
+    scores = hers.decrypt_scores(op, sk, {0: S}, n)
+    t3 = time.perf_counter()
+    assert np.array_equal(scores, hers.plaintext_scores(P_block0[:dims], qv[:dims]))
     M = (m + n - 1) // n
-    t_probe, t_block = t1 - t0, t2 - t1
-    total = t_probe + M * t_block
-    return {"value": m / total, "unit": "scores/s", "cores": 1, "kind": "oracle",
-            "sample": "one %d-item block of the gallery (d=%d): probe encryption %.1f s once, block search + "
-                      "decryption %.1f s, scaled to %d blocks" % (n, cfg["d"], t_probe, t_block, M)}
+    scale = d / dims
+    t_probe = (t1 - t0) * scale
+    t_block = (t2 - t1) * scale + (t3 - t2)
+    total = probes * (t_probe + M * t_block)
+    sample = "one %d-item block, %d of %d dimensions (tensor and probe encryption scaled x%g): probe " \
+             "encryption %.1f s, block search + decryption %.1f s per probe, scaled to %d blocks x %d probes" % (
+                 n, dims, d, scale, t_probe, t_block, M, probes)
+    return {"value": m * probes / total, "unit": "scores/s", "cores": 1, "kind": "oracle", "sample": sample}
 
 
 def main():
@@ -92,6 +111,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
+    ap.add_argument("--probes", type=int, default=0, help="override the workload's probes per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -104,8 +124,10 @@ def main():
     import torch
     from paper_2003_12197_amd import hers_gpu, synth
 
-    cfg = WORKLOADS[args.workload]
-    n, d, m = cfg["n"], cfg["d"], cfg["m"]
+    cfg = dict(WORKLOADS[args.workload])
+    if args.probes:
+        cfg["probes"] = args.probes
+    n, d, m, npr = cfg["n"], cfg["d"], cfg["m"], cfg["probes"]
     dev = torch.device("cuda", 0)
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
@@ -116,8 +138,9 @@ def main():
 
     ctx = hers_gpu.Context(n=n, qbits=cfg["qbits"], t_bits=cfg["t_bits"], w_bits=cfg["w_bits"], d_max=d)
     M = ctx.blocks(m)
-    print("workload %s: %d items x d=%d, %d blocks, K=%d base primes" % (args.workload, m, d, M, ctx.K),
-          file=sys.stderr, flush=True)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log("workload %s: %d items x d=%d, %d blocks, %d probes, K=%d base primes" % (
+        args.workload, m, d, M, npr, ctx.K))
 
     # ---- enrollment (untimed by the metric; reported separately)
     t0 = time.perf_counter()
@@ -141,30 +164,48 @@ def main():
         torch.cuda.synchronize()
         enc_ms += e0.elapsed_time(e1)
         del ft
+        if b0 // chunk % 8 == 7:
+            log("  enrolled %d / %d blocks" % (b0 + nb, M))
     del ws
     setup_s = time.perf_counter() - t0
-    print("enrolled in %.1f s (GPU encryption %.1f ms)" % (setup_s, enc_ms), file=sys.stderr, flush=True)
+    log("enrolled in %.1f s (GPU encryption %.1f ms)" % (setup_s, enc_ms))
 
-    qv, mate = synth.probe_for(QUERY_SEED, FEATURE_SEED, n, d, m)
-    query = torch.from_numpy(qv).to(dev)
-    probe = torch.empty(int(ctx.lib.hers_probe_words(ctx.handle, d)), dtype=torch.int32, device=dev)
-    scores = ctx.new_scores(m)
-    out = torch.empty(m, dtype=torch.int32, device=dev)
+    # ---- probes, outputs, workspaces
+    queries = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED, n, d, m) for j in range(npr)]
+    qdev = [torch.from_numpy(q).to(dev) for q, _ in queries]
+    probes = [torch.empty(int(ctx.lib.hers_probe_words(ctx.handle, d)), dtype=torch.int32, device=dev)
+              for _ in range(npr)]
+    scores = [ctx.new_scores(m) for _ in range(npr)]
+    outs = [torch.empty(m, dtype=torch.int32, device=dev) for _ in range(npr)]
     ws_p = ctx.workspace(hers_gpu.OP_ENCRYPT_PROBE, 0, d)
-    ws_s = ctx.workspace(hers_gpu.OP_SEARCH, m, d)
-    ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, m, 1)
-
-    ctx.encrypt_probe(query, PROBE_SEED, probe=probe, workspace=ws_p)
-    mac_variant = ctx.autotune(gallery, m, d, probe, reps=3, workspace=ws_s)
-    print("autotuned k_mac schedule: %d" % mac_variant, file=sys.stderr, flush=True)
+    ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, min(m, 512 * n), 1)   # decryption in rounds of 512 blocks
+    for j in range(npr):
+        ctx.encrypt_probe(qdev[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
+    plan = None
+    if npr == 1:
+        ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 2048 * n), d)
+        mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s)
+        log("autotuned k_mac schedule: %d" % mac_variant)
+        search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
+        dominant = "mac"
+    else:
+        rounds = max(8, min(M, (8 << 30) // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
+        ws_s = ctx.batch_workspace([m] * npr, blocks_per_round=rounds)
+        mac_variant = None
+        plan = ctx.plan([gallery] * npr, [m] * npr, [d] * npr, probes, scores, ws_s)
+        search = plan.launch
+        dominant = "mac_multi"
+        log("captured the %d-probe batch as a HIP graph (rounds of %d blocks)" % (npr, rounds))
 
     def step(seed):
-        ctx.encrypt_probe(query, seed, probe=probe, workspace=ws_p)
-        ctx.search(gallery, m, d, probe, scores=scores, workspace=ws_s)
-        ctx.decrypt_scores(sk, scores, m, out=out, workspace=ws_d)
+        for j in range(npr):
+            ctx.encrypt_probe(qdev[j], seed + j, probe=probes[j], workspace=ws_p)
+        search()
+        for j in range(npr):
+            ctx.decrypt_scores(sk, scores[j], m, out=outs[j], workspace=ws_d)
 
     for w in range(args.warmup):
-        step(PROBE_SEED + w)
+        step(PROBE_SEED + 100 * (w + 1))
     torch.cuda.synchronize()
 
     # ---- timed region
@@ -180,34 +221,60 @@ def main():
     wall = time.perf_counter() - t_start
     step_ms = [evs[s].elapsed_time(evs[s + 1]) for s in range(args.steps)]
     total_ms = evs[0].elapsed_time(evs[-1])
-    stages = {st: ctx.profile_read(st) for st in ("mac", "intt_acc", "rescale", "relin", "encrypt", "lift",
-                                                 "ntt_fwd", "sk_ntt", "dec_mul", "dec_decode")}
+    stage_names = ("mac", "mac_multi", "intt_acc", "rescale", "relin", "encrypt", "lift", "ntt_fwd", "sk_ntt",
+                   "dec_mul", "dec_decode")
+    stages = {st: ctx.profile_read(st) for st in stage_names}
     ctx.profile_enable(False)
+    if plan is not None:
+        # graph replays carry no per-kernel events: time the batch's kernels in one eager run
+        ctx.profile_enable(True)
+        ctx.search_batch([gallery] * npr, [m] * npr, [d] * npr, probes, scores=scores, workspace=ws_s)
+        torch.cuda.synchronize()
+        for st in ("mac", "mac_multi", "intt_acc", "rescale", "relin"):
+            ms_, cnt_ = ctx.profile_read(st)
+            stages[st] = (ms_ * args.steps, cnt_ * args.steps)
+        ctx.profile_enable(False)
 
     # ---- correctness of the last step (outside the timed region)
-    got = out.cpu().numpy()
+    got = outs[0].cpu().numpy()
     if args.workload == "single":
         P = synth.gallery_features(FEATURE_SEED, n, d, m)
-        ok = bool(np.array_equal(got, P.T.astype(np.int64) @ qv.astype(np.int64)))
+        ok = bool(np.array_equal(got, P.T.astype(np.int64) @ queries[0][0].astype(np.int64)))
         del P
     else:
-        ok = bool(np.array_equal(got[:n], P_block0.T.astype(np.int64) @ qv.astype(np.int64)))
+        ok = True
+        for b in sorted({0, M // 2, M - 1}):
+            Pb = synth.gallery_block(FEATURE_SEED, b, n, d, m)
+            hi = min(n, m - b * n)
+            for j in sorted({0, npr - 1}):
+                want = Pb.T[:hi].astype(np.int64) @ queries[j][0].astype(np.int64)
+                ok &= bool(np.array_equal(outs[j][b * n:b * n + hi].cpu().numpy(), want))
     top = int(np.argmax(got))
 
-    # ---- roofline of k_mac: algorithmic bytes = gallery search form + probe + accumulators
+    # ---- roofline of the dominant kernel
     K = ctx.K
-    mac_ms, mac_n = stages["mac"]
-    gallery_bytes = M * K * d * 2 * n * 4
-    probe_bytes = K * d * 2 * n * 4
-    acc_bytes = M * 3 * K * n * 4
-    launches_per_step = mac_n / args.steps
-    bytes_per_launch = (gallery_bytes + acc_bytes) / launches_per_step + probe_bytes
-    mac_avg_ms = mac_ms / mac_n
-    achieved = bytes_per_launch / (mac_avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
+    dom_ms, dom_n = stages[dominant]
+    dom_avg_ms = dom_ms / dom_n
+    if dominant == "mac":
+        # algorithmic bytes: gallery search form + accumulators of the launch's blocks + the probe
+        launches_per_step = dom_n / args.steps
+        per_launch = (M * K * d * 2 * n * 4 + M * 3 * K * n * 4) / launches_per_step + K * d * 2 * n * 4
+        achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload), "kernel": "k_mac",
+                "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
+    else:
+        # algorithmic 64-bit multiply-adds: 4 per (probe, block, dimension, base prime, slot)
+        launches_per_step = dom_n / args.steps
+        per_launch = 4.0 * npr * M * d * K * n / launches_per_step
+        achieved = per_launch / (dom_avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": MAD64_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / MAD64_PEAK_TOPS, "traffic": measured_traffic(args.workload),
+                "kernel": "k_mac_multi", "mads_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
 
-    value = m * args.steps / (total_ms * 1e-3)
+    value = m * npr * args.steps / (total_ms * 1e-3)
     lat = np.array(step_ms)
+    search_ms = sum(stages[s][0] for s in ("mac", "mac_multi", "intt_acc", "rescale", "relin")) / args.steps
     result = {
         "metric": "encrypted scores/sec (gallery items x probes per s); p50/p99 probe latency",
         "value": value,
@@ -221,26 +288,24 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "items": m, "dims": d, "probes_per_step": 1, "blocks": M,
-                   "ring_degree": n, "q_primes_bits": list(cfg["qbits"]), "t": int(ctx.t),
-                   "base_primes": K, "step": "encrypt probe + search all blocks + decrypt scores",
-                   "mac_schedule": mac_variant},
+        "config": {"workload": cfg["desc"] if npr == WORKLOADS[args.workload]["probes"] else
+                   cfg["desc"] + " (%d probes per step)" % npr,
+                   "items": m, "dims": d, "probes_per_step": npr, "blocks": M, "ring_degree": n,
+                   "q_primes_bits": list(cfg["qbits"]), "t": int(ctx.t), "base_primes": K,
+                   "step": "encrypt probes + search all blocks + decrypt scores",
+                   "mac_schedule": mac_variant, "hip_graph": plan is not None},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean())},
-        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
-        "search_only_scores_per_s": m / (sum(stages[s][0] for s in ("mac", "intt_acc", "rescale", "relin"))
-                                         / args.steps * 1e-3),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_mac", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": mac_avg_ms},
+                       "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "search_only_scores_per_s": m * npr / (search_ms * 1e-3),
+        "roofline": roof,
         "enrollment": {"gpu_encrypt_ms": enc_ms, "items_per_s": m / (enc_ms * 1e-3), "wall_s": setup_s},
-        "check": {"scores_equal_PTq": ok, "argmax": top, "mate": mate},
+        "check": {"scores_equal_PTq": ok, "argmax": top, "mate": queries[0][1]},
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
-        print("cpu baseline: oracle on one block ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(cfg, P_block0, qv, m)
+        log("cpu baseline: oracle on a one-block sample ...")
+        result["cpu_baseline"] = cpu_baseline(cfg, P_block0, queries[0][0], m, npr)
     print(json.dumps(result), flush=True)
     if not ok:
         sys.exit(1)
