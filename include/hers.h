@@ -212,6 +212,44 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
                   void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen);
 int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
 
+/* ---- serving ---------------------------------------------------------------
+ * A request loop over one context (the context then belongs to the server's
+ * worker thread until hers_server_destroy).  Galleries (search form, caller
+ * memory) and the evaluation key stay resident.  A query submitted with
+ * hers_server_submit is, on the GPU, encrypted (hers_encrypt_probe with the
+ * given seed), searched against its gallery and decrypted with sk_dev.
+ *   Admission: every request needs query + probe + score ciphertexts +
+ *   decrypted scores, and each wave a workspace, all carved from arena_dev
+ *   (arena_bytes of device memory owned by the caller) by a first-fit
+ *   allocator; a request that does not fit waits (counted in deferrals) until
+ *   results are collected with hers_server_wait, which frees its memory.
+ *   Batching: the worker admits queued requests in arrival order, up to
+ *   max_batch per wave, and runs a wave on one of two streams while the
+ *   previous wave may still run on the other; requests on the same gallery in
+ *   a wave share one pass over the gallery.  Each result is bit-identical to
+ *   the same request served alone.
+ * hers_server_submit copies the query (host int32 [d] of the gallery) and
+ * returns a ticket, or HERS_ENOMEM if one request alone exceeds the arena.
+ * hers_server_wait blocks until the ticket's scores are ready, optionally
+ * copies the decrypted scores (host int32 [m]) and the score ciphertexts
+ * (host u64 [M][2][k][n]) out, reports the latency from submission to scores
+ * ready on the GPU, and releases the ticket. */
+typedef struct hers_server hers_server;
+typedef struct {
+  int64_t submitted, completed, deferrals, waves, max_wave, queued, in_flight;
+  uint64_t arena_peak;
+} hers_server_stats;
+int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, size_t arena_bytes,
+                       int32_t max_batch, hers_server** out);
+int hers_server_add_gallery(hers_server* srv, const uint32_t* gallery_dev, int64_t m, int32_t d,
+                            int32_t* gallery_id);
+int hers_server_submit(hers_server* srv, int32_t gallery_id, const int32_t* query, uint64_t seed,
+                       int64_t* ticket);
+int hers_server_wait(hers_server* srv, int64_t ticket, int32_t* scores_out, uint64_t* ct_out,
+                     double* latency_ms);
+int hers_server_stats_get(hers_server* srv, hers_server_stats* out);
+void hers_server_destroy(hers_server* srv);
+
 /* ---- per-stage timing ---------------------------------------------------
  * While enabled, every kernel launch of the library is bracketed by HIP events
  * recorded on the stream it is launched on.  hers_profile_enable clears the

@@ -1,0 +1,394 @@
+// server.cpp -- continuous-batching request loop over the libhers C ABI.
+//
+// The server keeps encrypted galleries and the evaluation key resident (they
+// live in the context and in caller memory) and serves queries as they
+// arrive.  Each query runs the client and server halves of the search
+// protocol (App. B, Alg. "HERS Search"): probe encryption, the batched
+// encrypted search over its gallery, decryption of the scores.
+//
+// Admission is by memory: every request needs device memory for its query,
+// probe search form, score ciphertexts and decrypted scores, carved from a
+// caller-provided arena by a first-fit allocator; a request that does not fit
+// waits in the queue (a deferral) until earlier results are collected.  A
+// worker thread forms waves from the queue in arrival order and enqueues each
+// wave on one of two streams, so a wave admitted while the previous one is
+// still on the GPU overlaps with it.  Requests of a wave on the same gallery
+// share one pass over the gallery (hers_search_batch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hers.h"
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Gallery {
+  const uint32_t* ptr;
+  int64_t m;
+  int32_t d;
+};
+
+struct Request {
+  int64_t ticket;
+  int32_t gid;
+  std::vector<int32_t> query;
+  uint64_t seed;
+  double t_arrival = 0, t_start = 0, t_done = 0;
+  size_t off = 0, bytes = 0;          // one arena range: query | probe | score cts | scores
+  size_t o_query = 0, o_probe = 0, o_ct = 0, o_out = 0;
+  int state = 0;                      // 0 queued, 1 on the GPU, 2 done, 3 failed
+  std::string error;
+};
+
+struct Wave {
+  std::vector<Request*> reqs;
+  size_t ws_off = 0, ws_bytes = 0;
+  hipEvent_t ev = nullptr;
+  int stream = 0;
+};
+
+}  // namespace
+
+struct hers_server {
+  hers_ctx* ctx;
+  const uint8_t* sk;
+  char* arena_base;
+  Arena arena;
+  int max_batch;
+  hers_info info;
+  int device = 0;
+  std::vector<Gallery> galleries;
+  std::deque<Request*> queue;
+  std::map<int64_t, Request*> reqs;
+  std::vector<Wave> inflight;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread worker;
+  bool stop = false;
+  int64_t next_ticket = 1;
+  hipStream_t streams[2] = {nullptr, nullptr};
+  hipStream_t copy_stream = nullptr;
+  hers_server_stats st;
+  size_t enc_ws = 0, dec_ws = 0;
+
+  hers_server(hers_ctx* c, const uint8_t* s, char* base, size_t bytes, int mb)
+      : ctx(c), sk(s), arena_base(base), arena(bytes), max_batch(mb) {
+    std::memset(&st, 0, sizeof(st));
+  }
+};
+
+namespace {
+
+size_t request_bytes(const hers_server* s, const Gallery& g, size_t* oq, size_t* op, size_t* oc, size_t* oo) {
+  size_t off = 0;
+  *oq = off; off += align256((size_t)g.d * 4);
+  *op = off; off += align256(hers_probe_words(s->ctx, g.d) * 4);
+  *oc = off; off += align256(hers_blocks(s->ctx, g.m) * hers_ct_words(s->ctx) * 8);
+  *oo = off; off += align256((size_t)g.m * 4);
+  return off;
+}
+
+// Workspace of one wave: probe encryption + batched search (rounds of cb
+// blocks per request) + decryption.
+size_t wave_ws_bytes(hers_server* s, const std::vector<Request*>& w, int64_t cb) {
+  const size_t per = hers_workspace_bytes(s->ctx, 2, s->info.n, 1);
+  return align256(s->enc_ws) + align256(s->dec_ws) + align256(per * (size_t)cb * w.size());
+}
+
+// Marks a wave failed.  Work already enqueued may still use the wave's memory:
+// wait for its stream before the memory can be handed out again.
+void fail_wave(hers_server* s, Wave& w, const char* what) {
+  for (Request* r : w.reqs) {
+    r->state = 3;
+    r->error = std::string(what) + ": " + hers_last_error();
+  }
+  (void)hipStreamSynchronize(s->streams[w.stream]);
+}
+
+// Enqueues a wave; called with the lock released (the ctx belongs to the worker).
+void launch_wave(hers_server* s, Wave& w, int64_t cb) {
+  hipStream_t st = s->streams[w.stream];
+  char* base = s->arena_base;
+  char* ws = base + w.ws_off;
+  void* ws_enc = ws;
+  void* ws_dec = ws + align256(s->enc_ws);
+  void* ws_srch = ws + align256(s->enc_ws) + align256(s->dec_ws);
+  const size_t srch_bytes = w.ws_bytes - align256(s->enc_ws) - align256(s->dec_ws);
+  const size_t nr = w.reqs.size();
+  std::vector<const uint32_t*> gal(nr), prb(nr);
+  std::vector<int64_t> ms(nr);
+  std::vector<int32_t> ds(nr);
+  std::vector<uint64_t*> sc(nr);
+  for (size_t i = 0; i < nr; ++i) {
+    Request* r = w.reqs[i];
+    const Gallery& g = s->galleries[r->gid];
+    char* rb = base + r->off;
+    if (hipMemcpyAsync(rb + r->o_query, r->query.data(), r->query.size() * 4, hipMemcpyHostToDevice, st) !=
+        hipSuccess) { fail_wave(s, w, "query upload"); return; }
+    if (hers_encrypt_probe(s->ctx, (const int32_t*)(rb + r->o_query), g.d, r->seed, (uint32_t*)(rb + r->o_probe),
+                           nullptr, ws_enc, s->enc_ws, st)) { fail_wave(s, w, "hers_encrypt_probe"); return; }
+    gal[i] = g.ptr; ms[i] = g.m; ds[i] = g.d;
+    prb[i] = (const uint32_t*)(rb + r->o_probe);
+    sc[i] = (uint64_t*)(rb + r->o_ct);
+  }
+  if (hers_search_batch(s->ctx, (int32_t)nr, gal.data(), ms.data(), ds.data(), prb.data(), sc.data(), ws_srch,
+                        srch_bytes, st)) { fail_wave(s, w, "hers_search_batch"); return; }
+  for (size_t i = 0; i < nr; ++i) {
+    Request* r = w.reqs[i];
+    char* rb = base + r->off;
+    if (hers_decrypt_scores(s->ctx, s->sk, sc[i], ms[i], (int32_t*)(rb + r->o_out), ws_dec, s->dec_ws, st)) {
+      fail_wave(s, w, "hers_decrypt_scores");
+      return;
+    }
+  }
+  (void)cb;
+  if (hipEventRecord(w.ev, st) != hipSuccess) fail_wave(s, w, "event");
+}
+
+void worker_main(hers_server* s) {
+  (void)hipSetDevice(s->device);
+  int next_stream = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    // retire finished waves
+    for (size_t i = 0; i < s->inflight.size();) {
+      Wave& w = s->inflight[i];
+      const bool failed = !w.reqs.empty() && w.reqs[0]->state == 3;
+      if (failed || hipEventQuery(w.ev) == hipSuccess) {
+        const double t = now_ms();
+        for (Request* r : w.reqs) {
+          if (r->state != 3) r->state = 2;
+          r->t_done = t;
+          s->st.completed += 1;
+        }
+        s->arena.release(w.ws_off, w.ws_bytes);
+        (void)hipEventDestroy(w.ev);
+        s->inflight.erase(s->inflight.begin() + i);
+        s->cv_done.notify_all();
+      } else {
+        ++i;
+      }
+    }
+    if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+    // admit a wave: queued requests in arrival order while memory allows
+    if (s->inflight.size() < 2 && !s->queue.empty()) {
+      Wave w;
+      int64_t maxM = 0;
+      while (!s->queue.empty() && (int)w.reqs.size() < s->max_batch) {
+        Request* r = s->queue.front();
+        const Gallery& g = s->galleries[r->gid];
+        size_t off;
+        if (!s->arena.alloc(r->bytes, &off)) {
+          s->st.deferrals += 1;
+          break;
+        }
+        r->off = off;
+        r->state = 1;
+        r->t_start = now_ms();
+        w.reqs.push_back(r);
+        maxM = std::max<int64_t>(maxM, (int64_t)hers_blocks(s->ctx, g.m));
+        s->queue.pop_front();
+      }
+      int64_t cb = std::min<int64_t>(maxM, 64);
+      bool ok = !w.reqs.empty();
+      while (ok) {
+        w.ws_bytes = wave_ws_bytes(s, w.reqs, cb);
+        if (s->arena.alloc(w.ws_bytes, &w.ws_off)) break;
+        if (cb == 1) ok = false; else cb = (cb + 1) / 2;
+      }
+      if (!ok && !w.reqs.empty()) {
+        // no room for the wave's workspace: return its requests to the queue head
+        s->st.deferrals += 1;
+        for (auto it = w.reqs.rbegin(); it != w.reqs.rend(); ++it) {
+          (*it)->state = 0;
+          s->arena.release((*it)->off, (*it)->bytes);
+          s->queue.push_front(*it);
+        }
+        w.reqs.clear();
+      }
+      if (!w.reqs.empty()) {
+        if (hipEventCreateWithFlags(&w.ev, hipEventDisableTiming) != hipSuccess) w.ev = nullptr;
+        w.stream = next_stream;
+        next_stream ^= 1;
+        s->st.waves += 1;
+        s->st.max_wave = std::max<int64_t>(s->st.max_wave, (int64_t)w.reqs.size());
+        s->st.arena_peak = s->arena.peak();
+        lk.unlock();
+        if (w.ev) launch_wave(s, w, cb); else fail_wave(s, w, "event create");
+        lk.lock();
+        s->inflight.push_back(w);
+        continue;
+      }
+    }
+    if (s->inflight.empty())
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    else
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, size_t arena_bytes, int32_t max_batch,
+                       hers_server** out) {
+  if (!ctx || !sk_dev || !arena_dev || !out || max_batch < 1) return HERS_EINVAL;
+  *out = nullptr;
+  hers_server* s = new hers_server(ctx, sk_dev, (char*)arena_dev, arena_bytes, max_batch);
+  if (hers_ctx_info(ctx, &s->info)) { delete s; return HERS_EINVAL; }
+  (void)hipGetDevice(&s->device);
+  for (int i = 0; i < 2; ++i)
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) { delete s; return HERS_EDEVICE; }
+  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) { delete s; return HERS_EDEVICE; }
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return HERS_OK;
+}
+
+int hers_server_add_gallery(hers_server* s, const uint32_t* gallery_dev, int64_t m, int32_t d, int32_t* gallery_id) {
+  if (!s || !gallery_dev || m < 1 || d < 1 || !gallery_id) return HERS_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  s->galleries.push_back({gallery_dev, m, d});
+  *gallery_id = (int32_t)s->galleries.size() - 1;
+  s->enc_ws = std::max<size_t>(s->enc_ws, hers_workspace_bytes(s->ctx, 1, 0, d));
+  s->dec_ws = std::max<size_t>(s->dec_ws, hers_workspace_bytes(s->ctx, 3, std::min<int64_t>(m, 256 * (int64_t)s->info.n), 1));
+  return HERS_OK;
+}
+
+int hers_server_submit(hers_server* s, int32_t gallery_id, const int32_t* query, uint64_t seed, int64_t* ticket) {
+  if (!s || !query || !ticket) return HERS_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (gallery_id < 0 || gallery_id >= (int32_t)s->galleries.size()) return HERS_EINVAL;
+  const Gallery& gal = s->galleries[gallery_id];
+  Request* r = new Request();
+  r->ticket = s->next_ticket++;
+  r->gid = gallery_id;
+  r->query.assign(query, query + gal.d);
+  r->seed = seed;
+  r->t_arrival = now_ms();
+  r->bytes = request_bytes(s, gal, &r->o_query, &r->o_probe, &r->o_ct, &r->o_out);
+  std::vector<Request*> one{r};
+  if (r->bytes + wave_ws_bytes(s, one, 1) > s->arena.size()) { delete r; return HERS_ENOMEM; }
+  s->reqs[r->ticket] = r;
+  s->queue.push_back(r);
+  s->st.submitted += 1;
+  *ticket = r->ticket;
+  s->cv_work.notify_one();
+  return HERS_OK;
+}
+
+int hers_server_wait(hers_server* s, int64_t ticket, int32_t* scores_out, uint64_t* ct_out, double* latency_ms) {
+  if (!s) return HERS_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return HERS_EINVAL;
+  Request* r = it->second;
+  s->cv_done.wait(lk, [&] { return r->state >= 2; });
+  // only this caller holds the ticket now: copy without the lock
+  s->reqs.erase(it);
+  lk.unlock();
+  int rc = r->state == 2 ? HERS_OK : HERS_EDEVICE;
+  const Gallery g = s->galleries[r->gid];
+  char* rb = s->arena_base + r->off;
+  if (rc == HERS_OK && scores_out &&
+      hipMemcpyAsync(scores_out, rb + r->o_out, (size_t)g.m * 4, hipMemcpyDeviceToHost, s->copy_stream) != hipSuccess)
+    rc = HERS_EDEVICE;
+  if (rc == HERS_OK && ct_out &&
+      hipMemcpyAsync(ct_out, rb + r->o_ct, hers_blocks(s->ctx, g.m) * hers_ct_words(s->ctx) * 8,
+                     hipMemcpyDeviceToHost, s->copy_stream) != hipSuccess)
+    rc = HERS_EDEVICE;
+  if ((scores_out || ct_out) && hipStreamSynchronize(s->copy_stream) != hipSuccess) rc = HERS_EDEVICE;
+  if (latency_ms) *latency_ms = r->t_done - r->t_arrival;
+  lk.lock();
+  s->arena.release(r->off, r->bytes);
+  delete r;
+  s->cv_work.notify_one();
+  return rc;
+}
+
+int hers_server_stats_get(hers_server* s, hers_server_stats* out) {
+  if (!s || !out) return HERS_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  *out = s->st;
+  out->arena_peak = s->arena.peak();
+  out->queued = (int64_t)s->queue.size();
+  out->in_flight = (int64_t)s->inflight.size();
+  return HERS_OK;
+}
+
+void hers_server_destroy(hers_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->reqs) delete kv.second;
+  for (int i = 0; i < 2; ++i)
+    if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  delete s;
+}
+
+}  // extern "C"

@@ -66,6 +66,20 @@ EXPORTS = {
     "hers_profile_read": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_u64)]),
 }
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("deferrals", c_i64), ("waves", c_i64),
+                ("max_wave", c_i64), ("queued", c_i64), ("in_flight", c_i64), ("arena_peak", c_u64)]
+
+
+EXPORTS.update({
+    "hers_server_create": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_size_t, c_i32, ctypes.POINTER(c_vp)]),
+    "hers_server_add_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32)]),
+    "hers_server_submit": (c_i32, [c_vp, c_i32, c_vp, c_u64, ctypes.POINTER(c_i64)]),
+    "hers_server_wait": (c_i32, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(ctypes.c_double)]),
+    "hers_server_stats_get": (c_i32, [c_vp, ctypes.POINTER(ServerStats)]),
+    "hers_server_destroy": (None, [c_vp]),
+})
+
 OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT = 0, 1, 2, 3
 
 
@@ -305,6 +319,79 @@ class Plan:
     def close(self):
         if self.handle:
             self.ctx.lib.hers_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (hers_server) on a context.
+
+    The context belongs to the server's worker thread until close()."""
+
+    def __init__(self, ctx, sk, arena_bytes, max_batch=16):
+        import numpy as _np
+        self._np = _np
+        self.ctx, self.lib = ctx, ctx.lib
+        self.sk = sk
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=ctx.device)
+        torch.cuda.synchronize()
+        h = c_vp()
+        _check(self.lib, self.lib.hers_server_create(ctx.handle, _ptr(sk), _ptr(self.arena), self.arena.numel(),
+                                                     max_batch, ctypes.byref(h)), "hers_server_create")
+        self.handle = h
+        self.galleries = {}
+        self._tickets = {}
+
+    def add_gallery(self, gallery, m, d):
+        gid = c_i32()
+        _check(self.lib, self.lib.hers_server_add_gallery(self.handle, _ptr(gallery), int(m), int(d),
+                                                          ctypes.byref(gid)), "hers_server_add_gallery")
+        self.galleries[gid.value] = (gallery, int(m), int(d))
+        return gid.value
+
+    def submit(self, gid, query, seed):
+        q = self._np.ascontiguousarray(query, dtype=self._np.int32)
+        t = c_i64()
+        rc = self.lib.hers_server_submit(self.handle, gid, q.ctypes.data_as(c_vp), int(seed), ctypes.byref(t))
+        _check(self.lib, rc, "hers_server_submit")
+        self._tickets[t.value] = self.galleries[gid][1]
+        return t.value
+
+    def wait(self, ticket, scores=True, ciphertexts=False):
+        """(latency ms, decrypted scores int32 [m] or None, score ciphertexts or None)."""
+        gid_m = None
+        lat = ctypes.c_double()
+        out = ct = None
+        # sizes come from the gallery of the ticket; the server checks the ticket
+        if scores or ciphertexts:
+            gid_m = self._ticket_sizes(ticket)
+        if scores:
+            out = self._np.empty(gid_m[0], dtype=self._np.int32)
+        if ciphertexts:
+            ct = self._np.empty(gid_m[1], dtype=self._np.uint64)
+        rc = self.lib.hers_server_wait(self.handle, ticket, None if out is None else out.ctypes.data_as(c_vp),
+                                       None if ct is None else ct.ctypes.data_as(c_vp), ctypes.byref(lat))
+        self._tickets.pop(ticket, None)
+        _check(self.lib, rc, "hers_server_wait")
+        return lat.value, out, ct
+
+    def _ticket_sizes(self, ticket):
+        m = self._tickets[ticket]
+        return m, self.ctx.blocks(m) * 2 * self.ctx.k * self.ctx.n
+
+    def stats(self):
+        s = ServerStats()
+        _check(self.lib, self.lib.hers_server_stats_get(self.handle, ctypes.byref(s)), "hers_server_stats_get")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.hers_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
