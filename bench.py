@@ -14,6 +14,10 @@ Workloads (--workload):
   batched  64 probes in one captured HIP-graph submission vs 10,000,000 items
            x d=128, n=8192, q = 5 primes (218 bits), t ~ 2^21
   large    1 probe (or --probes 16) vs 100,000,000 items x d=32, n=4096
+  serving  Poisson query stream (200/s) against 8 resident galleries of sizes
+           log-uniform in [1e3, 5e6] and d in {16, 32, 64}, n=4096, served by the
+           continuous-batching request loop; also served one request at a time
+           for comparison (step = the whole stream)
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (durations from HIP events recorded on its launch stream), and the oracle
@@ -45,6 +49,10 @@ WORKLOADS = {
     "batched": dict(desc="64 probes in one HIP-graph submission vs 10,000,000-item gallery, d=128, n=8192, "
                          "q=3x44+2x43-bit primes, t=1,785,857",
                     n=8192, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0, d=128, m=10_000_000, probes=64),
+    "serving": dict(desc="Poisson stream of 200 queries/s against 8 resident galleries, sizes log-uniform in "
+                         "[1e3, 5e6], d in {16,32,64}, n=4096, q=3x36-bit primes",
+                    n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=64, m=0, probes=0,
+                    rate=200.0, requests=2000),
     "large": dict(desc="single probe vs 100,000,000-item gallery, d=32, n=4096, q=3x36-bit primes, t=1,032,193",
                   n=4096, qbits=(36, 36, 36), t_bits=20, w_bits=0, d=32, m=100_000_000, probes=1),
 }
@@ -105,6 +113,125 @@ def cpu_baseline(cfg, P_block0, qv, m, probes):
     return {"value": m * probes / total, "unit": "scores/s", "cores": 1, "kind": "oracle", "sample": sample}
 
 
+def run_serving(args, cfg):
+    """Serve a Poisson query stream with the request loop; report throughput and
+    latency, and the same stream served with one request per wave."""
+    import threading
+
+    import torch
+    from paper_2003_12197_amd import hers_gpu, synth
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    n = cfg["n"]
+    rate = args.rate or cfg["rate"]
+    nreq = args.requests or cfg["requests"]
+    ctx = hers_gpu.Context(n=n, qbits=cfg["qbits"], t_bits=cfg["t_bits"], w_bits=cfg["w_bits"], d_max=64)
+    sizes, dims = synth.serving_galleries(501)
+    t0 = time.perf_counter()
+    sk, pk, rlk = ctx.keygen(KEY_SEED)
+    gals = []
+    for gi, (m, d) in enumerate(zip(sizes, dims)):
+        M = ctx.blocks(m)
+        g = ctx.new_gallery(m, d)
+        chunk = max(1, min(M, (1 << 30) // (d * n * 4)))
+        ws = ctx.workspace(hers_gpu.OP_ENCRYPT_GALLERY, chunk * n, d)
+        for b0 in range(0, M, chunk):
+            nb = min(chunk, M - b0)
+            ft = torch.from_numpy(synth.gallery_features(FEATURE_SEED + 7919 * gi, n, d, m, b0, nb)).to(ctx.device)
+            ctx.encrypt_gallery(ft, m, GALLERY_SEED + gi, block0=b0, nblocks=nb, gallery=g, workspace=ws)
+        torch.cuda.synchronize()
+        del ws
+        gals.append((g, m, d))
+        log("  gallery %d: %d items x d=%d" % (gi, m, d))
+    setup_s = time.perf_counter() - t0
+    arrivals, targets = synth.poisson_arrivals(601, rate, nreq, len(gals))
+    queries = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED + 7919 * int(targets[j]), n, gals[targets[j]][2],
+                               gals[targets[j]][1])[0] for j in range(nreq)]
+    items_total = sum(gals[g][1] for g in targets)
+
+    def serve(max_batch, prof):
+        arena = 48 << 30
+        if prof:
+            ctx.profile_enable(True)
+        srv = hers_gpu.Server(ctx, sk, arena, max_batch=max_batch)
+        gids = [srv.add_gallery(*g) for g in gals]
+        tickets = [None] * nreq
+        lats = [0.0] * nreq
+        start = time.perf_counter()
+
+        stop = []
+
+        def submitter():
+            for j in range(nreq):
+                if stop:
+                    return
+                delay = arrivals[j] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[j] = srv.submit(gids[targets[j]], queries[j], PROBE_SEED + j)
+
+        th = threading.Thread(target=submitter, daemon=True)
+        th.start()
+        checked = 0
+        for j in range(nreq):
+            while tickets[j] is None:
+                time.sleep(0.0005)
+            check = j % 200 == 0
+            lat, out, _ = srv.wait(tickets[j], scores=check)
+            lats[j] = lat
+            if check:
+                g = targets[j]
+                m, d = gals[g][1], gals[g][2]
+                P = synth.gallery_features(FEATURE_SEED + 7919 * int(g), n, d, m)[:, :m]
+                if not np.array_equal(out, P.T.astype(np.int64) @ queries[j].astype(np.int64)):
+                    stop.append(1)
+                    th.join()
+                    srv.close()
+                    raise SystemExit("serving: request %d decrypted to wrong scores" % j)
+                checked += 1
+            if j % 500 == 499:
+                log("  served %d / %d" % (j + 1, nreq))
+        th.join()
+        elapsed = time.perf_counter() - start
+        stats = srv.stats()
+        srv.close()
+        stages = {}
+        if prof:
+            stages = {s: ctx.profile_read(s) for s in ("mac", "mac_multi", "intt_acc", "rescale", "relin")}
+            ctx.profile_enable(False)
+        return np.array(lats), elapsed, stats, stages, checked
+
+    lat_b, el_b, st_b, stages, checked = serve(16, True)
+    log("batched: p50 %.2f ms p99 %.2f ms, %.1f s" % (np.percentile(lat_b, 50), np.percentile(lat_b, 99), el_b))
+    lat_1, el_1, st_1, _, _ = serve(1, False)
+    log("one request per wave: p50 %.2f ms p99 %.2f ms, %.1f s" % (
+        np.percentile(lat_1, 50), np.percentile(lat_1, 99), el_1))
+    mac_ms = stages["mac"][0] + stages["mac_multi"][0]
+    achieved = st_b["gallery_bytes"] / (mac_ms * 1e-3) / 1e9 if mac_ms else 0.0
+    result = {
+        "metric": "encrypted scores/sec (gallery items x probes per s); p50/p99 probe latency",
+        "value": items_total / el_b,
+        "unit": "scores/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": el_b * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": cfg["desc"], "rate_per_s": rate, "requests": nreq,
+                   "galleries": [{"items": m, "dims": d} for _, m, d in gals], "max_batch": 16,
+                   "step": "the whole stream: arrival, probe encryption, search, decryption per request"},
+        "latency_ms": {"p50": float(np.percentile(lat_b, 50)), "p99": float(np.percentile(lat_b, 99)),
+                       "mean": float(lat_b.mean()), "per": "request, arrival to scores ready on the GPU"},
+        "unbatched": {"value": items_total / el_1, "p50_ms": float(np.percentile(lat_1, 50)),
+                      "p99_ms": float(np.percentile(lat_1, 99)), "waves": st_1["waves"]},
+        "server": {k: int(v) for k, v in st_b.items()},
+        "stage_ms": {k: v[0] for k, v in stages.items() if v[1]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_mac + k_mac_multi",
+                     "bytes": st_b["gallery_bytes"], "mac_ms": mac_ms},
+        "enrollment": {"wall_s": setup_s},
+        "check": {"requests_checked_against_PTq": checked},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +239,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
     ap.add_argument("--probes", type=int, default=0, help="override the workload's probes per step")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=0, help="serving: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -125,6 +254,8 @@ def main():
     from paper_2003_12197_amd import hers_gpu, synth
 
     cfg = dict(WORKLOADS[args.workload])
+    if args.workload == "serving":
+        return run_serving(args, cfg)
     if args.probes:
         cfg["probes"] = args.probes
     n, d, m, npr = cfg["n"], cfg["d"], cfg["m"], cfg["probes"]

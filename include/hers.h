@@ -238,6 +238,7 @@ typedef struct hers_server hers_server;
 typedef struct {
   int64_t submitted, completed, deferrals, waves, max_wave, queued, in_flight;
   uint64_t arena_peak;
+  uint64_t gallery_bytes;   /* search-form bytes streamed: once per gallery group of a wave */
 } hers_server_stats;
 int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, size_t arena_bytes,
                        int32_t max_batch, hers_server** out);

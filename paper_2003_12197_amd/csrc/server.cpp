@@ -178,6 +178,18 @@ void launch_wave(hers_server* s, Wave& w, int64_t cb) {
   std::vector<int64_t> ms(nr);
   std::vector<int32_t> ds(nr);
   std::vector<uint64_t*> sc(nr);
+  // algorithmic gallery bytes of the wave: groups of up to 16 requests per gallery stream it once
+  {
+    std::map<int32_t, int64_t> per;
+    for (Request* r : w.reqs) per[r->gid] += 1;
+    uint64_t bytes = 0;
+    for (auto& kv : per) {
+      const Gallery& g = s->galleries[kv.first];
+      bytes += (uint64_t)((kv.second + 15) / 16) * hers_gallery_words(s->ctx, g.m, g.d) * 4;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.gallery_bytes += bytes;
+  }
   for (size_t i = 0; i < nr; ++i) {
     Request* r = w.reqs[i];
     const Gallery& g = s->galleries[r->gid];

@@ -68,7 +68,8 @@ EXPORTS = {
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_i64), ("completed", c_i64), ("deferrals", c_i64), ("waves", c_i64),
-                ("max_wave", c_i64), ("queued", c_i64), ("in_flight", c_i64), ("arena_peak", c_u64)]
+                ("max_wave", c_i64), ("queued", c_i64), ("in_flight", c_i64), ("arena_peak", c_u64),
+                ("gallery_bytes", c_u64)]
 
 
 EXPORTS.update({

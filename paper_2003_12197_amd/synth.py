@@ -52,7 +52,8 @@ def gallery_block(seed, b, n, d, m_total):
 
 
 def gallery_features(seed, n, d, m_total, block0=0, nblocks=None):
-    """int32 [d][nblocks * n] for blocks block0 .. block0 + nblocks - 1."""
+    """int32 [d][nblocks * n] for blocks block0 .. block0 + nblocks - 1 (whole
+    blocks: columns past m_total are zero)."""
     M = (m_total + n - 1) // n
     if nblocks is None:
         nblocks = M - block0
