@@ -385,8 +385,8 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
     TIMED(ctx, "intt_acc", S(stream), hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
     ScorePtrs sp;
     sp.p[0] = scores_dev;
-    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, S(stream)));
-    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, digits, nb, lo, sp, 1, 0, S(stream)));
+    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, S(stream), C.k, C.K));
+    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, S(stream)));
   }
   return HERS_OK;
 }
@@ -535,8 +535,8 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         ScorePtrs sp;
         for (uint32_t j = 0; j < nr; ++j) sp.p[j] = scores[g.reqs[j0 + j]];
         TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
-        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s));
-        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, dig, hi - lo, lo, sp, nr, ds, s));
+        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s, C.k, C.K));
+        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, dig, hi - lo, lo, sp, nr, ds, s));
       }
     }
   }

@@ -58,6 +58,7 @@ struct HersConsts {
   uint32_t qmod_p[HC_MAXP];                          // q mod p_r
   uint32_t qinv_p[HC_MAXP], qinv_p_sh[HC_MAXP];      // q^-1 mod p_r
   uint32_t t_p[HC_MAXP], t_p_sh[HC_MAXP];            // t mod p_r
+  uint32_t p_r64[HC_MAXP], p_r64_sh[HC_MAXP];        // 2^64 mod p_r
 
   // ---- plaintext prime t
   uint64_t t_mu64;                                   // floor(2^64 / t)
@@ -185,8 +186,9 @@ HD int cbd20(uint64_t w) {
 // Mixed-radix digits a_i of x in [0, q) given residues v_i = x mod q_i
 // (Garner): x = a_0 + a_1 q_0 + a_2 q_0 q_1 + ..., 0 <= a_i < q_i.
 // Returns whether x > (q - 1)/2, i.e. whether the centred representative of x is x - q.
+template <int KQ = 0>
 HD bool garner_digits(const HersConsts& C, const uint64_t* v, uint64_t* a) {
-  const uint32_t k = C.k;
+  const uint32_t k = KQ ? KQ : C.k;
   for (uint32_t i = 0; i < k; ++i) {
     const uint64_t qi = C.q[i];
     uint64_t acc = v[i];
@@ -202,15 +204,32 @@ HD bool garner_digits(const HersConsts& C, const uint64_t* v, uint64_t* a) {
   return false;
 }
 
+// x mod p_r for x < 2^96 (high word below 2^32).
+HD uint32_t red128_p(const HersConsts& C, u128 x, uint32_t r) {
+  const uint32_t p = C.p[r];
+  const uint32_t lo = red_p((uint64_t)x, p, C.p_mu64[r]);
+  const uint32_t hi = shoup_p((uint32_t)(uint64_t)(x >> 64), C.p_r64[r], C.p_r64_sh[r], p);
+  return add_p(lo, hi, p);
+}
+
+// x mod q_i for any 128-bit x.
+HD uint64_t red128_q(const HersConsts& C, u128 x, uint32_t i) {
+  const uint64_t q = C.q[i];
+  const uint64_t lo = red_q((uint64_t)x, q, C.q_mu64[i]);
+  const uint64_t hi = shoup_q((uint64_t)(x >> 64), C.q_r64[i], C.q_r64_sh[i], q);
+  return add_q(lo, hi, q);
+}
+
 // Centred representative of the mixed-radix number (a, neg) modulo p_r.
+// sum_i a_i Qw_i < k 2^92: accumulated exactly, reduced once.
+template <int KQ = 0>
 HD uint32_t mixed_to_p(const HersConsts& C, const uint64_t* a, bool neg, uint32_t r) {
   const uint32_t p = C.p[r];
-  uint32_t acc = 0;
-  for (uint32_t i = 0; i < C.k; ++i) {
-    uint32_t ai = red_p(a[i], p, C.p_mu64[r]);
-    acc = add_p(acc, shoup_p(ai, C.Qw_p[i][r], C.Qw_p_sh[i][r], p), p);
-  }
-  return neg ? sub_p(acc, C.qmod_p[r], p) : acc;
+  const uint32_t k = KQ ? KQ : C.k;
+  u128 acc = 0;
+  for (uint32_t i = 0; i < k; ++i) acc += (u128)a[i] * C.Qw_p[i][r];
+  const uint32_t v = red128_p(C, acc, r);
+  return neg ? sub_p(v, C.qmod_p[r], p) : v;
 }
 
 // Centred representative of (a, neg) modulo t.
@@ -228,19 +247,21 @@ HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
 // y_r = [Y (P/p_r)^-1]_{p_r}; sum_r y_r / p_r = Y/P + gamma, so gamma is the
 // nearest integer to the sum (a quarter of headroom covers the rounding error
 // of the double-precision sum); Y = sum_r y_r (P/p_r) - gamma P.
+template <int KQ = 0, int KP = 0>
 HD void p_to_q(const HersConsts& C, const uint32_t* y_res, uint64_t* out) {
-  uint32_t y[HC_MAXP];
+  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K;
+  uint32_t y[KP ? KP : HC_MAXP];
   double s = 0.0;
-  for (uint32_t r = 0; r < C.K; ++r) {
+  for (uint32_t r = 0; r < K; ++r) {
     y[r] = shoup_p(y_res[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
     s += (double)y[r] * C.p_inv[r];
   }
   const uint64_t gamma = (uint64_t)__builtin_rint(s);
-  for (uint32_t i = 0; i < C.k; ++i) {
+  for (uint32_t i = 0; i < k; ++i) {
     const uint64_t qi = C.q[i];
-    uint64_t acc = 0;
-    for (uint32_t r = 0; r < C.K; ++r) acc = add_q(acc, shoup_q(y[r], C.phat_q[r][i], C.phat_q_sh[r][i], qi), qi);
-    out[i] = sub_q(acc, shoup_q(gamma, C.Pmod_q[i], C.Pmod_q_sh[i], qi), qi);
+    u128 acc = 0;                                   // sum_r y_r (P/p_r mod q_i) < K 2^91
+    for (uint32_t r = 0; r < K; ++r) acc += (u128)y[r] * C.phat_q[r][i];
+    out[i] = sub_q(red128_q(C, acc, i), shoup_q(gamma, C.Pmod_q[i], C.Pmod_q_sh[i], qi), qi);
   }
 }
 
@@ -249,19 +270,21 @@ HD void p_to_q(const HersConsts& C, const uint32_t* y_res, uint64_t* out) {
 // With T the centred representative of t X mod q, t X = q Y + T and |T| < q/2,
 // so Y = round(t X / q) = (t X - T) / q exactly; Y is formed in base P (q is
 // invertible there) and converted to base q.
+template <int KQ = 0, int KP = 0>
 HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
-  uint64_t xq[HC_MAXQ], a[HC_MAXQ];
-  p_to_q(C, x, xq);                                   // X mod q_i
-  for (uint32_t i = 0; i < C.k; ++i) xq[i] = shoup_q(xq[i], C.q_t[i], C.q_t_sh[i], C.q[i]);  // t X mod q_i
-  const bool neg = garner_digits(C, xq, a);           // T
-  uint32_t yr[HC_MAXP];
-  for (uint32_t r = 0; r < C.K; ++r) {
+  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K;
+  uint64_t xq[KQ ? KQ : HC_MAXQ], a[KQ ? KQ : HC_MAXQ];
+  p_to_q<KQ, KP>(C, x, xq);                           // X mod q_i
+  for (uint32_t i = 0; i < k; ++i) xq[i] = shoup_q(xq[i], C.q_t[i], C.q_t_sh[i], C.q[i]);  // t X mod q_i
+  const bool neg = garner_digits<KQ>(C, xq, a);       // T
+  uint32_t yr[KP ? KP : HC_MAXP];
+  for (uint32_t r = 0; r < K; ++r) {
     const uint32_t p = C.p[r];
     uint32_t tx = shoup_p(x[r], C.t_p[r], C.t_p_sh[r], p);
-    uint32_t T = mixed_to_p(C, a, neg, r);
+    uint32_t T = mixed_to_p<KQ>(C, a, neg, r);
     yr[r] = shoup_p(sub_p(tx, T, p), C.qinv_p[r], C.qinv_p_sh[r], p);
   }
-  p_to_q(C, yr, out);
+  p_to_q<KQ, KP>(C, yr, out);
 }
 
 // Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,

@@ -62,8 +62,8 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
                       int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
-                          uint64_t dig_stride, hipStream_t s);
-hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
+                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);
+hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
                         int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s);
 hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,
                          hipStream_t s);

@@ -26,7 +26,7 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
   const uint64_t q = C.q[rho];
   const ModQ mq{q};
   uint64_t* S = lds64;
-  uint64_t* A = lds64 + n;
+  uint64_t* A = lds64 + padded_len(n);
   const uint64_t* tw = T.qtw + (size_t)rho * n;
   const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
   const uint64_t* itw = T.qitw + (size_t)rho * n;
@@ -35,7 +35,7 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
   for (uint32_t j = tid; j < n; j += WG) {
     uint64_t w = philox_word(seed, HERS_DOMAIN_KEYGEN, 0, 0, 0, j >> 6);
     uint64_t s = (w >> (j & 63)) & 1;
-    S[j] = s;
+    S[PADX(j)] = s;
     if (job == 0 && rho == 0) sk[j] = (uint8_t)s;
   }
   // uniform a (job 0) or a_g (job 1 + g), residues rho, two per Philox block
@@ -47,44 +47,44 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
       uint64_t lo = b.v[2 * s], hi = b.v[2 * s + 1];
       uint64_t v = add_q(shoup_q(red_q(hi, q, C.q_mu64[rho]), C.q_r64[rho], C.q_r64_sh[rho], q),
                          red_q(lo, q, C.q_mu64[rho]), q);
-      A[2 * h + s] = v;
+      A[PADX(2 * h + s)] = v;
     }
   }
   uint64_t* out = job == 0 ? pk : rlk + (size_t)(job - 1) * 2 * k * n;        // this key's [2][k][n]
   uint64_t* out_ntt = job == 0 ? T.pk_ntt : T.rlk_ntt + (size_t)(job - 1) * 2 * k * n;
   uint64_t* out_sh = job == 0 ? T.pk_ntt_sh : T.rlk_ntt_sh + (size_t)(job - 1) * 2 * k * n;
   __syncthreads();
-  for (uint32_t j = tid; j < n; j += WG) out[((size_t)1 * k + rho) * n + j] = A[j];
-  ntt_forward(S, tw, twsh, mq, n, C.logn, tid, WG);
-  ntt_forward(A, tw, twsh, mq, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) out[((size_t)1 * k + rho) * n + j] = A[PADX(j)];
+  ntt_forward16(S, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG);
   const uint64_t gv = job == 0 ? 0 : C.g_val[job - 1][rho];
   const uint64_t gvsh = job == 0 ? 0 : C.g_val_sh[job - 1][rho];
   for (uint32_t j = tid; j < n; j += WG) {
-    const uint64_t a = A[j], s = S[j];
+    const uint64_t a = A[PADX(j)], s = S[PADX(j)];
     out_ntt[((size_t)1 * k + rho) * n + j] = a;
     out_sh[((size_t)1 * k + rho) * n + j] = shoup_companion_q(a, q, C.q_m128h[rho], C.q_m128l[rho]);
     uint64_t v = sub_q(0, mul_q(a, s, q, C.q_bar[rho], C.q_beta[rho]), q);        // -a s
     if (job) v = add_q(v, shoup_q(mul_q(s, s, q, C.q_bar[rho], C.q_beta[rho]), gv, gvsh, q), q);  // + g s^2
-    A[j] = v;
+    A[PADX(j)] = v;
   }
   __syncthreads();
-  ntt_inverse(A, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse16(A, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
   for (uint32_t g4 = tid; g4 < n / 4; g4 += WG) {
     Philox4 b = philox4x64_10(g4, oe0, oa1, 0, seed, HERS_DOMAIN_KEYGEN);
     for (int s = 0; s < 4; ++s) {
       const uint32_t j = 4 * g4 + s;
       const int e = cbd20(b.v[s]);
       const uint64_t em = e >= 0 ? (uint64_t)e : q - (uint64_t)(-e);
-      const uint64_t v = sub_q(A[j], em, q);
-      A[j] = v;
+      const uint64_t v = sub_q(A[PADX(j)], em, q);
+      A[PADX(j)] = v;
       out[((size_t)0 * k + rho) * n + j] = v;
     }
   }
   __syncthreads();
-  ntt_forward(A, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG);
   for (uint32_t j = tid; j < n; j += WG) {
-    out_ntt[((size_t)0 * k + rho) * n + j] = A[j];
-    out_sh[((size_t)0 * k + rho) * n + j] = shoup_companion_q(A[j], q, C.q_m128h[rho], C.q_m128l[rho]);
+    out_ntt[((size_t)0 * k + rho) * n + j] = A[PADX(j)];
+    out_sh[((size_t)0 * k + rho) * n + j] = shoup_companion_q(A[PADX(j)], q, C.q_m128h[rho], C.q_m128l[rho]);
   }
 }
 
@@ -101,12 +101,12 @@ k_load_keys(DevTabs T, const uint64_t* __restrict__ pk, const uint64_t* __restri
   uint64_t* dst = key == 0 ? T.pk_ntt : T.rlk_ntt + (size_t)(key - 1) * 2 * k * n;
   uint64_t* dsh = key == 0 ? T.pk_ntt_sh : T.rlk_ntt_sh + (size_t)(key - 1) * 2 * k * n;
   const size_t off = ((size_t)comp * k + rho) * n;
-  for (uint32_t j = tid; j < n; j += WG) lds64[j] = src[off + j];
+  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = src[off + j];
   __syncthreads();
-  ntt_forward(lds64, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, ModQ{q}, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, ModQ{q}, n, C.logn, tid, WG);
   for (uint32_t j = tid; j < n; j += WG) {
-    dst[off + j] = lds64[j];
-    dsh[off + j] = shoup_companion_q(lds64[j], q, C.q_m128h[rho], C.q_m128l[rho]);
+    dst[off + j] = lds64[PADX(j)];
+    dsh[off + j] = shoup_companion_q(lds64[PADX(j)], q, C.q_m128h[rho], C.q_m128l[rho]);
   }
 }
 
@@ -127,11 +127,11 @@ k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_tot
     int64_t v = item < m_total ? feats[(int64_t)i * ld + (int64_t)bl * n + j] : 0;
     int64_t z = v % (int64_t)t;
     if (z < 0) z += t;
-    lds32[bit_reverse(j, C.logn)] = (uint32_t)z;
+    lds32[PADX(bit_reverse(j, C.logn))] = (uint32_t)z;
   }
   __syncthreads();
-  ntt_inverse(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG);
-  for (uint32_t j = tid; j < n; j += WG) pt[(size_t)c * n + j] = lds32[j];
+  ntt_inverse16(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) pt[(size_t)c * n + j] = lds32[PADX(j)];
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
@@ -148,32 +148,32 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   const uint64_t o0 = query ? 0 : (uint64_t)(block0 + c / d);
   const uint64_t o1 = query ? c : c % d;
   uint64_t* U = lds64;
-  uint64_t* V = lds64 + n;
+  uint64_t* V = lds64 + padded_len(n);
   uint64_t* W = V;                      // n/64 words of u, consumed before V is written
   for (uint32_t bk = tid; bk < n / 256; bk += WG) {
     Philox4 b = philox4x64_10(bk, o0, o1, 0, seed, domain);
     for (int s = 0; s < 4; ++s) W[4 * bk + s] = b.v[s];
   }
   __syncthreads();
-  for (uint32_t j = tid; j < n; j += WG) U[j] = (W[j >> 6] >> (j & 63)) & 1;
+  for (uint32_t j = tid; j < n; j += WG) U[PADX(j)] = (W[j >> 6] >> (j & 63)) & 1;
   __syncthreads();
   const uint64_t* tw = T.qtw + (size_t)rho * n;
   const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
-  ntt_forward(U, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG);
   const uint64_t* pk0 = T.pk_ntt + (size_t)rho * n;
   const uint64_t* pk0s = T.pk_ntt_sh + (size_t)rho * n;
   const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
   const uint64_t* pk1s = T.pk_ntt_sh + ((size_t)k + rho) * n;
   for (uint32_t j = tid; j < n; j += WG) {
-    const uint64_t u = U[j];
-    V[j] = shoup_q(u, pk1[j], pk1s[j], q);
-    U[j] = shoup_q(u, pk0[j], pk0s[j], q);
+    const uint64_t u = U[PADX(j)];
+    V[PADX(j)] = shoup_q(u, pk1[j], pk1s[j], q);
+    U[PADX(j)] = shoup_q(u, pk0[j], pk0s[j], q);
   }
   __syncthreads();
   const uint64_t* itw = T.qitw + (size_t)rho * n;
   const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
-  ntt_inverse(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
-  ntt_inverse(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
   uint32_t qconst = 0;
   if (query) {
     int64_t z = (int64_t)query[c] % (int64_t)C.t;
@@ -189,9 +189,9 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
       const uint32_t j = 4 * g4 + s;
       const int e1 = cbd20(b1.v[s]), e2 = cbd20(b2.v[s]);
       const uint64_t m = query ? (j == 0 ? qconst : 0) : pt[(size_t)c * n + j];
-      uint64_t v0 = add_q(U[j], shoup_q(m, C.q_delta[rho], C.q_delta_sh[rho], q), q);
+      uint64_t v0 = add_q(U[PADX(j)], shoup_q(m, C.q_delta[rho], C.q_delta_sh[rho], q), q);
       v0 = e1 >= 0 ? add_q(v0, (uint64_t)e1, q) : sub_q(v0, (uint64_t)(-e1), q);
-      uint64_t v1 = e2 >= 0 ? add_q(V[j], (uint64_t)e2, q) : sub_q(V[j], (uint64_t)(-e2), q);
+      uint64_t v1 = e2 >= 0 ? add_q(V[PADX(j)], (uint64_t)e2, q) : sub_q(V[PADX(j)], (uint64_t)(-e2), q);
       o_ct0[j] = v0;
       o_ct1[j] = v1;
     }
@@ -233,15 +233,15 @@ k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, ui
   const uint32_t n = C.n, tid = threadIdx.x;
   const uint32_t r = (blockIdx.x / inner) % C.K;
   uint32_t* a = polys + (size_t)blockIdx.y * req_stride + (size_t)blockIdx.x * n;
-  for (uint32_t j = tid; j < n; j += WG) lds32[j] = a[j];
+  for (uint32_t j = tid; j < n; j += WG) lds32[PADX(j)] = a[j];
   __syncthreads();
   const ModP mp{C.p[r]};
   if (!inverse)
-    ntt_forward(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG);
+    ntt_forward16(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG);
   else
-    ntt_inverse(lds32, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r], C.p_ninv_sh[r],
+    ntt_inverse16(lds32, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r], C.p_ninv_sh[r],
                 mp, n, C.logn, tid, WG);
-  for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[j];
+  for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[PADX(j)];
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -446,7 +446,8 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   }
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+template <int KQ, int KP>
+__global__ void __launch_bounds__(WG)
 k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_lo, ScorePtrs SP,
           uint64_t* __restrict__ digits_b, uint64_t acc_stride, uint64_t dig_stride) {
   // Per coefficient of X_j (j = 0, 1, 2; residues mod p_r, |X| < P/4):
@@ -465,10 +466,10 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   const uint32_t c = (uint32_t)(idx % n);
   const int64_t bl = (int64_t)(bj / 3);
   const uint32_t j = (uint32_t)(bj % 3);
-  uint32_t x[HC_MAXP];
-  for (uint32_t r = 0; r < K; ++r) x[r] = X[(bj * K + r) * n + c];
-  uint64_t out[HC_MAXQ];
-  scale_round_coeff(C, x, out);
+  uint32_t x[KP ? KP : HC_MAXP];
+  for (uint32_t r = 0; r < (KP ? KP : K); ++r) x[r] = X[(bj * K + r) * n + c];
+  uint64_t out[KQ ? KQ : HC_MAXQ];
+  scale_round_coeff<KQ, KP>(C, x, out);
   const int64_t b = blk_lo + bl;
   if (j < 2) {
     for (uint32_t i = 0; i < k; ++i) scores[(((size_t)b * 2 + j) * k + i) * n + c] = out[i];
@@ -483,57 +484,46 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   }
 }
 
-template <int NPT>
-__global__ void __launch_bounds__(WG)
-k_relin(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride) {
-  // Relinearization of block blk_lo + blockIdx.x, residue sigma, request z:
-  // (c0, c1) += sum_g y_g (rlk_g0, rlk_g1) in R_q; products in the NTT domain.
+extern "C" __global__ void __launch_bounds__(WG)
+k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
+  // In-place forward negacyclic NTT mod q_sigma of polynomial blockIdx.x of
+  // set blockIdx.y, sigma = blockIdx.x mod k (layouts [..][k][n]).
   extern __shared__ uint64_t lds64[];
-  const uint64_t* __restrict__ digits = digits_b + (size_t)blockIdx.z * dig_stride;
-  uint64_t* __restrict__ scores = SP.p[blockIdx.z];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, tid = threadIdx.x;
+  const uint32_t sg = blockIdx.x % C.k;
+  uint64_t* a = polys + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * n;
+  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
+  __syncthreads();
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) a[j] = lds64[PADX(j)];
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride) {
+  // Relinearization, second half: for block blk_lo + blockIdx.x, residue
+  // sigma = blockIdx.y mod k and component comp = blockIdx.y / k of request z,
+  // c_comp += INTT(sum_g NTT(y_g) * rlk_g[comp]) mod q_sigma.
+  extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
-  const int64_t bl = blockIdx.x;
-  const int64_t b = blk_lo + bl;
-  const uint32_t sg = blockIdx.y;
+  const int64_t bl = blockIdx.x, b = blk_lo + bl;
+  const uint32_t sg = blockIdx.y % k, comp = blockIdx.y / k;
   const uint64_t q = C.q[sg];
-  const ModQ mq{q};
-  uint64_t acc0[NPT], acc1[NPT];
-#pragma unroll
-  for (int u = 0; u < NPT; ++u) { acc0[u] = 0; acc1[u] = 0; }
-  const uint64_t* tw = T.qtw + (size_t)sg * n;
-  const uint64_t* twsh = T.qtw_sh + (size_t)sg * n;
-  for (uint32_t g = 0; g < L; ++g) {
-    const uint64_t* src = digits + (((size_t)bl * L + g) * k + sg) * n;
-#pragma unroll
-    for (int u = 0; u < NPT; ++u) lds64[tid + u * WG] = src[tid + u * WG];
-    __syncthreads();
-    ntt_forward(lds64, tw, twsh, mq, n, C.logn, tid, WG);
-    const size_t r0 = (((size_t)g * 2 + 0) * k + sg) * n, r1 = (((size_t)g * 2 + 1) * k + sg) * n;
-#pragma unroll
-    for (int u = 0; u < NPT; ++u) {
-      const uint32_t jj = tid + u * WG;
-      const uint64_t y = lds64[jj];
-      acc0[u] = add_q(acc0[u], shoup_q(y, T.rlk_ntt[r0 + jj], T.rlk_ntt_sh[r0 + jj], q), q);
-      acc1[u] = add_q(acc1[u], shoup_q(y, T.rlk_ntt[r1 + jj], T.rlk_ntt_sh[r1 + jj], q), q);
+  const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
+  uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
+  for (uint32_t j = tid; j < n; j += WG) {
+    uint64_t acc = 0;
+    for (uint32_t g = 0; g < L; ++g) {
+      const size_t r = (((size_t)g * 2 + comp) * k + sg) * n + j;
+      acc = add_q(acc, shoup_q(digits[((size_t)g * k + sg) * n + j], T.rlk_ntt[r], T.rlk_ntt_sh[r], q), q);
     }
-    __syncthreads();
+    lds64[PADX(j)] = acc;
   }
-  const uint64_t* itw = T.qitw + (size_t)sg * n;
-  const uint64_t* itwsh = T.qitw_sh + (size_t)sg * n;
-  for (uint32_t comp = 0; comp < 2; ++comp) {
-#pragma unroll
-    for (int u = 0; u < NPT; ++u) lds64[tid + u * WG] = comp ? acc1[u] : acc0[u];
-    __syncthreads();
-    ntt_inverse(lds64, itw, itwsh, C.q_ninv[sg], C.q_ninv_sh[sg], mq, n, C.logn, tid, WG);
-    uint64_t* dst = scores + (((size_t)b * 2 + comp) * k + sg) * n;
-#pragma unroll
-    for (int u = 0; u < NPT; ++u) {
-      const uint32_t jj = tid + u * WG;
-      dst[jj] = add_q(dst[jj], lds64[jj], q);
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg],
+                ModQ{q}, n, C.logn, tid, WG);
+  for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], lds64[PADX(j)], q);
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
@@ -543,12 +533,12 @@ k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, ui
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, tid = threadIdx.x, sg = blockIdx.x;
   const uint64_t q = C.q[sg];
-  for (uint32_t j = tid; j < n; j += WG) lds64[j] = sk[j] ? 1 : 0;
+  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = sk[j] ? 1 : 0;
   __syncthreads();
-  ntt_forward(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG);
   for (uint32_t j = tid; j < n; j += WG) {
-    S[(size_t)sg * n + j] = lds64[j];
-    Ssh[(size_t)sg * n + j] = shoup_companion_q(lds64[j], q, C.q_m128h[sg], C.q_m128l[sg]);
+    S[(size_t)sg * n + j] = lds64[PADX(j)];
+    Ssh[(size_t)sg * n + j] = shoup_companion_q(lds64[PADX(j)], q, C.q_m128h[sg], C.q_m128l[sg]);
   }
 }
 
@@ -564,15 +554,15 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   const ModQ mq{q};
   const uint64_t* c0 = scores + (((size_t)b * 2 + 0) * k + sg) * n;
   const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * k + sg) * n;
-  for (uint32_t j = tid; j < n; j += WG) lds64[j] = c1[j];
+  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = c1[j];
   __syncthreads();
-  ntt_forward(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG);
   for (uint32_t j = tid; j < n; j += WG)
-    lds64[j] = shoup_q(lds64[j], S[(size_t)sg * n + j], Ssh[(size_t)sg * n + j], q);
+    lds64[PADX(j)] = shoup_q(lds64[PADX(j)], S[(size_t)sg * n + j], Ssh[(size_t)sg * n + j], q);
   __syncthreads();
-  ntt_inverse(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg], mq,
+  ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg], mq,
               n, C.logn, tid, WG);
-  for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[j], c0[j], q);
+  for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
@@ -586,14 +576,14 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
   for (uint32_t j = tid; j < n; j += WG) {
     uint64_t v[HC_MAXQ];
     for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
-    lds32[j] = decrypt_coeff(C, v);
+    lds32[PADX(j)] = decrypt_coeff(C, v);
   }
   __syncthreads();
-  ntt_forward(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG);
+  ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG);
   for (uint32_t s = tid; s < n; s += WG) {
     const int64_t item = b * n + s;
     if (item >= m) continue;
-    const uint32_t z = lds32[bit_reverse(s, C.logn)];
+    const uint32_t z = lds32[PADX(bit_reverse(s, C.logn))];
     out[item] = z >= (t + 1) / 2 ? (int32_t)z - (int32_t)t : (int32_t)z;
   }
 }
@@ -602,7 +592,8 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
 
 namespace hers {
 
-static size_t lds_bytes(uint32_t n, int words64) { return (size_t)n * 8 * words64; }
+static size_t lds_bytes(uint32_t n, int words64) { return (size_t)padded_len(n) * 8 * words64; }
+static size_t lds_bytes32(uint32_t n) { return (size_t)padded_len(n) * 4; }
 
 hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
                          uint64_t* pk, uint64_t* rlk, hipStream_t s) {
@@ -618,7 +609,7 @@ hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L
 
 hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t m_total,
                          int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt, hipStream_t s) {
-  hipLaunchKernelGGL(k_encode, dim3((uint32_t)(nblocks * d)), dim3(WG), (size_t)n * 4, s, T, feats, ld, m_total,
+  hipLaunchKernelGGL(k_encode, dim3((uint32_t)(nblocks * d)), dim3(WG), lds_bytes32(n), s, T, feats, ld, m_total,
                      d, block0, pt);
   return hipGetLastError();
 }
@@ -640,7 +631,7 @@ hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint
 
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
                         int inverse, hipStream_t s, uint32_t nsets, uint64_t set_stride) {
-  hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys, nsets), dim3(WG), (size_t)n * 4, s, T, polys, inner, inverse,
+  hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys, nsets), dim3(WG), lds_bytes32(n), s, T, polys, inner, inverse,
                      set_stride);
   return hipGetLastError();
 }
@@ -689,26 +680,30 @@ hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t gr
 
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
-                          uint64_t dig_stride, hipStream_t s) {
+                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K) {
   uint64_t total = (uint64_t)nblk * 3 * n;
-  hipLaunchKernelGGL(k_rescale, dim3((uint32_t)((total + WG - 1) / WG), nreq), dim3(WG), 0, s, T, X, nblk, blk_lo,
-                     SP, digits, acc_stride, dig_stride);
+  dim3 grid((uint32_t)((total + WG - 1) / WG), nreq);
+  // the parameter sets in use get fully unrolled bodies; others use runtime bounds
+  if (k == 3 && K == 8)
+    hipLaunchKernelGGL((k_rescale<3, 8>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
+  else if (k == 5 && K == 16)
+    hipLaunchKernelGGL((k_rescale<5, 16>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
+  else if (k == 2 && K == 8)
+    hipLaunchKernelGGL((k_rescale<2, 8>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
+  else
+    hipLaunchKernelGGL((k_rescale<0, 0>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
   return hipGetLastError();
 }
 
-hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* digits, int64_t nblk,
+hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
                         int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s) {
-  dim3 grid((uint32_t)nblk, k, nreq);
-  size_t lds = lds_bytes(n, 1);
-  switch (n / WG) {
-    case 1: hipLaunchKernelGGL(k_relin<1>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    case 2: hipLaunchKernelGGL(k_relin<2>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    case 4: hipLaunchKernelGGL(k_relin<4>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    case 8: hipLaunchKernelGGL(k_relin<8>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    case 16: hipLaunchKernelGGL(k_relin<16>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    case 32: hipLaunchKernelGGL(k_relin<32>, grid, dim3(WG), lds, s, T, digits, blk_lo, SP, dig_stride); break;
-    default: return hipErrorInvalidValue;
-  }
+  // digit NTTs (L k per block), then key products and inverse NTTs (2 k per block)
+  hipLaunchKernelGGL(k_ntt_q, dim3((uint32_t)(nblk * L * k), nreq), dim3(WG), lds_bytes(n, 1), s, T, digits,
+                     dig_stride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relin_acc, dim3((uint32_t)nblk, 2 * k, nreq), dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo,
+                     SP, dig_stride);
   return hipGetLastError();
 }
 
@@ -726,7 +721,7 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
 
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), (size_t)n * 4, s, T, x, blk_lo, m, out);
+  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), lds_bytes32(n), s, T, x, blk_lo, m, out);
   return hipGetLastError();
 }
 

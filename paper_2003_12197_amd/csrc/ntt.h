@@ -9,7 +9,7 @@
 //
 // The transforms are written once for a workgroup that owns the polynomial in
 // LDS (tid, nthr) and compile unchanged for a single host thread (tid = 0,
-// nthr = 1), which is how the host-side checks run them.
+// nthr = 1).
 #pragma once
 #include "hers_common.h"
 
@@ -33,44 +33,121 @@ struct ModQ {
   HD uint64_t mul(uint64_t a, uint64_t w, uint64_t wsh) const { return shoup_q(a, w, wsh, q); }
 };
 
-template <class M, class T>
-HD void ntt_forward(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn,
-                    uint32_t tid, uint32_t nthr) {
-  uint32_t lt = logn - 1;
-  for (uint32_t m = 1; m < n; m <<= 1, --lt) {
-    const uint32_t half = 1u << lt;
-    for (uint32_t bf = tid; bf < (n >> 1); bf += nthr) {
-      const uint32_t i = bf >> lt, j = bf & (half - 1);
-      const uint32_t idx = (i << (lt + 1)) + j;
-      const T w = tw[m + i], ws = twsh[m + i];
-      const T u = a[idx];
-      const T v = mod.mul(a[idx + half], w, ws);
-      a[idx] = mod.add(u, v);
-      a[idx + half] = mod.sub(u, v);
+// ---- LDS layout
+// A polynomial in LDS has one padding element after every 16 (element j at
+// PADX(j)), so lanes reading 16 consecutive elements, or elements 16 apart,
+// fall in different banks.
+#define PADX(j) ((j) + ((j) >> 4))
+HD uint32_t padded_len(uint32_t n) { return n + (n >> 4); }
+
+// ---- radix-16 passes
+// The stages are taken in passes of R <= 4.  In a pass over stages
+// s0 .. s0+R-1 (forward, half = n >> (s+1)) the 2^R elements
+// idx = c (n >> s0) + j h + o, j < 2^R, with h = n >> (s0+R), c < 2^s0 and o < h,
+// are closed under the pass's butterflies: a virtual thread (c, o) loads them
+// into registers with their 2^R - 1 twiddles, runs the R stages, and stores
+// them back.  Virtual threads of a pass touch disjoint elements, so one
+// barrier per pass suffices (and a single host thread can run them in turn).
+
+template <int R, class M, class T>
+HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t s0, uint32_t tid, uint32_t nthr) {
+  constexpr uint32_t E = 1u << R;
+  const uint32_t lh = 31 - __builtin_clz(n >> (s0 + R));   // log2 h
+  const uint32_t h = 1u << lh;
+  const uint32_t vts = n >> R;
+  for (uint32_t vt = tid; vt < vts; vt += nthr) {
+    const uint32_t c = vt >> lh, o = vt & (h - 1);
+    const uint32_t base = (c << (lh + R)) + o;
+    T x[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+#pragma unroll
+    for (uint32_t t = 0; t < R; ++t) {                // stage s0 + t: pairs (j, j + E/2^(t+1))
+      const uint32_t span = E >> (t + 1);
+      const uint32_t m = 1u << (s0 + t);
+#pragma unroll
+      for (uint32_t j = 0; j < E; ++j) {
+        if (j & span) continue;
+        const uint32_t i = (c << t) + (j / (2 * span));
+        const T w = tw[m + i], ws = twsh[m + i];
+        const T u = x[j], v = mod.mul(x[j + span], w, ws);
+        x[j] = mod.add(u, v);
+        x[j + span] = mod.sub(u, v);
+      }
     }
-    HERS_SYNC();
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = x[j];
+  }
+  HERS_SYNC();
+}
+
+template <int R, class M, class T>
+HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint32_t lh0, uint32_t tid,
+                     uint32_t nthr) {
+  // stages with half = 2^lh0 .. 2^(lh0+R-1); elements idx = c 2^(lh0+R) + j 2^lh0 + o
+  constexpr uint32_t E = 1u << R;
+  const uint32_t h = 1u << lh0;
+  const uint32_t vts = n >> R;
+  for (uint32_t vt = tid; vt < vts; vt += nthr) {
+    const uint32_t c = vt >> lh0, o = vt & (h - 1);
+    const uint32_t base = (c << (lh0 + R)) + o;
+    T x[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+#pragma unroll
+    for (uint32_t t = 0; t < R; ++t) {                // half = 2^(lh0+t): pairs (j, j + 2^t)
+      const uint32_t span = 1u << t;
+      const uint32_t m = n >> (lh0 + t + 1);
+#pragma unroll
+      for (uint32_t j = 0; j < E; ++j) {
+        if (j & span) continue;
+        const uint32_t i = (c << (R - 1 - t)) + (j >> (t + 1));
+        const T w = itw[m + i], ws = itwsh[m + i];
+        const T u = x[j], v = x[j + span];
+        x[j] = mod.add(u, v);
+        x[j + span] = mod.mul(mod.sub(u, v), w, ws);
+      }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = x[j];
+  }
+  HERS_SYNC();
+}
+
+// Forward transform in passes of 4, 4, ... stages (same result as ntt_forward).
+template <class M, class T>
+HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn, uint32_t tid,
+                      uint32_t nthr) {
+  uint32_t s0 = 0;
+  while (s0 < logn) {
+    const uint32_t r = logn - s0 < 4 ? logn - s0 : 4;
+    switch (r) {
+      case 4: ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      case 3: ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      case 2: ntt_fwd_pass<2>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      default: ntt_fwd_pass<1>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+    }
+    s0 += r;
   }
 }
 
+// Inverse transform in passes (same result as ntt_inverse), scaled by n^-1.
 template <class M, class T>
-HD void ntt_inverse(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n,
-                    uint32_t logn, uint32_t tid, uint32_t nthr) {
-  uint32_t lt = 0;
-  for (uint32_t m = n >> 1; m >= 1; m >>= 1, ++lt) {
-    const uint32_t half = 1u << lt;
-    for (uint32_t bf = tid; bf < (n >> 1); bf += nthr) {
-      const uint32_t i = bf >> lt, j = bf & (half - 1);
-      const uint32_t idx = (i << (lt + 1)) + j;
-      const T w = itw[m + i], ws = itwsh[m + i];
-      const T u = a[idx], v = a[idx + half];
-      a[idx] = mod.add(u, v);
-      a[idx + half] = mod.mul(mod.sub(u, v), w, ws);
+HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n, uint32_t logn,
+                      uint32_t tid, uint32_t nthr) {
+  uint32_t lh0 = 0;
+  while (lh0 < logn) {
+    const uint32_t r = logn - lh0 < 4 ? logn - lh0 : 4;
+    switch (r) {
+      case 4: ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 3: ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 2: ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
     }
-    HERS_SYNC();
+    lh0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[j] = mod.mul(a[j], ninv, ninv_sh);
+  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
   HERS_SYNC();
-  (void)logn;
 }
 
 HD uint32_t bit_reverse(uint32_t x, uint32_t bits) {

@@ -244,6 +244,8 @@ std::string precompute(const hers_params& prm, HostTables* T) {
     C.qinv_p_sh[r] = sh32(C.qinv_p[r], p);
     C.t_p[r] = (uint32_t)(t % p);
     C.t_p_sh[r] = sh32(C.t_p[r], p);
+    C.p_r64[r] = (uint32_t)(((u128)1 << 64) % p);
+    C.p_r64_sh[r] = sh32(C.p_r64[r], p);
   }
   for (uint32_t i = 0; i < k; ++i) {
     const uint64_t q = info.q[i];
