@@ -19,11 +19,19 @@
 #define HERS_SYNC() ((void)0)
 #endif
 
+// Lazy forms (Harvey, "Faster arithmetic for number-theoretic transforms",
+// 2014): mul_lazy leaves a w - floor(a wsh / 2^W) q in [0, 2m) without the
+// final correction; red2 subtracts 2m once.  Butterfly values stay in [0, 4m),
+// which needs 4m below the word size (p < 2^30, q < 2^62).
 struct ModP {
   uint32_t p;
   HD uint32_t add(uint32_t a, uint32_t b) const { return add_p(a, b, p); }
   HD uint32_t sub(uint32_t a, uint32_t b) const { return sub_p(a, b, p); }
   HD uint32_t mul(uint32_t a, uint32_t w, uint32_t wsh) const { return shoup_p(a, w, wsh, p); }
+  HD uint32_t mul_lazy(uint32_t a, uint32_t w, uint32_t wsh) const { return a * w - mulhi32(a, wsh) * p; }
+  HD uint32_t red2(uint32_t a) const { return a >= 2 * p ? a - 2 * p : a; }
+  HD uint32_t two() const { return 2 * p; }
+  HD uint32_t full(uint32_t a) const { a = a >= 2 * p ? a - 2 * p : a; return a >= p ? a - p : a; }
 };
 
 struct ModQ {
@@ -31,6 +39,10 @@ struct ModQ {
   HD uint64_t add(uint64_t a, uint64_t b) const { return add_q(a, b, q); }
   HD uint64_t sub(uint64_t a, uint64_t b) const { return sub_q(a, b, q); }
   HD uint64_t mul(uint64_t a, uint64_t w, uint64_t wsh) const { return shoup_q(a, w, wsh, q); }
+  HD uint64_t mul_lazy(uint64_t a, uint64_t w, uint64_t wsh) const { return a * w - mulhi64(a, wsh) * q; }
+  HD uint64_t red2(uint64_t a) const { return a >= 2 * q ? a - 2 * q : a; }
+  HD uint64_t two() const { return 2 * q; }
+  HD uint64_t full(uint64_t a) const { a = a >= 2 * q ? a - 2 * q : a; return a >= q ? a - q : a; }
 };
 
 // ---- LDS layout
@@ -70,9 +82,10 @@ HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32
         if (j & span) continue;
         const uint32_t i = (c << t) + (j / (2 * span));
         const T w = tw[m + i], ws = twsh[m + i];
-        const T u = x[j], v = mod.mul(x[j + span], w, ws);
-        x[j] = mod.add(u, v);
-        x[j + span] = mod.sub(u, v);
+        const T u = mod.red2(x[j]);                     // [0, 2m)
+        const T v = mod.mul_lazy(x[j + span], w, ws);   // [0, 2m)
+        x[j] = u + v;                                   // [0, 4m)
+        x[j + span] = u - v + mod.two();                // (0, 4m)
       }
     }
 #pragma unroll
@@ -104,8 +117,8 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
         const uint32_t i = (c << (R - 1 - t)) + (j >> (t + 1));
         const T w = itw[m + i], ws = itwsh[m + i];
         const T u = x[j], v = x[j + span];
-        x[j] = mod.add(u, v);
-        x[j + span] = mod.mul(mod.sub(u, v), w, ws);
+        x[j] = mod.red2(u + v);                                // [0, 2m)
+        x[j + span] = mod.mul_lazy(u - v + mod.two(), w, ws);  // [0, 2m)
       }
     }
 #pragma unroll
@@ -114,7 +127,7 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
   HERS_SYNC();
 }
 
-// Forward transform in passes of 4, 4, ... stages (same result as ntt_forward).
+// Forward transform in passes of 4, 4, ... stages; input in [0, 4m), output in [0, m).
 template <class M, class T>
 HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn, uint32_t tid,
                       uint32_t nthr) {
@@ -129,9 +142,11 @@ HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint3
     }
     s0 += r;
   }
+  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.full(a[PADX(j)]);
+  HERS_SYNC();
 }
 
-// Inverse transform in passes (same result as ntt_inverse), scaled by n^-1.
+// Inverse transform in passes, scaled by n^-1; input in [0, 2m), output in [0, m).
 template <class M, class T>
 HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n, uint32_t logn,
                       uint32_t tid, uint32_t nthr) {
