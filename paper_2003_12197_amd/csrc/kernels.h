@@ -17,8 +17,8 @@ struct DevTabs {
 // Batched multiply-accumulate: up to MB_PROBES probes of one gallery per group.
 #define MB_PROBES 16
 #define MB_WG (64 * MB_PROBES)
-#define MB_DC 16        // dimensions per register/LDS chunk
-#define MB_BLOCKS 8     // blocks per work item
+#define MB_DC 8         // dimensions per register/LDS chunk
+#define MB_BLOCKS 4     // blocks per work item
 #define MB_MAXG 15      // groups per launch (kernel arguments stay below 4 KiB)
 
 struct MacGroup {

@@ -365,18 +365,22 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
 // A work item is (group, block range of up to MB_BLOCKS blocks, prime r,
 // 64-slot tile); a group is up to MB_PROBES probes of one gallery.  The
 // workgroup's 16 waves are the group's probes: each lane keeps its probe's
-// values for a chunk of MB_DC dimensions in registers, the gallery tile of
-// the chunk is staged once in LDS and read by every wave, so one HBM read of
-// the gallery serves the whole group.  Folding as in k_mac.  Workgroups
-// stride over the items (static assignment, no atomics).
+// values for a chunk of MB_DC dimensions in registers.  The gallery words of
+// a chunk for all the item's blocks (MB_BLOCKS x MB_DC x 2 rows x 64 slots)
+// are staged once in LDS and read by every wave, so one HBM read of the
+// gallery serves the whole group; the next chunk's words are loaded into
+// registers while the current chunk is multiplied.  Folding as in k_mac.
+// Workgroups stride over the items (static assignment, no atomics).
+#define MB_STAGE (MB_BLOCKS * MB_DC * 2 * 64)           // words per staged chunk
+#define MB_PER_THREAD (MB_STAGE / MB_WG)
+
 __global__ void __launch_bounds__(MB_WG)
 k_mac_multi(DevTabs T, MacBatchArgs A) {
-  __shared__ uint32_t tileG[2][MB_DC][2][64];
+  __shared__ uint32_t tileG[MB_STAGE];                 // [u][v][poly][64]
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tiles = n / 64;
-  uint32_t stage = 0;   // consecutive stagings alternate LDS buffers; each reuse is two barriers apart
   for (uint64_t item = blockIdx.x; item < A.total_items; item += gridDim.x) {
     int g = 0;
     while (g + 1 < A.ngroups && item >= A.g[g + 1].item_begin) ++g;
@@ -392,36 +396,60 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
     const bool active = wave < (uint32_t)G.nprobe;
     const uint32_t slot = tile * 64 + lane;
     const uint32_t* pr = active ? G.probe[wave] + (size_t)r * d * 2 * n + slot : nullptr;
+    const uint32_t* gbase = G.gallery + tile * 64;
+    // gallery word of staged index w in chunk dc: block b0 + u, row 2 (dc + v) + poly, slot c
+    auto fetch = [&](int32_t dc, int32_t dn, uint32_t (&reg)[MB_PER_THREAD]) {
+#pragma unroll
+      for (int e = 0; e < MB_PER_THREAD; ++e) {
+        const uint32_t w = tid + e * MB_WG;
+        const uint32_t c = w & 63, row = w >> 6;
+        const uint32_t poly = row & 1, uv = row >> 1;
+        const uint32_t u = uv / (uint32_t)dn, v = uv - u * (uint32_t)dn;
+        reg[e] = (int)u < nblk
+                     ? __builtin_nontemporal_load(gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v) + poly) * n + c)
+                     : 0u;
+      }
+    };
     uint64_t a0[MB_BLOCKS], a1[MB_BLOCKS], a2[MB_BLOCKS];
 #pragma unroll
     for (int u = 0; u < MB_BLOCKS; ++u) { a0[u] = 0; a1[u] = 0; a2[u] = 0; }
-    for (int32_t dc = 0; dc < d; dc += MB_DC) {
-      const int32_t dn = d - dc < MB_DC ? d - dc : MB_DC;
-      uint32_t P0[MB_DC], P1[MB_DC];
+    uint32_t stage[MB_PER_THREAD];
+    uint32_t P0[MB_DC], P1[MB_DC];                     // this lane's probe values for the chunk
+    auto fetch_probe = [&](int32_t dc, int32_t dn) {
 #pragma unroll
       for (int v = 0; v < MB_DC; ++v) {
         P0[v] = active && v < dn ? pr[(size_t)(2 * (dc + v)) * n] : 0;
         P1[v] = active && v < dn ? pr[(size_t)(2 * (dc + v) + 1) * n] : 0;
       }
+    };
+    fetch(0, d < MB_DC ? d : MB_DC, stage);
+    fetch_probe(0, d < MB_DC ? d : MB_DC);
+    for (int32_t dc = 0; dc < d; dc += MB_DC) {
+      const int32_t dn = d - dc < MB_DC ? d - dc : MB_DC;
+      __syncthreads();                                 // previous chunk fully consumed
 #pragma unroll
-      for (int u = 0; u < MB_BLOCKS; ++u) {
-        if (u >= nblk) break;
-        const uint32_t* gb = G.gallery + (((size_t)(b0 + u) * K + r) * d * 2) * n + tile * 64;
-        uint32_t (*buf)[2][64] = tileG[stage++ & 1];
-        // stage rows (dc .. dc+dn) x 2 polys x 64 slots: 2 * MB_DC * 64 words, 2 per thread
-        for (uint32_t w = tid; w < (uint32_t)(2 * dn * 64); w += MB_WG) {
-          const uint32_t rowi = w >> 6, c = w & 63;
-          buf[rowi >> 1][rowi & 1][c] = __builtin_nontemporal_load(gb + (size_t)(2 * dc + rowi) * n + c);
-        }
-        __syncthreads();
-        if (active) {
+      for (int e = 0; e < MB_PER_THREAD; ++e) tileG[tid + e * MB_WG] = stage[e];
+      __syncthreads();
+      uint32_t Q0[MB_DC], Q1[MB_DC];
+#pragma unroll
+      for (int v = 0; v < MB_DC; ++v) { Q0[v] = P0[v]; Q1[v] = P1[v]; }
+      if (dc + MB_DC < d) {                            // next chunk in flight during the products
+        const int32_t nd = d - dc - MB_DC < MB_DC ? d - dc - MB_DC : MB_DC;
+        fetch(dc + MB_DC, nd, stage);
+        fetch_probe(dc + MB_DC, nd);
+      }
+      if (active) {
+#pragma unroll
+        for (int u = 0; u < MB_BLOCKS; ++u) {
+          if (u >= nblk) break;
+          const uint32_t* t0 = tileG + (uint32_t)u * dn * 128 + lane;
 #pragma unroll
           for (int v = 0; v < MB_DC; ++v) {
             if (v < dn) {
-              const uint64_t g0 = buf[v][0][lane], g1 = buf[v][1][lane];
-              a0[u] += (uint64_t)P0[v] * g0;
-              a1[u] += (uint64_t)P0[v] * g1 + (uint64_t)P1[v] * g0;
-              a2[u] += (uint64_t)P1[v] * g1;
+              const uint64_t g0 = t0[v * 128], g1 = t0[v * 128 + 64];
+              a0[u] += (uint64_t)Q0[v] * g0;
+              a1[u] += (uint64_t)Q0[v] * g1 + (uint64_t)Q1[v] * g0;
+              a2[u] += (uint64_t)Q1[v] * g1;
             }
             if ((v & 7) == 7) a1[u] = red_p(a1[u], p, mu);
           }
