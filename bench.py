@@ -5,7 +5,8 @@ Metric: encrypted scores per second (gallery items x probes per second), with
 p50/p99 probe latency.  One step is one batch of queries through the whole
 per-query path on data resident in HBM: encrypt the probes (one ciphertext per
 dimension), search every gallery block (fused multiply-accumulate over d, exact
-t/q rescale, one relinearization per block), decrypt and decode the scores.
+t/q rescale, one relinearization per block), decrypt and decode the scores and
+take the 10 nearest neighbours.
 The one-time enrollment (key generation, gallery encoding, encryption and
 lift) runs before the timed region and is reported on its own.
 
@@ -316,7 +317,7 @@ def main():
     if npr == 1:
         ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 2048 * n), d)
         mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s)
-        log("autotuned k_mac schedule: %d" % mac_variant)
+        log("autotuned k_mac schedule: %d, NTT pass radix 2^%d" % (mac_variant, ctx.get_option("ntt_radix_log2")))
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
@@ -328,12 +329,20 @@ def main():
         dominant = "mac_multi"
         log("captured the %d-probe batch as a HIP graph (rounds of %d blocks)" % (npr, rounds))
 
+    TOPK = 10
+    tk_idx = torch.empty(npr * TOPK, dtype=torch.int64, device=dev)
+    tk_val = torch.empty(npr * TOPK, dtype=torch.int32, device=dev)
+    ws_k = torch.empty(max(256, int(ctx.lib.hers_topk_workspace_bytes(m, TOPK))), dtype=torch.uint8, device=dev)
+
     def step(seed):
         for j in range(npr):
             ctx.encrypt_probe(qdev[j], seed + j, probe=probes[j], workspace=ws_p)
         search()
         for j in range(npr):
             ctx.decrypt_scores(sk, scores[j], m, out=outs[j], workspace=ws_d)
+            hers_gpu._check(ctx.lib, ctx.lib.hers_topk(
+                ctx.handle, hers_gpu._ptr(outs[j]), m, TOPK, hers_gpu._ptr(tk_idx[j * TOPK:]),
+                hers_gpu._ptr(tk_val[j * TOPK:]), hers_gpu._ptr(ws_k), ws_k.numel(), hers_gpu._stream()), "hers_topk")
 
     for w in range(args.warmup):
         step(PROBE_SEED + 100 * (w + 1))
@@ -353,7 +362,7 @@ def main():
     step_ms = [evs[s].elapsed_time(evs[s + 1]) for s in range(args.steps)]
     total_ms = evs[0].elapsed_time(evs[-1])
     stage_names = ("mac", "mac_multi", "intt_acc", "rescale", "relin", "encrypt", "lift", "ntt_fwd", "sk_ntt",
-                   "dec_mul", "dec_decode")
+                   "dec_mul", "dec_decode", "topk")
     stages = {st: ctx.profile_read(st) for st in stage_names}
     ctx.profile_enable(False)
     if plan is not None:
@@ -381,6 +390,7 @@ def main():
                 want = Pb.T[:hi].astype(np.int64) @ queries[j][0].astype(np.int64)
                 ok &= bool(np.array_equal(outs[j][b * n:b * n + hi].cpu().numpy(), want))
     top = int(np.argmax(got))
+    ok &= int(tk_idx[0].item()) == top and int(tk_val[0].item()) == int(got[top])
 
     # ---- roofline of the dominant kernel
     K = ctx.K
@@ -423,8 +433,9 @@ def main():
                    cfg["desc"] + " (%d probes per step)" % npr,
                    "items": m, "dims": d, "probes_per_step": npr, "blocks": M, "ring_degree": n,
                    "q_primes_bits": list(cfg["qbits"]), "t": int(ctx.t), "base_primes": K,
-                   "step": "encrypt probes + search all blocks + decrypt scores",
-                   "mac_schedule": mac_variant, "hip_graph": plan is not None},
+                   "step": "encrypt probes + search all blocks + decrypt scores + top-10",
+                   "mac_schedule": mac_variant, "ntt_radix": 1 << ctx.get_option("ntt_radix_log2"),
+                   "hip_graph": plan is not None},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},

@@ -200,17 +200,31 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
  *                  0 (1,2,no) 1 (2,2,no) 2 (1,4,no) 3 (2,4,no) 4 (1,2,yes)
  *                  5 (2,2,yes) 6 (1,4,yes) 7 (2,4,yes) 8 (4,1,yes)
  *                  9 (4,2,yes) 10 (2,1,yes) 11 (1,1,yes).
+ *   "ntt_radix_log2" stages per NTT pass, 1..4 (radix 2, 4, 8, 16; default 4):
+ *                  each pass keeps 2^r elements per lane in registers and
+ *                  costs one barrier.
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
 
 /* Autotuner: times every "mac_variant" schedule on the caller's gallery and
  * probe (reps launches each, over as many leading blocks as the search
- * workspace holds), keeps the fastest in the context and returns it in
- * *chosen (may be NULL).  The workspace contents are overwritten. */
+ * workspace holds), then the search epilogue's transforms under NTT pass
+ * radix 4, 8 and 16, keeps the fastest of each in the context and returns
+ * the schedule in *chosen (may be NULL).  The workspace contents are
+ * overwritten. */
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
                   void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen);
 int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
+
+/* ---- nearest neighbours (App. B, Alg. "HERS Search": argmax of the decrypted scores) ----
+ * The k highest of scores_dev (int32 [m], as written by hers_decrypt_scores),
+ * highest first; equal scores are ordered by lower item index.
+ * idx_dev int64 [k], val_dev int32 [k]; 1 <= k <= 512, m <= 2^32;
+ * workspace of hers_topk_workspace_bytes(m, k). */
+uint64_t hers_topk_workspace_bytes(int64_t m, int32_t k);
+int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, int64_t* idx_dev, int32_t* val_dev,
+              void* work_dev, size_t work_bytes, void* stream);
 
 /* ---- serving ---------------------------------------------------------------
  * A request loop over one context (the context then belongs to the server's
@@ -256,7 +270,7 @@ void hers_server_destroy(hers_server* srv);
  * recorded on the stream it is launched on.  hers_profile_enable clears the
  * records.  hers_profile_read waits for the recorded events and returns the
  * summed duration (ms) and launch count of one stage: "mac" (the fused
- * multiply-accumulate), "mac_multi" (its batched form), "intt_acc", "rescale", "relin", "encrypt", "lift",
+ * multiply-accumulate), "mac_multi" (its batched form), "topk", "intt_acc", "rescale", "relin", "encrypt", "lift",
  * "ntt_fwd", "encode", "keygen", "sk_ntt", "dec_mul", "dec_decode". */
 int hers_profile_enable(hers_ctx* ctx, int on);
 int hers_profile_read(hers_ctx* ctx, const char* stage, double* total_ms, uint64_t* launches);

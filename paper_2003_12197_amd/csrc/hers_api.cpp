@@ -177,6 +177,7 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
   c->T.C = dC;
+  c->T.ntt_r = 4;
   c->T.pk_ntt = (uint64_t*)pk;
   c->T.pk_ntt_sh = (uint64_t*)pks;
   c->T.rlk_ntt = (uint64_t*)rl;
@@ -200,11 +201,48 @@ void hers_ctx_destroy(hers_ctx* ctx) {
   delete ctx;
 }
 
+uint64_t hers_topk_workspace_bytes(int64_t m, int32_t k) {
+  if (m < 1 || k < 1) return 0;
+  const uint64_t tiles = ((uint64_t)m + 2047) / 2048;
+  return 2 * align256(tiles * (uint64_t)k * 8);
+}
+
+int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, int64_t* idx_dev, int32_t* val_dev,
+              void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !scores_dev || !idx_dev || !val_dev) return fail(HERS_EINVAL, "null argument");
+  if (m < 1 || m > ((int64_t)1 << 32)) return fail(HERS_EINVAL, "m must be in [1, 2^32]");
+  if (k < 1 || k > 512 || k > m) return fail(HERS_EINVAL, "k must be in [1, min(512, m)]");
+  if (!work_dev || work_bytes < hers_topk_workspace_bytes(m, k)) return fail(HERS_ESPACE, "workspace too small");
+  const uint64_t tiles = ((uint64_t)m + 2047) / 2048;
+  uint64_t* buf[2] = {(uint64_t*)work_dev, (uint64_t*)((char*)work_dev + align256(tiles * (uint64_t)k * 8))};
+  DeviceGuard g(ctx->device);
+  // first pass reads the scores; each further pass reduces tiles of 2048 keys to k keys
+  TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(scores_dev, nullptr, (uint64_t)m, (uint32_t)k, buf[0], S(stream)));
+  uint64_t count = tiles * (uint64_t)k;
+  int cur = 0;
+  while (count > 2048) {
+    TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(nullptr, buf[cur], count, (uint32_t)k, buf[cur ^ 1], S(stream)));
+    count = (count + 2047) / 2048 * (uint64_t)k;
+    cur ^= 1;
+  }
+  if (tiles > 1) {
+    TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(nullptr, buf[cur], count, (uint32_t)k, buf[cur ^ 1], S(stream)));
+    cur ^= 1;
+  }
+  TIMED(ctx, "topk", S(stream), hers::launch_topk_decode(buf[cur], (uint32_t)k, idx_dev, val_dev, S(stream)));
+  return HERS_OK;
+}
+
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
   if (!ctx || !key) return fail(HERS_EINVAL, "null argument");
   if (!std::strcmp(key, "mac_variant")) {
     if (value < 0 || value > 11) return fail(HERS_EINVAL, "mac_variant must be in [0, 11]");
     ctx->mac_variant = (int)value;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "ntt_radix_log2")) {
+    if (value < 1 || value > 4) return fail(HERS_EINVAL, "ntt_radix_log2 must be in [1, 4]");
+    ctx->T.ntt_r = (uint32_t)value;
     return HERS_OK;
   }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
@@ -214,6 +252,10 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   if (!ctx || !key || !value) return fail(HERS_EINVAL, "null argument");
   if (!std::strcmp(key, "mac_variant")) {
     *value = ctx->mac_variant;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "ntt_radix_log2")) {
+    *value = ctx->T.ntt_r;
     return HERS_OK;
   }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
@@ -418,6 +460,33 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
     if (v == 0 || ms < best) { best = ms; best_v = v; }
+  }
+  // NTT pass radix: time the search epilogue's transforms under radix 4, 8, 16:
+  // inverse NTTs of the accumulators, then one block's relinearization (digit
+  // NTTs, key products, inverse NTTs) writing into the accumulator area, which
+  // holds 12 K n bytes per block, more than the 16 k n it writes (K > 2k).
+  if (rc == HERS_OK) {
+    uint32_t* acc = (uint32_t*)work_dev;
+    uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)hi * 3 * C.K * C.n * 4));
+    ScorePtrs sp;
+    sp.p[0] = (uint64_t*)work_dev;
+    float best_r = 0.f;
+    uint32_t best_rl = ctx->T.ntt_r;
+    for (uint32_t rl = 2; rl <= 4 && rc == HERS_OK; ++rl) {
+      ctx->T.ntt_r = rl;
+      hipError_t e = hipEventRecord(e0, S(stream));
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)hi * 3 * C.K, 1, 1, S(stream));
+        if (e == hipSuccess) e = hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, 1, 0, sp, 1, 0, S(stream));
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      if (rl == 2 || ms < best_r) { best_r = ms; best_rl = rl; }
+    }
+    ctx->T.ntt_r = best_rl;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

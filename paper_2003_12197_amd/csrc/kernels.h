@@ -12,6 +12,7 @@ struct DevTabs {
   const uint32_t *ttw, *ttw_sh, *titw, *titw_sh;   // [n]
   uint64_t *pk_ntt, *pk_ntt_sh;                    // [2][k][n] NTT domain
   uint64_t *rlk_ntt, *rlk_ntt_sh;                  // [L][2][k][n] NTT domain
+  uint32_t ntt_r;                                  // stages per NTT pass (1..4: radix 2..16)
 };
 
 // Batched multiply-accumulate: up to MB_PROBES probes of one gallery per group.
@@ -71,4 +72,7 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
                           int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s);
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s);
+hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
+                            uint64_t* keys_out, hipStream_t s);
+hipError_t launch_topk_decode(const uint64_t* keys, uint32_t k, int64_t* idx, int32_t* val, hipStream_t s);
 }  // namespace hers

@@ -55,8 +55,8 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
   uint64_t* out_sh = job == 0 ? T.pk_ntt_sh : T.rlk_ntt_sh + (size_t)(job - 1) * 2 * k * n;
   __syncthreads();
   for (uint32_t j = tid; j < n; j += WG) out[((size_t)1 * k + rho) * n + j] = A[PADX(j)];
-  ntt_forward16(S, tw, twsh, mq, n, C.logn, tid, WG);
-  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(S, tw, twsh, mq, n, C.logn, tid, WG, T.ntt_r);
+  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG, T.ntt_r);
   const uint64_t gv = job == 0 ? 0 : C.g_val[job - 1][rho];
   const uint64_t gvsh = job == 0 ? 0 : C.g_val_sh[job - 1][rho];
   for (uint32_t j = tid; j < n; j += WG) {
@@ -68,7 +68,7 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
     A[PADX(j)] = v;
   }
   __syncthreads();
-  ntt_inverse16(A, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse16(A, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t g4 = tid; g4 < n / 4; g4 += WG) {
     Philox4 b = philox4x64_10(g4, oe0, oa1, 0, seed, HERS_DOMAIN_KEYGEN);
     for (int s = 0; s < 4; ++s) {
@@ -81,7 +81,7 @@ k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restric
     }
   }
   __syncthreads();
-  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(A, tw, twsh, mq, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) {
     out_ntt[((size_t)0 * k + rho) * n + j] = A[PADX(j)];
     out_sh[((size_t)0 * k + rho) * n + j] = shoup_companion_q(A[PADX(j)], q, C.q_m128h[rho], C.q_m128l[rho]);
@@ -103,7 +103,7 @@ k_load_keys(DevTabs T, const uint64_t* __restrict__ pk, const uint64_t* __restri
   const size_t off = ((size_t)comp * k + rho) * n;
   for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = src[off + j];
   __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, ModQ{q}, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, ModQ{q}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) {
     dst[off + j] = lds64[PADX(j)];
     dsh[off + j] = shoup_companion_q(lds64[PADX(j)], q, C.q_m128h[rho], C.q_m128l[rho]);
@@ -130,7 +130,7 @@ k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_tot
     lds32[PADX(bit_reverse(j, C.logn))] = (uint32_t)z;
   }
   __syncthreads();
-  ntt_inverse16(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG);
+  ntt_inverse16(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) pt[(size_t)c * n + j] = lds32[PADX(j)];
 }
 
@@ -159,7 +159,7 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   __syncthreads();
   const uint64_t* tw = T.qtw + (size_t)rho * n;
   const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
-  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG);
+  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG, T.ntt_r);
   const uint64_t* pk0 = T.pk_ntt + (size_t)rho * n;
   const uint64_t* pk0s = T.pk_ntt_sh + (size_t)rho * n;
   const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
@@ -172,8 +172,8 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   __syncthreads();
   const uint64_t* itw = T.qitw + (size_t)rho * n;
   const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
-  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
-  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG);
+  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG, T.ntt_r);
+  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG, T.ntt_r);
   uint32_t qconst = 0;
   if (query) {
     int64_t z = (int64_t)query[c] % (int64_t)C.t;
@@ -237,10 +237,10 @@ k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, ui
   __syncthreads();
   const ModP mp{C.p[r]};
   if (!inverse)
-    ntt_forward16(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG);
+    ntt_forward16(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG, T.ntt_r);
   else
     ntt_inverse16(lds32, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r], C.p_ninv_sh[r],
-                mp, n, C.logn, tid, WG);
+                mp, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[PADX(j)];
 }
 
@@ -523,7 +523,7 @@ k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
   uint64_t* a = polys + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * n;
   for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
   __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) a[j] = lds64[PADX(j)];
 }
 
@@ -550,7 +550,7 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   }
   __syncthreads();
   ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg],
-                ModQ{q}, n, C.logn, tid, WG);
+                ModQ{q}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], lds64[PADX(j)], q);
 }
 
@@ -563,7 +563,7 @@ k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, ui
   const uint64_t q = C.q[sg];
   for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = sk[j] ? 1 : 0;
   __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) {
     S[(size_t)sg * n + j] = lds64[PADX(j)];
     Ssh[(size_t)sg * n + j] = shoup_companion_q(lds64[PADX(j)], q, C.q_m128h[sg], C.q_m128l[sg]);
@@ -584,12 +584,12 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * k + sg) * n;
   for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = c1[j];
   __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG);
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG)
     lds64[PADX(j)] = shoup_q(lds64[PADX(j)], S[(size_t)sg * n + j], Ssh[(size_t)sg * n + j], q);
   __syncthreads();
   ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg], mq,
-              n, C.logn, tid, WG);
+              n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
 }
 
@@ -607,12 +607,62 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
     lds32[PADX(j)] = decrypt_coeff(C, v);
   }
   __syncthreads();
-  ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG);
+  ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t s = tid; s < n; s += WG) {
     const int64_t item = b * n + s;
     if (item >= m) continue;
     const uint32_t z = lds32[PADX(bit_reverse(s, C.logn))];
     out[item] = z >= (t + 1) / 2 ? (int32_t)z - (int32_t)t : (int32_t)z;
+  }
+}
+
+// ---------------------------------------------------------------- top-k of decrypted scores
+// The client's last step (App. B, Alg. "HERS Search"): the nearest neighbour
+// is the argmax of the decrypted scores.  A key packs (score + 2^31) in the
+// high word and the complement of the item index in the low word, so larger
+// keys are higher scores and, among equal scores, lower indices.  Each pass
+// bitonic-sorts tiles of TK_TILE keys in LDS (descending) and keeps the first
+// k of each tile; passes repeat until one tile remains.
+#define TK_TILE 2048
+
+__device__ __forceinline__ uint64_t score_key(int32_t s, uint64_t idx) {
+  return ((uint64_t)((uint32_t)s ^ 0x80000000u) << 32) | (uint32_t)~(uint32_t)idx;
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_topk_pass(const int32_t* __restrict__ scores, const uint64_t* __restrict__ keys_in, uint64_t count, uint32_t k,
+            uint64_t* __restrict__ keys_out) {
+  __shared__ uint64_t tile[TK_TILE];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = (uint64_t)blockIdx.x * TK_TILE;
+  for (uint32_t j = tid; j < TK_TILE; j += WG) {
+    const uint64_t i = base + j;
+    uint64_t key = 0;
+    if (i < count) key = scores ? score_key(scores[i], i) : keys_in[i];
+    tile[j] = key;
+  }
+  __syncthreads();
+  // bitonic sort, descending
+  for (uint32_t size = 2; size <= TK_TILE; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = tid; t < TK_TILE / 2; t += WG) {
+        const uint32_t lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const uint64_t a = tile[lo], b = tile[hi];
+        if ((a < b) == desc) { tile[lo] = b; tile[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t j = tid; j < k; j += WG) keys_out[(uint64_t)blockIdx.x * k + j] = tile[j];
+}
+
+extern "C" __global__ void k_topk_decode(const uint64_t* __restrict__ keys, uint32_t k, int64_t* __restrict__ idx,
+                                         int32_t* __restrict__ val) {
+  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
+    const uint64_t key = keys[j];
+    idx[j] = (int64_t)(uint32_t)~(uint32_t)key;
+    val[j] = (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
   }
 }
 
@@ -750,6 +800,18 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), lds_bytes32(n), s, T, x, blk_lo, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
+                            uint64_t* keys_out, hipStream_t s) {
+  const uint64_t tiles = (count + TK_TILE - 1) / TK_TILE;
+  hipLaunchKernelGGL(k_topk_pass, dim3((uint32_t)tiles), dim3(WG), 0, s, scores, keys_in, count, k, keys_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_decode(const uint64_t* keys, uint32_t k, int64_t* idx, int32_t* val, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_decode, dim3(1), dim3(WG), 0, s, keys, k, idx, val);
   return hipGetLastError();
 }
 

@@ -127,13 +127,13 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
   HERS_SYNC();
 }
 
-// Forward transform in passes of 4, 4, ... stages; input in [0, 4m), output in [0, m).
+// Forward transform in passes of rmax (<= 4) stages; input in [0, 4m), output in [0, m).
 template <class M, class T>
 HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn, uint32_t tid,
-                      uint32_t nthr) {
+                      uint32_t nthr, uint32_t rmax = 4) {
   uint32_t s0 = 0;
   while (s0 < logn) {
-    const uint32_t r = logn - s0 < 4 ? logn - s0 : 4;
+    const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
     switch (r) {
       case 4: ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
       case 3: ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
@@ -146,13 +146,14 @@ HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint3
   HERS_SYNC();
 }
 
-// Inverse transform in passes, scaled by n^-1; input in [0, 2m), output in [0, m).
+// Inverse transform in passes of rmax (<= 4) stages, scaled by n^-1; input in [0, 2m),
+// output in [0, m).
 template <class M, class T>
 HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n, uint32_t logn,
-                      uint32_t tid, uint32_t nthr) {
+                      uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
   uint32_t lh0 = 0;
   while (lh0 < logn) {
-    const uint32_t r = logn - lh0 < 4 ? logn - lh0 : 4;
+    const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
     switch (r) {
       case 4: ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
       case 3: ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;

@@ -62,6 +62,8 @@ EXPORTS = {
     "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
                               ctypes.POINTER(c_i64)]),
     "hers_get_option": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(c_i64)]),
+    "hers_topk_workspace_bytes": (c_u64, [c_i64, c_i32]),
+    "hers_topk": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_profile_enable": (c_i32, [c_vp, c_i32]),
     "hers_profile_read": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_u64)]),
 }
@@ -285,6 +287,16 @@ class Context:
         v = c_i64()
         _check(self.lib, self.lib.hers_get_option(self.handle, key.encode(), ctypes.byref(v)), "hers_get_option")
         return v.value
+
+    def topk(self, scores, m, k):
+        """(indices int64 [k], values int32 [k]) of the k highest decrypted scores."""
+        idx = self._empty(k, torch.int64)
+        val = self._empty(k, torch.int32)
+        ws = torch.empty(max(256, int(self.lib.hers_topk_workspace_bytes(int(m), int(k)))), dtype=torch.uint8,
+                         device=self.device)
+        _check(self.lib, self.lib.hers_topk(self.handle, _ptr(scores), int(m), int(k), _ptr(idx), _ptr(val),
+                                            _ptr(ws), ws.numel(), _stream()), "hers_topk")
+        return idx, val
 
     def profile_enable(self, on=True):
         _check(self.lib, self.lib.hers_profile_enable(self.handle, 1 if on else 0), "hers_profile_enable")

@@ -295,3 +295,43 @@ def test_plan_replays_match_eager(batch_setup, case_r36):
         for j, r in enumerate(reqs):
             assert torch.equal(scores[j], _single_scores(ctx, r[0], r[1], r[2], prs[j])), (rep, j)
     plan.close()
+
+
+def test_schedules_and_radices_give_same_bits(case_r36):
+    """Every multiply-accumulate schedule and NTT pass radix computes the same
+    ciphertexts (gallery encryption and search)."""
+    c = case_r36
+    ctx = c.ctx
+    base_g, base_s = c.gallery.clone(), c.scores.clone()
+    try:
+        for rl in (1, 2, 3, 4):
+            ctx.set_option("ntt_radix_log2", rl)
+            g = ctx.encrypt_gallery(c.feats, c.m, c.gal_seed)
+            assert torch.equal(g, base_g), rl
+            for v in range(12):
+                ctx.set_option("mac_variant", v)
+                assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), (rl, v)
+        chosen = ctx.autotune(c.gallery, c.m, c.d, c.probe, reps=1)
+        assert 0 <= chosen < 12 and 2 <= ctx.get_option("ntt_radix_log2") <= 4
+        assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s)
+    finally:
+        ctx.set_option("ntt_radix_log2", 4)
+        ctx.set_option("mac_variant", 8)
+
+
+def test_topk_of_decrypted_scores(case_r36, gpu_lib):
+    """Alg. "HERS Search" ends with the argmax of the decrypted scores: the GPU
+    top-k equals a stable sort (score descending, then index ascending)."""
+    c = case_r36
+    out = c.ctx.decrypt_scores(c.sk, c.scores, c.m)
+    s = out.cpu().numpy()
+    for k in (1, 10, 100):
+        idx, val = c.ctx.topk(out, c.m, k)
+        order = np.lexsort((np.arange(c.m), -s.astype(np.int64)))[:k]
+        assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), s[order])
+    rng = np.random.default_rng(17)
+    big = rng.integers(-300, 301, size=3_000_017).astype(np.int32)   # many ties, ragged last tile
+    bt = torch.from_numpy(big).to(c.ctx.device)
+    idx, val = c.ctx.topk(bt, big.size, 512)
+    order = np.lexsort((np.arange(big.size), -big.astype(np.int64)))[:512]
+    assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), big[order])
