@@ -2,6 +2,7 @@
 // size queries, argument checks and the launch sequences of each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <string>
@@ -201,10 +202,45 @@ void hers_ctx_destroy(hers_ctx* ctx) {
   delete ctx;
 }
 
+// Workspace of hers_topk: tile maxima, two ping-pong buffers of the generic
+// passes, the k best tile maxima and the k * k filtered candidates.
+struct TopkLayout {
+  uint64_t tiles, nbest, maxes, pp, best, cand, total;
+};
+
+static TopkLayout topk_layout(uint64_t m, uint64_t k) {
+  TopkLayout L{};
+  L.tiles = (m + HERS_TOPK_TM - 1) >> HERS_TOPK_TM_LOG2;
+  L.nbest = std::min<uint64_t>(k, L.tiles);
+  const uint64_t first = std::max((L.tiles + HERS_TOPK_TILE - 1) / HERS_TOPK_TILE * L.nbest,
+                                  (L.nbest * k + HERS_TOPK_TILE - 1) / HERS_TOPK_TILE * k);
+  L.maxes = align256(L.tiles * 8);
+  L.pp = align256(first * 8);
+  L.best = align256(k * 8);
+  L.cand = align256(L.nbest * k * 8);
+  L.total = L.maxes + 2 * L.pp + L.best + L.cand;
+  return L;
+}
+
 uint64_t hers_topk_workspace_bytes(int64_t m, int32_t k) {
   if (m < 1 || k < 1) return 0;
-  const uint64_t tiles = ((uint64_t)m + 2047) / 2048;
-  return 2 * align256(tiles * (uint64_t)k * 8);
+  return topk_layout((uint64_t)m, (uint64_t)k).total;
+}
+
+// Top k of keys[0, count) by generic passes; the last pass (one workgroup)
+// writes keys to out_keys, or decoded (index, score) when idx is set.
+static int topk_reduce(hers_ctx* ctx, const uint64_t* keys, uint64_t count, uint32_t k, uint64_t* pp0, uint64_t* pp1,
+                       uint64_t* out_keys, int64_t* idx, int32_t* val, hipStream_t s) {
+  uint64_t* pp[2] = {pp0, pp1};
+  int cur = 0;
+  while (count > HERS_TOPK_TILE) {
+    TIMED(ctx, "topk", s, hers::launch_topk_pass(nullptr, keys, count, k, pp[cur], nullptr, nullptr, s));
+    keys = pp[cur];
+    count = (count + HERS_TOPK_TILE - 1) / HERS_TOPK_TILE * k;
+    cur ^= 1;
+  }
+  TIMED(ctx, "topk", s, hers::launch_topk_pass(nullptr, keys, count, k, out_keys, idx, val, s));
+  return HERS_OK;
 }
 
 int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, int64_t* idx_dev, int32_t* val_dev,
@@ -213,24 +249,26 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
   if (m < 1 || m > ((int64_t)1 << 32)) return fail(HERS_EINVAL, "m must be in [1, 2^32]");
   if (k < 1 || k > 512 || k > m) return fail(HERS_EINVAL, "k must be in [1, min(512, m)]");
   if (!work_dev || work_bytes < hers_topk_workspace_bytes(m, k)) return fail(HERS_ESPACE, "workspace too small");
-  const uint64_t tiles = ((uint64_t)m + 2047) / 2048;
-  uint64_t* buf[2] = {(uint64_t*)work_dev, (uint64_t*)((char*)work_dev + align256(tiles * (uint64_t)k * 8))};
   DeviceGuard g(ctx->device);
-  // first pass reads the scores; each further pass reduces tiles of 2048 keys to k keys
-  TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(scores_dev, nullptr, (uint64_t)m, (uint32_t)k, buf[0], S(stream)));
-  uint64_t count = tiles * (uint64_t)k;
-  int cur = 0;
-  while (count > 2048) {
-    TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(nullptr, buf[cur], count, (uint32_t)k, buf[cur ^ 1], S(stream)));
-    count = (count + 2047) / 2048 * (uint64_t)k;
-    cur ^= 1;
+  const hipStream_t s = S(stream);
+  if (m <= HERS_TOPK_TILE) {   // one tile: sort it directly
+    TIMED(ctx, "topk", s, hers::launch_topk_pass(scores_dev, nullptr, (uint64_t)m, (uint32_t)k, nullptr, idx_dev,
+                                                 val_dev, s));
+    return HERS_OK;
   }
-  if (tiles > 1) {
-    TIMED(ctx, "topk", S(stream), hers::launch_topk_pass(nullptr, buf[cur], count, (uint32_t)k, buf[cur ^ 1], S(stream)));
-    cur ^= 1;
-  }
-  TIMED(ctx, "topk", S(stream), hers::launch_topk_decode(buf[cur], (uint32_t)k, idx_dev, val_dev, S(stream)));
-  return HERS_OK;
+  const TopkLayout L = topk_layout((uint64_t)m, (uint64_t)k);
+  char* w = (char*)work_dev;
+  uint64_t* maxes = (uint64_t*)w;
+  uint64_t* pp0 = (uint64_t*)(w + L.maxes);
+  uint64_t* pp1 = (uint64_t*)(w + L.maxes + L.pp);
+  uint64_t* best = (uint64_t*)(w + L.maxes + 2 * L.pp);
+  uint64_t* cand = (uint64_t*)(w + L.maxes + 2 * L.pp + L.best);
+  TIMED(ctx, "topk", s, hers::launch_topk_tilemax(scores_dev, (uint64_t)m, maxes, s));
+  int rc = topk_reduce(ctx, maxes, L.tiles, (uint32_t)L.nbest, pp0, pp1, best, nullptr, nullptr, s);
+  if (rc != HERS_OK) return rc;
+  TIMED(ctx, "topk", s, hers::launch_topk_filter(scores_dev, (uint64_t)m, best, (uint32_t)L.nbest,
+                                                 L.tiles >= (uint64_t)k, (uint32_t)k, cand, s));
+  return topk_reduce(ctx, cand, L.nbest * (uint64_t)k, (uint32_t)k, pp0, pp1, nullptr, idx_dev, val_dev, s);
 }
 
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {

@@ -72,7 +72,14 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
                           int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s);
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s);
+// top-k of decrypted scores (topk.hip): generic passes over tiles of
+// HERS_TOPK_TILE keys, tile maxima over tiles of HERS_TOPK_TM scores
+#define HERS_TOPK_TILE 2048
+#define HERS_TOPK_TM_LOG2 12
+#define HERS_TOPK_TM (1u << HERS_TOPK_TM_LOG2)
 hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
-                            uint64_t* keys_out, hipStream_t s);
-hipError_t launch_topk_decode(const uint64_t* keys, uint32_t k, int64_t* idx, int32_t* val, hipStream_t s);
+                            uint64_t* keys_out, int64_t* idx_out, int32_t* val_out, hipStream_t s);
+hipError_t launch_topk_tilemax(const int32_t* scores, uint64_t m, uint64_t* maxes, hipStream_t s);
+hipError_t launch_topk_filter(const int32_t* scores, uint64_t m, const uint64_t* best, uint32_t nbest, int use_tau,
+                              uint32_t k, uint64_t* cand, hipStream_t s);
 }  // namespace hers

@@ -616,56 +616,6 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
   }
 }
 
-// ---------------------------------------------------------------- top-k of decrypted scores
-// The client's last step (App. B, Alg. "HERS Search"): the nearest neighbour
-// is the argmax of the decrypted scores.  A key packs (score + 2^31) in the
-// high word and the complement of the item index in the low word, so larger
-// keys are higher scores and, among equal scores, lower indices.  Each pass
-// bitonic-sorts tiles of TK_TILE keys in LDS (descending) and keeps the first
-// k of each tile; passes repeat until one tile remains.
-#define TK_TILE 2048
-
-__device__ __forceinline__ uint64_t score_key(int32_t s, uint64_t idx) {
-  return ((uint64_t)((uint32_t)s ^ 0x80000000u) << 32) | (uint32_t)~(uint32_t)idx;
-}
-
-extern "C" __global__ void __launch_bounds__(WG)
-k_topk_pass(const int32_t* __restrict__ scores, const uint64_t* __restrict__ keys_in, uint64_t count, uint32_t k,
-            uint64_t* __restrict__ keys_out) {
-  __shared__ uint64_t tile[TK_TILE];
-  const uint32_t tid = threadIdx.x;
-  const uint64_t base = (uint64_t)blockIdx.x * TK_TILE;
-  for (uint32_t j = tid; j < TK_TILE; j += WG) {
-    const uint64_t i = base + j;
-    uint64_t key = 0;
-    if (i < count) key = scores ? score_key(scores[i], i) : keys_in[i];
-    tile[j] = key;
-  }
-  __syncthreads();
-  // bitonic sort, descending
-  for (uint32_t size = 2; size <= TK_TILE; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t t = tid; t < TK_TILE / 2; t += WG) {
-        const uint32_t lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
-        const bool desc = (lo & size) == 0;
-        const uint64_t a = tile[lo], b = tile[hi];
-        if ((a < b) == desc) { tile[lo] = b; tile[hi] = a; }
-      }
-      __syncthreads();
-    }
-  }
-  for (uint32_t j = tid; j < k; j += WG) keys_out[(uint64_t)blockIdx.x * k + j] = tile[j];
-}
-
-extern "C" __global__ void k_topk_decode(const uint64_t* __restrict__ keys, uint32_t k, int64_t* __restrict__ idx,
-                                         int32_t* __restrict__ val) {
-  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
-    const uint64_t key = keys[j];
-    idx[j] = (int64_t)(uint32_t)~(uint32_t)key;
-    val[j] = (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
-  }
-}
-
 // ---------------------------------------------------------------- launchers
 
 namespace hers {
@@ -800,18 +750,6 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), lds_bytes32(n), s, T, x, blk_lo, m, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
-                            uint64_t* keys_out, hipStream_t s) {
-  const uint64_t tiles = (count + TK_TILE - 1) / TK_TILE;
-  hipLaunchKernelGGL(k_topk_pass, dim3((uint32_t)tiles), dim3(WG), 0, s, scores, keys_in, count, k, keys_out);
-  return hipGetLastError();
-}
-
-hipError_t launch_topk_decode(const uint64_t* keys, uint32_t k, int64_t* idx, int32_t* val, hipStream_t s) {
-  hipLaunchKernelGGL(k_topk_decode, dim3(1), dim3(WG), 0, s, keys, k, idx, val);
   return hipGetLastError();
 }
 
