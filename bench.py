@@ -315,9 +315,10 @@ def main():
         ctx.encrypt_probe(qdev[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
     plan = None
     if npr == 1:
-        ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 2048 * n), d)
-        mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s)
-        log("autotuned k_mac schedule: %d, NTT pass radix 2^%d" % (mac_variant, ctx.get_option("ntt_radix_log2")))
+        ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 8192 * n), d)
+        mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s, scores=scores[0])
+        log("autotuned k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d" % (
+            mac_variant, ctx.get_option("ntt_radix_log2"), ctx.get_option("overlap_chunks")))
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
@@ -435,6 +436,8 @@ def main():
                    "q_primes_bits": list(cfg["qbits"]), "t": int(ctx.t), "base_primes": K,
                    "step": "encrypt probes + search all blocks + decrypt scores + top-10",
                    "mac_schedule": mac_variant, "ntt_radix": 1 << ctx.get_option("ntt_radix_log2"),
+                   "overlap_chunks": ctx.get_option("overlap_chunks"),
+                   "mac_wgs_per_cu": ctx.get_option("mac_wgs_per_cu") or 8,
                    "hip_graph": plan is not None},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},

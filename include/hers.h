@@ -155,7 +155,10 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
  * X_2 = sum_i P_i1 G_bi1 over Z[x]/(x^n+1) (centred representatives), then
  * c_j = [round(t X_j / q)]_q (Alg. "Ciphertext Multiplication"), then one
  * relinearization with the context's evaluation keys.
- *   scores_dev canonical score cts [M][2][k][n]. */
+ *   scores_dev canonical score cts [M][2][k][n].
+ * Work is ordered on `stream`; with "overlap_chunks" it is split between
+ * `stream` and the context's own stream and joined back into `stream`
+ * (one context must not run two searches from different host threads). */
 int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
                 const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
                 size_t work_bytes, void* stream);
@@ -203,6 +206,15 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
  *   "ntt_radix_log2" stages per NTT pass, 1..4 (radix 2, 4, 8, 16; default 4):
  *                  each pass keeps 2^r elements per lane in registers and
  *                  costs one barrier.
+ *   "overlap_chunks" hers_search in this many block chunks, 0..64 (0 =
+ *                  automatic: 8 from 4096 blocks up, else off; 1 = off):
+ *                  each chunk's rescale and relinearization run on the
+ *                  context's own stream beside the next chunk's
+ *                  multiply-accumulate.  The caller's stream waits for that
+ *                  stream before hers_search returns, so stream order holds.
+ *   "mac_wgs_per_cu" workgroups per compute unit of a hers_search
+ *                  multiply-accumulate launch, 0..64 (0 = 8); fewer leave
+ *                  room on each CU for an overlapped epilogue.
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
@@ -210,11 +222,15 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
 /* Autotuner: times every "mac_variant" schedule on the caller's gallery and
  * probe (reps launches each, over as many leading blocks as the search
  * workspace holds), then the search epilogue's transforms under NTT pass
- * radix 4, 8 and 16, keeps the fastest of each in the context and returns
- * the schedule in *chosen (may be NULL).  The workspace contents are
- * overwritten. */
+ * radix 4, 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not
+ * NULL -- whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16
+ * (chunks of at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule
+ * found first or schedule 10.  Keeps the fastest of each in the context
+ * and returns the schedule in *chosen (may be NULL).  The workspace and
+ * scores_dev contents are overwritten; the call synchronizes `stream`. */
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                  void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen);
+                  uint64_t* scores_dev, void* work_dev, size_t work_bytes, int reps, void* stream,
+                  int64_t* chosen);
 int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
 
 /* ---- nearest neighbours (App. B, Alg. "HERS Search": argmax of the decrypted scores) ----

@@ -34,6 +34,14 @@ struct hers_ctx {
   DevTabs T;
   bool keys_loaded;
   int mac_variant = 8;   // k_mac schedule (see hers_set_option)
+  // overlapped search: chunk count (0 automatic, 1 off), the stream the
+  // per-block epilogue runs on, and its events (MAC done, join, one per
+  // workspace region)
+  int overlap_chunks = 0;
+  int mac_wgs_per_cu = 0;   // multiply-accumulate grid, workgroups per CU (0 = 8)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_mac = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> ev_free;
   // per-stage timing
   struct Rec { std::string stage; hipEvent_t a, b; };
   bool prof_on = false;
@@ -174,6 +182,12 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
     hers_ctx_destroy(c);
     return fail(rc, msg);
   }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_mac, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    hers_ctx_destroy(c);
+    return fail(HERS_EDEVICE, "stream or event creation failed");
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
@@ -197,6 +211,11 @@ void hers_ctx_destroy(hers_ctx* ctx) {
       (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+    if (ctx->ev_mac) (void)hipEventDestroy(ctx->ev_mac);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     for (void* p : ctx->allocs) (void)hipFree(p);
   }
   delete ctx;
@@ -283,6 +302,16 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     ctx->T.ntt_r = (uint32_t)value;
     return HERS_OK;
   }
+  if (!std::strcmp(key, "overlap_chunks")) {
+    if (value < 0 || value > 64) return fail(HERS_EINVAL, "overlap_chunks must be in [0, 64]");
+    ctx->overlap_chunks = (int)value;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "mac_wgs_per_cu")) {
+    if (value < 0 || value > 64) return fail(HERS_EINVAL, "mac_wgs_per_cu must be in [0, 64]");
+    ctx->mac_wgs_per_cu = (int)value;
+    return HERS_OK;
+  }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
 }
 
@@ -294,6 +323,14 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   }
   if (!std::strcmp(key, "ntt_radix_log2")) {
     *value = ctx->T.ntt_r;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "overlap_chunks")) {
+    *value = ctx->overlap_chunks;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "mac_wgs_per_cu")) {
+    *value = ctx->mac_wgs_per_cu;
     return HERS_OK;
   }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
@@ -443,6 +480,25 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
   return HERS_OK;
 }
 
+// Workgroups of a multiply-accumulate launch.
+static uint32_t mac_grid(const hers_ctx* ctx) {
+  return (uint32_t)(ctx->mac_wgs_per_cu ? ctx->mac_wgs_per_cu : 8) * (uint32_t)ctx->num_cus;
+}
+
+// Per-block epilogue of blocks [lo, hi): inverse NTT of the accumulators,
+// exact rescale (with the relinearization digits), relinearization.
+static int search_epilogue(hers_ctx* ctx, uint32_t* acc, uint64_t* digits, int64_t lo, int64_t hi,
+                           uint64_t* scores_dev, hipStream_t s) {
+  const HersConsts& C = ctx->host.C;
+  const int64_t nb = hi - lo;
+  TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
+  ScorePtrs sp;
+  sp.p[0] = scores_dev;
+  TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, s, C.k, C.K));
+  TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, s));
+  return HERS_OK;
+}
+
 int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
                 uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream) {
   if (!ctx || !gallery_dev || !probe_dev || !scores_dev) return fail(HERS_EINVAL, "null argument");
@@ -453,26 +509,69 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
   const int64_t M = (int64_t)hers_blocks(ctx, m);
   const size_t per = search_ws_per_block(C);
   if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
-  const int64_t chunk = (int64_t)(work_bytes / per);
+  const int64_t cap = (int64_t)(work_bytes / per);
   DeviceGuard g(ctx->device);
-  for (int64_t lo = 0; lo < M; lo += chunk) {
-    const int64_t hi = lo + chunk < M ? lo + chunk : M;
-    const int64_t nb = hi - lo;
-    uint32_t* acc = (uint32_t*)work_dev;
-    uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)nb * 3 * C.K * C.n * 4));
-    TIMED(ctx, "mac", S(stream), hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, S(stream),
-                                                       ctx->mac_variant));
-    TIMED(ctx, "intt_acc", S(stream), hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, S(stream)));
-    ScorePtrs sp;
-    sp.p[0] = scores_dev;
-    TIMED(ctx, "rescale", S(stream), hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, S(stream), C.k, C.K));
-    TIMED(ctx, "relin", S(stream), hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, S(stream)));
+  const hipStream_t s = S(stream);
+  int64_t nch = ctx->overlap_chunks;
+  if (nch == 0) nch = M >= 4096 ? 8 : 1;
+  if (nch <= 1 || cap < 2) {
+    for (int64_t lo = 0; lo < M; lo += cap) {
+      const int64_t hi = lo + cap < M ? lo + cap : M;
+      uint32_t* acc = (uint32_t*)work_dev;
+      uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)(hi - lo) * 3 * C.K * C.n * 4));
+      TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s,
+                                            ctx->mac_variant, mac_grid(ctx)));
+      if (int rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, s)) return rc;
+    }
+    return HERS_OK;
   }
+  // Overlapped: the blocks go in chunks of `sub`; chunk c's multiply-accumulate
+  // runs on the caller's stream into workspace region c mod nreg, its epilogue
+  // on the side stream, so the epilogue of one chunk (VALU-bound) runs beside
+  // the next chunk's multiply-accumulate (HBM-bound).  A chunk waits for the
+  // epilogue that last used its region; the caller's stream waits for the
+  // side stream before the call returns.
+  int64_t sub = (M + nch - 1) / nch;
+  if (sub > cap / 2) sub = cap / 2;
+  const int64_t nreg = std::min<int64_t>(cap / sub, (M + sub - 1) / sub);
+  while ((int64_t)ctx->ev_free.size() < nreg) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->ev_free.push_back(e);
+  }
+  const size_t region = (size_t)sub * per;
+  int rc = HERS_OK;
+  hipError_t e = hipSuccess;
+  for (int64_t c = 0, lo = 0; lo < M && rc == HERS_OK && e == hipSuccess; ++c, lo += sub) {
+    const int64_t hi = lo + sub < M ? lo + sub : M;
+    const int64_t r = c % nreg;
+    char* base = (char*)work_dev + (size_t)r * region;
+    uint32_t* acc = (uint32_t*)base;
+    uint64_t* digits = (uint64_t*)(base + align256((size_t)(hi - lo) * 3 * C.K * C.n * 4));
+    if (c >= nreg) e = hipStreamWaitEvent(s, ctx->ev_free[r], 0);
+    if (e != hipSuccess) break;
+    {
+      StageTimer st(ctx, "mac", s);
+      e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s, ctx->mac_variant,
+                           mac_grid(ctx));
+    }
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_mac, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->ev_mac, 0);
+    if (e != hipSuccess) break;
+    rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, ctx->side);
+    if (rc == HERS_OK) e = hipEventRecord(ctx->ev_free[r], ctx->side);
+  }
+  // join even after a failure, so nothing of this call is left unordered
+  hipError_t ej = hipEventRecord(ctx->ev_join, ctx->side);
+  if (ej == hipSuccess) ej = hipStreamWaitEvent(s, ctx->ev_join, 0);
+  if (rc != HERS_OK) return rc;
+  if (e != hipSuccess) return fail(HERS_EDEVICE, std::string("overlapped search: ") + hipGetErrorString(e));
+  if (ej != hipSuccess) return fail(HERS_EDEVICE, std::string("overlapped search join: ") + hipGetErrorString(ej));
   return HERS_OK;
 }
 
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                  void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen) {
+                  uint64_t* scores_dev, void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen) {
   if (!ctx || !gallery_dev || !probe_dev || reps < 1) return fail(HERS_EINVAL, "bad argument");
   if (int rc = check_d(ctx, d)) return rc;
   const HersConsts& C = ctx->host.C;
@@ -526,10 +625,47 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
     }
     ctx->T.ntt_r = best_rl;
   }
+  if (rc == HERS_OK) ctx->mac_variant = best_v;
+  // overlapped search: whole searches over chunk counts 1, 2, 4, 8, 16
+  // (chunks of at least 16 blocks) x MAC workgroups per CU (8, 1, 2) x the
+  // schedule chosen above or schedule 10 (fewer registers, so epilogue waves
+  // fit beside it)
+  if (rc == HERS_OK && scores_dev) {
+    float best_o = 0.f;
+    int best_nch = 1, best_w = 0, best_mv = best_v;
+    const int vs[2] = {best_v, 10};
+    bool first = true;
+    for (int nch = 1; nch <= 16 && rc == HERS_OK; nch *= 2) {
+      if (nch > 1 && M / nch < 16) break;
+      for (int w : {0, 1, 2}) {
+        if (rc != HERS_OK) break;
+        for (int vi = 0; vi < 2 && rc == HERS_OK; ++vi) {
+          if (vi == 1 && vs[1] == vs[0]) continue;
+          ctx->overlap_chunks = nch;
+          ctx->mac_wgs_per_cu = w;
+          ctx->mac_variant = vs[vi];
+          rc = hers_search(ctx, gallery_dev, m, d, probe_dev, scores_dev, work_dev, work_bytes, stream);
+          hipError_t e = rc == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
+          for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
+            rc = hers_search(ctx, gallery_dev, m, d, probe_dev, scores_dev, work_dev, work_bytes, stream);
+          if (rc != HERS_OK) break;
+          if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+          if (first || ms < best_o) { best_o = ms; best_nch = nch; best_w = w; best_mv = vs[vi]; first = false; }
+        }
+      }
+    }
+    ctx->overlap_chunks = best_nch;
+    ctx->mac_wgs_per_cu = best_w;
+    ctx->mac_variant = best_mv;
+    best_v = best_mv;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  ctx->mac_variant = best_v;
   if (chosen) *chosen = best_v;
   return HERS_OK;
 }

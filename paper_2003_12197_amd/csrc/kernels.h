@@ -60,7 +60,8 @@ hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
                         int inverse, hipStream_t s, uint32_t nsets = 1, uint64_t set_stride = 0);
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
-                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant);
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant,
+                      uint32_t target_wgs = 0);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
                           uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);

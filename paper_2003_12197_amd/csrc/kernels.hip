@@ -665,14 +665,15 @@ hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t 
 }
 
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
-                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant) {
+                      int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant,
+                      uint32_t target_wgs) {
   const int64_t nb = blk_hi - blk_lo;
   const uint32_t lanes = n / 4 < WG ? n / 4 : WG;          // 4 slots per lane
   const uint64_t tiles = n / 4 / lanes;
   static const int nb_of[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 4, 2, 1};
   const int NB = variant >= 0 && variant < 12 ? nb_of[variant] : 1;
-  // about 2048 workgroups (8 per compute unit), groups a multiple of NB blocks
-  uint64_t bpg = (uint64_t)nb * tiles * K / 2048;
+  // about target_wgs workgroups, groups a multiple of NB blocks
+  uint64_t bpg = (uint64_t)nb * tiles * K / (target_wgs ? target_wgs : 2048);
   if (bpg < (uint64_t)NB) bpg = NB;
   bpg = (bpg + NB - 1) / NB * NB;
   const uint64_t groups = ((uint64_t)nb + bpg - 1) / bpg;

@@ -59,7 +59,7 @@ EXPORTS = {
     "hers_plan_destroy": (None, [c_vp]),
     "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_set_option": (c_i32, [c_vp, ctypes.c_char_p, c_i64]),
-    "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
+    "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
                               ctypes.POINTER(c_i64)]),
     "hers_get_option": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(c_i64)]),
     "hers_topk_workspace_bytes": (c_u64, [c_i64, c_i32]),
@@ -273,12 +273,14 @@ class Context:
     def set_option(self, key, value):
         _check(self.lib, self.lib.hers_set_option(self.handle, key.encode(), int(value)), "hers_set_option")
 
-    def autotune(self, gallery, m, d, probe, reps=3, workspace=None):
-        """Pick the fastest multiply-accumulate schedule for this gallery; returns it."""
+    def autotune(self, gallery, m, d, probe, reps=3, workspace=None, scores=None):
+        """Pick the fastest multiply-accumulate schedule, NTT radix and (when a
+        score buffer is given) overlap chunk count for this gallery; returns the schedule."""
         if workspace is None:
             workspace = self.workspace(OP_SEARCH, m, d)
         v = c_i64()
         _check(self.lib, self.lib.hers_autotune(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
+                                                _ptr(scores) if scores is not None else None,
                                                 _ptr(workspace), workspace.numel(), int(reps), _stream(),
                                                 ctypes.byref(v)), "hers_autotune")
         return v.value

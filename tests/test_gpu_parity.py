@@ -235,6 +235,19 @@ def test_full_size_single_probe_sampled_parity(gpu_lib):
     scores = sc[b].cpu().numpy()
     assert np.array_equal(scores[0], res(S[0], op.q_primes))
     assert np.array_equal(scores[1], res(S[1], op.q_primes))
+    # searches whose chunk epilogues overlap the next chunk's
+    # multiply-accumulate (also with a small MAC grid and a workspace of 40
+    # blocks, so chunks reuse regions) give the same ciphertexts
+    per = int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, d))
+    try:
+        for oc, w, nblk in ((2, 0, None), (8, 1, None), (3, 2, 40)):
+            ctx.set_option("overlap_chunks", oc)
+            ctx.set_option("mac_wgs_per_cu", w)
+            ws = None if nblk is None else torch.empty(per * nblk, dtype=torch.uint8, device=ctx.device)
+            assert torch.equal(ctx.search(gal, m, d, pr, workspace=ws), sc), (oc, w, nblk)
+    finally:
+        ctx.set_option("overlap_chunks", 0)
+        ctx.set_option("mac_wgs_per_cu", 0)
 
 
 def _single_scores(ctx, gal, m, d, probe):
@@ -311,12 +324,15 @@ def test_schedules_and_radices_give_same_bits(case_r36):
             for v in range(12):
                 ctx.set_option("mac_variant", v)
                 assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), (rl, v)
-        chosen = ctx.autotune(c.gallery, c.m, c.d, c.probe, reps=1)
+        chosen = ctx.autotune(c.gallery, c.m, c.d, c.probe, reps=1, scores=ctx.new_scores(c.m))
         assert 0 <= chosen < 12 and 2 <= ctx.get_option("ntt_radix_log2") <= 4
+        assert ctx.get_option("overlap_chunks") == 1     # 3 blocks: no chunking worth timing
         assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s)
     finally:
         ctx.set_option("ntt_radix_log2", 4)
         ctx.set_option("mac_variant", 8)
+        ctx.set_option("overlap_chunks", 0)
+        ctx.set_option("mac_wgs_per_cu", 0)
 
 
 def test_topk_of_decrypted_scores(case_r36, gpu_lib):
@@ -335,3 +351,22 @@ def test_topk_of_decrypted_scores(case_r36, gpu_lib):
     idx, val = c.ctx.topk(bt, big.size, 512)
     order = np.lexsort((np.arange(big.size), -big.astype(np.int64)))[:512]
     assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), big[order])
+
+
+def test_overlapped_search_gives_same_bits(case_r36):
+    """Chunked searches whose epilogues run on the context's second stream
+    (including workspaces of 2 and 3 blocks, which make chunks wait for the
+    region they reuse) give the same score ciphertexts."""
+    c = case_r36
+    ctx = c.ctx
+    per = int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, ctx.n, c.d))
+    try:
+        for oc in (1, 2, 3):
+            for nblk in (None, 2, 3):
+                ctx.set_option("overlap_chunks", oc)
+                ctx.set_option("mac_wgs_per_cu", nblk or 0)
+                ws = None if nblk is None else torch.empty(per * nblk, dtype=torch.uint8, device=ctx.device)
+                assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe, workspace=ws), c.scores), (oc, nblk)
+    finally:
+        ctx.set_option("overlap_chunks", 0)
+        ctx.set_option("mac_wgs_per_cu", 0)
