@@ -243,6 +243,7 @@ def main():
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=0, help="serving: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-literal", action="store_true", help="skip timing the paper-literal schedule")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -393,6 +394,31 @@ def main():
     top = int(np.argmax(got))
     ok &= int(tk_idx[0].item()) == top and int(tk_val[0].item()) == int(got[top])
 
+    # ---- side measurements (outside the timed region): one fused search
+    # alone, and the paper-literal per-dimension schedule on the same data
+    side = {}
+    if npr == 1:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        search()
+        torch.cuda.synchronize()
+        e0.record()
+        search()
+        e1.record()
+        torch.cuda.synchronize()
+        side["search_ms"] = e0.elapsed_time(e1)
+        if not args.no_literal:
+            ws_l = ctx.workspace(hers_gpu.OP_SEARCH_LITERAL, min(m, 2048 * n), d)
+            e0.record()
+            ctx.search_literal(gallery, m, d, probes[0], scores=scores[0], workspace=ws_l)
+            e1.record()
+            torch.cuda.synchronize()
+            side["literal_schedule_search_ms"] = e0.elapsed_time(e1)
+            side["literal_over_fused"] = side["literal_schedule_search_ms"] / side["search_ms"]
+            lit = ctx.decrypt_scores(sk, scores[0], m, out=outs[0], workspace=ws_d).cpu().numpy()
+            side["literal_scores_equal_fused"] = bool(np.array_equal(lit, got))
+            ok &= side["literal_scores_equal_fused"]
+            del ws_l
+
     # ---- roofline of the dominant kernel
     K = ctx.K
     dom_ms, dom_n = stages[dominant]
@@ -442,7 +468,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
-        "search_only_scores_per_s": m * npr / (search_ms * 1e-3),
+        "search_only_scores_per_s": m * npr / ((side.get("search_ms") or search_ms) * 1e-3),
+        "side": side,
         "roofline": roof,
         "enrollment": {"gpu_encrypt_ms": enc_ms, "items_per_s": m / (enc_ms * 1e-3), "wall_s": setup_s},
         "check": {"scores_equal_PTq": ok, "argmax": top, "mate": queries[0][1]},

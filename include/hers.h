@@ -108,7 +108,8 @@ uint64_t hers_gallery_words(const hers_ctx* ctx, int64_t m, int32_t d); /* u32: 
 uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d);            /* u32: K d 2 n search form */
 /* workspace bytes for one call; `op` is 0 = encrypt_gallery (per block of
  * the chunk size given in `m` items), 1 = encrypt_probe, 2 = search over m
- * items, 3 = decrypt_scores over m items. */
+ * items, 3 = decrypt_scores over m items, 4 = enroll_append of a batch of
+ * m items, 5 = search_literal over m items. */
 uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d);
 
 /* ---- keys (App. A, Alg. "Key Generation") ------------------------------- */
@@ -141,6 +142,26 @@ int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, in
                          uint32_t* gallery_dev, uint64_t* canon_dev, void* work_dev,
                          size_t work_bytes, void* stream);
 
+/* ---- online enrollment (App. B Alg. "HERS Enrollment", online form) ------
+ * Appends c items (feats_dev int32 [d][ld], ld >= c: items k0 .. k0+c-1) to
+ * a gallery that holds items 0 .. k0-1.  Client half: the batch is split at
+ * block boundaries; for every block b it touches, dimension i is
+ * Encrypt(BatchEncode(the batch's values of dimension i in their slots,
+ * zero elsewhere)) with Philox key (seed, 4) and objects (b, i, 0|1|2)
+ * (a seed must not be reused for another batch).  Server half: CipherAdd
+ * into block b's running ciphertext; a block that held no item starts from
+ * the trivial zero ciphertext (reading of the algorithm's Encrypt(0), whose
+ * rollover branch also drops the incoming ciphertext -- here the batch is
+ * split instead).  Touched blocks are lifted again into the search form.
+ *   canon_dev    running canonical cts [M][d][2][k][n] (hers_encrypt_gallery's
+ *                optional output, or earlier appends), updated in place;
+ *                blocks past the last one holding an item may hold anything.
+ *   gallery_dev  search form u32 [M][K][d][2][n], touched blocks rewritten.
+ *   M must cover item k0 + c - 1.  work_dev: hers_workspace_bytes(ctx, 4, c, d). */
+int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t k0, int64_t c,
+                       int32_t d, uint64_t seed, uint64_t* canon_dev, uint32_t* gallery_dev,
+                       void* work_dev, size_t work_bytes, void* stream);
+
 /* ---- query (App. B Alg. "HERS Search", client side) ---------------------
  * Dimension i is the constant plaintext [q_i]_t (Eq. 2), encrypted with the
  * public key (Philox key (seed, 3), objects (0, i, 0|1|2)).
@@ -162,6 +183,17 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
 int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
                 const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
                 size_t work_bytes, void* stream);
+
+/* The paper-literal schedule (App. B Alg. "HERS Search" as printed): for
+ * every dimension i, CipherMultiply(probe_i, gallery_i) -- tensor, rescale,
+ * relinearization -- then CipherAdd into the block's score ciphertext.  The
+ * same decrypted scores as hers_search (the plaintext products are summed
+ * either way) from d times the rescales and relinearizations and other
+ * ciphertext bits; kept as the timed comparison for the fused schedule.
+ *   work_dev  hers_workspace_bytes(ctx, 5, m, d) (or less: blocks in chunks). */
+int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
+                        const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
+                        size_t work_bytes, void* stream);
 
 /* Batched search: nreq independent (gallery, probe) requests in one
  * submission; request r reads galleries[r] (m[r] items, d[r] dims) and

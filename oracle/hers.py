@@ -123,6 +123,32 @@ def encrypt_gallery(params, pk, P, seed, block_ids=None):
     return {b: encrypt_gallery_block(params, pk, P, b, seed) for b in ids}
 
 
+def enroll_append(params, pk, running, P_new, k0, seed):
+    """Alg. "HERS Enrollment", online form.  `running` maps block b to its d
+    ciphertexts and holds items 0 .. k0-1; P_new [d][c] are items k0 .. k0+c-1.
+    The client encodes the batch at its slot offset (v = k0 mod n), split at
+    block boundaries, and encrypts one ciphertext per (block, dimension) with
+    randomness object (b, i) under key (seed, ENROLL); the server adds each
+    into the block's running ciphertext, which for a block that held no item
+    is the trivial zero ciphertext.  Returns the updated dict."""
+    n = params.n
+    P_new = np.asarray(P_new, dtype=np.int64)
+    d, c = P_new.shape
+    key = (seed, philox.DOMAIN_ENROLL)
+    out = dict(running)
+    for b in range(k0 // n, (k0 + c - 1) // n + 1):
+        lo, hi = max(k0, b * n), min(k0 + c, (b + 1) * n)
+        z = np.zeros((d, n), dtype=np.int64)
+        z[:, lo - b * n: hi - b * n] = P_new[:, lo - k0: hi - k0]
+        fresh = [fv.encrypt(params, pk, [int(v) for v in row], key, (b, i))
+                 for i, row in enumerate(encode_slots(params, z))]
+        if k0 <= b * n:
+            out[b] = fresh
+        else:
+            out[b] = [fv.add(params, r, f) for r, f in zip(out[b], fresh)]
+    return out
+
+
 def encrypt_probe(params, pk, qvec, seed):
     """Alg. "HERS Search", client side: one ciphertext per dimension."""
     key = (seed, philox.DOMAIN_PROBE)

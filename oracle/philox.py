@@ -33,6 +33,7 @@ PHILOX_W1 = 0xBB67AE8584CAA73B
 DOMAIN_KEYGEN = 1
 DOMAIN_GALLERY = 2
 DOMAIN_PROBE = 3
+DOMAIN_ENROLL = 4
 
 
 def philox4x64_10(ctr, key):

@@ -406,6 +406,8 @@ uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d)
     case 1: return align256((size_t)d * 2 * C.k * C.n * 8);
     case 2: return M * search_ws_per_block(C);
     case 3: return decrypt_ws_fixed(C) + M * decrypt_ws_per_block(C);
+    case 4: return (M + 1) * enc_ws_per_block(C, d, false);
+    case 5: return M * (search_ws_per_block(C) + align256((size_t)2 * C.k * C.n * 8));
     default: return 0;
   }
 }
@@ -450,13 +452,47 @@ int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, in
     uint32_t* pt = (uint32_t*)work_dev;
     uint64_t* canon = canon_dev ? canon_dev + (size_t)lo * d * 2 * C.k * C.n
                                 : (uint64_t*)((char*)work_dev + align256((size_t)nb * d * C.n * 4));
-    const int32_t* f = feats_dev + (lo - block0) * (int64_t)C.n;
-    TIMED(ctx, "encode", S(stream), hers::launch_encode(ctx->T, C.n, f, ld, m_total, d, lo, nb, pt, S(stream)));
+    TIMED(ctx, "encode", S(stream), hers::launch_encode(ctx->T, C.n, feats_dev, ld, 0, m_total, block0 * (int64_t)C.n,
+                                                        d, lo, nb, pt, S(stream)));
     TIMED(ctx, "encrypt", S(stream), hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)(nb * d), pt, nullptr, d, lo, seed,
                                  HERS_DOMAIN_GALLERY, canon, S(stream)));
     TIMED(ctx, "lift", S(stream), hers::launch_lift(ctx->T, C.n, canon, (uint32_t)(nb * d), d, lo, gallery_dev, S(stream)));
     TIMED(ctx, "ntt_fwd", S(stream), hers::launch_ntt_p(ctx->T, C.n, gallery_dev + (size_t)lo * C.K * d * 2 * C.n,
                                (uint64_t)nb * C.K * d * 2, 2 * d, 0, S(stream)));
+  }
+  return HERS_OK;
+}
+
+int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t k0, int64_t c, int32_t d,
+                       uint64_t seed, uint64_t* canon_dev, uint32_t* gallery_dev, void* work_dev, size_t work_bytes,
+                       void* stream) {
+  if (!ctx || !feats_dev || !canon_dev || !gallery_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  if (k0 < 0 || c < 1) return fail(HERS_EINVAL, "need k0 >= 0 and c >= 1");
+  if (ld < c) return fail(HERS_EINVAL, "feature row stride smaller than the batch");
+  const HersConsts& C = ctx->host.C;
+  const int64_t n = C.n;
+  const int64_t b_lo = k0 / n, b_hi = (k0 + c - 1) / n + 1;   // blocks the batch touches
+  const size_t per = enc_ws_per_block(C, d, false);
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t chunk = (int64_t)(work_bytes / per);
+  const int64_t first_empty = (k0 + n - 1) / n;               // blocks from here held no item
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = S(stream);
+  for (int64_t lo = b_lo; lo < b_hi; lo += chunk) {
+    const int64_t nb = lo + chunk < b_hi ? chunk : b_hi - lo;
+    const uint32_t nct = (uint32_t)(nb * d);
+    uint32_t* pt = (uint32_t*)work_dev;
+    uint64_t* fresh = (uint64_t*)((char*)work_dev + align256((size_t)nb * d * C.n * 4));
+    uint64_t* run = canon_dev + (size_t)lo * d * 2 * C.k * C.n;
+    TIMED(ctx, "encode", s, hers::launch_encode(ctx->T, C.n, feats_dev, ld, k0, k0 + c, k0, d, lo, nb, pt, s));
+    TIMED(ctx, "encrypt", s, hers::launch_encrypt(ctx->T, C.n, C.k, nct, pt, nullptr, d, lo, seed,
+                                                  HERS_DOMAIN_ENROLL, fresh, s));
+    TIMED(ctx, "ct_add", s, hers::launch_ct_add(ctx->T, C.n, C.k, run, fresh, nct, d, lo, first_empty, s));
+    TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, run, nct, d, lo, gallery_dev, s));
+    TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, gallery_dev + (size_t)lo * C.K * d * 2 * C.n,
+                                                (uint64_t)nb * C.K * d * 2, 2 * d, 0, s));
   }
   return HERS_OK;
 }
@@ -567,6 +603,43 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
   if (rc != HERS_OK) return rc;
   if (e != hipSuccess) return fail(HERS_EDEVICE, std::string("overlapped search: ") + hipGetErrorString(e));
   if (ej != hipSuccess) return fail(HERS_EDEVICE, std::string("overlapped search join: ") + hipGetErrorString(ej));
+  return HERS_OK;
+}
+
+int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
+                        uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !gallery_dev || !probe_dev || !scores_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (m < 1) return fail(HERS_EINVAL, "empty gallery");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m);
+  const size_t ct_bytes = align256((size_t)2 * C.k * C.n * 8);
+  const size_t per = search_ws_per_block(C) + ct_bytes;
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t cap = (int64_t)(work_bytes / per);
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = S(stream);
+  for (int64_t lo = 0; lo < M; lo += cap) {
+    const int64_t hi = lo + cap < M ? lo + cap : M;
+    const int64_t nb = hi - lo;
+    uint32_t* acc = (uint32_t*)work_dev;
+    uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)nb * 3 * C.K * C.n * 4));
+    uint64_t* prod = (uint64_t*)((char*)work_dev + (size_t)nb * search_ws_per_block(C));
+    ScorePtrs sp;
+    sp.p[0] = prod;                                   // indexed from block lo (blk_lo 0 below)
+    for (int32_t i = 0; i < d; ++i) {
+      // CipherMultiply(probe_i, gallery_i): tensor, rescale, relinearization ...
+      TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s,
+                                            ctx->mac_variant, mac_grid(ctx), i, 1));
+      TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
+      TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, 0, sp, 1, digits, 0, 0, s, C.k, C.K));
+      TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s));
+      // ... then CipherAdd into the block's score (the first product starts it)
+      TIMED(ctx, "ct_add", s, hers::launch_ct_add(ctx->T, C.n, C.k, scores_dev + (size_t)lo * 2 * C.k * C.n, prod,
+                                                  (uint32_t)nb, 1, 0, i == 0 ? 0 : INT64_MAX, s));
+    }
+  }
   return HERS_OK;
 }
 

@@ -50,8 +50,11 @@ hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, u
                          uint64_t* pk, uint64_t* rlk, hipStream_t s);
 hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, const uint64_t* pk,
                             const uint64_t* rlk, hipStream_t s);
-hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t m_total,
-                         int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt, hipStream_t s);
+hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t item_lo,
+                         int64_t item_hi, int64_t fbase, int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt,
+                         hipStream_t s);
+hipError_t launch_ct_add(const DevTabs& T, uint32_t n, uint32_t k, uint64_t* dst, const uint64_t* fresh, uint32_t nct,
+                         int32_t d, int64_t block0, int64_t first_empty_block, hipStream_t s);
 hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct, const uint32_t* pt,
                           const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
                           uint64_t* canon, hipStream_t s);
@@ -61,7 +64,7 @@ hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t 
                         int inverse, hipStream_t s, uint32_t nsets = 1, uint64_t set_stride = 0);
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
                       int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant,
-                      uint32_t target_wgs = 0);
+                      uint32_t target_wgs = 0, int32_t dim0 = 0, int32_t dcount = 0);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
                           uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);

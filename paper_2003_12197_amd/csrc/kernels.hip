@@ -111,10 +111,11 @@ k_load_keys(DevTabs T, const uint64_t* __restrict__ pk, const uint64_t* __restri
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
-k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_total, int32_t d,
-         int64_t block0, uint32_t* __restrict__ pt) {
+k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t item_lo, int64_t item_hi,
+         int64_t fbase, int32_t d, int64_t block0, uint32_t* __restrict__ pt) {
   // Eq. 3 with slot packing: slot j of (block b, dimension i) holds item
-  // b n + j; the plaintext is the inverse negacyclic NTT mod t of the slots
+  // b n + j when item_lo <= b n + j < item_hi (feature column item - fbase),
+  // else 0; the plaintext is the inverse negacyclic NTT mod t of the slots
   // placed at bit-reversed positions (out[i] = m(psi^(2 brv(i)+1))).
   extern __shared__ uint32_t lds32[];
   const HersConsts& C = *T.C;
@@ -124,7 +125,7 @@ k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_tot
   const int64_t b = block0 + bl;
   for (uint32_t j = tid; j < n; j += WG) {
     const int64_t item = b * n + j;
-    int64_t v = item < m_total ? feats[(int64_t)i * ld + (int64_t)bl * n + j] : 0;
+    int64_t v = item >= item_lo && item < item_hi ? feats[(int64_t)i * ld + (item - fbase)] : 0;
     int64_t z = v % (int64_t)t;
     if (z < 0) z += t;
     lds32[PADX(bit_reverse(j, C.logn))] = (uint32_t)z;
@@ -132,6 +133,23 @@ k_encode(DevTabs T, const int32_t* __restrict__ feats, int64_t ld, int64_t m_tot
   __syncthreads();
   ntt_inverse16(lds32, T.titw, T.titw_sh, C.t_ninv, C.t_ninv_sh, ModP{t}, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG) pt[(size_t)c * n + j] = lds32[PADX(j)];
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_ct_add(DevTabs T, uint64_t* __restrict__ dst, const uint64_t* __restrict__ fresh, uint32_t nct, int32_t d,
+         int64_t block0, int64_t first_empty_block) {
+  // Server half of the online enrollment (App. B, Alg. "HERS Enrollment"):
+  // CipherAdd of the fresh ciphertexts of blocks block0 .. into the running
+  // ones, [a + b]_q per residue; a block at or past first_empty_block held no
+  // item, so its running ciphertext is the trivial zero and becomes the
+  // fresh one.  Layout [nct][2][k][n], ciphertext c of block block0 + c / d.
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k;
+  const uint64_t w = (uint64_t)blockIdx.x * WG + threadIdx.x;
+  if (w >= (uint64_t)nct * 2 * k * n) return;
+  const uint32_t rho = (uint32_t)((w / n) % k);
+  const int64_t b = block0 + (int64_t)(w / ((uint64_t)2 * k * n) / d);
+  dst[w] = b >= first_empty_block ? fresh[w] : add_q(dst[w], fresh[w], C.q[rho]);
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
@@ -285,7 +303,8 @@ struct MacBatch {
 template <int NB, int U, bool NT>
 __global__ void __launch_bounds__(WG)
 k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe, int32_t d,
-      int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group, uint32_t* __restrict__ acc) {
+      int32_t dim0, int32_t dcount, int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group,
+      uint32_t* __restrict__ acc) {
   static_assert(8 % U == 0, "U divides the fold period");
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
@@ -296,14 +315,15 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
   const int64_t b0 = blk_lo + (int64_t)blockIdx.z * blocks_per_group;
   const int64_t b1 = b0 + blocks_per_group < blk_hi ? b0 + blocks_per_group : blk_hi;
   const size_t row = n / 4;                               // u32x4 between dimension rows
-  const u32x4* pr = (const u32x4*)(probe + (size_t)r * d * 2 * n + slot);
-  const int32_t dfull = d / U * U;
+  // dimensions dim0 .. dim0 + dcount - 1 of the d in the layouts
+  const u32x4* pr = (const u32x4*)(probe + ((size_t)r * d + dim0) * 2 * n + slot);
+  const int32_t dfull = dcount / U * U;
   for (int64_t b = b0; b < b1; b += NB) {
     const u32x4* gb[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int64_t bb = b + u < b1 ? b + u : b;          // a short tail recomputes block b, not stored
-      gb[u] = (const u32x4*)(gallery + (((size_t)bb * K + r) * d * 2) * n + slot);
+      gb[u] = (const u32x4*)(gallery + (((size_t)bb * K + r) * d + dim0) * 2 * n + slot);
     }
     uint64_t a0[NB][4], a1[NB][4], a2[NB][4];
 #pragma unroll
@@ -342,7 +362,7 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
       if ((done & 7) == 0) fold((done & 15) == 0);
       cur = nxt;
     }
-    for (int32_t i = dfull; i < d; ++i) {                   // remainder, one dimension at a time
+    for (int32_t i = dfull; i < dcount; ++i) {              // remainder, one dimension at a time
       MacBatch<NB, 1, NT> one;
       one.load(pr, gb, i, row);
       mac(one.P0[0], one.P1[0], one.G0[0], one.G1[0]);
@@ -635,10 +655,19 @@ hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L
   return hipGetLastError();
 }
 
-hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t m_total,
-                         int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt, hipStream_t s) {
-  hipLaunchKernelGGL(k_encode, dim3((uint32_t)(nblocks * d)), dim3(WG), lds_bytes32(n), s, T, feats, ld, m_total,
-                     d, block0, pt);
+hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t item_lo,
+                         int64_t item_hi, int64_t fbase, int32_t d, int64_t block0, int64_t nblocks, uint32_t* pt,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_encode, dim3((uint32_t)(nblocks * d)), dim3(WG), lds_bytes32(n), s, T, feats, ld, item_lo,
+                     item_hi, fbase, d, block0, pt);
+  return hipGetLastError();
+}
+
+hipError_t launch_ct_add(const DevTabs& T, uint32_t n, uint32_t k, uint64_t* dst, const uint64_t* fresh, uint32_t nct,
+                         int32_t d, int64_t block0, int64_t first_empty_block, hipStream_t s) {
+  const uint64_t words = (uint64_t)nct * 2 * k * n;
+  hipLaunchKernelGGL(k_ct_add, dim3((uint32_t)((words + WG - 1) / WG)), dim3(WG), 0, s, T, dst, fresh, nct, d, block0,
+                     first_empty_block);
   return hipGetLastError();
 }
 
@@ -666,7 +695,9 @@ hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t 
 
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
                       int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant,
-                      uint32_t target_wgs) {
+                      uint32_t target_wgs, int32_t dim0, int32_t dcount) {
+  if (dcount <= 0) dcount = d;
+  if (dim0 < 0 || dim0 + dcount > d) return hipErrorInvalidValue;
   const int64_t nb = blk_hi - blk_lo;
   const uint32_t lanes = n / 4 < WG ? n / 4 : WG;          // 4 slots per lane
   const uint64_t tiles = n / 4 / lanes;
@@ -680,8 +711,8 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
   dim3 grid((uint32_t)tiles, K, (uint32_t)groups);
 #define MAC_CASE(V, NB_, U_, NT_)                                                                    \
   case V:                                                                                            \
-    hipLaunchKernelGGL((k_mac<NB_, U_, NT_>), grid, dim3(lanes), 0, s, T, gallery, probe, d, blk_lo, \
-                       blk_hi, (uint32_t)bpg, acc);                                                  \
+    hipLaunchKernelGGL((k_mac<NB_, U_, NT_>), grid, dim3(lanes), 0, s, T, gallery, probe, d, dim0, dcount, \
+                       blk_lo, blk_hi, (uint32_t)bpg, acc);                                          \
     break;
   switch (variant) {
     MAC_CASE(0, 1, 2, false)

@@ -46,6 +46,9 @@ EXPORTS = {
     "hers_workspace_bytes": (c_u64, [c_vp, ctypes.c_int, c_i64, c_i32]),
     "hers_keygen": (c_i32, [c_vp, c_u64, c_vp, c_vp, c_vp, c_vp]),
     "hers_load_keys": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "hers_enroll_append": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_u64, c_vp, c_vp, c_vp,
+                                    ctypes.c_size_t, c_vp]),
+    "hers_search_literal": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                      ctypes.c_size_t, c_vp]),
     "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
@@ -83,7 +86,7 @@ EXPORTS.update({
     "hers_server_destroy": (None, [c_vp]),
 })
 
-OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT = 0, 1, 2, 3
+OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT, OP_ENROLL, OP_SEARCH_LITERAL = 0, 1, 2, 3, 4, 5
 
 
 class HersError(RuntimeError):
@@ -216,6 +219,25 @@ class Context:
             _ptr(canon), _ptr(workspace), workspace.numel(), _stream()), "hers_encrypt_gallery")
         return gallery
 
+    def new_canonical(self, m, d):
+        """Canonical gallery ciphertexts u64 [M][d][2][k][n] (uninitialised)."""
+        return torch.empty((self.blocks(m), d, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+
+    def enroll_append(self, feats, k0, seed, gallery, canon, workspace=None):
+        """Online enrollment of items k0 .. k0 + c - 1 (feats int32 [d][c] on the
+        device) into a gallery of k0 items; updates canon and gallery in place."""
+        d, c = feats.shape
+        feats = feats.contiguous()
+        need_g = int(self.lib.hers_gallery_words(self.handle, int(k0) + c, d))
+        need_c = self.blocks(int(k0) + c) * d * 2 * self.k * self.n
+        if gallery.numel() * gallery.element_size() < need_g * 4 or canon.numel() * canon.element_size() < need_c * 8:
+            raise ValueError("gallery or canonical buffer does not cover item %d" % (int(k0) + c - 1))
+        if workspace is None:
+            workspace = self.workspace(OP_ENROLL, c, d)
+        _check(self.lib, self.lib.hers_enroll_append(
+            self.handle, _ptr(feats), c, int(k0), c, d, int(seed), _ptr(canon), _ptr(gallery),
+            _ptr(workspace), workspace.numel(), _stream()), "hers_enroll_append")
+
     def encrypt_probe(self, query, seed, canon=None, probe=None, workspace=None):
         """query: int32 [d] on the device; returns the search-form probe."""
         d = query.numel()
@@ -240,6 +262,17 @@ class Context:
         _check(self.lib, self.lib.hers_search(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
                                               _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
                "hers_search")
+        return scores
+
+    def search_literal(self, gallery, m, d, probe, scores=None, workspace=None):
+        """The paper-literal per-dimension schedule (multiply, rescale, relinearize, add)."""
+        if scores is None:
+            scores = self.new_scores(m)
+        if workspace is None:
+            workspace = self.workspace(OP_SEARCH_LITERAL, m, d)
+        _check(self.lib, self.lib.hers_search_literal(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
+                                                      _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
+               "hers_search_literal")
         return scores
 
     def batch_workspace(self, ms, blocks_per_round=None):

@@ -370,3 +370,57 @@ def test_overlapped_search_gives_same_bits(case_r36):
     finally:
         ctx.set_option("overlap_chunks", 0)
         ctx.set_option("mac_wgs_per_cu", 0)
+
+
+def test_online_enrollment_bit_exact(case_r36):
+    """Alg. "HERS Enrollment", online form: batches that start mid-block,
+    straddle block boundaries and open new blocks give the oracle's running
+    ciphertexts bit for bit; the search over the appended gallery gives the
+    oracle's score ciphertext and decrypts to P^T q."""
+    c = case_r36
+    ctx, op, n, d = c.ctx, c.op, c.ctx.n, 3
+    print("case enroll: n=2048 q=3x36 d=3 batches 5,1,2100,1990,2048,3", flush=True)
+    sizes = [5, 1, 2100, 1990, 2048, 3]
+    total = sum(sizes)
+    P, qv = synth.uniform_features(77, d, total)
+    gal = ctx.new_gallery(total, d)
+    canon = ctx.new_canonical(total, d).fill_(-1)     # blocks not yet holding items: any content
+    run, k0 = {}, 0
+    for j, cnt in enumerate(sizes):
+        ctx.enroll_append(torch.from_numpy(P[:, k0:k0 + cnt].copy()).to(ctx.device), k0, 900 + j, gal, canon)
+        run = hers.enroll_append(op, c.opk, run, P[:, k0:k0 + cnt], k0, 900 + j)
+        k0 += cnt
+        got = canon.cpu().numpy()
+        for b in range(k0 // n - (1 if k0 % n == 0 else 0), hers.blocks(k0, n)):
+            for i in range(d):
+                for comp in range(2):
+                    assert np.array_equal(got[b, i, comp], res(run[b][i][comp], op.q_primes)), (j, b, i, comp)
+    pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 55)
+    sc = ctx.search(gal, total, d, pr)
+    oq = hers.encrypt_probe(op, c.opk, qv, 55)
+    S = hers.search_block(op, c.orlk, oq, run[1])
+    got = sc[1].cpu().numpy()
+    assert np.array_equal(got[0], res(S[0], op.q_primes)) and np.array_equal(got[1], res(S[1], op.q_primes))
+    out = ctx.decrypt_scores(c.sk, sc, total).cpu().numpy()
+    assert np.array_equal(out, hers.plaintext_scores(P, qv))
+
+
+def test_literal_schedule_bit_exact(case_r36):
+    """The paper-literal schedule (per dimension: multiply, rescale,
+    relinearize, add) equals the oracle's form L bit for bit, on a full and a
+    ragged block and with a one-block workspace, and decrypts to P^T q like
+    the fused form, whose ciphertext bits differ."""
+    c = case_r36
+    ctx = c.ctx
+    oq = c.oracle_probe()
+    want = {b: hers.search_block_literal(c.op, c.orlk, oq, c.oracle_gallery_block(b)) for b in (0, 2)}
+    one = torch.empty(int(ctx.lib.hers_workspace_bytes(ctx.handle, 5, 1, c.d)), dtype=torch.uint8, device=ctx.device)
+    for ws in (None, one):
+        sc = ctx.search_literal(c.gallery, c.m, c.d, c.probe, workspace=ws)
+        got = sc.cpu().numpy()
+        for b, S in want.items():
+            assert np.array_equal(got[b, 0], res(S[0], c.op.q_primes)), b
+            assert np.array_equal(got[b, 1], res(S[1], c.op.q_primes)), b
+        out = ctx.decrypt_scores(c.sk, sc, c.m).cpu().numpy()
+        assert np.array_equal(out, hers.plaintext_scores(c.P, c.qv))
+    assert not torch.equal(sc, c.scores)

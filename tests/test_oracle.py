@@ -317,6 +317,51 @@ def test_fused_and_literal_forms_decrypt_alike():
     assert np.array_equal(hers.decrypt_scores(p, sk, L, m), want)
 
 
+def test_online_enrollment_fills_slots_at_offsets():
+    """Alg. "HERS Enrollment", online form: after batches that start mid-block
+    and straddle block boundaries, every block decrypts to the enrolled items
+    in their slots (item b*n + j in slot j) and zero in empty slots, and the
+    search over the appended gallery decrypts to P^T q."""
+    p = fv.Params(n=64, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 8)
+    rng = np.random.default_rng(12)
+    d, n = 3, 64
+    sizes = [5, 1, 70, 52, 64, 3]        # mid-block start, straddles, exact fill, new block
+    P, qv = _features(rng, d, sum(sizes))
+    run, k0 = {}, 0
+    for j, c in enumerate(sizes):
+        run = hers.enroll_append(p, pk, run, P[:, k0:k0 + c], k0, 700 + j)
+        k0 += c
+        for b, cts in run.items():
+            for i, ct in enumerate(cts):
+                z = hers.decode_slots(p, fv.decrypt(p, sk, ct))
+                z = np.where(z >= (p.t + 1) // 2, z - p.t, z)
+                lo, hi = b * n, min(k0, (b + 1) * n)
+                want = np.zeros(n, dtype=np.int64)
+                want[: hi - lo] = P[i, lo:hi]
+                assert np.array_equal(z, want), (j, b, i)
+    assert sorted(run) == list(range(hers.blocks(k0, n)))
+    Q = hers.encrypt_probe(p, pk, qv, 43)
+    S = {b: hers.search_block(p, rlk, Q, run[b]) for b in run}
+    assert np.array_equal(hers.decrypt_scores(p, sk, S, k0), hers.plaintext_scores(P, qv))
+
+
+def test_online_enrollment_adds_fresh_encryptions():
+    """The server half is CipherAdd: a block filled by two batches holds the
+    sum of the two fresh encryptions, which differ from the batch-form
+    gallery encryption (another randomness domain)."""
+    p = fv.Params(n=32, qbits=(36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 9)
+    rng = np.random.default_rng(13)
+    P, _ = _features(rng, 2, 32)
+    one = hers.enroll_append(p, pk, {}, P[:, :10], 0, 1)
+    two = hers.enroll_append(p, pk, one, P[:, 10:], 10, 2)
+    alone = hers.enroll_append(p, pk, {}, np.concatenate([np.zeros((2, 10), np.int64), P[:, 10:]], 1), 0, 2)
+    for i in range(2):
+        assert two[0][i] == fv.add(p, one[0][i], alone[0][i])
+    assert two[0][0] != hers.encrypt_gallery_block(p, pk, P, 0, 2)[0]
+
+
 def test_search_with_digit_split_gadget():
     p = fv.Params(n=128, qbits=(54, 54), t_bits=20, w_bits=18)
     sk, pk, rlk = fv.keygen(p, 7)
