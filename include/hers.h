@@ -257,8 +257,10 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * radix 4, 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not
  * NULL -- whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16
  * (chunks of at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule
- * found first or schedule 10.  Keeps the fastest of each in the context
- * and returns the schedule in *chosen (may be NULL).  The workspace and
+ * found first or schedule 10 (a combination other than no chunks, default
+ * grid, schedule found first must be 3% faster to be kept).  Keeps the
+ * fastest of each in the context and returns the schedule in *chosen (may
+ * be NULL).  The workspace and
  * scores_dev contents are overwritten; the call synchronizes `stream`. */
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
                   uint64_t* scores_dev, void* work_dev, size_t work_bytes, int reps, void* stream,
@@ -285,11 +287,12 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
  *   (arena_bytes of device memory owned by the caller) by a first-fit
  *   allocator; a request that does not fit waits (counted in deferrals) until
  *   results are collected with hers_server_wait, which frees its memory.
- *   Batching: the worker admits queued requests in arrival order, up to
- *   max_batch per wave, and runs a wave on one of two streams while the
- *   previous wave may still run on the other; requests on the same gallery in
- *   a wave share one pass over the gallery.  Each result is bit-identical to
- *   the same request served alone.
+ *   Batching: a wave is the oldest queued request and the later queued
+ *   requests on the same gallery (up to max_batch, arrival order), which
+ *   share one pass over the gallery; requests on other galleries form waves
+ *   of their own, so a short search never waits for a long one in its wave.
+ *   Up to four waves run at once, each on its own stream.  Each result is
+ *   bit-identical to the same request served alone.
  * hers_server_submit copies the query (host int32 [d] of the gallery) and
  * returns a ticket, or HERS_ENOMEM if one request alone exceeds the arena.
  * hers_server_wait blocks until the ticket's scores are ready, optionally

@@ -704,7 +704,7 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   // schedule chosen above or schedule 10 (fewer registers, so epilogue waves
   // fit beside it)
   if (rc == HERS_OK && scores_dev) {
-    float best_o = 0.f;
+    float best_o = 0.f, plain_ms = 0.f;
     int best_nch = 1, best_w = 0, best_mv = best_v;
     const int vs[2] = {best_v, 10};
     bool first = true;
@@ -727,10 +727,14 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
           float ms = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
           if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+          if (first) plain_ms = ms;                        // nch 1, default grid, schedule found first
           if (first || ms < best_o) { best_o = ms; best_nch = nch; best_w = w; best_mv = vs[vi]; first = false; }
         }
       }
     }
+    // keep the plain schedule (no chunks, default grid) unless another wins
+    // clearly: differences within timing noise would only make runs disagree
+    if (best_o > 0.97f * plain_ms) { best_nch = 1; best_w = 0; best_mv = best_v; }
     ctx->overlap_chunks = best_nch;
     ctx->mac_wgs_per_cu = best_w;
     ctx->mac_variant = best_mv;

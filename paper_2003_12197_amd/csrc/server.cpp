@@ -10,10 +10,12 @@
 // probe search form, score ciphertexts and decrypted scores, carved from a
 // caller-provided arena by a first-fit allocator; a request that does not fit
 // waits in the queue (a deferral) until earlier results are collected.  A
-// worker thread forms waves from the queue in arrival order and enqueues each
-// wave on one of two streams, so a wave admitted while the previous one is
-// still on the GPU overlaps with it.  Requests of a wave on the same gallery
-// share one pass over the gallery (hers_search_batch).
+// worker thread forms waves: the oldest queued request and the later queued
+// requests on the same gallery, which share one pass over it
+// (hers_search_batch).  Requests on other galleries would share nothing and
+// would only wait for the wave's largest search, so they go in waves of their
+// own.  Up to SRV_STREAMS waves are in flight, each on its own stream, so
+// small searches run beside large ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,6 +101,9 @@ struct Request {
   std::string error;
 };
 
+#define SRV_STREAMS 4
+#define SRV_MAX_ROUND 256   // blocks per search round of a wave (halved while the arena is short)
+
 struct Wave {
   std::vector<Request*> reqs;
   size_t ws_off = 0, ws_bytes = 0;
@@ -125,7 +130,8 @@ struct hers_server {
   std::thread worker;
   bool stop = false;
   int64_t next_ticket = 1;
-  hipStream_t streams[2] = {nullptr, nullptr};
+  hipStream_t streams[SRV_STREAMS] = {};
+  bool stream_busy[SRV_STREAMS] = {};
   hipStream_t copy_stream = nullptr;
   hers_server_stats st;
   size_t enc_ws = 0, dec_ws = 0;
@@ -218,7 +224,6 @@ void launch_wave(hers_server* s, Wave& w, int64_t cb) {
 
 void worker_main(hers_server* s) {
   (void)hipSetDevice(s->device);
-  int next_stream = 0;
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
     // retire finished waves
@@ -233,6 +238,7 @@ void worker_main(hers_server* s) {
           s->st.completed += 1;
         }
         s->arena.release(w.ws_off, w.ws_bytes);
+        s->stream_busy[w.stream] = false;
         (void)hipEventDestroy(w.ev);
         s->inflight.erase(s->inflight.begin() + i);
         s->cv_done.notify_all();
@@ -241,13 +247,15 @@ void worker_main(hers_server* s) {
       }
     }
     if (s->stop && s->queue.empty() && s->inflight.empty()) break;
-    // admit a wave: queued requests in arrival order while memory allows
-    if (s->inflight.size() < 2 && !s->queue.empty()) {
+    // admit a wave: the oldest queued request and the later ones on its
+    // gallery, in arrival order, while memory allows
+    if ((int)s->inflight.size() < SRV_STREAMS && !s->queue.empty()) {
       Wave w;
-      int64_t maxM = 0;
-      while (!s->queue.empty() && (int)w.reqs.size() < s->max_batch) {
-        Request* r = s->queue.front();
-        const Gallery& g = s->galleries[r->gid];
+      const int32_t gid = s->queue.front()->gid;
+      const int64_t maxM = (int64_t)hers_blocks(s->ctx, s->galleries[gid].m);
+      for (auto it = s->queue.begin(); it != s->queue.end() && (int)w.reqs.size() < s->max_batch;) {
+        Request* r = *it;
+        if (r->gid != gid) { ++it; continue; }
         size_t off;
         if (!s->arena.alloc(r->bytes, &off)) {
           s->st.deferrals += 1;
@@ -257,10 +265,9 @@ void worker_main(hers_server* s) {
         r->state = 1;
         r->t_start = now_ms();
         w.reqs.push_back(r);
-        maxM = std::max<int64_t>(maxM, (int64_t)hers_blocks(s->ctx, g.m));
-        s->queue.pop_front();
+        it = s->queue.erase(it);
       }
-      int64_t cb = std::min<int64_t>(maxM, 64);
+      int64_t cb = std::min<int64_t>(maxM, SRV_MAX_ROUND);
       bool ok = !w.reqs.empty();
       while (ok) {
         w.ws_bytes = wave_ws_bytes(s, w.reqs, cb);
@@ -279,8 +286,9 @@ void worker_main(hers_server* s) {
       }
       if (!w.reqs.empty()) {
         if (hipEventCreateWithFlags(&w.ev, hipEventDisableTiming) != hipSuccess) w.ev = nullptr;
-        w.stream = next_stream;
-        next_stream ^= 1;
+        w.stream = 0;
+        while (s->stream_busy[w.stream]) ++w.stream;     // fewer than SRV_STREAMS waves are in flight
+        s->stream_busy[w.stream] = true;
         s->st.waves += 1;
         s->st.max_wave = std::max<int64_t>(s->st.max_wave, (int64_t)w.reqs.size());
         s->st.arena_peak = s->arena.peak();
@@ -309,8 +317,12 @@ int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, si
   hers_server* s = new hers_server(ctx, sk_dev, (char*)arena_dev, arena_bytes, max_batch);
   if (hers_ctx_info(ctx, &s->info)) { delete s; return HERS_EINVAL; }
   (void)hipGetDevice(&s->device);
-  for (int i = 0; i < 2; ++i)
-    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) { delete s; return HERS_EDEVICE; }
+  for (int i = 0; i < SRV_STREAMS; ++i)
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
+      delete s;
+      return HERS_EDEVICE;
+    }
   if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) { delete s; return HERS_EDEVICE; }
   s->worker = std::thread(worker_main, s);
   *out = s;
@@ -397,7 +409,7 @@ void hers_server_destroy(hers_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto& kv : s->reqs) delete kv.second;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SRV_STREAMS; ++i)
     if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;
