@@ -244,6 +244,8 @@ def main():
     ap.add_argument("--requests", type=int, default=0, help="serving: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-literal", action="store_true", help="skip timing the paper-literal schedule")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default schedules (profiling runs: no tuning launches in the trace)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -317,9 +319,13 @@ def main():
     plan = None
     if npr == 1:
         ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 8192 * n), d)
-        mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s, scores=scores[0])
-        log("autotuned k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d" % (
-            mac_variant, ctx.get_option("ntt_radix_log2"), ctx.get_option("overlap_chunks")))
+        if args.no_autotune:
+            mac_variant = ctx.get_option("mac_variant")
+        else:
+            mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s, scores=scores[0])
+        log("%s k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d" % (
+            "default" if args.no_autotune else "autotuned", mac_variant, ctx.get_option("ntt_radix_log2"),
+            ctx.get_option("overlap_chunks")))
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
