@@ -62,10 +62,19 @@ KEY_SEED, GALLERY_SEED, PROBE_SEED, FEATURE_SEED, QUERY_SEED = 201, 301, 401, 10
 
 
 def kernel_source_digest():
+    """Digest of the single-probe multiply-accumulate kernel's source: the
+    k_mac kernel and its load batches, its launcher and the shared modular
+    helpers (a change anywhere else leaves the counter figures valid)."""
+    csrc = os.path.join(ROOT, "paper_2003_12197_amd", "csrc")
+    k = open(os.path.join(csrc, "kernels.hip")).read()
+    a = k.index("typedef uint32_t u32x4")
+    b = k.index("// ---------------------------------------------------------------- batched multiply-accumulate")
+    c = k.index("hipError_t launch_mac(")
+    e = k.index("hipError_t launch_mac_multi(")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "hers_common.h", "ntt.h"):
-        with open(os.path.join(ROOT, "paper_2003_12197_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    h.update(k[a:b].encode())
+    h.update(k[c:e].encode())
+    h.update(open(os.path.join(csrc, "hers_common.h"), "rb").read())
     return h.hexdigest()[:16]
 
 

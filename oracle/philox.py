@@ -34,6 +34,8 @@ DOMAIN_KEYGEN = 1
 DOMAIN_GALLERY = 2
 DOMAIN_PROBE = 3
 DOMAIN_ENROLL = 4
+DOMAIN_RERANK_ITEMS = 5
+DOMAIN_RERANK_PROBE = 6
 
 
 def philox4x64_10(ctr, key):

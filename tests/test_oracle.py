@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 from sympy import isprime
 
-from oracle import fv, hers, philox
+from oracle import fv, hers, philox, primes, rerank
 from oracle.primes import ntt_primes, plain_modulus, psi
 from oracle.ring import center, negacyclic_mul, negacyclic_mul_schoolbook, negacyclic_sum_of_products
 
@@ -360,6 +360,71 @@ def test_online_enrollment_adds_fresh_encryptions():
     for i in range(2):
         assert two[0][i] == fv.add(p, one[0][i], alone[0][i])
     assert two[0][0] != hers.encrypt_gallery_block(p, pk, P, 0, 2)[0]
+
+
+def _horner_at(poly, x, t):
+    acc = 0
+    for c in reversed(list(poly)):
+        acc = (acc * x + int(c)) % t
+    return acc
+
+
+def test_automorphism_moves_slot_positions():
+    """m(x) -> m(x^g) evaluated at psi^(2j+1) is m at psi^(g(2j+1)) (checked by
+    Horner on both sides), so g = 5^s moves position p + s to position p in
+    both rows of the slot layout."""
+    p = fv.Params(n=64, qbits=(36,), t_bits=20)
+    n, t = p.n, p.t
+    rng = np.random.default_rng(21)
+    z = rng.integers(0, t, size=n)
+    m = [int(v) for v in hers.encode_slots(p, z)]
+    root = primes.psi(t, 2 * n)
+    for s in (1, 2, 5, 31):
+        g = rerank.galois_element(n, s)
+        mg = rerank.automorphism(m, g, t)
+        for j in range(n):
+            assert _horner_at(mg, pow(root, 2 * j + 1, t), t) == _horner_at(m, pow(root, g * (2 * j + 1), t), t)
+        zg = hers.decode_slots(p, mg)
+        for r in (0, 1):
+            for pos in range(n // 2):
+                src = rerank.slot_of_position(n, r, (pos + s) % (n // 2))
+                assert zg[rerank.slot_of_position(n, r, pos)] == z[src]
+    # the positions of both rows cover every slot once
+    slots = {rerank.slot_of_position(n, r, pos) for r in (0, 1) for pos in range(n // 2)}
+    assert slots == set(range(n))
+
+
+def test_rotation_decrypts_to_automorphism():
+    """Key switching with a rotation key: Dec(rotate(Enc(m))) = m(x^g) mod t."""
+    p = fv.Params(n=64, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 22)
+    keys = rerank.rotation_keygen(p, 22, 8)
+    rng = np.random.default_rng(23)
+    m = [int(v) for v in rng.integers(0, p.t, size=p.n)]
+    ct = fv.encrypt(p, pk, m, (5, philox.DOMAIN_PROBE), (0, 0))
+    for key, s in zip(keys, rerank.steps(8)):
+        g = rerank.galois_element(p.n, s)
+        assert fv.decrypt(p, sk, rerank.rotate(p, key, ct, g)) == rerank.automorphism(m, g, p.t)
+
+
+def test_rerank_scores_equal_inner_products():
+    """Packed 1:1 re-ranking: every item's score is its inner product with the
+    probe (Eq. 1 restricted to the item); segments past the last item are 0."""
+    p = fv.Params(n=128, qbits=(36, 36, 36), t_bits=20)
+    sk, pk, rlk = fv.keygen(p, 24)
+    W, D = 16, 12
+    keys = rerank.rotation_keygen(p, 24, W)
+    rng = np.random.default_rng(25)
+    S = rerank.segments_per_ct(p.n, W)
+    count = 2 * S + 3
+    F, qv = rng.integers(-63, 64, size=(D, count)), rng.integers(-63, 64, size=D)
+    items = rerank.encrypt_items(p, pk, F, W, 26)
+    probe = rerank.encrypt_probe(p, pk, qv, W, 27)
+    want = F.T.astype(np.int64) @ qv.astype(np.int64)
+    for c, item in enumerate(items):
+        got = rerank.decrypt_scores(p, sk, rerank.rerank_ct(p, rlk, keys, probe, item, W), W)
+        lo, hi = c * S, min(count, (c + 1) * S)
+        assert np.array_equal(got[: hi - lo], want[lo:hi]) and not got[hi - lo:].any(), c
 
 
 def test_search_with_digit_split_gadget():
