@@ -109,7 +109,9 @@ uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d);            /* u32: K 
 /* workspace bytes for one call; `op` is 0 = encrypt_gallery (per block of
  * the chunk size given in `m` items), 1 = encrypt_probe, 2 = search over m
  * items, 3 = decrypt_scores over m items, 4 = enroll_append of a batch of
- * m items, 5 = search_literal over m items. */
+ * m items, 5 = search_literal over m items, 6 = rerank_encrypt of m
+ * ciphertexts, 7 = rerank of m selected ciphertexts, 8 = rerank_decrypt of m
+ * ciphertexts. */
 uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d);
 
 /* ---- keys (App. A, Alg. "Key Generation") ------------------------------- */
@@ -226,6 +228,56 @@ void hers_plan_destroy(hers_plan* plan);
 int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev,
                         int64_t m, int32_t* scores_out_dev, void* work_dev, size_t work_bytes,
                         void* stream);
+
+/* ---- two-stage search, second stage (Sec. 4 "Two Stage Search") ----------
+ * The first stage is a HERS search on a low-dimensional representation and
+ * hers_topk of its decrypted scores; the second re-ranks the candidates with
+ * the full representation under an encryption that addresses single items.
+ * The paper names a 1:1 matcher for this stage without giving its steps;
+ * this is a packed one:
+ *   Packing: S = n / W items per ciphertext (W a power of two in [2, n/2],
+ *   features D <= W, D <= d_max), item x in ciphertext x / S, segment x mod S
+ *   of W slots; the probe is repeated in every segment.  Position p of row r
+ *   is slot j with 2j + 1 = (-1)^r 5^p mod 2n; segment c of row r holds
+ *   positions [W c, W c + W) (segment index r n / 2W + c).
+ *   Score: one ciphertext product (tensor, rescale, relinearization), then
+ *   for s = 1, 2, ..., W/2: ct += rotate(ct, 5^s), a rotation being the
+ *   automorphism x -> x^(5^s) of both components and key switching from
+ *   s(x^(5^s)) to s; each segment's first position then holds the item's
+ *   inner product with the probe (|score| must stay below t/2).
+ * Rotation keys: one per step, ([-(a s + e) + g_l s(x^(5^s))]_q, a) for every
+ * gadget element g_l; Philox key (seed, 1), objects a (5, l, step), e (6, l,
+ * step), s as in hers_keygen (same seed gives the same secret).
+ *   rk_dev canonical [log2 W][L][2][k][n] (hers_rotation_key_words); the NTT
+ *   form stays in the context. */
+uint64_t hers_rotation_key_words(const hers_ctx* ctx, int32_t W);
+int hers_rotation_keygen(hers_ctx* ctx, uint64_t seed, int32_t W, uint64_t* rk_dev, void* stream);
+
+/* Encrypts items (replicate = 0: feats_dev int32 [D][ld], columns 0..count-1,
+ * ceil(count / S) ciphertexts, Philox key (seed, 5), objects (c, 0, 0|1|2))
+ * or a probe (replicate = 1, count = 1: column 0 in every segment, one
+ * ciphertext, key (seed, 6), objects (0, 0, 0|1|2)).
+ *   search_dev u32 [nct][K][2][n] (search form, d = 1); canon_dev optional
+ *   canonical [nct][2][k][n]; work_dev hers_workspace_bytes(ctx, 6, nct, 0). */
+int hers_rerank_encrypt(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t count, int32_t D,
+                        int32_t W, int replicate, uint64_t seed, uint32_t* search_dev, uint64_t* canon_dev,
+                        void* work_dev, size_t work_bytes, void* stream);
+
+/* Server: scores the probe against the nsel ciphertexts ids_dev (device int64
+ * [nsel], indices into items_search of nct_total ciphertexts; an index outside
+ * [0, nct_total) selects an all-zero ciphertext, whose scores are 0).
+ *   out_cts canonical [nsel][2][k][n]; work_dev hers_workspace_bytes(ctx, 7,
+ *   nsel, 0) or less (ciphertexts in chunks).  Needs hers_rotation_keygen
+ *   with this W (or a larger one) first. */
+int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, const int64_t* ids_dev,
+                int32_t nsel, const uint32_t* probe_search, int32_t W, uint64_t* out_cts, void* work_dev,
+                size_t work_bytes, void* stream);
+
+/* Client: decrypts the nsel re-rank ciphertexts and reads every segment's
+ * score: scores_out int32 [nsel][n / W] (score of item ids[c] * S + seg at
+ * [c][seg]); work_dev hers_workspace_bytes(ctx, 8, nsel, 0). */
+int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* cts, int32_t nsel, int32_t W,
+                        int32_t* scores_out, void* work_dev, size_t work_bytes, void* stream);
 
 /* ---- tuning --------------------------------------------------------------
  * Kernel schedule knobs, normally chosen by hers_autotune.  Keys:

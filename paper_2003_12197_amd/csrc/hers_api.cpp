@@ -39,6 +39,10 @@ struct hers_ctx {
   // workspace region)
   int overlap_chunks = 0;
   int mac_wgs_per_cu = 0;   // multiply-accumulate grid, workgroups per CU (0 = 8)
+  // rotation keys of the re-rank stage, NTT form [steps][L][2][k][n]
+  uint64_t* rk_ntt = nullptr;
+  uint64_t* rk_ntt_sh = nullptr;
+  int rk_steps = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_mac = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_free;
@@ -135,6 +139,12 @@ size_t enc_ws_per_block(const HersConsts& C, int32_t d, bool canon_given) {
   return b;
 }
 
+// re-rank workspace per ciphertext: gathered search form, accumulators,
+// digits, one ping-pong ciphertext
+size_t rerank_ws_per_ct(const HersConsts& C) {
+  return align256((size_t)C.K * 2 * C.n * 4) + search_ws_per_block(C) + align256((size_t)2 * C.k * C.n * 8);
+}
+
 int check_d(const hers_ctx* c, int32_t d) {
   if (d < 1 || (uint32_t)d > c->prm.d_max) return fail(HERS_EDIM, "d must be in [1, d_max]");
   return HERS_OK;
@@ -216,6 +226,8 @@ void hers_ctx_destroy(hers_ctx* ctx) {
     if (ctx->ev_mac) (void)hipEventDestroy(ctx->ev_mac);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->rk_ntt) (void)hipFree(ctx->rk_ntt);
+    if (ctx->rk_ntt_sh) (void)hipFree(ctx->rk_ntt_sh);
     for (void* p : ctx->allocs) (void)hipFree(p);
   }
   delete ctx;
@@ -408,6 +420,9 @@ uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d)
     case 3: return decrypt_ws_fixed(C) + M * decrypt_ws_per_block(C);
     case 4: return (M + 1) * enc_ws_per_block(C, d, false);
     case 5: return M * (search_ws_per_block(C) + align256((size_t)2 * C.k * C.n * 8));
+    case 6: return (uint64_t)m * (align256((size_t)C.n * 4) + align256((size_t)2 * C.k * C.n * 8));
+    case 7: return (uint64_t)m * rerank_ws_per_ct(C);
+    case 8: return decrypt_ws_fixed(C) + (uint64_t)m * (decrypt_ws_per_block(C) + align256((size_t)C.n * 4));
     default: return 0;
   }
 }
@@ -640,6 +655,153 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, i
                                                   (uint32_t)nb, 1, 0, i == 0 ? 0 : INT64_MAX, s));
     }
   }
+  return HERS_OK;
+}
+
+static int log2_pow2(int32_t W) {
+  int l = 0;
+  while ((1 << l) < W) ++l;
+  return (1 << l) == W ? l : -1;
+}
+
+static int check_w(const hers_ctx* ctx, int32_t W) {
+  const int l = log2_pow2(W);
+  if (l < 1 || W > (int32_t)(ctx->host.C.n / 2)) return fail(HERS_EINVAL, "W must be a power of two in [2, n/2]");
+  return HERS_OK;
+}
+
+uint64_t hers_rotation_key_words(const hers_ctx* ctx, int32_t W) {
+  if (!ctx || log2_pow2(W) < 1) return 0;
+  return (uint64_t)log2_pow2(W) * ctx->host.C.L * 2 * ctx->host.C.k * ctx->host.C.n;
+}
+
+int hers_rotation_keygen(hers_ctx* ctx, uint64_t seed, int32_t W, uint64_t* rk_dev, void* stream) {
+  if (!ctx || !rk_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_w(ctx, W)) return rc;
+  const HersConsts& C = ctx->host.C;
+  const int steps = log2_pow2(W);
+  DeviceGuard g(ctx->device);
+  if (!ctx->rk_ntt) {
+    // room for every step up to W = n/2 (a setup call: the keys live in the context)
+    const size_t bytes = (size_t)log2_pow2((int32_t)C.n / 2) * C.L * 2 * C.k * C.n * 8;
+    if (hipMalloc((void**)&ctx->rk_ntt, bytes) != hipSuccess ||
+        hipMalloc((void**)&ctx->rk_ntt_sh, bytes) != hipSuccess)
+      return fail(HERS_ENOMEM, "hipMalloc of rotation keys failed");
+  }
+  TIMED(ctx, "keygen", S(stream), hers::launch_rotkey(ctx->T, C.n, C.k, C.L, (uint32_t)steps, seed, rk_dev,
+                                                      ctx->rk_ntt, ctx->rk_ntt_sh, S(stream)));
+  ctx->rk_steps = steps;
+  return HERS_OK;
+}
+
+int hers_rerank_encrypt(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t count, int32_t D, int32_t W,
+                        int replicate, uint64_t seed, uint32_t* search_dev, uint64_t* canon_dev, void* work_dev,
+                        size_t work_bytes, void* stream) {
+  if (!ctx || !feats_dev || !search_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_w(ctx, W)) return rc;
+  if (int rc = check_d(ctx, D)) return rc;
+  if (D > W) return fail(HERS_EINVAL, "D must not exceed W");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  if (count < 1 || (replicate && count != 1)) return fail(HERS_EINVAL, "count must be >= 1 (1 with replicate)");
+  if (ld < count) return fail(HERS_EINVAL, "feature row stride smaller than count");
+  const HersConsts& C = ctx->host.C;
+  const int64_t S_ = C.n / W;
+  const int64_t nct = replicate ? 1 : (count + S_ - 1) / S_;
+  const size_t per = align256((size_t)C.n * 4) + (canon_dev ? 0 : align256((size_t)2 * C.k * C.n * 8));
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one ciphertext");
+  const int64_t chunk = (int64_t)(work_bytes / per);
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = S(stream);
+  const uint32_t domain = replicate ? HERS_DOMAIN_RERANK_PROBE : HERS_DOMAIN_RERANK_ITEMS;
+  for (int64_t lo = 0; lo < nct; lo += chunk) {
+    const int64_t nb = lo + chunk < nct ? chunk : nct - lo;
+    uint32_t* pt = (uint32_t*)work_dev;
+    uint64_t* canon = canon_dev ? canon_dev + (size_t)lo * 2 * C.k * C.n
+                                : (uint64_t*)((char*)work_dev + align256((size_t)nb * C.n * 4));
+    const int32_t* f = replicate ? feats_dev : feats_dev + lo * S_;
+    TIMED(ctx, "encode", s, hers::launch_encode_packed(ctx->T, C.n, f, ld, replicate ? 1 : count - lo * S_, D, W,
+                                                       replicate, (uint32_t)nb, pt, s));
+    TIMED(ctx, "encrypt", s, hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)nb, pt, nullptr, 1, lo, seed, domain,
+                                                  canon, s));
+    TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, canon, (uint32_t)nb, 1, lo, search_dev, s));
+    TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, search_dev + (size_t)lo * C.K * 2 * C.n,
+                                                (uint64_t)nb * C.K * 2, 2, 0, s));
+  }
+  return HERS_OK;
+}
+
+int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, const int64_t* ids_dev, int32_t nsel,
+                const uint32_t* probe_search, int32_t W, uint64_t* out_cts, void* work_dev, size_t work_bytes,
+                void* stream) {
+  if (!ctx || !items_search || !ids_dev || !probe_search || !out_cts) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_w(ctx, W)) return rc;
+  if (nsel < 1 || nct_total < 1) return fail(HERS_EINVAL, "need nsel >= 1 and nct_total >= 1");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  const int steps = log2_pow2(W);
+  if (ctx->rk_steps < steps) return fail(HERS_EINVAL, "rotation keys for this W not generated");
+  const HersConsts& C = ctx->host.C;
+  const size_t per = rerank_ws_per_ct(C);
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one ciphertext");
+  int64_t cap = (int64_t)(work_bytes / per);
+  if (cap > 65535) cap = 65535;
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = S(stream);
+  const size_t ct_words = (size_t)2 * C.k * C.n;
+  const size_t key_words = (size_t)C.L * ct_words;
+  for (int64_t lo = 0; lo < nsel; lo += cap) {
+    const int64_t nb = lo + cap < nsel ? cap : nsel - lo;
+    char* w = (char*)work_dev;
+    uint32_t* gath = (uint32_t*)w;
+    w += align256((size_t)nb * C.K * 2 * C.n * 4);
+    uint32_t* acc = (uint32_t*)w;
+    w += align256((size_t)nb * 3 * C.K * C.n * 4);
+    uint64_t* digits = (uint64_t*)w;
+    w += align256((size_t)nb * C.L * C.k * C.n * 8);
+    uint64_t* tmp = (uint64_t*)w;
+    TIMED(ctx, "gather", s, hers::launch_gather_cts(items_search, (uint64_t)C.K * 2 * C.n, nct_total, ids_dev + lo,
+                                                   (uint32_t)nb, gath, s));
+    // one ciphertext product per selected ciphertext (a search with d = 1)
+    TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gath, probe_search, 1, 0, nb, acc, s, ctx->mac_variant,
+                                          mac_grid(ctx)));
+    if (int rc = search_epilogue(ctx, acc, digits, 0, nb, out_cts + (size_t)lo * ct_words, s)) return rc;
+    // rotate-and-add: cur -> nxt, ping-pong between out_cts and tmp
+    uint64_t* cur = out_cts + (size_t)lo * ct_words;
+    uint64_t* nxt = tmp;
+    for (int st = 0; st < steps; ++st) {
+      uint32_t gel = 5;
+      for (int i = 0; i < st; ++i) gel = (gel * gel) & (2 * C.n - 1);
+      TIMED(ctx, "rotate", s, hers::launch_rot_digits(ctx->T, C.n, C.k, cur, nxt, digits, (uint32_t)nb, gel, s));
+      ScorePtrs sp;
+      sp.p[0] = nxt;
+      TIMED(ctx, "rotate", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s,
+                                                 ctx->rk_ntt + (size_t)st * key_words,
+                                                 ctx->rk_ntt_sh + (size_t)st * key_words));
+      std::swap(cur, nxt);
+    }
+    if (cur != out_cts + (size_t)lo * ct_words)
+      HIP_TRY(hipMemcpyAsync(out_cts + (size_t)lo * ct_words, cur, (size_t)nb * ct_words * 8,
+                             hipMemcpyDeviceToDevice, s));
+  }
+  return HERS_OK;
+}
+
+int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* cts, int32_t nsel, int32_t W,
+                        int32_t* scores_out, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !sk_dev || !cts || !scores_out) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_w(ctx, W)) return rc;
+  if (nsel < 1) return fail(HERS_EINVAL, "need nsel >= 1");
+  const HersConsts& C = ctx->host.C;
+  const size_t slots_bytes = align256((size_t)nsel * C.n * 4);
+  if (!work_dev || work_bytes < slots_bytes + decrypt_ws_fixed(C) + decrypt_ws_per_block(C))
+    return fail(HERS_ESPACE, "workspace too small");
+  DeviceGuard g(ctx->device);
+  int32_t* slots = (int32_t*)work_dev;
+  // decrypt every ciphertext as a block of n "items" (its slots), then pick
+  // each segment's first position
+  if (int rc = hers_decrypt_scores(ctx, sk_dev, cts, (int64_t)nsel * C.n, slots, (char*)work_dev + slots_bytes,
+                                   work_bytes - slots_bytes, stream))
+    return rc;
+  TIMED(ctx, "dec_decode", S(stream), hers::launch_rerank_pick(C.n, slots, (uint32_t)nsel, W, scores_out, S(stream)));
   return HERS_OK;
 }
 

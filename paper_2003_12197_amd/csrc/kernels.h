@@ -69,7 +69,19 @@ hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
                           uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
-                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s);
+                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s,
+                        const uint64_t* key = nullptr, const uint64_t* key_sh = nullptr);
+// two-stage search, second stage (rerank.hip)
+hipError_t launch_encode_packed(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t count,
+                                int32_t D, int32_t W, int replicate, uint32_t nct, uint32_t* pt, hipStream_t s);
+hipError_t launch_rotkey(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint32_t nsteps, uint64_t seed,
+                         uint64_t* rk, uint64_t* rk_ntt, uint64_t* rk_ntt_sh, hipStream_t s);
+hipError_t launch_rot_digits(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* ct_in, uint64_t* ct_out,
+                             uint64_t* digits, uint32_t nct, uint32_t g, hipStream_t s);
+hipError_t launch_gather_cts(const uint32_t* items, uint64_t words_per_ct, int64_t nct_total, const int64_t* ids,
+                             uint32_t nsel, uint32_t* out, hipStream_t s);
+hipError_t launch_rerank_pick(uint32_t n, const int32_t* slot_scores, uint32_t nsel, int32_t W, int32_t* out,
+                              hipStream_t s);
 hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,
                          hipStream_t s);
 hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,

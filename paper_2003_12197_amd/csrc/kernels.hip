@@ -548,10 +548,13 @@ k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
 }
 
 extern "C" __global__ void __launch_bounds__(WG)
-k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride) {
-  // Relinearization, second half: for block blk_lo + blockIdx.x, residue
-  // sigma = blockIdx.y mod k and component comp = blockIdx.y / k of request z,
-  // c_comp += INTT(sum_g NTT(y_g) * rlk_g[comp]) mod q_sigma.
+k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
+            const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
+  // Relinearization (or key switching), second half: for block
+  // blk_lo + blockIdx.x, residue sigma = blockIdx.y mod k and component
+  // comp = blockIdx.y / k of request z, c_comp += INTT(sum_g NTT(y_g) *
+  // key_g[comp]) mod q_sigma, key [L][2][k][n] in NTT form (the evaluation
+  // keys, or a rotation key).
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
@@ -564,7 +567,7 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
     uint64_t acc = 0;
     for (uint32_t g = 0; g < L; ++g) {
       const size_t r = (((size_t)g * 2 + comp) * k + sg) * n + j;
-      acc = add_q(acc, shoup_q(digits[((size_t)g * k + sg) * n + j], T.rlk_ntt[r], T.rlk_ntt_sh[r], q), q);
+      acc = add_q(acc, shoup_q(digits[((size_t)g * k + sg) * n + j], key[r], key_sh[r], q), q);
     }
     lds64[PADX(j)] = acc;
   }
@@ -756,14 +759,16 @@ hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64
 }
 
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
-                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s) {
+                        int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s,
+                        const uint64_t* key, const uint64_t* key_sh) {
+  if (!key) { key = T.rlk_ntt; key_sh = T.rlk_ntt_sh; }
   // digit NTTs (L k per block), then key products and inverse NTTs (2 k per block)
   hipLaunchKernelGGL(k_ntt_q, dim3((uint32_t)(nblk * L * k), nreq), dim3(WG), lds_bytes(n, 1), s, T, digits,
                      dig_stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_relin_acc, dim3((uint32_t)nblk, 2 * k, nreq), dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo,
-                     SP, dig_stride);
+                     SP, dig_stride, key, key_sh);
   return hipGetLastError();
 }
 

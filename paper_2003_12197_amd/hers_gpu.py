@@ -49,6 +49,12 @@ EXPORTS = {
     "hers_enroll_append": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_u64, c_vp, c_vp, c_vp,
                                     ctypes.c_size_t, c_vp]),
     "hers_search_literal": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_rotation_key_words": (c_u64, [c_vp, c_i32]),
+    "hers_rotation_keygen": (c_i32, [c_vp, c_u64, c_i32, c_vp, c_vp]),
+    "hers_rerank_encrypt": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i32, ctypes.c_int, c_u64, c_vp, c_vp, c_vp,
+                                     ctypes.c_size_t, c_vp]),
+    "hers_rerank": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_rerank_decrypt": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                      ctypes.c_size_t, c_vp]),
     "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
@@ -87,6 +93,7 @@ EXPORTS.update({
 })
 
 OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT, OP_ENROLL, OP_SEARCH_LITERAL = 0, 1, 2, 3, 4, 5
+OP_RERANK_ENCRYPT, OP_RERANK, OP_RERANK_DECRYPT = 6, 7, 8
 
 
 class HersError(RuntimeError):
@@ -274,6 +281,54 @@ class Context:
                                                       _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
                "hers_search_literal")
         return scores
+
+    # ---- two-stage search, second stage (packed 1:1 re-ranking)
+    def rotation_keygen(self, seed, W):
+        """Rotation keys for segments of W slots (canonical [log2 W][L][2][k][n]); loaded into the context."""
+        rk = self._empty(self.lib.hers_rotation_key_words(self.handle, int(W)), torch.int64)
+        _check(self.lib, self.lib.hers_rotation_keygen(self.handle, int(seed), int(W), _ptr(rk), _stream()),
+               "hers_rotation_keygen")
+        return rk
+
+    def rerank_encrypt(self, feats, W, seed, replicate=False, canon=None):
+        """Packed encryption of items (feats int32 [D][count]) or of a probe
+        (feats [D][1], replicate=True); returns the search form [nct][K][2][n]."""
+        D, count = feats.shape
+        feats = feats.contiguous()
+        nct = 1 if replicate else -(-count // (self.n // W))
+        search = torch.empty((nct, self.K, 2, self.n), dtype=torch.int32, device=self.device)
+        if canon is not None and canon.numel() * canon.element_size() < nct * 2 * self.k * self.n * 8:
+            raise ValueError("canonical buffer too small")
+        ws = self.workspace(OP_RERANK_ENCRYPT, nct, 0)
+        _check(self.lib, self.lib.hers_rerank_encrypt(
+            self.handle, _ptr(feats), count, count, D, int(W), int(bool(replicate)), int(seed), _ptr(search),
+            _ptr(canon), _ptr(ws), ws.numel(), _stream()), "hers_rerank_encrypt")
+        return search
+
+    def rerank(self, items, ids, probe, W, out=None, workspace=None):
+        """Encrypted scores of the probe against the ciphertexts `ids` (device int64) of `items`."""
+        ids = ids.to(device=self.device, dtype=torch.int64).contiguous()
+        nsel = ids.numel()
+        if out is None:
+            out = torch.empty((nsel, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        if workspace is None:
+            workspace = self.workspace(OP_RERANK, nsel, 0)
+        _check(self.lib, self.lib.hers_rerank(self.handle, _ptr(items), items.shape[0], _ptr(ids), nsel, _ptr(probe),
+                                              int(W), _ptr(out), _ptr(workspace), workspace.numel(), _stream()),
+               "hers_rerank")
+        return out
+
+    def rerank_decrypt(self, sk, cts, W, out=None, workspace=None):
+        """Client: int32 [nsel][n / W] scores of the segments of the re-rank ciphertexts."""
+        nsel = cts.shape[0]
+        if out is None:
+            out = torch.empty((nsel, self.n // W), dtype=torch.int32, device=self.device)
+        if workspace is None:
+            workspace = self.workspace(OP_RERANK_DECRYPT, nsel, 0)
+        _check(self.lib, self.lib.hers_rerank_decrypt(self.handle, _ptr(sk), _ptr(cts), nsel, int(W), _ptr(out),
+                                                      _ptr(workspace), workspace.numel(), _stream()),
+               "hers_rerank_decrypt")
+        return out
 
     def batch_workspace(self, ms, blocks_per_round=None):
         """Workspace for search_batch: every request's accumulators for a round of blocks."""
