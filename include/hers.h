@@ -322,8 +322,11 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
 /* ---- nearest neighbours (App. B, Alg. "HERS Search": argmax of the decrypted scores) ----
  * The k highest of scores_dev (int32 [m], as written by hers_decrypt_scores),
  * highest first; equal scores are ordered by lower item index.
- * idx_dev int64 [k], val_dev int32 [k]; 1 <= k <= 512, m <= 2^32;
- * workspace of hers_topk_workspace_bytes(m, k). */
+ * idx_dev int64 [k], val_dev int32 [k]; 1 <= k <= 16384 (and k <= m),
+ * m <= 2^32; workspace of hers_topk_workspace_bytes(m, k).  Up to k = 512
+ * the k tiles of 4096 scores with the largest maxima are filtered and
+ * sorted; above, the k-th largest (score, index) key is found by radix
+ * select and the k keys at or above it are ranked. */
 uint64_t hers_topk_workspace_bytes(int64_t m, int32_t k);
 int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, int64_t* idx_dev, int32_t* val_dev,
               void* work_dev, size_t work_bytes, void* stream);

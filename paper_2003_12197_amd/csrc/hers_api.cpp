@@ -255,6 +255,7 @@ static TopkLayout topk_layout(uint64_t m, uint64_t k) {
 
 uint64_t hers_topk_workspace_bytes(int64_t m, int32_t k) {
   if (m < 1 || k < 1) return 0;
+  if (k > HERS_TOPK_TILE_K) return hers::topk_large_state_bytes() + align256((uint64_t)k * 8);
   return topk_layout((uint64_t)m, (uint64_t)k).total;
 }
 
@@ -278,10 +279,16 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
               void* work_dev, size_t work_bytes, void* stream) {
   if (!ctx || !scores_dev || !idx_dev || !val_dev) return fail(HERS_EINVAL, "null argument");
   if (m < 1 || m > ((int64_t)1 << 32)) return fail(HERS_EINVAL, "m must be in [1, 2^32]");
-  if (k < 1 || k > 512 || k > m) return fail(HERS_EINVAL, "k must be in [1, min(512, m)]");
+  if (k < 1 || k > HERS_TOPK_MAX_K || k > m) return fail(HERS_EINVAL, "k must be in [1, min(16384, m)]");
   if (!work_dev || work_bytes < hers_topk_workspace_bytes(m, k)) return fail(HERS_ESPACE, "workspace too small");
   DeviceGuard g(ctx->device);
   const hipStream_t s = S(stream);
+  if (k > HERS_TOPK_TILE_K) {   // radix select, then ranks
+    uint64_t* keys = (uint64_t*)((char*)work_dev + hers::topk_large_state_bytes());
+    TIMED(ctx, "topk", s, hers::launch_topk_large(scores_dev, (uint64_t)m, (uint32_t)k, work_dev, keys, idx_dev,
+                                                  val_dev, (uint32_t)ctx->num_cus, s));
+    return HERS_OK;
+  }
   if (m <= HERS_TOPK_TILE) {   // one tile: sort it directly
     TIMED(ctx, "topk", s, hers::launch_topk_pass(scores_dev, nullptr, (uint64_t)m, (uint32_t)k, nullptr, idx_dev,
                                                  val_dev, s));

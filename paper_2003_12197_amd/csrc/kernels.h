@@ -93,6 +93,11 @@ hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, in
 #define HERS_TOPK_TILE 2048
 #define HERS_TOPK_TM_LOG2 12
 #define HERS_TOPK_TM (1u << HERS_TOPK_TM_LOG2)
+#define HERS_TOPK_TILE_K 512     // largest k of the tile path
+#define HERS_TOPK_MAX_K 16384    // largest k (radix-select path above HERS_TOPK_TILE_K)
+size_t topk_large_state_bytes();
+hipError_t launch_topk_large(const int32_t* scores, uint64_t m, uint32_t k, void* work, uint64_t* keys,
+                             int64_t* idx_out, int32_t* val_out, uint32_t num_cus, hipStream_t s);
 hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
                             uint64_t* keys_out, int64_t* idx_out, int32_t* val_out, hipStream_t s);
 hipError_t launch_topk_tilemax(const int32_t* scores, uint64_t m, uint64_t* maxes, hipStream_t s);

@@ -138,7 +138,141 @@ k_topk_filter(const int32_t* __restrict__ scores, uint64_t m, const uint64_t* __
   for (uint32_t j = tid; j < k; j += TK_WG) cand[(uint64_t)blockIdx.x * k + j] = j < c ? buf[j] : 0;
 }
 
+// ---------------------------------------------------------------- large k (radix select)
+// For k above the tile path's limit: the k-th largest key tau is found digit
+// by digit from the top (digits of 11, 11, 11, 11, 11 and 9 bits): a pass
+// histograms the current digit of the keys that agree with tau's digits
+// found so far and picks the digit where the count from the top reaches the
+// keys still missing.  Keys are distinct, so exactly k keys are >= tau; they
+// are collected (any order) and each is written at its rank, the number of
+// collected keys above it.
+#define TK_RS_BINS 2048
+
+struct RselState {
+  uint64_t prefix;      // digits of tau found so far
+  uint32_t need;        // keys still to place at or below the current prefix
+  uint32_t count;       // collected keys
+};
+
+__device__ __forceinline__ bool rsel_match(uint64_t key, uint64_t prefix, uint32_t hi_shift) {
+  return hi_shift >= 64 || (key >> hi_shift) == (prefix >> hi_shift);
+}
+
+extern "C" __global__ void __launch_bounds__(TK_WG)
+k_rsel_hist(const int32_t* __restrict__ scores, uint64_t m, const RselState* __restrict__ st, uint32_t shift,
+            uint32_t width, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[TK_RS_BINS];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < TK_RS_BINS; b += TK_WG) h[b] = 0;
+  __syncthreads();
+  const uint64_t prefix = st->prefix;
+  const uint32_t hi_shift = shift + width;
+  for (uint64_t i = (uint64_t)blockIdx.x * TK_WG + tid; i < m; i += (uint64_t)gridDim.x * TK_WG) {
+    const uint64_t key = score_key(scores[i], i);
+    if (rsel_match(key, prefix, hi_shift)) atomicAdd(&h[(uint32_t)(key >> shift) & ((1u << width) - 1)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = tid; b < TK_RS_BINS; b += TK_WG)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+extern "C" __global__ void __launch_bounds__(TK_WG)
+k_rsel_choose(RselState* __restrict__ st, uint32_t shift, uint32_t width, uint32_t* __restrict__ hist) {
+  // One workgroup: extend the prefix by the digit where the count from the
+  // top reaches `need`, then clear the histogram for the next pass.
+  __shared__ uint32_t h[TK_RS_BINS];
+  const uint32_t tid = threadIdx.x, nb = 1u << width;
+  for (uint32_t b = tid; b < TK_RS_BINS; b += TK_WG) {
+    h[b] = b < nb ? hist[b] : 0;
+    hist[b] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t need = st->need, cum = 0, b = nb;
+    while (b > 0) {
+      --b;
+      if (cum + h[b] >= need) break;
+      cum += h[b];
+    }
+    st->prefix |= (uint64_t)b << shift;
+    st->need = need - cum;
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(TK_WG)
+k_rsel_collect(const int32_t* __restrict__ scores, uint64_t m, RselState* __restrict__ st, uint32_t k,
+               uint64_t* __restrict__ out) {
+  const uint64_t tau = st->prefix;
+  for (uint64_t i = (uint64_t)blockIdx.x * TK_WG + threadIdx.x; i < m; i += (uint64_t)gridDim.x * TK_WG) {
+    const uint64_t key = score_key(scores[i], i);
+    if (key >= tau) {
+      const uint32_t slot = atomicAdd(&st->count, 1u);
+      if (slot < k) out[slot] = key;
+    }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(TK_WG)
+k_rank_sort(const uint64_t* __restrict__ keys, uint32_t k, int64_t* __restrict__ idx_out,
+            int32_t* __restrict__ val_out) {
+  // Key keys[i] goes to position #{j : keys[j] > keys[i]} (keys distinct).
+  __shared__ uint64_t tile[HERS_TOPK_TILE];
+  const uint32_t i = blockIdx.x * TK_WG + threadIdx.x;
+  const uint64_t key = i < k ? keys[i] : 0;
+  uint32_t rank = 0;
+  for (uint32_t base = 0; base < k; base += HERS_TOPK_TILE) {
+    const uint32_t cnt = k - base < HERS_TOPK_TILE ? k - base : HERS_TOPK_TILE;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += TK_WG) tile[j] = keys[base + j];
+    __syncthreads();
+    for (uint32_t j = 0; j < cnt; ++j) rank += tile[j] > key;
+  }
+  if (i < k) {
+    idx_out[rank] = key_index(key);
+    val_out[rank] = key_score(key);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(TK_WG) k_rsel_init(RselState* st, uint32_t k, uint32_t* hist) {
+  // state and histogram of the first pass (the workspace holds anything)
+  for (uint32_t b = threadIdx.x; b < TK_RS_BINS; b += TK_WG) hist[b] = 0;
+  if (threadIdx.x == 0) {
+    st->prefix = 0;
+    st->need = k;
+    st->count = 0;
+  }
+}
+
 namespace hers {
+
+size_t topk_large_state_bytes() { return 256 + TK_RS_BINS * 4; }
+
+hipError_t launch_topk_large(const int32_t* scores, uint64_t m, uint32_t k, void* work, uint64_t* keys,
+                             int64_t* idx_out, int32_t* val_out, uint32_t num_cus, hipStream_t s) {
+  RselState* st = (RselState*)work;
+  uint32_t* hist = (uint32_t*)((char*)work + 256);
+  // k_rsel_init clears the histogram for the first pass, k_rsel_choose after every pass
+  hipLaunchKernelGGL(k_rsel_init, dim3(1), dim3(TK_WG), 0, s, st, k, hist);
+  hipError_t e = hipGetLastError();
+  uint64_t grid = (m + TK_WG - 1) / TK_WG;
+  if (grid > (uint64_t)num_cus * 4) grid = (uint64_t)num_cus * 4;
+  static const uint32_t widths[6] = {11, 11, 11, 11, 11, 9};
+  uint32_t shift = 64;
+  for (int p = 0; p < 6 && e == hipSuccess; ++p) {
+    shift -= widths[p];
+    hipLaunchKernelGGL(k_rsel_hist, dim3((uint32_t)grid), dim3(TK_WG), 0, s, scores, m, st, shift, widths[p], hist);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_rsel_choose, dim3(1), dim3(TK_WG), 0, s, st, shift, widths[p], hist);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rsel_collect, dim3((uint32_t)grid), dim3(TK_WG), 0, s, scores, m, st, k, keys);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_sort, dim3((k + TK_WG - 1) / TK_WG), dim3(TK_WG), 0, s, keys, k, idx_out, val_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_topk_pass(const int32_t* scores, const uint64_t* keys_in, uint64_t count, uint32_t k,
                             uint64_t* keys_out, int64_t* idx_out, int32_t* val_out, hipStream_t s) {

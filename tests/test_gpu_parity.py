@@ -341,16 +341,17 @@ def test_topk_of_decrypted_scores(case_r36, gpu_lib):
     c = case_r36
     out = c.ctx.decrypt_scores(c.sk, c.scores, c.m)
     s = out.cpu().numpy()
-    for k in (1, 10, 100):
+    for k in (1, 10, 100, 513, 4133):
         idx, val = c.ctx.topk(out, c.m, k)
         order = np.lexsort((np.arange(c.m), -s.astype(np.int64)))[:k]
         assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), s[order])
     rng = np.random.default_rng(17)
     big = rng.integers(-300, 301, size=3_000_017).astype(np.int32)   # many ties, ragged last tile
     bt = torch.from_numpy(big).to(c.ctx.device)
-    idx, val = c.ctx.topk(bt, big.size, 512)
-    order = np.lexsort((np.arange(big.size), -big.astype(np.int64)))[:512]
-    assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), big[order])
+    order = np.lexsort((np.arange(big.size), -big.astype(np.int64)))
+    for k in (512, 10000, 16384):                       # the tile path, then radix select
+        idx, val = c.ctx.topk(bt, big.size, k)
+        assert np.array_equal(idx.cpu().numpy(), order[:k]) and np.array_equal(val.cpu().numpy(), big[order[:k]]), k
 
 
 def test_overlapped_search_gives_same_bits(case_r36):

@@ -94,12 +94,12 @@ def test_rerank_bit_exact_and_scores(rr):
 
 def test_two_stage_pipeline_full_size(gpu_lib):
     """The two-stage search at n = 4096: HERS on 16 dimensions over 2^17
-    items, top-512 on the GPU, then re-ranking of the candidates' packed
+    items, top-1000 on the GPU, then re-ranking of the candidates' packed
     ciphertexts with 192 features (W = 256): every re-ranked score equals the
     plain 192-dimensional inner product, and the best re-ranked item is the
     probe's mate."""
-    print("case two-stage: n=4096 m=2^17 d1=16 D=192 K=512", flush=True)
-    n, m, d1, D, W, K = 4096, 1 << 17, 16, 192, 256, 512
+    print("case two-stage: n=4096 m=2^17 d1=16 D=192 K=1000", flush=True)
+    n, m, d1, D, W, K = 4096, 1 << 17, 16, 192, 256, 1000
     ctx1 = gpu_lib.Context(n=n, qbits=(36, 36, 36), t_bits=20, w_bits=0, d_max=16)
     ctx2 = gpu_lib.Context(n=n, qbits=(36, 36, 36), t_bits=22, w_bits=0, d_max=192)
     sk1, _, _ = ctx1.keygen(51)
