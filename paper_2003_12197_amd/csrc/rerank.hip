@@ -130,20 +130,22 @@ k_rotkey(DevTabs T, uint64_t seed, uint64_t* __restrict__ rk, uint64_t* __restri
 
 extern "C" __global__ void __launch_bounds__(WG)
 k_rot_digits(DevTabs T, const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t* __restrict__ digits,
-             uint32_t nct, uint32_t g) {
+             uint32_t nct, uint32_t ginv) {
   // First half of rotate-and-add for ciphertexts [nct][2][k][n]: out =
   // (c0 + tau(c0), c1) and the gadget digits of tau(c1) ([nct][L][k][n],
-  // reduced mod every q_sigma), tau: x^i -> +-x^(i g mod n).  One thread per
-  // source coefficient i; the map i -> i g mod n is a bijection, so every
-  // destination is written once.
+  // reduced mod every q_sigma), tau: x^i -> +-x^(i g mod 2n).  One thread per
+  // destination coefficient dst (coalesced writes): with ginv = g^-1 mod 2n,
+  // i = dst ginv mod 2n is the source if i < n (sign +), else i - n is, with
+  // sign - (x^(i - n) maps to x^(dst + n) = -x^dst).
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L;
   const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
   if (idx >= (uint64_t)nct * n) return;
   const uint64_t c = idx >> C.logn;
-  const uint32_t i = (uint32_t)(idx & (n - 1));
-  const uint32_t e = (i * g) & (2 * n - 1), dst = e & (n - 1);
+  const uint32_t dst = (uint32_t)(idx & (n - 1));
+  const uint32_t e = (dst * ginv) & (2 * n - 1);
   const bool neg = e >= n;
+  const uint32_t i = e & (n - 1);
   const uint64_t* c0 = in + c * 2 * k * n;
   const uint64_t* c1 = c0 + (size_t)k * n;
   uint64_t* o0 = out + c * 2 * k * n;
@@ -211,9 +213,16 @@ hipError_t launch_rotkey(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, u
 hipError_t launch_rot_digits(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* ct_in, uint64_t* ct_out,
                              uint64_t* digits, uint32_t nct, uint32_t g, hipStream_t s) {
   (void)k;
+  // g^-1 mod 2n (g odd): the group has order n, so g^-1 = g^(n - 1)
+  const uint32_t mask = 2 * n - 1;
+  uint32_t ginv = 1, b = g;
+  for (uint32_t x = n - 1; x; x >>= 1) {
+    if (x & 1) ginv = (uint32_t)(((uint64_t)ginv * b) & mask);
+    b = (uint32_t)(((uint64_t)b * b) & mask);
+  }
   const uint64_t total = (uint64_t)nct * n;
   hipLaunchKernelGGL(k_rot_digits, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, ct_in, ct_out, digits,
-                     nct, g);
+                     nct, ginv);
   return hipGetLastError();
 }
 
