@@ -69,7 +69,8 @@ KEY_SEED, GALLERY_SEED, PROBE_SEED, FEATURE_SEED, QUERY_SEED = 201, 301, 401, 10
 def kernel_source_digest():
     """Digest of the single-probe multiply-accumulate kernel's source: the
     k_mac kernel and its load batches, its launcher and the shared modular
-    helpers (a change anywhere else leaves the counter figures valid)."""
+    helpers without the randomness-domain numbers (a change anywhere else
+    leaves the counter figures valid)."""
     csrc = os.path.join(ROOT, "paper_2003_12197_amd", "csrc")
     k = open(os.path.join(csrc, "kernels.hip")).read()
     a = k.index("typedef uint32_t u32x4")
@@ -79,7 +80,8 @@ def kernel_source_digest():
     h = hashlib.sha256()
     h.update(k[a:b].encode())
     h.update(k[c:e].encode())
-    h.update(open(os.path.join(csrc, "hers_common.h"), "rb").read())
+    common = open(os.path.join(csrc, "hers_common.h")).read().splitlines(True)
+    h.update("".join(l for l in common if not l.startswith("#define HERS_DOMAIN_")).encode())
     return h.hexdigest()[:16]
 
 
@@ -267,6 +269,8 @@ def run_two_stage(args, cfg):
     t0 = time.perf_counter()
     sk1, _, _ = ctx1.keygen(KEY_SEED)
     sk2, _, _ = ctx2.keygen(KEY_SEED + 1)
+    ctx1.load_secret_key(sk1)        # the client keeps its keys' transforms
+    ctx2.load_secret_key(sk2)
     ctx2.rotation_keygen(KEY_SEED + 1, W)
     full = synth.gallery_features(FEATURE_SEED, n, D, m)
     g1 = ctx1.encrypt_gallery(torch.from_numpy(np.ascontiguousarray(full[:d1])).to(dev), m, GALLERY_SEED)
@@ -293,13 +297,13 @@ def run_two_stage(args, cfg):
     def step(seed):
         ctx1.encrypt_probe(q1, seed, probe=p1, workspace=ws_p)
         ctx1.search(g1, m, d1, p1, scores=sc1, workspace=ws_s)
-        ctx1.decrypt_scores(sk1, sc1, m, out=out1, workspace=ws_d)
+        ctx1.decrypt_scores(None, sc1, m, out=out1, workspace=ws_d)
         idx, _ = ctx1.topk(out1, m, K)
         cts = np.unique(idx.cpu().numpy() // S)             # client: ciphertexts holding the candidates
         ids = torch.from_numpy(cts).to(dev)
         p2 = ctx2.rerank_encrypt(q2, W, seed + 1, replicate=True)
         ctx2.rerank(items, ids, p2, W, out=rcts[:len(cts)], workspace=ws_r)
-        ctx2.rerank_decrypt(sk2, rcts[:len(cts)], W, out=rsc[:len(cts)], workspace=ws_rd)
+        ctx2.rerank_decrypt(None, rcts[:len(cts)], W, out=rsc[:len(cts)], workspace=ws_rd)
         flat = rsc[:len(cts)].reshape(-1)
         tidx, tval = ctx2.topk(flat, flat.numel(), 10)
         state.update(cts=cts, idx=idx, tidx=tidx, tval=tval)
@@ -445,6 +449,7 @@ def main():
     ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, min(m, 512 * n), 1)   # decryption in rounds of 512 blocks
     for j in range(npr):
         ctx.encrypt_probe(qdev[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
+    ctx.load_secret_key(sk)          # the client keeps its key's transform
     plan = None
     if npr == 1:
         ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 8192 * n), d)
@@ -476,7 +481,7 @@ def main():
             ctx.encrypt_probe(qdev[j], seed + j, probe=probes[j], workspace=ws_p)
         search()
         for j in range(npr):
-            ctx.decrypt_scores(sk, scores[j], m, out=outs[j], workspace=ws_d)
+            ctx.decrypt_scores(None, scores[j], m, out=outs[j], workspace=ws_d)
             hers_gpu._check(ctx.lib, ctx.lib.hers_topk(
                 ctx.handle, hers_gpu._ptr(outs[j]), m, TOPK, hers_gpu._ptr(tk_idx[j * TOPK:]),
                 hers_gpu._ptr(tk_val[j * TOPK:]), hers_gpu._ptr(ws_k), ws_k.numel(), hers_gpu._stream()), "hers_topk")

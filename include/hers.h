@@ -224,7 +224,13 @@ void hers_plan_destroy(hers_plan* plan);
 
 /* ---- decryption (App. B Alg. "HERS Search", client side) ----------------
  * pt = [round(t/q [c0 + c1 s]_q)]_t (Alg. "Decryption"), slot decode, centred
- * into [-t/2, t/2): scores_out_dev int32 [m], item b*n + j from slot j of block b. */
+ * into [-t/2, t/2): scores_out_dev int32 [m], item b*n + j from slot j of block b.
+ * sk_dev uint8 [n], or NULL to use the key of hers_load_secret_key (whose
+ * transform is then not repeated per call); work_dev
+ * hers_workspace_bytes(ctx, 3, m, 1) (blocks in chunks if smaller). */
+/* Keeps the NTT form of a client's secret key in the context (stream-ordered
+ * on `stream`; a later call replaces it). */
+int hers_load_secret_key(hers_ctx* ctx, const uint8_t* sk_dev, void* stream);
 int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev,
                         int64_t m, int32_t* scores_out_dev, void* work_dev, size_t work_bytes,
                         void* stream);
@@ -275,7 +281,8 @@ int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, 
 
 /* Client: decrypts the nsel re-rank ciphertexts and reads every segment's
  * score: scores_out int32 [nsel][n / W] (score of item ids[c] * S + seg at
- * [c][seg]); work_dev hers_workspace_bytes(ctx, 8, nsel, 0). */
+ * [c][seg]); sk_dev as for hers_decrypt_scores (NULL: the loaded key);
+ * work_dev hers_workspace_bytes(ctx, 8, nsel, 0). */
 int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* cts, int32_t nsel, int32_t W,
                         int32_t* scores_out, void* work_dev, size_t work_bytes, void* stream);
 

@@ -43,6 +43,9 @@ struct hers_ctx {
   uint64_t* rk_ntt = nullptr;
   uint64_t* rk_ntt_sh = nullptr;
   int rk_steps = 0;
+  // secret key in NTT form for decryptions without a key argument
+  uint64_t* sk_ntt = nullptr;
+  bool sk_loaded = false;
   hipStream_t side = nullptr;
   hipEvent_t ev_mac = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_free;
@@ -227,6 +230,7 @@ void hers_ctx_destroy(hers_ctx* ctx) {
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->rk_ntt) (void)hipFree(ctx->rk_ntt);
+    if (ctx->sk_ntt) (void)hipFree(ctx->sk_ntt);
     if (ctx->rk_ntt_sh) (void)hipFree(ctx->rk_ntt_sh);
     for (void* p : ctx->allocs) (void)hipFree(p);
   }
@@ -794,7 +798,7 @@ int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, 
 
 int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* cts, int32_t nsel, int32_t W,
                         int32_t* scores_out, void* work_dev, size_t work_bytes, void* stream) {
-  if (!ctx || !sk_dev || !cts || !scores_out) return fail(HERS_EINVAL, "null argument");
+  if (!ctx || !cts || !scores_out) return fail(HERS_EINVAL, "null argument");
   if (int rc = check_w(ctx, W)) return rc;
   if (nsel < 1) return fail(HERS_EINVAL, "need nsel >= 1");
   const HersConsts& C = ctx->host.C;
@@ -1100,20 +1104,33 @@ void hers_plan_destroy(hers_plan* plan) {
   delete plan;
 }
 
+int hers_load_secret_key(hers_ctx* ctx, const uint8_t* sk_dev, void* stream) {
+  if (!ctx || !sk_dev) return fail(HERS_EINVAL, "null argument");
+  const HersConsts& C = ctx->host.C;
+  DeviceGuard g(ctx->device);
+  if (!ctx->sk_ntt && hipMalloc((void**)&ctx->sk_ntt, (size_t)2 * C.k * C.n * 8) != hipSuccess)
+    return fail(HERS_ENOMEM, "hipMalloc of the secret key form failed");
+  TIMED(ctx, "sk_ntt", S(stream), hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, ctx->sk_ntt,
+                                                      ctx->sk_ntt + (size_t)C.k * C.n, S(stream)));
+  ctx->sk_loaded = true;
+  return HERS_OK;
+}
+
 int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* scores_dev, int64_t m,
                         int32_t* scores_out_dev, void* work_dev, size_t work_bytes, void* stream) {
-  if (!ctx || !sk_dev || !scores_dev || !scores_out_dev) return fail(HERS_EINVAL, "null argument");
+  if (!ctx || !scores_dev || !scores_out_dev) return fail(HERS_EINVAL, "null argument");
+  if (!sk_dev && !ctx->sk_loaded) return fail(HERS_EINVAL, "no secret key given or loaded");
   if (m < 1) return fail(HERS_EINVAL, "empty gallery");
   const HersConsts& C = ctx->host.C;
   const int64_t M = (int64_t)hers_blocks(ctx, m);
   const size_t fixed = decrypt_ws_fixed(C), per = decrypt_ws_per_block(C);
   if (!work_dev || work_bytes < fixed + per) return fail(HERS_ESPACE, "workspace too small");
   const int64_t chunk = (int64_t)((work_bytes - fixed) / per);
-  uint64_t* Sn = (uint64_t*)work_dev;
+  uint64_t* Sn = sk_dev ? (uint64_t*)work_dev : ctx->sk_ntt;
   uint64_t* Ssh = Sn + (size_t)C.k * C.n;
   uint64_t* x = (uint64_t*)((char*)work_dev + fixed);
   DeviceGuard g(ctx->device);
-  TIMED(ctx, "sk_ntt", S(stream), hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
+  if (sk_dev) TIMED(ctx, "sk_ntt", S(stream), hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
   for (int64_t lo = 0; lo < M; lo += chunk) {
     const int64_t nb = lo + chunk < M ? chunk : M - lo;
     TIMED(ctx, "dec_mul", S(stream), hers::launch_dec_mul(ctx->T, C.n, C.k, scores_dev, nb, lo, Sn, Ssh, x, S(stream)));

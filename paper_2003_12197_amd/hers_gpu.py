@@ -55,6 +55,7 @@ EXPORTS = {
                                      ctypes.c_size_t, c_vp]),
     "hers_rerank": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_rerank_decrypt": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_load_secret_key": (c_i32, [c_vp, c_vp, c_vp]),
     "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                      ctypes.c_size_t, c_vp]),
     "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
@@ -397,6 +398,10 @@ class Context:
         _check(self.lib, self.lib.hers_profile_read(self.handle, stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
                "hers_profile_read")
         return ms.value, cnt.value
+
+    def load_secret_key(self, sk):
+        """Keep sk's transform in the context; decrypt_scores(None, ...) then uses it."""
+        _check(self.lib, self.lib.hers_load_secret_key(self.handle, _ptr(sk), _stream()), "hers_load_secret_key")
 
     def decrypt_scores(self, sk, scores, m, out=None, workspace=None):
         """int32 [m] decrypted scores (client side)."""

@@ -143,6 +143,15 @@ def test_decrypted_scores_equal_plaintext_inner_products(name, request):
     assert np.array_equal(tail, out[(c.M - 1) * c.op.n:])
 
 
+def test_loaded_secret_key_decrypts_alike(case_r36):
+    """hers_load_secret_key + decryption without a key argument gives the same
+    scores as decryption with the key passed each time."""
+    c = case_r36
+    want = c.ctx.decrypt_scores(c.sk, c.scores, c.m).cpu().numpy()
+    c.ctx.load_secret_key(c.sk)
+    assert np.array_equal(c.ctx.decrypt_scores(None, c.scores, c.m).cpu().numpy(), want)
+
+
 def test_single_prime_config_decrypts_wrongly(case_c1):
     """q of one 54-bit prime: ciphertexts are exact, the noise exceeds Delta/2."""
     c = case_c1
