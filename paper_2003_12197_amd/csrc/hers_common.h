@@ -20,6 +20,7 @@
 #define HC_MAXQ 8      // ciphertext primes
 #define HC_MAXP 32     // exact-product base primes
 #define HC_MAXL 64     // gadget digits (evaluation keys)
+#define HC_MAXW 10     // 64-bit words of the rescale's fixed-point fractions
 
 typedef unsigned __int128 u128;
 
@@ -43,9 +44,13 @@ struct HersConsts {
   uint64_t garner[HC_MAXQ][HC_MAXQ];                 // [i][j]: q_j^-1 mod q_i, j < i
   uint64_t garner_sh[HC_MAXQ][HC_MAXQ];
   uint64_t half_digit[HC_MAXQ];                      // mixed-radix digits of (q-1)/2
-  uint64_t Pmod_q[HC_MAXQ], Pmod_q_sh[HC_MAXQ];      // P mod q_i
-  uint64_t phat_q[HC_MAXP][HC_MAXQ];                 // (P/p_r) mod q_i
-  uint64_t phat_q_sh[HC_MAXP][HC_MAXQ];
+  // rescale constants: t (P/p_r) / q = I_r + phi_r and t P / q = J + psi,
+  // integer parts modulo q_i, fractions in fr_words 64-bit words (little-endian)
+  uint64_t fr_I[HC_MAXP][HC_MAXQ];                   // I_r mod q_i
+  uint64_t fr_J[HC_MAXQ], fr_J_sh[HC_MAXQ];          // J mod q_i
+  uint64_t fr_phi[HC_MAXP][HC_MAXW];
+  uint64_t fr_psi[HC_MAXW];
+  uint32_t fr_words, pad2;
 
   // ---- exact-product base primes p_r
   uint32_t p[HC_MAXP];
@@ -56,8 +61,6 @@ struct HersConsts {
   uint32_t Qw_p[HC_MAXQ][HC_MAXP];                   // (q_0 ... q_{i-1}) mod p_r
   uint32_t Qw_p_sh[HC_MAXQ][HC_MAXP];
   uint32_t qmod_p[HC_MAXP];                          // q mod p_r
-  uint32_t qinv_p[HC_MAXP], qinv_p_sh[HC_MAXP];      // q^-1 mod p_r
-  uint32_t t_p[HC_MAXP], t_p_sh[HC_MAXP];            // t mod p_r
   uint32_t p_r64[HC_MAXP], p_r64_sh[HC_MAXP];        // 2^64 mod p_r
 
   // ---- plaintext prime t
@@ -246,48 +249,63 @@ HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
   return neg ? sub_p(acc, C.qmod_t, t) : acc;
 }
 
-// Exact conversion from base P to base q of an integer Y with |Y| < P/4:
-// y_r = [Y (P/p_r)^-1]_{p_r}; sum_r y_r / p_r = Y/P + gamma, so gamma is the
-// nearest integer to the sum (a quarter of headroom covers the rounding error
-// of the double-precision sum); Y = sum_r y_r (P/p_r) - gamma P.
+// Scale and round of one coefficient (Alg. "Ciphertext Multiplication"):
+// given x_r = X mod p_r of an integer X with |X| < P/4, returns
+// c_i = [round(t X / q)]_q mod q_i.
+// With y_r = [x_r (P/p_r)^-1]_{p_r}, X = sum_r y_r (P/p_r) - gamma P, where
+// gamma is the nearest integer to sum_r y_r / p_r (the quarter of headroom
+// covers the double-precision error).  Hence
+//   t X / q = sum_r y_r (I_r + phi_r) - gamma (J + psi),
+// I_r, J integers and phi_r, psi in [0, 1), and
+//   round(t X / q) = sum_r y_r I_r - gamma J + round(F),  F = sum_r y_r phi_r - gamma psi.
+// F is formed in fixed point with 64 fr_words fraction bits, truncated
+// fractions: the error is below max(sum_r y_r, gamma) 2^-(64 fr_words), less
+// than 1/(2q), while t X / q (denominator q, odd) is at least 1/(2q) away from
+// every half-integer, so the rounding is exact.
 template <int KQ = 0, int KP = 0>
-HD void p_to_q(const HersConsts& C, const uint32_t* y_res, uint64_t* out) {
-  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K;
+HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
+  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = C.fr_words;
   uint32_t y[KP ? KP : HC_MAXP];
   double s = 0.0;
   for (uint32_t r = 0; r < K; ++r) {
-    y[r] = shoup_p(y_res[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
+    y[r] = shoup_p(x[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
     s += (double)y[r] * C.p_inv[r];
   }
   const uint64_t gamma = (uint64_t)__builtin_rint(s);
-  for (uint32_t i = 0; i < k; ++i) {
-    const uint64_t qi = C.q[i];
-    u128 acc = 0;                                   // sum_r y_r (P/p_r mod q_i) < K 2^91
-    for (uint32_t r = 0; r < K; ++r) acc += (u128)y[r] * C.phat_q[r][i];
-    out[i] = sub_q(red128_q(C, acc, i), shoup_q(gamma, C.Pmod_q[i], C.Pmod_q_sh[i], qi), qi);
-  }
-}
-
-// Scale and round of one coefficient (Alg. "Ciphertext Multiplication"):
-// given X mod p_r (|X| < P/4), returns c_i = [round(t X / q)]_q mod q_i.
-// With T the centred representative of t X mod q, t X = q Y + T and |T| < q/2,
-// so Y = round(t X / q) = (t X - T) / q exactly; Y is formed in base P (q is
-// invertible there) and converted to base q.
-template <int KQ = 0, int KP = 0>
-HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
-  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K;
-  uint64_t xq[KQ ? KQ : HC_MAXQ], a[KQ ? KQ : HC_MAXQ];
-  p_to_q<KQ, KP>(C, x, xq);                           // X mod q_i
-  for (uint32_t i = 0; i < k; ++i) xq[i] = shoup_q(xq[i], C.q_t[i], C.q_t_sh[i], C.q[i]);  // t X mod q_i
-  const bool neg = garner_digits<KQ>(C, xq, a);       // T
-  uint32_t yr[KP ? KP : HC_MAXP];
+  // F in fixed point: f[0 .. W-1] fraction words, f[W] the integer part (two's complement)
+  uint64_t f[HC_MAXW + 1];
+  for (uint32_t w = 0; w <= W; ++w) f[w] = 0;
   for (uint32_t r = 0; r < K; ++r) {
-    const uint32_t p = C.p[r];
-    uint32_t tx = shoup_p(x[r], C.t_p[r], C.t_p_sh[r], p);
-    uint32_t T = mixed_to_p<KQ>(C, a, neg, r);
-    yr[r] = shoup_p(sub_p(tx, T, p), C.qinv_p[r], C.qinv_p_sh[r], p);
+    uint64_t carry = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+      const u128 v = (u128)y[r] * C.fr_phi[r][w] + f[w] + carry;
+      f[w] = (uint64_t)v;
+      carry = (uint64_t)(v >> 64);
+    }
+    f[W] += carry;
   }
-  p_to_q<KQ, KP>(C, yr, out);
+  {
+    uint64_t carry = 0, borrow = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+      const u128 g = (u128)gamma * C.fr_psi[w] + carry;
+      carry = (uint64_t)(g >> 64);
+      const uint64_t gl = (uint64_t)g;
+      const uint64_t d = f[w] - gl - borrow;
+      borrow = (f[w] < gl || (f[w] == gl && borrow)) ? 1 : 0;
+      f[w] = d;
+    }
+    f[W] -= carry + borrow;
+  }
+  const int64_t rf = (int64_t)f[W] + (int64_t)(f[W - 1] >> 63);   // round(F)
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint64_t q = C.q[i];
+    u128 acc = 0;                                   // sum_r y_r (I_r mod q_i) < K 2^91
+    for (uint32_t r = 0; r < K; ++r) acc += (u128)y[r] * C.fr_I[r][i];
+    uint64_t v = sub_q(red128_q(C, acc, i), shoup_q(gamma, C.fr_J[i], C.fr_J_sh[i], q), q);
+    const uint64_t ra = red_q(rf >= 0 ? (uint64_t)rf : (uint64_t)(-rf), q, C.q_mu64[i]);
+    const uint64_t rm = rf >= 0 ? ra : (ra ? q - ra : 0);
+    out[i] = add_q(v, rm, q);
+  }
 }
 
 // Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,

@@ -147,7 +147,7 @@ k_ct_add(DevTabs T, uint64_t* __restrict__ dst, const uint64_t* __restrict__ fre
   const uint32_t n = C.n, k = C.k;
   const uint64_t w = (uint64_t)blockIdx.x * WG + threadIdx.x;
   if (w >= (uint64_t)nct * 2 * k * n) return;
-  const uint32_t rho = (uint32_t)((w / n) % k);
+  const uint32_t rho = (uint32_t)((w >> C.logn) % k);
   const int64_t b = block0 + (int64_t)(w / ((uint64_t)2 * k * n) / d);
   dst[w] = b >= first_empty_block ? fresh[w] : add_q(dst[w], fresh[w], C.q[rho]);
 }
@@ -227,7 +227,7 @@ k_lift(DevTabs T, const uint64_t* __restrict__ canon, uint32_t nct, int32_t d, i
   const uint32_t n = C.n, k = C.k, K = C.K;
   const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
   if (idx >= (uint64_t)nct * n) return;
-  const uint32_t c = (uint32_t)(idx / n), j = (uint32_t)(idx % n);
+  const uint32_t c = (uint32_t)(idx >> C.logn), j = (uint32_t)(idx & (n - 1));
   const int64_t b = block0 + c / d;
   const uint32_t i = c % d;
   for (uint32_t poly = 0; poly < 2; ++poly) {
@@ -510,8 +510,8 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   const uint32_t n = C.n, k = C.k, K = C.K, L = C.L;
   const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
   if (idx >= (uint64_t)nblk * 3 * n) return;
-  const uint64_t bj = idx / n;
-  const uint32_t c = (uint32_t)(idx % n);
+  const uint64_t bj = idx >> C.logn;                  // n is a power of two
+  const uint32_t c = (uint32_t)(idx & (n - 1));
   const int64_t bl = (int64_t)(bj / 3);
   const uint32_t j = (uint32_t)(bj % 3);
   uint32_t x[KP ? KP : HC_MAXP];

@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 namespace hers {
 
@@ -106,6 +107,109 @@ static uint32_t bitrev(uint32_t x, uint32_t bits) {
 
 static uint64_t sh64(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 static uint32_t sh32(uint32_t w, uint32_t p) { return (uint32_t)(((uint64_t)w << 32) / p); }
+
+// ---- unsigned multi-word integers for the rescale constants (little-endian
+// 32-bit limbs, no leading zero limbs)
+struct Big {
+  std::vector<uint32_t> w;
+};
+
+static void big_trim(Big& a) {
+  while (!a.w.empty() && !a.w.back()) a.w.pop_back();
+}
+
+static Big big_from(uint64_t v) {
+  Big a;
+  a.w = {(uint32_t)v, (uint32_t)(v >> 32)};
+  big_trim(a);
+  return a;
+}
+
+static Big big_mul(const Big& a, const Big& b) {
+  Big c;
+  c.w.assign(a.w.size() + b.w.size() + 1, 0);
+  for (size_t i = 0; i < a.w.size(); ++i) {
+    uint64_t carry = 0;
+    for (size_t j = 0; j < b.w.size(); ++j) {
+      const uint64_t v = (uint64_t)a.w[i] * b.w[j] + c.w[i + j] + carry;
+      c.w[i + j] = (uint32_t)v;
+      carry = v >> 32;
+    }
+    for (size_t j = i + b.w.size(); carry; ++j) {
+      const uint64_t v = (uint64_t)c.w[j] + carry;
+      c.w[j] = (uint32_t)v;
+      carry = v >> 32;
+    }
+  }
+  big_trim(c);
+  return c;
+}
+
+static size_t big_bits(const Big& a) {
+  return a.w.empty() ? 0 : 32 * (a.w.size() - 1) + (32 - __builtin_clz(a.w.back()));
+}
+
+static bool big_bit(const Big& a, size_t i) { return i / 32 < a.w.size() && ((a.w[i / 32] >> (i % 32)) & 1); }
+
+static Big big_shl(const Big& a, size_t bits) {
+  Big c;
+  c.w.assign(a.w.size() + bits / 32 + 1, 0);
+  for (size_t i = 0; i < a.w.size(); ++i) {
+    const uint64_t v = (uint64_t)a.w[i] << (bits % 32);
+    c.w[i + bits / 32] |= (uint32_t)v;
+    c.w[i + bits / 32 + 1] |= (uint32_t)(v >> 32);
+  }
+  big_trim(c);
+  return c;
+}
+
+static int big_cmp(const Big& a, const Big& b) {
+  if (a.w.size() != b.w.size()) return a.w.size() < b.w.size() ? -1 : 1;
+  for (size_t i = a.w.size(); i-- > 0;)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+  return 0;
+}
+
+static void big_sub_in(Big& a, const Big& b) {   // a -= b, a >= b
+  int64_t borrow = 0;
+  for (size_t i = 0; i < a.w.size(); ++i) {
+    int64_t v = (int64_t)a.w[i] - (i < b.w.size() ? (int64_t)b.w[i] : 0) - borrow;
+    borrow = v < 0;
+    a.w[i] = (uint32_t)(v + (borrow << 32));
+  }
+  big_trim(a);
+}
+
+// quotient and remainder of a / b (b > 0), one bit at a time
+static void big_divmod(const Big& a, const Big& b, Big* q, Big* r) {
+  Big quo, rem;
+  quo.w.assign(a.w.size() + 1, 0);
+  for (size_t i = big_bits(a); i-- > 0;) {
+    rem = big_shl(rem, 1);
+    if (big_bit(a, i)) {
+      if (rem.w.empty()) rem.w.push_back(0);
+      rem.w[0] |= 1;
+    }
+    if (big_cmp(rem, b) >= 0) {
+      big_sub_in(rem, b);
+      quo.w[i / 32] |= 1u << (i % 32);
+    }
+  }
+  big_trim(quo);
+  *q = quo;
+  *r = rem;
+}
+
+static uint64_t big_mod_small(const Big& a, uint64_t m) {
+  u128 v = 0;
+  for (size_t i = a.w.size(); i-- > 0;) v = ((v << 32) | a.w[i]) % m;
+  return (uint64_t)v;
+}
+
+static uint64_t big_word64(const Big& a, size_t w) {
+  const uint64_t lo = 2 * w < a.w.size() ? a.w[2 * w] : 0, hi = 2 * w + 1 < a.w.size() ? a.w[2 * w + 1] : 0;
+  return lo | (hi << 32);
+}
 
 std::string resolve(const hers_params& prm, hers_info* info) {
   std::memset(info, 0, sizeof(*info));
@@ -240,25 +344,33 @@ std::string precompute(const hers_params& prm, HostTables* T) {
       qm = mulmod(qm, info.q[i] % p, p);
     }
     C.qmod_p[r] = (uint32_t)qm;
-    C.qinv_p[r] = (uint32_t)invmod(qm, p);
-    C.qinv_p_sh[r] = sh32(C.qinv_p[r], p);
-    C.t_p[r] = (uint32_t)(t % p);
-    C.t_p_sh[r] = sh32(C.t_p[r], p);
     C.p_r64[r] = (uint32_t)(((u128)1 << 64) % p);
     C.p_r64_sh[r] = sh32(C.p_r64[r], p);
   }
-  for (uint32_t i = 0; i < k; ++i) {
-    const uint64_t q = info.q[i];
-    uint64_t Pm = 1;
-    for (uint32_t r = 0; r < K; ++r) Pm = mulmod(Pm, info.aux[r] % q, q);
-    C.Pmod_q[i] = Pm;
-    C.Pmod_q_sh[i] = sh64(Pm, q);
+  // rescale constants: t (P/p_r) / q = I_r + phi_r, t P / q = J + psi, fractions
+  // in W words with 64 W > log2(K 2^30) + 1 + log2 q + 2 (exactness margin)
+  {
+    const double need = std::log2((double)K) + 30.0 + 1.0 + info.log2_q + 2.0;
+    const uint32_t W = (uint32_t)std::ceil(need / 64.0);
+    if (W > HC_MAXW) return "rescale fractions would need too many words";
+    C.fr_words = W;
+    Big Q = big_from(1), P = big_from(1);
+    for (uint32_t i = 0; i < k; ++i) Q = big_mul(Q, big_from(info.q[i]));
+    for (uint32_t r = 0; r < K; ++r) P = big_mul(P, big_from(info.aux[r]));
+    auto split = [&](const Big& A, uint64_t* Imod, uint64_t* frac) {
+      Big I, R, F, R2;
+      big_divmod(A, Q, &I, &R);
+      for (uint32_t i = 0; i < k; ++i) Imod[i] = big_mod_small(I, info.q[i]);
+      big_divmod(big_shl(R, 64 * W), Q, &F, &R2);
+      for (uint32_t w = 0; w < W; ++w) frac[w] = big_word64(F, w);
+    };
     for (uint32_t r = 0; r < K; ++r) {
-      uint64_t ph = 1;
-      for (uint32_t s = 0; s < K; ++s) if (s != r) ph = mulmod(ph, info.aux[s] % q, q);
-      C.phat_q[r][i] = ph;
-      C.phat_q_sh[r][i] = sh64(ph, q);
+      Big Pr = big_from(t);
+      for (uint32_t s = 0; s < K; ++s) if (s != r) Pr = big_mul(Pr, big_from(info.aux[s]));
+      split(Pr, C.fr_I[r], C.fr_phi[r]);
     }
+    split(big_mul(P, big_from(t)), C.fr_J, C.fr_psi);
+    for (uint32_t i = 0; i < k; ++i) C.fr_J_sh[i] = sh64(C.fr_J[i], info.q[i]);
   }
 
   // ---- plaintext prime
