@@ -85,9 +85,19 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+MAC_SCHEDULES = {0: (1, 2, 0), 1: (2, 2, 0), 2: (1, 4, 0), 3: (2, 4, 0), 4: (1, 2, 1), 5: (2, 2, 1), 6: (1, 4, 1),
+                 7: (2, 4, 1), 8: (4, 1, 1), 9: (4, 2, 1), 10: (2, 1, 1), 11: (1, 1, 1)}
+
+
+def mac_kernel_name(variant):
+    nb, u, nt = MAC_SCHEDULES[variant]
+    return "k_mac<%d, %d, %s>" % (nb, u, "true" if nt else "false")
+
+
+def measured_traffic(workload, variant=None):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, or None when missing or taken on different kernel sources."""
+    counter summary, or None when missing, taken on different kernel sources
+    or for another multiply-accumulate schedule than `variant`."""
     path = os.path.join(ROOT, "profiles", "k_mac_%s_pmc.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -95,6 +105,8 @@ def measured_traffic(workload):
     m = re.search(r"TRAFFIC_BYTES_PER_LAUNCH=(\d+)", text)
     s = re.search(r"KERNEL_SOURCE_DIGEST=(\w+)", text)
     if not m or not s or s.group(1) != kernel_source_digest():
+        return None
+    if variant is not None and not text.startswith("rocprofv3 counter passes for %s " % mac_kernel_name(variant)):
         return None
     return int(m.group(1))
 
@@ -569,7 +581,8 @@ def main():
         per_launch = (M * K * d * 2 * n * 4 + M * 3 * K * n * 4) / launches_per_step + K * d * 2 * n * 4
         achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload), "kernel": "k_mac",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, mac_variant),
+                "kernel": mac_kernel_name(mac_variant),
                 "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
     else:
         # algorithmic 64-bit multiply-adds: 4 per (probe, block, dimension, base prime, slot)

@@ -312,7 +312,8 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
 
 /* Autotuner: times every "mac_variant" schedule on the caller's gallery and
  * probe (reps launches each, over as many leading blocks as the search
- * workspace holds), then the search epilogue's transforms under NTT pass
+ * workspace holds; another schedule replaces the current one only if 3%
+ * faster), then the search epilogue's transforms under NTT pass
  * radix 4, 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not
  * NULL -- whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16
  * (chunks of at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule

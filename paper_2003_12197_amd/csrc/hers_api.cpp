@@ -829,7 +829,7 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  float best = 0.f;
+  float best = 0.f, cur_ms = 0.f;
   int best_v = ctx->mac_variant;
   int rc = HERS_OK;
   for (int v = 0; v < 12 && rc == HERS_OK; ++v) {
@@ -843,7 +843,11 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
     if (v == 0 || ms < best) { best = ms; best_v = v; }
+    if (v == ctx->mac_variant) cur_ms = ms;
   }
+  // keep the current schedule unless another is clearly faster (timing noise
+  // between near-equal schedules would only make runs disagree)
+  if (rc == HERS_OK && best > 0.97f * cur_ms) best_v = ctx->mac_variant;
   // NTT pass radix: time the search epilogue's transforms under radix 4, 8, 16:
   // inverse NTTs of the accumulators, then one block's relinearization (digit
   // NTTs, key products, inverse NTTs) writing into the accumulator area, which
