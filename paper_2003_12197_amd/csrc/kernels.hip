@@ -12,6 +12,11 @@
 #include "ntt.h"
 
 #define WG 256
+// wider workgroups for kernels launched with few workgroups (one per probe
+// ciphertext or block): more waves per CU hide the latency of their
+// element-wise phases (k_encrypt needs ~133 VGPRs, so at most 512 lanes)
+#define WG_ENC 512
+#define WG_DEC 1024
 
 extern "C" __global__ void __launch_bounds__(WG)
 k_keygen(DevTabs T, uint64_t seed, uint8_t* __restrict__ sk, uint64_t* __restrict__ pk,
@@ -152,7 +157,7 @@ k_ct_add(DevTabs T, uint64_t* __restrict__ dst, const uint64_t* __restrict__ fre
   dst[w] = b >= first_empty_block ? fresh[w] : add_q(dst[w], fresh[w], C.q[rho]);
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+extern "C" __global__ void __launch_bounds__(WG_ENC)
 k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict__ query,
           int32_t d, int64_t block0, uint64_t seed, uint32_t domain, uint64_t* __restrict__ canon) {
   // Alg. "Encryption" for ciphertext c (gallery: c = b_local d + i, or probe
@@ -168,21 +173,21 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   uint64_t* U = lds64;
   uint64_t* V = lds64 + padded_len(n);
   uint64_t* W = V;                      // n/64 words of u, consumed before V is written
-  for (uint32_t bk = tid; bk < n / 256; bk += WG) {
+  for (uint32_t bk = tid; bk < n / 256; bk += WG_ENC) {
     Philox4 b = philox4x64_10(bk, o0, o1, 0, seed, domain);
     for (int s = 0; s < 4; ++s) W[4 * bk + s] = b.v[s];
   }
   __syncthreads();
-  for (uint32_t j = tid; j < n; j += WG) U[PADX(j)] = (W[j >> 6] >> (j & 63)) & 1;
+  for (uint32_t j = tid; j < n; j += WG_ENC) U[PADX(j)] = (W[j >> 6] >> (j & 63)) & 1;
   __syncthreads();
   const uint64_t* tw = T.qtw + (size_t)rho * n;
   const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
-  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG, T.ntt_r);
+  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG_ENC, T.ntt_r);
   const uint64_t* pk0 = T.pk_ntt + (size_t)rho * n;
   const uint64_t* pk0s = T.pk_ntt_sh + (size_t)rho * n;
   const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
   const uint64_t* pk1s = T.pk_ntt_sh + ((size_t)k + rho) * n;
-  for (uint32_t j = tid; j < n; j += WG) {
+  for (uint32_t j = tid; j < n; j += WG_ENC) {
     const uint64_t u = U[PADX(j)];
     V[PADX(j)] = shoup_q(u, pk1[j], pk1s[j], q);
     U[PADX(j)] = shoup_q(u, pk0[j], pk0s[j], q);
@@ -190,8 +195,8 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   __syncthreads();
   const uint64_t* itw = T.qitw + (size_t)rho * n;
   const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
-  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG, T.ntt_r);
-  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG, T.ntt_r);
+  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
+  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
   uint32_t qconst = 0;
   if (query) {
     int64_t z = (int64_t)query[c] % (int64_t)C.t;
@@ -200,7 +205,7 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   }
   uint64_t* o_ct0 = canon + (((size_t)c * 2 + 0) * k + rho) * n;
   uint64_t* o_ct1 = canon + (((size_t)c * 2 + 1) * k + rho) * n;
-  for (uint32_t g4 = tid; g4 < n / 4; g4 += WG) {
+  for (uint32_t g4 = tid; g4 < n / 4; g4 += WG_ENC) {
     Philox4 b1 = philox4x64_10(g4, o0, o1, 1, seed, domain);
     Philox4 b2 = philox4x64_10(g4, o0, o1, 2, seed, domain);
     for (int s = 0; s < 4; ++s) {
@@ -459,6 +464,11 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
         fetch_probe(dc + MB_DC, nd);
       }
       if (active) {
+        // products are below 2^60: after a fold (value < p) 16 more fit in
+        // 64 bits, i.e. a chunk of MB_DC = 8 dimensions for a1 (two per
+        // dimension) and two chunks for a0, a2
+        static_assert(MB_DC == 8, "fold schedule assumes 8 dimensions per chunk");
+        const bool fold02 = ((dc / MB_DC) & 1) || dc + MB_DC >= d;
 #pragma unroll
         for (int u = 0; u < MB_BLOCKS; ++u) {
           if (u >= nblk) break;
@@ -471,11 +481,12 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
               a1[u] += (uint64_t)Q0[v] * g1 + (uint64_t)Q1[v] * g0;
               a2[u] += (uint64_t)Q1[v] * g1;
             }
-            if ((v & 7) == 7) a1[u] = red_p(a1[u], p, mu);
           }
-          a0[u] = red_p(a0[u], p, mu);
           a1[u] = red_p(a1[u], p, mu);
-          a2[u] = red_p(a2[u], p, mu);
+          if (fold02) {
+            a0[u] = red_p(a0[u], p, mu);
+            a2[u] = red_p(a2[u], p, mu);
+          }
         }
       }
     }
@@ -616,7 +627,7 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+extern "C" __global__ void __launch_bounds__(WG_DEC)
 k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t m, int32_t* __restrict__ out) {
   // pt = [round(t x / q)]_t coefficient-wise, then slot j = pt(psi^(2j+1))
   // (forward NTT mod t, read at brv(j)), centred into [-t/2, t/2).
@@ -624,14 +635,14 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, tid = threadIdx.x, t = C.t;
   const int64_t bl = blockIdx.x, b = blk_lo + bl;
-  for (uint32_t j = tid; j < n; j += WG) {
+  for (uint32_t j = tid; j < n; j += WG_DEC) {
     uint64_t v[HC_MAXQ];
     for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
     lds32[PADX(j)] = decrypt_coeff(C, v);
   }
   __syncthreads();
-  ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t s = tid; s < n; s += WG) {
+  ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG_DEC, T.ntt_r);
+  for (uint32_t s = tid; s < n; s += WG_DEC) {
     const int64_t item = b * n + s;
     if (item >= m) continue;
     const uint32_t z = lds32[PADX(bit_reverse(s, C.logn))];
@@ -678,7 +689,7 @@ hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct
                           const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
                           uint64_t* canon, hipStream_t s) {
   size_t lds = lds_bytes(n, 2);
-  hipLaunchKernelGGL(k_encrypt, dim3(nct, k), dim3(WG), lds, s, T, pt, query, d, block0, seed, domain, canon);
+  hipLaunchKernelGGL(k_encrypt, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain, canon);
   return hipGetLastError();
 }
 
@@ -786,7 +797,7 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
 
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG), lds_bytes32(n), s, T, x, blk_lo, m, out);
+  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG_DEC), lds_bytes32(n), s, T, x, blk_lo, m, out);
   return hipGetLastError();
 }
 
