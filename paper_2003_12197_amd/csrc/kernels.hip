@@ -401,7 +401,7 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
 
 __global__ void __launch_bounds__(MB_WG)
 k_mac_multi(DevTabs T, MacBatchArgs A) {
-  __shared__ uint32_t tileG[MB_STAGE];                 // [u][v][poly][64]
+  __shared__ uint32_t tileG[MB_STAGE];                 // [u][v][64][poly]: a slot's two words together
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -453,7 +453,10 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
       const int32_t dn = d - dc < MB_DC ? d - dc : MB_DC;
       __syncthreads();                                 // previous chunk fully consumed
 #pragma unroll
-      for (int e = 0; e < MB_PER_THREAD; ++e) tileG[tid + e * MB_WG] = stage[e];
+      for (int e = 0; e < MB_PER_THREAD; ++e) {
+        const uint32_t w = tid + e * MB_WG;               // staged index: row w >> 6 = 2 uv + poly, slot w & 63
+        tileG[((((w >> 7) << 6) + (w & 63)) << 1) + ((w >> 6) & 1)] = stage[e];
+      }
       __syncthreads();
       uint32_t Q0[MB_DC], Q1[MB_DC];
 #pragma unroll
@@ -472,11 +475,12 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
 #pragma unroll
         for (int u = 0; u < MB_BLOCKS; ++u) {
           if (u >= nblk) break;
-          const uint32_t* t0 = tileG + (uint32_t)u * dn * 128 + lane;
+          const uint2* t0 = (const uint2*)tileG + (uint32_t)u * dn * 64 + lane;
 #pragma unroll
           for (int v = 0; v < MB_DC; ++v) {
             if (v < dn) {
-              const uint64_t g0 = t0[v * 128], g1 = t0[v * 128 + 64];
+              const uint2 gv = t0[v * 64];                  // one 64-bit LDS read: both polynomials
+              const uint64_t g0 = gv.x, g1 = gv.y;
               a0[u] += (uint64_t)Q0[v] * g0;
               a1[u] += (uint64_t)Q0[v] * g1 + (uint64_t)Q1[v] * g0;
               a2[u] += (uint64_t)Q1[v] * g1;
