@@ -306,6 +306,12 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *   "mac_wgs_per_cu" workgroups per compute unit of a hers_search
  *                  multiply-accumulate launch, 0..64 (0 = 8); fewer leave
  *                  room on each CU for an overlapped epilogue.
+ *   "relin_fuse_min_wgs" relinearizations (and rotations) launched with at
+ *                  least this many workgroups (blocks x primes x requests)
+ *                  run as one fused kernel per (block, prime): digit
+ *                  transforms, key products, inverse transforms without the
+ *                  transformed digits in memory; smaller ones as two kernels
+ *                  with more workgroups.  0 = 8 per compute unit; 1 = always.
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);

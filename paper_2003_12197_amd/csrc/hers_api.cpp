@@ -39,6 +39,7 @@ struct hers_ctx {
   // workspace region)
   int overlap_chunks = 0;
   int mac_wgs_per_cu = 0;   // multiply-accumulate grid, workgroups per CU (0 = 8)
+  int64_t relin_fuse_min_wgs = 0;   // fused relinearization from this many workgroups (0 = 8 per CU)
   // rotation keys of the re-rank stage, NTT form [steps][L][2][k][n]
   uint64_t* rk_ntt = nullptr;
   uint64_t* rk_ntt_sh = nullptr;
@@ -335,6 +336,11 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     ctx->mac_wgs_per_cu = (int)value;
     return HERS_OK;
   }
+  if (!std::strcmp(key, "relin_fuse_min_wgs")) {
+    if (value < 0 || value > (1ll << 30)) return fail(HERS_EINVAL, "relin_fuse_min_wgs must be in [0, 2^30]");
+    ctx->relin_fuse_min_wgs = value;
+    return HERS_OK;
+  }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
 }
 
@@ -354,6 +360,10 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   }
   if (!std::strcmp(key, "mac_wgs_per_cu")) {
     *value = ctx->mac_wgs_per_cu;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "relin_fuse_min_wgs")) {
+    *value = ctx->relin_fuse_min_wgs;
     return HERS_OK;
   }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
@@ -542,6 +552,12 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
   return HERS_OK;
 }
 
+// Relinearization launches with at least this many workgroups use the fused
+// kernel (8 per CU); smaller ones split digit transforms and key products.
+static uint32_t fuse_wgs(const hers_ctx* ctx) {
+  return ctx->relin_fuse_min_wgs ? (uint32_t)ctx->relin_fuse_min_wgs : 8u * (uint32_t)ctx->num_cus;
+}
+
 // Workgroups of a multiply-accumulate launch.
 static uint32_t mac_grid(const hers_ctx* ctx) {
   return (uint32_t)(ctx->mac_wgs_per_cu ? ctx->mac_wgs_per_cu : 8) * (uint32_t)ctx->num_cus;
@@ -557,7 +573,8 @@ static int search_epilogue(hers_ctx* ctx, uint32_t* acc, uint64_t* digits, int64
   ScorePtrs sp;
   sp.p[0] = scores_dev;
   TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, s, C.k, C.K));
-  TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, s));
+  TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, s, nullptr, nullptr,
+                                            fuse_wgs(ctx)));
   return HERS_OK;
 }
 
@@ -660,7 +677,8 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, i
                                             ctx->mac_variant, mac_grid(ctx), i, 1));
       TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
       TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, 0, sp, 1, digits, 0, 0, s, C.k, C.K));
-      TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s));
+      TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s, nullptr, nullptr,
+                                                fuse_wgs(ctx)));
       // ... then CipherAdd into the block's score (the first product starts it)
       TIMED(ctx, "ct_add", s, hers::launch_ct_add(ctx->T, C.n, C.k, scores_dev + (size_t)lo * 2 * C.k * C.n, prod,
                                                   (uint32_t)nb, 1, 0, i == 0 ? 0 : INT64_MAX, s));
@@ -786,7 +804,7 @@ int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, 
       sp.p[0] = nxt;
       TIMED(ctx, "rotate", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s,
                                                  ctx->rk_ntt + (size_t)st * key_words,
-                                                 ctx->rk_ntt_sh + (size_t)st * key_words));
+                                                 ctx->rk_ntt_sh + (size_t)st * key_words, fuse_wgs(ctx)));
       std::swap(cur, nxt);
     }
     if (cur != out_cts + (size_t)lo * ct_words)
@@ -864,7 +882,9 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
       hipError_t e = hipEventRecord(e0, S(stream));
       for (int r = 0; r < reps && e == hipSuccess; ++r) {
         e = hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)hi * 3 * C.K, 1, 1, S(stream));
-        if (e == hipSuccess) e = hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, 1, 0, sp, 1, 0, S(stream));
+        if (e == hipSuccess)
+          e = hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, 1, 0, sp, 1, 0, S(stream), nullptr, nullptr,
+                                 fuse_wgs(ctx));
       }
       if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1033,7 +1053,8 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         for (uint32_t j = 0; j < nr; ++j) sp.p[j] = scores[g.reqs[j0 + j]];
         TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
         TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s, C.k, C.K));
-        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, dig, hi - lo, lo, sp, nr, ds, s));
+        TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, dig, hi - lo, lo, sp, nr, ds, s, nullptr,
+                                                  nullptr, fuse_wgs(ctx)));
       }
     }
   }

@@ -70,7 +70,8 @@ hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64
                           uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
                         int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s,
-                        const uint64_t* key = nullptr, const uint64_t* key_sh = nullptr);
+                        const uint64_t* key = nullptr, const uint64_t* key_sh = nullptr,
+                        uint32_t fuse_min_wgs = 2048);
 // two-stage search, second stage (rerank.hip)
 hipError_t launch_encode_packed(const DevTabs& T, uint32_t n, const int32_t* feats, int64_t ld, int64_t count,
                                 int32_t D, int32_t W, int replicate, uint32_t nct, uint32_t* pt, hipStream_t s);

@@ -592,6 +592,69 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], lds64[PADX(j)], q);
 }
 
+// Fused relinearization / key switching: one workgroup per (block, residue
+// sigma, request) of n / RL_PER lanes, each owning RL_PER coefficients.  For
+// every gadget digit the digit polynomial mod q_sigma is transformed in LDS
+// and multiplied into both key components, accumulated in registers; then
+// the two sums are transformed back and added to c0, c1.  Same result as the
+// digit transforms of k_ntt_q followed by k_relin_acc, without writing the
+// transformed digits to memory.
+#define RL_PER 16
+#define RL_UNROLL 16  // full unroll of the per-lane loops: the accumulators stay in registers
+
+extern "C" __global__ void __launch_bounds__(512)
+k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
+              const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t bl = blockIdx.x, b = blk_lo + bl;
+  const uint32_t sg = blockIdx.y;
+  const uint64_t q = C.q[sg];
+  const ModQ mq{q};
+  const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
+  const uint64_t* tw = T.qtw + (size_t)sg * n;
+  const uint64_t* twsh = T.qtw_sh + (size_t)sg * n;
+  uint64_t acc0[RL_PER], acc1[RL_PER];
+#pragma unroll RL_UNROLL
+  for (uint32_t e = 0; e < RL_PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
+  for (uint32_t g = 0; g < L; ++g) {
+    const uint64_t* dg = digits + ((size_t)g * k + sg) * n;
+    __syncthreads();                                    // previous digit's products read
+#pragma unroll RL_UNROLL
+    for (uint32_t e = 0; e < RL_PER; ++e)
+      if (tid + e * nthr < n) lds64[PADX(tid + e * nthr)] = dg[tid + e * nthr];
+    __syncthreads();
+    ntt_forward16(lds64, tw, twsh, mq, n, C.logn, tid, nthr, T.ntt_r);
+    const size_t k0 = (((size_t)g * 2 + 0) * k + sg) * n, k1 = (((size_t)g * 2 + 1) * k + sg) * n;
+#pragma unroll RL_UNROLL
+    for (uint32_t e = 0; e < RL_PER; ++e) {
+      const uint32_t j = tid + e * nthr;
+      if (j >= n) break;                                // never on the GPU: n / RL_PER lanes
+      const uint64_t D = lds64[PADX(j)];
+      acc0[e] = add_q(acc0[e], shoup_q(D, key[k0 + j], key_sh[k0 + j], q), q);
+      acc1[e] = add_q(acc1[e], shoup_q(D, key[k1 + j], key_sh[k1 + j], q), q);
+    }
+  }
+  const uint64_t* itw = T.qitw + (size_t)sg * n;
+  const uint64_t* itwsh = T.qitw_sh + (size_t)sg * n;
+  for (uint32_t comp = 0; comp < 2; ++comp) {
+    __syncthreads();
+#pragma unroll RL_UNROLL
+    for (uint32_t e = 0; e < RL_PER; ++e)
+      if (tid + e * nthr < n) lds64[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
+    __syncthreads();
+    ntt_inverse16(lds64, itw, itwsh, C.q_ninv[sg], C.q_ninv_sh[sg], mq, n, C.logn, tid, nthr, T.ntt_r);
+    uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
+#pragma unroll RL_UNROLL
+    for (uint32_t e = 0; e < RL_PER; ++e) {
+      const uint32_t j = tid + e * nthr;
+      if (j >= n) break;
+      dst[j] = add_q(dst[j], lds64[PADX(j)], q);
+    }
+  }
+}
+
 extern "C" __global__ void __launch_bounds__(WG)
 k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, uint64_t* __restrict__ Ssh) {
   // NTT of the secret key mod q_sigma with Shoup companions (decryption).
@@ -775,9 +838,20 @@ hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64
 
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
                         int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s,
-                        const uint64_t* key, const uint64_t* key_sh) {
+                        const uint64_t* key, const uint64_t* key_sh, uint32_t fuse_min_wgs) {
   if (!key) { key = T.rlk_ntt; key_sh = T.rlk_ntt_sh; }
-  // digit NTTs (L k per block), then key products and inverse NTTs (2 k per block)
+  if ((uint64_t)nblk * k * nreq >= (uint64_t)fuse_min_wgs) {
+    // many workgroups: one per (block, residue, request) does the digit
+    // transforms, key products and both inverse transforms (no transformed
+    // digits in memory)
+    const uint32_t lanes = n / RL_PER;                 // n >= 256: at least 16 lanes
+    hipLaunchKernelGGL(k_relin_fused, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T, digits,
+                       blk_lo, SP, dig_stride, key, key_sh);
+    return hipGetLastError();
+  }
+  // few workgroups: the digit transforms (L k per block), then key products
+  // and inverse transforms (2 k per block), as separate launches with more
+  // workgroups each
   hipLaunchKernelGGL(k_ntt_q, dim3((uint32_t)(nblk * L * k), nreq), dim3(WG), lds_bytes(n, 1), s, T, digits,
                      dig_stride);
   hipError_t e = hipGetLastError();

@@ -333,6 +333,10 @@ def test_schedules_and_radices_give_same_bits(case_r36):
             for v in range(12):
                 ctx.set_option("mac_variant", v)
                 assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), (rl, v)
+        for fuse in (1, 1 << 30):                         # fused relinearization, then always two kernels
+            ctx.set_option("relin_fuse_min_wgs", fuse)
+            assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), fuse
+        ctx.set_option("relin_fuse_min_wgs", 0)
         chosen = ctx.autotune(c.gallery, c.m, c.d, c.probe, reps=1, scores=ctx.new_scores(c.m))
         assert 0 <= chosen < 12 and 2 <= ctx.get_option("ntt_radix_log2") <= 4
         assert ctx.get_option("overlap_chunks") == 1     # 3 blocks: no chunking worth timing
@@ -342,6 +346,7 @@ def test_schedules_and_radices_give_same_bits(case_r36):
         ctx.set_option("mac_variant", 8)
         ctx.set_option("overlap_chunks", 0)
         ctx.set_option("mac_wgs_per_cu", 0)
+        ctx.set_option("relin_fuse_min_wgs", 0)
 
 
 def test_topk_of_decrypted_scores(case_r36, gpu_lib):

@@ -76,7 +76,8 @@ def test_rerank_bit_exact_and_scores(rr):
     ork = rerank.rotation_keygen(op, 41, W)
     one = torch.empty(int(ctx.lib.hers_workspace_bytes(ctx.handle, 7, 1, 0)), dtype=torch.uint8, device=ctx.device)
     want = {3: rerank.rerank_ct(op, rr["orlk"], ork, oprobe, oitems[3], W)}
-    for ws in (None, one):
+    for ws, fuse in ((None, 1), (one, 0)):                  # fused key switching, then the default choice
+        ctx.set_option("relin_fuse_min_wgs", fuse)
         out = ctx.rerank(rr["items"], ids, probe, W, workspace=ws)
         got = out.cpu().numpy()
         assert np.array_equal(got[0, 0], res(want[3][0], op.q_primes))
@@ -90,6 +91,7 @@ def test_rerank_bit_exact_and_scores(rr):
             if c < 4:
                 exp[: hi - lo] = plain[lo:hi]
             assert np.array_equal(sc[j], exp), (j, c)
+    ctx.set_option("relin_fuse_min_wgs", 0)
 
 
 def test_two_stage_pipeline_full_size(gpu_lib):
