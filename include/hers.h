@@ -311,7 +311,8 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  run as one fused kernel per (block, prime): digit
  *                  transforms, key products, inverse transforms without the
  *                  transformed digits in memory; smaller ones as two kernels
- *                  with more workgroups.  0 = 8 per compute unit; 1 = always.
+ *                  with more workgroups.  0 = 8 per compute unit at
+ *                  n >= 8192, never below; 1 = always.
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);

@@ -553,9 +553,12 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
 }
 
 // Relinearization launches with at least this many workgroups use the fused
-// kernel (8 per CU); smaller ones split digit transforms and key products.
+// kernel.  Default: 8 per CU at n >= 8192 (measured faster there: each
+// transformed digit saved is 64 KB); at smaller n the two-kernel form, whose
+// launches keep more waves per CU, measured faster at every size.
 static uint32_t fuse_wgs(const hers_ctx* ctx) {
-  return ctx->relin_fuse_min_wgs ? (uint32_t)ctx->relin_fuse_min_wgs : 8u * (uint32_t)ctx->num_cus;
+  if (ctx->relin_fuse_min_wgs) return (uint32_t)ctx->relin_fuse_min_wgs;
+  return ctx->host.C.n >= 8192 ? 8u * (uint32_t)ctx->num_cus : 0xffffffffu;
 }
 
 // Workgroups of a multiply-accumulate launch.
