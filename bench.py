@@ -455,7 +455,22 @@ def main():
     qdev = [torch.from_numpy(q).to(dev) for q, _ in queries]
     probes = [torch.empty(int(ctx.lib.hers_probe_words(ctx.handle, d)), dtype=torch.int32, device=dev)
               for _ in range(npr)]
-    scores = [ctx.new_scores(m) for _ in range(npr)]
+    # A batch whose score ciphertexts (npr x blocks x 2 x k x n words) do not
+    # fit beside the gallery runs as consecutive block ranges of the gallery,
+    # each a captured batch over all probes writing the same score buffers, so
+    # the gallery is still read once per step.
+    blk_words = int(ctx.lib.hers_gallery_words(ctx.handle, n, d))
+    slices = [(0, M)]
+    if npr > 1:
+        free = torch.cuda.mem_get_info()[0]
+        per_block = npr * 2 * ctx.k * n * 8
+        fit = max(1, (free - npr * m * 4 - (12 << 30)) // per_block)
+        nsl = -(-M // fit)
+        size = -(-M // nsl)
+        slices = [(b, min(M, b + size)) for b in range(0, M, size)]
+    span = max(hi - lo for lo, hi in slices)
+    m_of = lambda lo, hi: min(m, hi * n) - lo * n
+    scores = [ctx.new_scores(m if len(slices) == 1 else span * n) for _ in range(npr)]
     outs = [torch.empty(m, dtype=torch.int32, device=dev) for _ in range(npr)]
     ws_p = ctx.workspace(hers_gpu.OP_ENCRYPT_PROBE, 0, d)
     ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, min(m, 512 * n), 1)   # decryption in rounds of 512 blocks
@@ -475,13 +490,16 @@ def main():
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
-        rounds = max(8, min(M, (8 << 30) // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
-        ws_s = ctx.batch_workspace([m] * npr, blocks_per_round=rounds)
+        rounds = max(8, min(span, (8 << 30) // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
+        ws_s = ctx.batch_workspace([span * n] * npr, blocks_per_round=rounds)
         mac_variant = None
-        plan = ctx.plan([gallery] * npr, [m] * npr, [d] * npr, probes, scores, ws_s)
-        search = plan.launch
+        gal_of = lambda lo, hi: gallery[lo * blk_words:hi * blk_words]
+        plans = [ctx.plan([gal_of(lo, hi)] * npr, [m_of(lo, hi)] * npr, [d] * npr, probes, scores, ws_s)
+                 for lo, hi in slices]
+        plan = plans[0]
         dominant = "mac_multi"
-        log("captured the %d-probe batch as a HIP graph (rounds of %d blocks)" % (npr, rounds))
+        log("captured the %d-probe batch as %d HIP graph(s) over gallery block ranges of <= %d blocks "
+            "(rounds of %d blocks)" % (npr, len(plans), span, rounds))
 
     TOPK = 10
     tk_idx = torch.empty(npr * TOPK, dtype=torch.int64, device=dev)
@@ -491,9 +509,17 @@ def main():
     def step(seed):
         for j in range(npr):
             ctx.encrypt_probe(qdev[j], seed + j, probe=probes[j], workspace=ws_p)
-        search()
+        if plan is None:
+            search()
+            for j in range(npr):
+                ctx.decrypt_scores(None, scores[j], m, out=outs[j], workspace=ws_d)
+        else:
+            for (lo, hi), pl in zip(slices, plans):
+                pl.launch()
+                for j in range(npr):
+                    ctx.decrypt_scores(None, scores[j], m_of(lo, hi), out=outs[j][lo * n:lo * n + m_of(lo, hi)],
+                                       workspace=ws_d)
         for j in range(npr):
-            ctx.decrypt_scores(None, scores[j], m, out=outs[j], workspace=ws_d)
             hers_gpu._check(ctx.lib, ctx.lib.hers_topk(
                 ctx.handle, hers_gpu._ptr(outs[j]), m, TOPK, hers_gpu._ptr(tk_idx[j * TOPK:]),
                 hers_gpu._ptr(tk_val[j * TOPK:]), hers_gpu._ptr(ws_k), ws_k.numel(), hers_gpu._stream()), "hers_topk")
@@ -522,7 +548,9 @@ def main():
     if plan is not None:
         # graph replays carry no per-kernel events: time the batch's kernels in one eager run
         ctx.profile_enable(True)
-        ctx.search_batch([gallery] * npr, [m] * npr, [d] * npr, probes, scores=scores, workspace=ws_s)
+        for lo, hi in slices:
+            ctx.search_batch([gal_of(lo, hi)] * npr, [m_of(lo, hi)] * npr, [d] * npr, probes, scores=scores,
+                             workspace=ws_s)
         torch.cuda.synchronize()
         for st in ("mac", "mac_multi", "intt_acc", "rescale", "relin"):
             ms_, cnt_ = ctx.profile_read(st)
@@ -617,7 +645,7 @@ def main():
                    "mac_schedule": mac_variant, "ntt_radix": 1 << ctx.get_option("ntt_radix_log2"),
                    "overlap_chunks": ctx.get_option("overlap_chunks"),
                    "mac_wgs_per_cu": ctx.get_option("mac_wgs_per_cu") or 8,
-                   "hip_graph": plan is not None},
+                   "hip_graph": plan is not None, "gallery_ranges_per_step": len(slices)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},

@@ -575,7 +575,8 @@ static int search_epilogue(hers_ctx* ctx, uint32_t* acc, uint64_t* digits, int64
   TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
   ScorePtrs sp;
   sp.p[0] = scores_dev;
-  TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, s, C.k, C.K));
+  TIMED(ctx, "rescale", s,
+        hers::launch_rescale(ctx->T, C.n, acc, nb, lo, sp, 1, digits, 0, 0, s, C.k, C.K, C.fr_words));
   TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, lo, sp, 1, 0, s, nullptr, nullptr,
                                             fuse_wgs(ctx)));
   return HERS_OK;
@@ -679,7 +680,8 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, i
       TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s,
                                             ctx->mac_variant, mac_grid(ctx), i, 1));
       TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
-      TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, nb, 0, sp, 1, digits, 0, 0, s, C.k, C.K));
+      TIMED(ctx, "rescale", s,
+            hers::launch_rescale(ctx->T, C.n, acc, nb, 0, sp, 1, digits, 0, 0, s, C.k, C.K, C.fr_words));
       TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s, nullptr, nullptr,
                                                 fuse_wgs(ctx)));
       // ... then CipherAdd into the block's score (the first product starts it)
@@ -1055,7 +1057,8 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         ScorePtrs sp;
         for (uint32_t j = 0; j < nr; ++j) sp.p[j] = scores[g.reqs[j0 + j]];
         TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
-        TIMED(ctx, "rescale", s, hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s, C.k, C.K));
+        TIMED(ctx, "rescale", s,
+              hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s, C.k, C.K, C.fr_words));
         TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, dig, hi - lo, lo, sp, nr, ds, s, nullptr,
                                                   nullptr, fuse_wgs(ctx)));
       }

@@ -262,9 +262,11 @@ HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
 // fractions: the error is below max(sum_r y_r, gamma) 2^-(64 fr_words), less
 // than 1/(2q), while t X / q (denominator q, odd) is at least 1/(2q) away from
 // every half-integer, so the rounding is exact.
-template <int KQ = 0, int KP = 0>
+// KQ, KP, FW fix k, K and fr_words at compile time (0 = read from C), so
+// the fixed-point words stay in statically indexed registers.
+template <int KQ = 0, int KP = 0, int FW = 0>
 HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
-  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = C.fr_words;
+  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = FW ? FW : C.fr_words;
   uint32_t y[KP ? KP : HC_MAXP];
   double s = 0.0;
   for (uint32_t r = 0; r < K; ++r) {
@@ -273,7 +275,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   }
   const uint64_t gamma = (uint64_t)__builtin_rint(s);
   // F in fixed point: f[0 .. W-1] fraction words, f[W] the integer part (two's complement)
-  uint64_t f[HC_MAXW + 1];
+  uint64_t f[(FW ? FW : HC_MAXW) + 1];
   for (uint32_t w = 0; w <= W; ++w) f[w] = 0;
   for (uint32_t r = 0; r < K; ++r) {
     uint64_t carry = 0;

@@ -67,7 +67,7 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
                       uint32_t target_wgs = 0, int32_t dim0 = 0, int32_t dcount = 0);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
-                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K);
+                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K, uint32_t W);
 hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t* digits, int64_t nblk,
                         int64_t blk_lo, const ScorePtrs& SP, uint32_t nreq, uint64_t dig_stride, hipStream_t s,
                         const uint64_t* key = nullptr, const uint64_t* key_sh = nullptr,

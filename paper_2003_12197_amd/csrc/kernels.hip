@@ -509,7 +509,7 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   }
 }
 
-template <int KQ, int KP>
+template <int KQ, int KP, int FW>
 __global__ void __launch_bounds__(WG)
 k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_lo, ScorePtrs SP,
           uint64_t* __restrict__ digits_b, uint64_t acc_stride, uint64_t dig_stride) {
@@ -532,18 +532,22 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   uint32_t x[KP ? KP : HC_MAXP];
   for (uint32_t r = 0; r < (KP ? KP : K); ++r) x[r] = X[(bj * K + r) * n + c];
   uint64_t out[KQ ? KQ : HC_MAXQ];
-  scale_round_coeff<KQ, KP>(C, x, out);
+  scale_round_coeff<KQ, KP, FW>(C, x, out);
   const int64_t b = blk_lo + bl;
   if (j < 2) {
     for (uint32_t i = 0; i < k; ++i) scores[(((size_t)b * 2 + j) * k + i) * n + c] = out[i];
     return;
   }
-  for (uint32_t g = 0; g < L; ++g) {
-    const uint32_t rho = C.g_rho[g];
+  // gadget digits come prime-major (all digits of q_rho, then of q_rho+1), so
+  // out[rho] is indexed by the unrolled loop counter
+  uint32_t g = 0;
+  for (uint32_t rho = 0; rho < k; ++rho) {
     const uint64_t y = shoup_q(out[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
-    const uint64_t dg = C.w_bits ? (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1) : y;
-    for (uint32_t s = 0; s < k; ++s)
-      digits[(((size_t)bl * L + g) * k + s) * n + c] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+    for (; g < L && C.g_rho[g] == rho; ++g) {
+      const uint64_t dg = C.w_bits ? (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1) : y;
+      for (uint32_t s = 0; s < k; ++s)
+        digits[(((size_t)bl * L + g) * k + s) * n + c] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+    }
   }
 }
 
@@ -821,18 +825,22 @@ hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t gr
 
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
-                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K) {
+                          uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K, uint32_t W) {
   uint64_t total = (uint64_t)nblk * 3 * n;
   dim3 grid((uint32_t)((total + WG - 1) / WG), nreq);
   // the parameter sets in use get fully unrolled bodies; others use runtime bounds
-  if (k == 3 && K == 8)
-    hipLaunchKernelGGL((k_rescale<3, 8>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
-  else if (k == 5 && K == 16)
-    hipLaunchKernelGGL((k_rescale<5, 16>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
-  else if (k == 2 && K == 8)
-    hipLaunchKernelGGL((k_rescale<2, 8>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
+  if (k == 3 && K == 8 && W == 3)
+    hipLaunchKernelGGL((k_rescale<3, 8, 3>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride,
+                       dig_stride);
+  else if (k == 5 && K == 16 && W == 4)
+    hipLaunchKernelGGL((k_rescale<5, 16, 4>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride,
+                       dig_stride);
+  else if (k == 2 && K == 8 && W == 3)
+    hipLaunchKernelGGL((k_rescale<2, 8, 3>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride,
+                       dig_stride);
   else
-    hipLaunchKernelGGL((k_rescale<0, 0>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride, dig_stride);
+    hipLaunchKernelGGL((k_rescale<0, 0, 0>), grid, dim3(WG), 0, s, T, X, nblk, blk_lo, SP, digits, acc_stride,
+                       dig_stride);
   return hipGetLastError();
 }
 
