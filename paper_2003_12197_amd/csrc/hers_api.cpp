@@ -167,6 +167,18 @@ int hers_params_resolve(const hers_params* params, hers_info* out) {
   return HERS_OK;
 }
 
+static std::vector<double> to_double(const std::vector<uint64_t>& v) { return std::vector<double>(v.begin(), v.end()); }
+
+static std::vector<double> qf_consts(const HersConsts& C) {
+  std::vector<double> f(3 * HC_MAXQ, 0.0);
+  for (uint32_t i = 0; i < C.k; ++i) {
+    f[i] = (double)C.q[i];
+    f[HC_MAXQ + i] = 1.0 / (double)C.q[i];
+    f[2 * HC_MAXQ + i] = (double)C.q_ninv[i];
+  }
+  return f;
+}
+
 int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
   if (!params || !out) return fail(HERS_EINVAL, "null argument");
   *out = nullptr;
@@ -189,6 +201,9 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
       (rc = upload(c, c->host.pitw, &c->T.pitw)) || (rc = upload(c, c->host.pitw_sh, &c->T.pitw_sh)) ||
       (rc = upload(c, c->host.ttw, &c->T.ttw)) || (rc = upload(c, c->host.ttw_sh, &c->T.ttw_sh)) ||
       (rc = upload(c, c->host.titw, &c->T.titw)) || (rc = upload(c, c->host.titw_sh, &c->T.titw_sh)) ||
+      (rc = upload(c, to_double(c->host.qtw), &c->T.qtw_f)) ||
+      (rc = upload(c, to_double(c->host.qitw), &c->T.qitw_f)) ||
+      (rc = upload(c, qf_consts(C), &c->T.qf)) ||
       (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pk)) || (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pks)) ||
       (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rl)) ||
       (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rls))) {
@@ -207,6 +222,8 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
     c->num_cus = cus;
   c->T.C = dC;
   c->T.ntt_r = 4;
+  c->T.qf_ok = 1;
+  for (uint32_t i = 0; i < C.k; ++i) c->T.qf_ok &= C.q[i] < (1ull << 48);
   c->T.pk_ntt = (uint64_t*)pk;
   c->T.pk_ntt_sh = (uint64_t*)pks;
   c->T.rlk_ntt = (uint64_t*)rl;

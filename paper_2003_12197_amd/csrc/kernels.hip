@@ -7,6 +7,8 @@
 //   accumulators           u32 [M][3][K][n]   sum_i of the tensor, NTT then coefficient domain
 //   relin digits           u64 [M][L][k][n]   digit g of c2, reduced mod q_sigma
 // Workgroups are 256 lanes (four wave64s).
+#include <type_traits>
+
 #include "kernels.h"
 
 #include "ntt.h"
@@ -157,7 +159,8 @@ k_ct_add(DevTabs T, uint64_t* __restrict__ dst, const uint64_t* __restrict__ fre
   dst[w] = b >= first_empty_block ? fresh[w] : add_q(dst[w], fresh[w], C.q[rho]);
 }
 
-extern "C" __global__ void __launch_bounds__(WG_ENC)
+template <bool QF>
+__global__ void __launch_bounds__(WG_ENC)
 k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict__ query,
           int32_t d, int64_t block0, uint64_t seed, uint32_t domain, uint64_t* __restrict__ canon) {
   // Alg. "Encryption" for ciphertext c (gallery: c = b_local d + i, or probe
@@ -178,25 +181,51 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
     for (int s = 0; s < 4; ++s) W[4 * bk + s] = b.v[s];
   }
   __syncthreads();
-  for (uint32_t j = tid; j < n; j += WG_ENC) U[PADX(j)] = (W[j >> 6] >> (j & 63)) & 1;
-  __syncthreads();
-  const uint64_t* tw = T.qtw + (size_t)rho * n;
-  const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
-  ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG_ENC, T.ntt_r);
   const uint64_t* pk0 = T.pk_ntt + (size_t)rho * n;
   const uint64_t* pk0s = T.pk_ntt_sh + (size_t)rho * n;
   const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
   const uint64_t* pk1s = T.pk_ntt_sh + ((size_t)k + rho) * n;
-  for (uint32_t j = tid; j < n; j += WG_ENC) {
-    const uint64_t u = U[PADX(j)];
-    V[PADX(j)] = shoup_q(u, pk1[j], pk1s[j], q);
-    U[PADX(j)] = shoup_q(u, pk0[j], pk0s[j], q);
+  if constexpr (QF) {
+    // u pk0 and u pk1 in double-precision modular arithmetic (ModQF)
+    double* Uf = reinterpret_cast<double*>(U);
+    double* Vf = reinterpret_cast<double*>(V);
+    const ModQF mf{T.qf[rho], T.qf[HC_MAXQ + rho]};
+    for (uint32_t j = tid; j < n; j += WG_ENC) Uf[PADX(j)] = (double)((W[j >> 6] >> (j & 63)) & 1);
+    __syncthreads();
+    const double* twf = T.qtw_f + (size_t)rho * n;
+    ntt_forward16(Uf, twf, twf, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG_ENC) {
+      const double u = Uf[PADX(j)];
+      Vf[PADX(j)] = mf.mul(u, u64_to_f(pk1[j]), 0.0);
+      Uf[PADX(j)] = mf.mul(u, u64_to_f(pk0[j]), 0.0);
+    }
+    __syncthreads();
+    const double* itwf = T.qitw_f + (size_t)rho * n;
+    const double ninv = T.qf[2 * HC_MAXQ + rho];
+    ntt_inverse16(Uf, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
+    ntt_inverse16(Vf, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG_ENC) {
+      U[PADX(j)] = f_to_u64(Uf[PADX(j)]);
+      V[PADX(j)] = f_to_u64(Vf[PADX(j)]);
+    }
+    __syncthreads();
+  } else {
+    for (uint32_t j = tid; j < n; j += WG_ENC) U[PADX(j)] = (W[j >> 6] >> (j & 63)) & 1;
+    __syncthreads();
+    const uint64_t* tw = T.qtw + (size_t)rho * n;
+    const uint64_t* twsh = T.qtw_sh + (size_t)rho * n;
+    ntt_forward16(U, tw, twsh, mq, n, C.logn, tid, WG_ENC, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG_ENC) {
+      const uint64_t u = U[PADX(j)];
+      V[PADX(j)] = shoup_q(u, pk1[j], pk1s[j], q);
+      U[PADX(j)] = shoup_q(u, pk0[j], pk0s[j], q);
+    }
+    __syncthreads();
+    const uint64_t* itw = T.qitw + (size_t)rho * n;
+    const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
+    ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
+    ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
   }
-  __syncthreads();
-  const uint64_t* itw = T.qitw + (size_t)rho * n;
-  const uint64_t* itwsh = T.qitw_sh + (size_t)rho * n;
-  ntt_inverse16(U, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
-  ntt_inverse16(V, itw, itwsh, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n, C.logn, tid, WG_ENC, T.ntt_r);
   uint32_t qconst = 0;
   if (query) {
     int64_t z = (int64_t)query[c] % (int64_t)C.t;
@@ -551,22 +580,35 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   }
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+template <bool QF>
+__global__ void __launch_bounds__(WG)
 k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
   // In-place forward negacyclic NTT mod q_sigma of polynomial blockIdx.x of
-  // set blockIdx.y, sigma = blockIdx.x mod k (layouts [..][k][n]).
+  // set blockIdx.y, sigma = blockIdx.x mod k (layouts [..][k][n]); QF: in
+  // double-precision modular arithmetic (ModQF), same residues.
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, tid = threadIdx.x;
   const uint32_t sg = blockIdx.x % C.k;
   uint64_t* a = polys + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * n;
-  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
-  __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t j = tid; j < n; j += WG) a[j] = lds64[PADX(j)];
+  if constexpr (QF) {
+    double* f = reinterpret_cast<double*>(lds64);
+    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(a[j]);
+    __syncthreads();
+    const double* tw = T.qtw_f + (size_t)sg * n;
+    ntt_forward16(f, tw, tw, ModQF{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG) a[j] = f_to_u64(f[PADX(j)]);
+  } else {
+    for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
+    __syncthreads();
+    ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG,
+                  T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG) a[j] = lds64[PADX(j)];
+  }
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+template <bool QF>
+__global__ void __launch_bounds__(WG)
 k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
             const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
   // Relinearization (or key switching), second half: for block
@@ -582,6 +624,25 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   const uint64_t q = C.q[sg];
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
   uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
+  if constexpr (QF) {
+    const ModQF mq{T.qf[sg], T.qf[HC_MAXQ + sg]};
+    double* f = reinterpret_cast<double*>(lds64);
+    for (uint32_t j = tid; j < n; j += WG) {
+      double acc = 0.0;
+      for (uint32_t g = 0; g < L; ++g) {
+        const size_t r = (((size_t)g * 2 + comp) * k + sg) * n + j;
+        acc += mq.mul(u64_to_f(digits[((size_t)g * k + sg) * n + j]), u64_to_f(key[r]), 0.0);
+        acc = acc >= mq.q ? acc - mq.q : acc;
+      }
+      f[PADX(j)] = acc;
+    }
+    __syncthreads();
+    const double* itw = T.qitw_f + (size_t)sg * n;
+    const double ninv = T.qf[2 * HC_MAXQ + sg];
+    ntt_inverse16(f, itw, itw, ninv, ninv, mq, n, C.logn, tid, WG, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
+    return;
+  }
   for (uint32_t j = tid; j < n; j += WG) {
     uint64_t acc = 0;
     for (uint32_t g = 0; g < L; ++g) {
@@ -606,20 +667,51 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
 #define RL_PER 16
 #define RL_UNROLL 16  // full unroll of the per-lane loops: the accumulators stay in registers
 
-extern "C" __global__ void __launch_bounds__(512)
+template <bool QF>
+__global__ void __launch_bounds__(512)
 k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
               const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
+  // QF: the transforms and key products in double-precision modular
+  // arithmetic (ModQF) on elements of type E, converted at the memory edges
+  using E = typename std::conditional<QF, double, uint64_t>::type;
+  using M = typename std::conditional<QF, ModQF, ModQ>::type;
   extern __shared__ uint64_t lds64[];
+  E* a = reinterpret_cast<E*>(lds64);
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x, nthr = blockDim.x;
   const int64_t bl = blockIdx.x, b = blk_lo + bl;
   const uint32_t sg = blockIdx.y;
   const uint64_t q = C.q[sg];
-  const ModQ mq{q};
+  M mod;
+  const E *tw, *twsh, *itw, *itwsh;
+  E ninv, ninv_sh;
+  if constexpr (QF) {
+    mod = ModQF{T.qf[sg], T.qf[HC_MAXQ + sg]};
+    tw = twsh = T.qtw_f + (size_t)sg * n;
+    itw = itwsh = T.qitw_f + (size_t)sg * n;
+    ninv = ninv_sh = T.qf[2 * HC_MAXQ + sg];
+  } else {
+    mod = ModQ{q};
+    tw = T.qtw + (size_t)sg * n;
+    twsh = T.qtw_sh + (size_t)sg * n;
+    itw = T.qitw + (size_t)sg * n;
+    itwsh = T.qitw_sh + (size_t)sg * n;
+    ninv = C.q_ninv[sg];
+    ninv_sh = C.q_ninv_sh[sg];
+  }
+  auto in = [](uint64_t v) -> E { if constexpr (QF) return u64_to_f(v); else return v; };
+  auto out = [](E v) -> uint64_t { if constexpr (QF) return f_to_u64(v); else return v; };
+  // acc + D key mod q, both accumulators fully reduced
+  auto mac = [&](E acc, E D, uint64_t kw, uint64_t ks) -> E {
+    if constexpr (QF) {
+      const E s = acc + mod.mul(D, u64_to_f(kw), 0.0);
+      return s >= mod.q ? s - mod.q : s;
+    } else {
+      return add_q(acc, shoup_q(D, kw, ks, q), q);
+    }
+  };
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
-  const uint64_t* tw = T.qtw + (size_t)sg * n;
-  const uint64_t* twsh = T.qtw_sh + (size_t)sg * n;
-  uint64_t acc0[RL_PER], acc1[RL_PER];
+  E acc0[RL_PER], acc1[RL_PER];
 #pragma unroll RL_UNROLL
   for (uint32_t e = 0; e < RL_PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
   for (uint32_t g = 0; g < L; ++g) {
@@ -627,34 +719,32 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
     __syncthreads();                                    // previous digit's products read
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e)
-      if (tid + e * nthr < n) lds64[PADX(tid + e * nthr)] = dg[tid + e * nthr];
+      if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(dg[tid + e * nthr]);
     __syncthreads();
-    ntt_forward16(lds64, tw, twsh, mq, n, C.logn, tid, nthr, T.ntt_r);
+    ntt_forward16(a, tw, twsh, mod, n, C.logn, tid, nthr, T.ntt_r);
     const size_t k0 = (((size_t)g * 2 + 0) * k + sg) * n, k1 = (((size_t)g * 2 + 1) * k + sg) * n;
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e) {
       const uint32_t j = tid + e * nthr;
       if (j >= n) break;                                // never on the GPU: n / RL_PER lanes
-      const uint64_t D = lds64[PADX(j)];
-      acc0[e] = add_q(acc0[e], shoup_q(D, key[k0 + j], key_sh[k0 + j], q), q);
-      acc1[e] = add_q(acc1[e], shoup_q(D, key[k1 + j], key_sh[k1 + j], q), q);
+      const E D = a[PADX(j)];
+      acc0[e] = mac(acc0[e], D, key[k0 + j], key_sh[k0 + j]);
+      acc1[e] = mac(acc1[e], D, key[k1 + j], key_sh[k1 + j]);
     }
   }
-  const uint64_t* itw = T.qitw + (size_t)sg * n;
-  const uint64_t* itwsh = T.qitw_sh + (size_t)sg * n;
   for (uint32_t comp = 0; comp < 2; ++comp) {
     __syncthreads();
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e)
-      if (tid + e * nthr < n) lds64[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
+      if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
     __syncthreads();
-    ntt_inverse16(lds64, itw, itwsh, C.q_ninv[sg], C.q_ninv_sh[sg], mq, n, C.logn, tid, nthr, T.ntt_r);
+    ntt_inverse16(a, itw, itwsh, ninv, ninv_sh, mod, n, C.logn, tid, nthr, T.ntt_r);
     uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e) {
       const uint32_t j = tid + e * nthr;
       if (j >= n) break;
-      dst[j] = add_q(dst[j], lds64[PADX(j)], q);
+      dst[j] = add_q(dst[j], out(a[PADX(j)]), q);
     }
   }
 }
@@ -675,7 +765,8 @@ k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, ui
   }
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+template <bool QF>
+__global__ void __launch_bounds__(WG)
 k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const uint64_t* __restrict__ S,
           const uint64_t* __restrict__ Ssh, uint64_t* __restrict__ xout) {
   // x = [c0 + c1 s]_q for block blk_lo + blockIdx.x, residue sigma.
@@ -687,6 +778,22 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   const ModQ mq{q};
   const uint64_t* c0 = scores + (((size_t)b * 2 + 0) * k + sg) * n;
   const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * k + sg) * n;
+  if constexpr (QF) {
+    // the same product in double-precision modular arithmetic (ModQF)
+    double* f = reinterpret_cast<double*>(lds64);
+    const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
+    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(c1[j]);
+    __syncthreads();
+    const double* twf = T.qtw_f + (size_t)sg * n;
+    ntt_forward16(f, twf, twf, mf, n, C.logn, tid, WG, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(S[(size_t)sg * n + j]), 0.0);
+    __syncthreads();
+    const double* itwf = T.qitw_f + (size_t)sg * n;
+    const double ninv = T.qf[2 * HC_MAXQ + sg];
+    ntt_inverse16(f, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG, T.ntt_r);
+    for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(f_to_u64(f[PADX(j)]), c0[j], q);
+    return;
+  }
   for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = c1[j];
   __syncthreads();
   ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG, T.ntt_r);
@@ -760,7 +867,12 @@ hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct
                           const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
                           uint64_t* canon, hipStream_t s) {
   size_t lds = lds_bytes(n, 2);
-  hipLaunchKernelGGL(k_encrypt, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain, canon);
+  if (T.qf_ok)
+    hipLaunchKernelGGL(k_encrypt<true>, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain,
+                       canon);
+  else
+    hipLaunchKernelGGL(k_encrypt<false>, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain,
+                       canon);
   return hipGetLastError();
 }
 
@@ -853,19 +965,30 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
     // transforms, key products and both inverse transforms (no transformed
     // digits in memory)
     const uint32_t lanes = n / RL_PER;                 // n >= 256: at least 16 lanes
-    hipLaunchKernelGGL(k_relin_fused, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T, digits,
-                       blk_lo, SP, dig_stride, key, key_sh);
+    if (T.qf_ok)
+      hipLaunchKernelGGL(k_relin_fused<true>, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T,
+                         digits, blk_lo, SP, dig_stride, key, key_sh);
+    else
+      hipLaunchKernelGGL(k_relin_fused<false>, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T,
+                         digits, blk_lo, SP, dig_stride, key, key_sh);
     return hipGetLastError();
   }
   // few workgroups: the digit transforms (L k per block), then key products
   // and inverse transforms (2 k per block), as separate launches with more
   // workgroups each
-  hipLaunchKernelGGL(k_ntt_q, dim3((uint32_t)(nblk * L * k), nreq), dim3(WG), lds_bytes(n, 1), s, T, digits,
-                     dig_stride);
+  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)nblk, 2 * k, nreq);
+  if (T.qf_ok)
+    hipLaunchKernelGGL(k_ntt_q<true>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
+  else
+    hipLaunchKernelGGL(k_ntt_q<false>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_relin_acc, dim3((uint32_t)nblk, 2 * k, nreq), dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo,
-                     SP, dig_stride, key, key_sh);
+  if (T.qf_ok)
+    hipLaunchKernelGGL(k_relin_acc<true>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
+                       key_sh);
+  else
+    hipLaunchKernelGGL(k_relin_acc<false>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
+                       key_sh);
   return hipGetLastError();
 }
 
@@ -877,7 +1000,12 @@ hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t
 
 hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,
                           int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_dec_mul, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
+  if (T.qf_ok)
+    hipLaunchKernelGGL(k_dec_mul<true>, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S,
+                       Ssh, x);
+  else
+    hipLaunchKernelGGL(k_dec_mul<false>, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S,
+                       Ssh, x);
   return hipGetLastError();
 }
 

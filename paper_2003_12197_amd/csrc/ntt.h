@@ -45,6 +45,47 @@ struct ModQ {
   HD uint64_t full(uint64_t a) const { a = a >= 2 * q ? a - 2 * q : a; return a >= q ? a - q : a; }
 };
 
+// Arithmetic mod q < 2^48 on exact integers held in doubles (all values below
+// 2^50, so every operand and every partial result used below is an integer
+// that a double holds exactly).  a w mod q: hi = fl(a w) and lo = a w - hi
+// (exact, by one fused multiply-add) split the product; qt = rint(hi / q)
+// (within 3/4 of hi / q, the reciprocal's and the product's rounding errors
+// being below 2^-52 relative); hi - qt q then lies in [-3q/4, 3q/4] and comes
+// exactly out of one fused multiply-add, and |lo| <= a w 2^-53 < q / 8, so
+// r = (hi - qt q) + lo is exact and in (-q, q); one conditional add of q
+// gives [0, q).  These are full-rate double operations where the 64-bit
+// integer Shoup product takes half-rate 32-bit multiply-adds.
+struct ModQF {
+  double q, qinv;   // qinv = fl(1 / q)
+  HD double mul_lazy(double a, double w, double) const {
+#pragma clang fp contract(off)
+    const double hi = a * w;
+    const double lo = __builtin_fma(a, w, -hi);
+    const double qt = __builtin_rint(hi * qinv);
+    const double r = __builtin_fma(-qt, q, hi) + lo;
+    return r < 0.0 ? r + q : r;
+  }
+  HD double mul(double a, double w, double ws) const { return mul_lazy(a, w, ws); }
+  // x mod q for an integer 0 <= x < 2^50: x - rint(x / q) q is exact and in (-q, q)
+  HD double reduce(double x) const {
+#pragma clang fp contract(off)
+    const double r = __builtin_fma(-__builtin_rint(x * qinv), q, x);
+    return r < 0.0 ? r + q : r;
+  }
+  HD double red2(double a) const { return a >= 2.0 * q ? a - 2.0 * q : a; }
+  HD double two() const { return 2.0 * q; }
+  HD double full(double a) const { a = a >= 2.0 * q ? a - 2.0 * q : a; return a >= q ? a - q : a; }
+};
+
+// Exact conversions between integers below 2^52 and doubles: a double with
+// exponent field 0x433 holds 2^52 + (its 52 mantissa bits).
+HD double u64_to_f(uint64_t v) {
+  return __builtin_bit_cast(double, v | 0x4330000000000000ull) - 4503599627370496.0;
+}
+HD uint64_t f_to_u64(double x) {
+  return __builtin_bit_cast(uint64_t, x + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
 // ---- LDS layout
 // A polynomial in LDS has one padding element after every 16 (element j at
 // PADX(j)), so lanes reading 16 consecutive elements, or elements 16 apart,
