@@ -420,17 +420,24 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
 // 64-slot tile); a group is up to MB_PROBES probes of one gallery.  The
 // workgroup's 16 waves are the group's probes: each lane keeps its probe's
 // values for a chunk of MB_DC dimensions in registers.  The gallery words of
-// a chunk for all the item's blocks (MB_BLOCKS x MB_DC x 2 rows x 64 slots)
-// are staged once in LDS and read by every wave, so one HBM read of the
-// gallery serves the whole group; the next chunk's words are loaded into
-// registers while the current chunk is multiplied.  Folding as in k_mac.
+// a chunk for all the item's blocks (MB_BLOCKS x MB_DC x 64 slots, both
+// polynomials) are staged once in LDS and read by every wave, so one HBM read
+// of the gallery serves the whole group; the next chunk's words are loaded
+// into registers while the current chunk is multiplied.
+// The tensor's cross term is taken by Karatsuba: A1 = sum_i (P_i0 + P_i1)
+// (G_i0 + G_i1) - A0 - A2 mod p, with both sums reduced mod p first (the
+// gallery's once per staged word, shared by all probe waves), so a dimension
+// costs three products instead of four and every accumulator takes one
+// product (< 2^60) per dimension: 16 fit in 64 bits after a fold, and all
+// three fold every second chunk.  The residues written are the same.
 // Workgroups stride over the items (static assignment, no atomics).
-#define MB_STAGE (MB_BLOCKS * MB_DC * 2 * 64)           // words per staged chunk
-#define MB_PER_THREAD (MB_STAGE / MB_WG)
+#define MB_PAIRS (MB_BLOCKS * MB_DC * 64)              // (block, dimension, slot) words per staged chunk
+#define MB_PER_THREAD (MB_PAIRS / MB_WG)
 
 __global__ void __launch_bounds__(MB_WG)
 k_mac_multi(DevTabs T, MacBatchArgs A) {
-  __shared__ uint32_t tileG[MB_STAGE];                 // [u][v][64][poly]: a slot's two words together
+  __shared__ uint2 tileG[MB_PAIRS];                    // [u][v][64]: (G0, G1) of a slot
+  __shared__ uint32_t tileS[MB_PAIRS];                 // [u][v][64]: G0 + G1 mod p
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -451,24 +458,26 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
     const uint32_t slot = tile * 64 + lane;
     const uint32_t* pr = active ? G.probe[wave] + (size_t)r * d * 2 * n + slot : nullptr;
     const uint32_t* gbase = G.gallery + tile * 64;
-    // gallery word of staged index w in chunk dc: block b0 + u, row 2 (dc + v) + poly, slot c
-    auto fetch = [&](int32_t dc, int32_t dn, uint32_t (&reg)[MB_PER_THREAD]) {
+    // staged pair w of chunk dc: block b0 + u, dimension dc + v, slot w mod 64
+    auto fetch = [&](int32_t dc, int32_t dn, uint2 (&reg)[MB_PER_THREAD]) {
 #pragma unroll
       for (int e = 0; e < MB_PER_THREAD; ++e) {
         const uint32_t w = tid + e * MB_WG;
-        const uint32_t c = w & 63, row = w >> 6;
-        const uint32_t poly = row & 1, uv = row >> 1;
+        const uint32_t c = w & 63, uv = w >> 6;
         const uint32_t u = uv / (uint32_t)dn, v = uv - u * (uint32_t)dn;
-        reg[e] = (int)u < nblk
-                     ? __builtin_nontemporal_load(gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v) + poly) * n + c)
-                     : 0u;
+        if ((int)u < nblk) {
+          const uint32_t* src = gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v)) * n + c;
+          reg[e] = uint2{__builtin_nontemporal_load(src), __builtin_nontemporal_load(src + n)};
+        } else {
+          reg[e] = uint2{0u, 0u};
+        }
       }
     };
-    uint64_t a0[MB_BLOCKS], a1[MB_BLOCKS], a2[MB_BLOCKS];
+    uint64_t a0[MB_BLOCKS], a2[MB_BLOCKS], as[MB_BLOCKS];
 #pragma unroll
-    for (int u = 0; u < MB_BLOCKS; ++u) { a0[u] = 0; a1[u] = 0; a2[u] = 0; }
-    uint32_t stage[MB_PER_THREAD];
-    uint32_t P0[MB_DC], P1[MB_DC];                     // this lane's probe values for the chunk
+    for (int u = 0; u < MB_BLOCKS; ++u) { a0[u] = 0; a2[u] = 0; as[u] = 0; }
+    uint2 stage[MB_PER_THREAD];
+    uint32_t P0[MB_DC], P1[MB_DC];                     // this lane's probe values for the next chunk
     auto fetch_probe = [&](int32_t dc, int32_t dn) {
 #pragma unroll
       for (int v = 0; v < MB_DC; ++v) {
@@ -483,8 +492,9 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
       __syncthreads();                                 // previous chunk fully consumed
 #pragma unroll
       for (int e = 0; e < MB_PER_THREAD; ++e) {
-        const uint32_t w = tid + e * MB_WG;               // staged index: row w >> 6 = 2 uv + poly, slot w & 63
-        tileG[((((w >> 7) << 6) + (w & 63)) << 1) + ((w >> 6) & 1)] = stage[e];
+        const uint32_t w = tid + e * MB_WG;
+        tileG[w] = stage[e];
+        tileS[w] = add_p(stage[e].x, stage[e].y, p);
       }
       __syncthreads();
       uint32_t Q0[MB_DC], Q1[MB_DC];
@@ -496,29 +506,45 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
         fetch_probe(dc + MB_DC, nd);
       }
       if (active) {
-        // products are below 2^60: after a fold (value < p) 16 more fit in
-        // 64 bits, i.e. a chunk of MB_DC = 8 dimensions for a1 (two per
-        // dimension) and two chunks for a0, a2
         static_assert(MB_DC == 8, "fold schedule assumes 8 dimensions per chunk");
-        const bool fold02 = ((dc / MB_DC) & 1) || dc + MB_DC >= d;
-#pragma unroll
-        for (int u = 0; u < MB_BLOCKS; ++u) {
-          if (u >= nblk) break;
-          const uint2* t0 = (const uint2*)tileG + (uint32_t)u * dn * 64 + lane;
+        if (dn == MB_DC && nblk == MB_BLOCKS) {        // full chunk: no bounds in the product loop
 #pragma unroll
           for (int v = 0; v < MB_DC; ++v) {
-            if (v < dn) {
-              const uint2 gv = t0[v * 64];                  // one 64-bit LDS read: both polynomials
-              const uint64_t g0 = gv.x, g1 = gv.y;
-              a0[u] += (uint64_t)Q0[v] * g0;
-              a1[u] += (uint64_t)Q0[v] * g1 + (uint64_t)Q1[v] * g0;
-              a2[u] += (uint64_t)Q1[v] * g1;
+            const uint32_t qs = add_p(Q0[v], Q1[v], p);
+#pragma unroll
+            for (int u = 0; u < MB_BLOCKS; ++u) {
+              const uint32_t w = (uint32_t)(u * MB_DC + v) * 64 + lane;
+              const uint2 gv = tileG[w];
+              const uint32_t gs = tileS[w];
+              a0[u] += (uint64_t)Q0[v] * gv.x;
+              a2[u] += (uint64_t)Q1[v] * gv.y;
+              as[u] += (uint64_t)qs * gs;
             }
           }
-          a1[u] = red_p(a1[u], p, mu);
-          if (fold02) {
+        } else {
+#pragma unroll
+          for (int v = 0; v < MB_DC; ++v) {
+            if (v >= dn) break;
+            const uint32_t qs = add_p(Q0[v], Q1[v], p);
+#pragma unroll
+            for (int u = 0; u < MB_BLOCKS; ++u) {
+              if (u >= nblk) break;
+              const uint32_t w = ((uint32_t)u * dn + v) * 64 + lane;
+              const uint2 gv = tileG[w];
+              const uint32_t gs = tileS[w];
+              a0[u] += (uint64_t)Q0[v] * gv.x;
+              a2[u] += (uint64_t)Q1[v] * gv.y;
+              as[u] += (uint64_t)qs * gs;
+            }
+          }
+        }
+        if (((dc / MB_DC) & 1) || dc + MB_DC >= d) {
+#pragma unroll
+          for (int u = 0; u < MB_BLOCKS; ++u) {
+            if (u >= nblk) break;
             a0[u] = red_p(a0[u], p, mu);
             a2[u] = red_p(a2[u], p, mu);
+            as[u] = red_p(as[u], p, mu);
           }
         }
       }
@@ -528,9 +554,13 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
 #pragma unroll
       for (int u = 0; u < MB_BLOCKS; ++u) {
         if (u >= nblk) break;
+        // A1 = S - A0 - A2 mod p, all three below p
+        uint64_t a1 = as[u] + 2 * (uint64_t)p - a0[u] - a2[u];
+        a1 = a1 >= p ? a1 - p : a1;
+        a1 = a1 >= p ? a1 - p : a1;
         uint32_t* o = ob + ((size_t)(b0 + u - G.blk_lo) * 3 * K + r) * n + slot;
         o[0] = (uint32_t)a0[u];
-        o[(size_t)K * n] = (uint32_t)a1[u];
+        o[(size_t)K * n] = (uint32_t)a1;
         o[(size_t)2 * K * n] = (uint32_t)a2[u];
       }
     }

@@ -21,6 +21,8 @@ CONFIGS = {
     "c1b": dict(n=2048, qbits=(54, 54), t_bits=20, w_bits=0),
     # three 36-bit primes (the paper's q shape) at n = 2048
     "r36": dict(n=2048, qbits=(36, 36, 36), t_bits=20, w_bits=0),
+    # the batched configuration's q shape (five primes of 44 and 43 bits, t of 21 bits) at a small ring
+    "c3s": dict(n=256, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0),
 }
 
 
@@ -85,7 +87,13 @@ def case_r36(gpu_lib):
     return Case(gpu_lib, "r36", 5, 2 * 2048 + 37)
 
 
-CASES = ["case_c1", "case_c1b", "case_r36"]
+@pytest.fixture(scope="module")
+def case_c3s(gpu_lib):
+    print("case c3s: n=256 q=44,44,44,43,43 t=21 bits d=6 m=2*256+17 (ragged)", flush=True)
+    return Case(gpu_lib, "c3s", 6, 2 * 256 + 17)
+
+
+CASES = ["case_c1", "case_c1b", "case_r36", "case_c3s"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -130,7 +138,7 @@ def test_score_ciphertexts_bit_exact(name, request):
         assert np.array_equal(scores[b, 1], res(S[1], c.op.q_primes)), b
 
 
-@pytest.mark.parametrize("name", ["case_c1b", "case_r36"])
+@pytest.mark.parametrize("name", ["case_c1b", "case_r36", "case_c3s"])
 def test_decrypted_scores_equal_plaintext_inner_products(name, request):
     c = request.getfixturevalue(name)
     out = c.ctx.decrypt_scores(c.sk, c.scores, c.m).cpu().numpy()
@@ -141,6 +149,20 @@ def test_decrypted_scores_equal_plaintext_inner_products(name, request):
              [int(x) for x in fv.from_residues(scores[b, 1].tolist(), c.op.q_primes)]) for b in [c.M - 1]}
     tail = hers.decrypt_scores(c.op, c.osk, S, c.m)
     assert np.array_equal(tail, out[(c.M - 1) * c.op.n:])
+
+
+@pytest.mark.parametrize("name", ["case_c1b", "case_c3s"])
+def test_relinearization_forms_give_same_bits(name, request):
+    """Relinearization as one fused kernel per (block, prime) and as two
+    kernels give the oracle-checked score ciphertexts, with integer (54-bit
+    primes) and double-precision (44-bit primes) modular arithmetic."""
+    c = request.getfixturevalue(name)
+    try:
+        for fuse in (1, 1 << 30):
+            c.ctx.set_option("relin_fuse_min_wgs", fuse)
+            assert torch.equal(c.ctx.search(c.gallery, c.m, c.d, c.probe), c.scores), fuse
+    finally:
+        c.ctx.set_option("relin_fuse_min_wgs", 0)
 
 
 def test_loaded_secret_key_decrypts_alike(case_r36):
@@ -265,7 +287,10 @@ def _single_scores(ctx, gal, m, d, probe):
 
 @pytest.fixture(scope="module")
 def batch_setup(case_r36):
-    """Two galleries of uneven size and d on one context, 23 probes."""
+    """Three galleries of uneven size and d on one context, 40 probes: 20 on
+    the case's gallery (d = 5), 3 on one of 2048 + 900 items (d = 16), and 17
+    on one of 4 x 2048 + 5 items (d = 12: a full chunk of 8 dimensions over 4
+    blocks, a ragged chunk of 4, a one-block tail, a one-probe group)."""
     a = case_r36
     ctx = a.ctx
     P2, _ = synth.uniform_features(55, 16, 2048 + 900)
@@ -280,12 +305,19 @@ def batch_setup(case_r36):
         qv = rng.integers(-63, 64, size=16).astype(np.int32)
         pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 2000 + j)
         reqs.append((g2, P2.shape[1], 16, pr, P2, qv))
+    P3, _ = synth.uniform_features(56, 12, 4 * 2048 + 5)
+    g3 = ctx.encrypt_gallery(torch.from_numpy(P3).to(ctx.device), P3.shape[1], 78)
+    for j in range(17):
+        qv = rng.integers(-63, 64, size=12).astype(np.int32)
+        pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 3000 + j)
+        reqs.append((g3, P3.shape[1], 12, pr, P3, qv))
     return ctx, reqs
 
 
 def test_batch_multi_probe_equals_single(batch_setup, case_r36):
-    """Grouped requests (16 + 4 on one gallery, 3 on another) in one submission
-    give the same score ciphertexts as one hers_search per request."""
+    """Grouped requests (16 + 4 on one gallery, 3 on another, 16 + 1 on a
+    third) in one submission give the same score ciphertexts as one
+    hers_search per request."""
     ctx, reqs = batch_setup
     gals, ms, ds, prs = [r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
     for ws in (ctx.batch_workspace(ms), ctx.batch_workspace(ms, blocks_per_round=1)):
@@ -296,6 +328,9 @@ def test_batch_multi_probe_equals_single(batch_setup, case_r36):
     assert np.array_equal(dec, hers.plaintext_scores(reqs[5][4], reqs[5][5]))
     dec = ctx.decrypt_scores(case_r36.sk, outs[21], ms[21]).cpu().numpy()
     assert np.array_equal(dec, hers.plaintext_scores(reqs[21][4], reqs[21][5]))
+    for j in (23, 39):
+        dec = ctx.decrypt_scores(case_r36.sk, outs[j], ms[j]).cpu().numpy()
+        assert np.array_equal(dec, hers.plaintext_scores(reqs[j][4], reqs[j][5])), j
 
 
 def test_plan_replays_match_eager(batch_setup, case_r36):
