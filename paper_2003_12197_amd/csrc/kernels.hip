@@ -428,8 +428,12 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
 // (G_i0 + G_i1) - A0 - A2 mod p, with both sums reduced mod p first (the
 // gallery's once per staged word, shared by all probe waves), so a dimension
 // costs three products instead of four and every accumulator takes one
-// product (< 2^60) per dimension: 16 fit in 64 bits after a fold, and all
-// three fold every second chunk.  The residues written are the same.
+// product (< 2^60) per dimension.  After every chunk each sum is folded
+// cheaply, a -> (a >> 34) (2^34 mod p) + (a mod 2^34) < 2^60 + 2^34, which
+// leaves room for the next chunk's 8 products (< 9 2^60 < 2^64); one full
+// reduction at the end.  The residues written are the same.
+// The wave index is read as wave-uniform, so probe and staging addresses are
+// scalar bases plus the lane's offset.
 // Workgroups stride over the items (static assignment, no atomics).
 #define MB_PAIRS (MB_BLOCKS * MB_DC * 64)              // (block, dimension, slot) words per staged chunk
 #define MB_PER_THREAD (MB_PAIRS / MB_WG)
@@ -440,7 +444,8 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   __shared__ uint32_t tileS[MB_PAIRS];                 // [u][v][64]: G0 + G1 mod p
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t tiles = n / 64;
   for (uint64_t item = blockIdx.x; item < A.total_items; item += gridDim.x) {
     int g = 0;
@@ -454,20 +459,21 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
     const int32_t d = G.d;
     const uint32_t p = C.p[r];
     const uint64_t mu = C.p_mu64[r];
+    const uint32_t c34 = (uint32_t)((1ull << 34) - (uint64_t)p * (mu >> 30));   // 2^34 mod p (mu = floor(2^64/p))
     const bool active = wave < (uint32_t)G.nprobe;
     const uint32_t slot = tile * 64 + lane;
-    const uint32_t* pr = active ? G.probe[wave] + (size_t)r * d * 2 * n + slot : nullptr;
+    const uint32_t* pbase = active ? G.probe[wave] + (size_t)r * d * 2 * n + tile * 64 : nullptr;
     const uint32_t* gbase = G.gallery + tile * 64;
-    // staged pair w of chunk dc: block b0 + u, dimension dc + v, slot w mod 64
+    // staged pair w = tid + e MB_WG of chunk dc: block b0 + u, dimension dc + v
+    // with u, v from the wave-uniform row w / 64, slot w mod 64 = lane
     auto fetch = [&](int32_t dc, int32_t dn, uint2 (&reg)[MB_PER_THREAD]) {
 #pragma unroll
       for (int e = 0; e < MB_PER_THREAD; ++e) {
-        const uint32_t w = tid + e * MB_WG;
-        const uint32_t c = w & 63, uv = w >> 6;
+        const uint32_t uv = wave + e * (MB_WG / 64);
         const uint32_t u = uv / (uint32_t)dn, v = uv - u * (uint32_t)dn;
         if ((int)u < nblk) {
-          const uint32_t* src = gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v)) * n + c;
-          reg[e] = uint2{__builtin_nontemporal_load(src), __builtin_nontemporal_load(src + n)};
+          const uint32_t* src = gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v)) * n;
+          reg[e] = uint2{__builtin_nontemporal_load(src + lane), __builtin_nontemporal_load(src + n + lane)};
         } else {
           reg[e] = uint2{0u, 0u};
         }
@@ -481,8 +487,8 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
     auto fetch_probe = [&](int32_t dc, int32_t dn) {
 #pragma unroll
       for (int v = 0; v < MB_DC; ++v) {
-        P0[v] = active && v < dn ? pr[(size_t)(2 * (dc + v)) * n] : 0;
-        P1[v] = active && v < dn ? pr[(size_t)(2 * (dc + v) + 1) * n] : 0;
+        P0[v] = active && v < dn ? pbase[(size_t)(2 * (dc + v)) * n + lane] : 0;
+        P1[v] = active && v < dn ? pbase[(size_t)(2 * (dc + v) + 1) * n + lane] : 0;
       }
     };
     fetch(0, d < MB_DC ? d : MB_DC, stage);
@@ -506,7 +512,7 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
         fetch_probe(dc + MB_DC, nd);
       }
       if (active) {
-        static_assert(MB_DC == 8, "fold schedule assumes 8 dimensions per chunk");
+        static_assert(MB_DC <= 15, "a folded sum plus one chunk's products must stay below 2^64");
         if (dn == MB_DC && nblk == MB_BLOCKS) {        // full chunk: no bounds in the product loop
 #pragma unroll
           for (int v = 0; v < MB_DC; ++v) {
@@ -538,14 +544,13 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
             }
           }
         }
-        if (((dc / MB_DC) & 1) || dc + MB_DC >= d) {
+        auto fold = [&](uint64_t a) { return (uint64_t)(uint32_t)(a >> 34) * c34 + (a & ((1ull << 34) - 1)); };
 #pragma unroll
-          for (int u = 0; u < MB_BLOCKS; ++u) {
-            if (u >= nblk) break;
-            a0[u] = red_p(a0[u], p, mu);
-            a2[u] = red_p(a2[u], p, mu);
-            as[u] = red_p(as[u], p, mu);
-          }
+        for (int u = 0; u < MB_BLOCKS; ++u) {
+          if (u >= nblk) break;
+          a0[u] = fold(a0[u]);
+          a2[u] = fold(a2[u]);
+          as[u] = fold(as[u]);
         }
       }
     }
@@ -554,6 +559,9 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
 #pragma unroll
       for (int u = 0; u < MB_BLOCKS; ++u) {
         if (u >= nblk) break;
+        a0[u] = red_p(a0[u], p, mu);
+        a2[u] = red_p(a2[u], p, mu);
+        as[u] = red_p(as[u], p, mu);
         // A1 = S - A0 - A2 mod p, all three below p
         uint64_t a1 = as[u] + 2 * (uint64_t)p - a0[u] - a2[u];
         a1 = a1 >= p ? a1 - p : a1;
