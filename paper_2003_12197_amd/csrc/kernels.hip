@@ -650,15 +650,16 @@ __global__ void __launch_bounds__(WG)
 k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
             const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
   // Relinearization (or key switching), second half: for block
-  // blk_lo + blockIdx.x, residue sigma = blockIdx.y mod k and component
-  // comp = blockIdx.y / k of request z, c_comp += INTT(sum_g NTT(y_g) *
+  // blk_lo + blockIdx.x / 2, component comp = blockIdx.x mod 2 and residue
+  // sigma = blockIdx.y of request z, c_comp += INTT(sum_g NTT(y_g) *
   // key_g[comp]) mod q_sigma, key [L][2][k][n] in NTT form (the evaluation
-  // keys, or a rotation key).
+  // keys, or a rotation key).  The two components of a (block, residue) are
+  // neighbouring workgroups, so the second reads the digits from cache.
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
-  const int64_t bl = blockIdx.x, b = blk_lo + bl;
-  const uint32_t sg = blockIdx.y % k, comp = blockIdx.y / k;
+  const int64_t bl = blockIdx.x >> 1, b = blk_lo + bl;
+  const uint32_t sg = blockIdx.y, comp = blockIdx.x & 1;
   const uint64_t q = C.q[sg];
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
   uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
@@ -1014,7 +1015,7 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
   // few workgroups: the digit transforms (L k per block), then key products
   // and inverse transforms (2 k per block), as separate launches with more
   // workgroups each
-  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)nblk, 2 * k, nreq);
+  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)(2 * nblk), k, nreq);
   if (T.qf_ok)
     hipLaunchKernelGGL(k_ntt_q<true>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
   else
