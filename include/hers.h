@@ -394,6 +394,11 @@ void hers_server_destroy(hers_server* srv);
  * multiply-accumulate), "mac_multi" (its batched form), "topk", "intt_acc", "rescale", "relin", "encrypt", "lift",
  * "ntt_fwd", "encode", "keygen", "sk_ntt", "dec_mul", "dec_decode". */
 int hers_profile_enable(hers_ctx* ctx, int on);
+/* Restricts the timing to the stages named in `stages`, a comma-separated
+ * list of the names above (e.g. "mac"); NULL or "" times every stage.  Each
+ * timed launch costs two event records on its stream, a few microseconds of
+ * GPU time, so a caller timing a whole query times only the stage it needs. */
+int hers_profile_select(hers_ctx* ctx, const char* stages);
 int hers_profile_read(hers_ctx* ctx, const char* stage, double* total_ms, uint64_t* launches);
 
 #ifdef __cplusplus

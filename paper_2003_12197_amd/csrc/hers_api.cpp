@@ -53,6 +53,7 @@ struct hers_ctx {
   // per-stage timing
   struct Rec { std::string stage; hipEvent_t a, b; };
   bool prof_on = false;
+  std::vector<std::string> prof_sel;   // stages timed while profiling is on (empty: all)
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<double, uint64_t>> totals;
@@ -102,13 +103,20 @@ hipEvent_t take_event(hers_ctx* c) {
 }
 
 // Brackets one launch with events on its stream while profiling is enabled.
+static bool selected(const hers_ctx* c, const char* stage) {
+  if (c->prof_sel.empty()) return true;
+  for (const auto& s : c->prof_sel)
+    if (s == stage) return true;
+  return false;
+}
+
 struct StageTimer {
   hers_ctx* c;
   hipStream_t s;
   hipEvent_t a = nullptr;
   const char* stage;
   StageTimer(hers_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream), stage(name) {
-    if (c->prof_on && (a = take_event(c))) (void)hipEventRecord(a, s);
+    if (c->prof_on && selected(c, name) && (a = take_event(c))) (void)hipEventRecord(a, s);
   }
   ~StageTimer() {
     if (!a) return;
@@ -397,6 +405,23 @@ int hers_profile_enable(hers_ctx* ctx, int on) {
   ctx->pending.clear();
   ctx->totals.clear();
   ctx->prof_on = on != 0;
+  return HERS_OK;
+}
+
+int hers_profile_select(hers_ctx* ctx, const char* stages) {
+  if (!ctx) return fail(HERS_EINVAL, "null argument");
+  ctx->prof_sel.clear();
+  if (!stages) return HERS_OK;
+  std::string cur;
+  for (const char* c = stages;; ++c) {
+    if (*c == ',' || *c == '\0') {
+      if (!cur.empty()) ctx->prof_sel.push_back(cur);
+      cur.clear();
+      if (!*c) break;
+    } else if (*c != ' ') {
+      cur.push_back(*c);
+    }
+  }
   return HERS_OK;
 }
 

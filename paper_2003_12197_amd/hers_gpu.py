@@ -75,6 +75,7 @@ EXPORTS = {
     "hers_topk_workspace_bytes": (c_u64, [c_i64, c_i32]),
     "hers_topk": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_profile_enable": (c_i32, [c_vp, c_i32]),
+    "hers_profile_select": (c_i32, [c_vp, ctypes.c_char_p]),
     "hers_profile_read": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_u64)]),
 }
 
@@ -391,6 +392,11 @@ class Context:
 
     def profile_enable(self, on=True):
         _check(self.lib, self.lib.hers_profile_enable(self.handle, 1 if on else 0), "hers_profile_enable")
+
+    def profile_select(self, stages=None):
+        """Time only the named stages (an iterable of names) while profiling; None: every stage."""
+        arg = None if not stages else ",".join(stages).encode()
+        _check(self.lib, self.lib.hers_profile_select(self.handle, arg), "hers_profile_select")
 
     def profile_read(self, stage):
         """(total ms, launches) of one stage since profile_enable."""

@@ -165,6 +165,26 @@ def test_relinearization_forms_give_same_bits(name, request):
         c.ctx.set_option("relin_fuse_min_wgs", 0)
 
 
+def test_profile_select_times_only_named_stages(case_r36):
+    """With "mac" selected only the multiply-accumulate launches carry timing
+    events; with no selection every stage does."""
+    c = case_r36
+    ctx = c.ctx
+    try:
+        ctx.profile_select(["mac"])
+        ctx.profile_enable(True)
+        ctx.search(c.gallery, c.m, c.d, c.probe)
+        assert ctx.profile_read("mac")[1] >= 1
+        assert ctx.profile_read("rescale")[1] == 0 and ctx.profile_read("relin")[1] == 0
+        ctx.profile_select(None)
+        ctx.profile_enable(True)
+        ctx.search(c.gallery, c.m, c.d, c.probe)
+        assert ctx.profile_read("mac")[1] >= 1 and ctx.profile_read("rescale")[1] >= 1
+    finally:
+        ctx.profile_select(None)
+        ctx.profile_enable(False)
+
+
 def test_loaded_secret_key_decrypts_alike(case_r36):
     """hers_load_secret_key + decryption without a key argument gives the same
     scores as decryption with the key passed each time."""
