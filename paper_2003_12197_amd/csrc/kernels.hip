@@ -314,8 +314,13 @@ __device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
 // (double buffering), so a wave's arithmetic overlaps its own memory traffic.
 // Gallery rows are read once, so NT streams them past the cache.  Products of
 // residues below 2^30 are < 2^60: A0 and A2 take one product per dimension and
-// fold every 16 dimensions, A1 takes two and folds every 8.  acc is indexed
-// from blk_lo.
+// A1 two; the 64-bit sums are partially folded (three instructions) every 4
+// dimensions and fully reduced at the end.  acc is indexed from blk_lo.
+// a -> (a >> 34) (2^34 mod p) + (a mod 2^34), congruent mod p and below 2^60 + 2^34
+__device__ __forceinline__ uint64_t fold34(uint64_t a, uint32_t c34) {
+  return (uint64_t)(uint32_t)(a >> 34) * c34 + (a & ((1ull << 34) - 1));
+}
+
 template <int NB, int U, bool NT>
 struct MacBatch {
   u32x4 P0[U], P1[U], G0[U][NB], G1[U][NB];
@@ -339,13 +344,14 @@ __global__ void __launch_bounds__(WG)
 k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe, int32_t d,
       int32_t dim0, int32_t dcount, int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group,
       uint32_t* __restrict__ acc) {
-  static_assert(8 % U == 0, "U divides the fold period");
+  static_assert(4 % U == 0, "U divides the fold period");
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
   const uint32_t slot = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
   const uint32_t r = blockIdx.y;
   const uint32_t p = C.p[r];
   const uint64_t mu = C.p_mu64[r];
+  const uint32_t c34 = (uint32_t)((1ull << 34) - (uint64_t)p * (mu >> 30));   // 2^34 mod p (mu = floor(2^64/p))
   const int64_t b0 = blk_lo + (int64_t)blockIdx.z * blocks_per_group;
   const int64_t b1 = b0 + blocks_per_group < blk_hi ? b0 + blocks_per_group : blk_hi;
   const size_t row = n / 4;                               // u32x4 between dimension rows
@@ -376,13 +382,18 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
           a2[u][s] += (uint64_t)P1[s] * G1[u][s];
         }
     };
-    auto fold = [&](bool all) {
+    // partial fold a -> (a >> 34) (2^34 mod p) + (a mod 2^34) < 2^60 + 2^34
+    // (three instructions), which leaves room for 8 more products: all three
+    // sums fold every 4 dimensions (a1 takes two products per dimension), and
+    // at most 3 dimensions follow the last fold
+    auto fold = [&]() {
 #pragma unroll
       for (int u = 0; u < NB; ++u)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          a1[u][s] = red_p(a1[u][s], p, mu);
-          if (all) { a0[u][s] = red_p(a0[u][s], p, mu); a2[u][s] = red_p(a2[u][s], p, mu); }
+          a0[u][s] = fold34(a0[u][s], c34);
+          a1[u][s] = fold34(a1[u][s], c34);
+          a2[u][s] = fold34(a2[u][s], c34);
         }
     };
 
@@ -393,7 +404,7 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
 #pragma unroll
       for (int v = 0; v < U; ++v) mac(cur.P0[v], cur.P1[v], cur.G0[v], cur.G1[v]);
       const int32_t done = i + U;
-      if ((done & 7) == 0) fold((done & 15) == 0);
+      if ((done & 3) == 0) fold();
       cur = nxt;
     }
     for (int32_t i = dfull; i < dcount; ++i) {              // remainder, one dimension at a time
@@ -401,7 +412,14 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
       one.load(pr, gb, i, row);
       mac(one.P0[0], one.P1[0], one.G0[0], one.G1[0]);
     }
-    fold(true);
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a0[u][s] = red_p(a0[u][s], p, mu);
+        a1[u][s] = red_p(a1[u][s], p, mu);
+        a2[u][s] = red_p(a2[u][s], p, mu);
+      }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       if (b + u >= b1) break;
@@ -544,13 +562,12 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
             }
           }
         }
-        auto fold = [&](uint64_t a) { return (uint64_t)(uint32_t)(a >> 34) * c34 + (a & ((1ull << 34) - 1)); };
 #pragma unroll
         for (int u = 0; u < MB_BLOCKS; ++u) {
           if (u >= nblk) break;
-          a0[u] = fold(a0[u]);
-          a2[u] = fold(a2[u]);
-          as[u] = fold(as[u]);
+          a0[u] = fold34(a0[u], c34);
+          a2[u] = fold34(a2[u], c34);
+          as[u] = fold34(as[u], c34);
         }
       }
     }
