@@ -167,9 +167,22 @@ k_rsel_hist(const int32_t* __restrict__ scores, uint64_t m, const RselState* __r
   __syncthreads();
   const uint64_t prefix = st->prefix;
   const uint32_t hi_shift = shift + width;
+  const uint32_t lane = __lane_id();
   for (uint64_t i = (uint64_t)blockIdx.x * TK_WG + tid; i < m; i += (uint64_t)gridDim.x * TK_WG) {
     const uint64_t key = score_key(scores[i], i);
-    if (rsel_match(key, prefix, hi_shift)) atomicAdd(&h[(uint32_t)(key >> shift) & ((1u << width) - 1)], 1u);
+    const uint32_t bin =
+        rsel_match(key, prefix, hi_shift) ? (uint32_t)(key >> shift) & ((1u << width) - 1) : 0xffffffffu;
+    // Scores span few high digits, so most lanes of a wave share a bin: the
+    // lanes in the first active lane's bin add their count with one atomic,
+    // the others one each (same-address LDS atomics would serialize).
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(bin);
+    const uint64_t same = __ballot(bin == b0);
+    if (bin == b0) {
+      if (b0 != 0xffffffffu && lane == (uint32_t)(__ffsll((unsigned long long)same) - 1))
+        atomicAdd(&h[b0], (uint32_t)__popcll(same));
+    } else if (bin != 0xffffffffu) {
+      atomicAdd(&h[bin], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t b = tid; b < TK_RS_BINS; b += TK_WG)
@@ -180,19 +193,34 @@ extern "C" __global__ void __launch_bounds__(TK_WG)
 k_rsel_choose(RselState* __restrict__ st, uint32_t shift, uint32_t width, uint32_t* __restrict__ hist) {
   // One workgroup: extend the prefix by the digit where the count from the
   // top reaches `need`, then clear the histogram for the next pass.
+  // Thread j sums the j-th group of `per` bins counted from the top; one
+  // lane scans the 256 group sums, then the bins of the group where the
+  // count reaches `need`.
   __shared__ uint32_t h[TK_RS_BINS];
+  __shared__ uint32_t gsum[TK_WG];
   const uint32_t tid = threadIdx.x, nb = 1u << width;
+  const uint32_t per = (nb + TK_WG - 1) / TK_WG;
   for (uint32_t b = tid; b < TK_RS_BINS; b += TK_WG) {
     h[b] = b < nb ? hist[b] : 0;
     hist[b] = 0;
   }
   __syncthreads();
+  uint32_t s = 0;
+  for (uint32_t e = 0; e < per; ++e) {
+    const uint32_t r = tid * per + e;                   // rank from the top
+    if (r < nb) s += h[nb - 1 - r];
+  }
+  gsum[tid] = s;
+  __syncthreads();
   if (tid == 0) {
-    uint32_t need = st->need, cum = 0, b = nb;
-    while (b > 0) {
-      --b;
-      if (cum + h[b] >= need) break;
+    const uint32_t need = st->need;
+    uint32_t cum = 0, g = 0;
+    while (g + 1 < TK_WG && cum + gsum[g] < need) cum += gsum[g++];
+    uint32_t r = g * per, b = nb - 1 - r;
+    while (r + 1 < nb && cum + h[b] < need) {
       cum += h[b];
+      ++r;
+      b = nb - 1 - r;
     }
     st->prefix |= (uint64_t)b << shift;
     st->need = need - cum;
@@ -256,11 +284,14 @@ hipError_t launch_topk_large(const int32_t* scores, uint64_t m, uint32_t k, void
   hipError_t e = hipGetLastError();
   uint64_t grid = (m + TK_WG - 1) / TK_WG;
   if (grid > (uint64_t)num_cus * 4) grid = (uint64_t)num_cus * 4;
+  // histogram passes: one workgroup per CU, since every workgroup adds its
+  // count of the few hot bins to the same global words
+  const uint64_t hgrid = grid < num_cus ? grid : num_cus;
   static const uint32_t widths[6] = {11, 11, 11, 11, 11, 9};
   uint32_t shift = 64;
   for (int p = 0; p < 6 && e == hipSuccess; ++p) {
     shift -= widths[p];
-    hipLaunchKernelGGL(k_rsel_hist, dim3((uint32_t)grid), dim3(TK_WG), 0, s, scores, m, st, shift, widths[p], hist);
+    hipLaunchKernelGGL(k_rsel_hist, dim3((uint32_t)hgrid), dim3(TK_WG), 0, s, scores, m, st, shift, widths[p], hist);
     e = hipGetLastError();
     if (e != hipSuccess) break;
     hipLaunchKernelGGL(k_rsel_choose, dim3(1), dim3(TK_WG), 0, s, st, shift, widths[p], hist);
