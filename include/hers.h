@@ -324,8 +324,9 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * radix 4, 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not
  * NULL -- whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16
  * (chunks of at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule
- * found first or schedule 10 (a combination other than no chunks, default
- * grid, schedule found first must be 3% faster to be kept).  Keeps the
+ * found first, schedule 8 or schedule 10 (a combination other than no
+ * chunks, default grid, schedule found first must be 3% faster to be
+ * kept).  Keeps the
  * fastest of each in the context and returns the schedule in *chosen (may
  * be NULL).  The workspace and
  * scores_dev contents are overwritten; the call synchronizes `stream`. */

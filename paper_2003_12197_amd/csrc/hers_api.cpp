@@ -945,19 +945,20 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   if (rc == HERS_OK) ctx->mac_variant = best_v;
   // overlapped search: whole searches over chunk counts 1, 2, 4, 8, 16
   // (chunks of at least 16 blocks) x MAC workgroups per CU (8, 1, 2) x the
-  // schedule chosen above or schedule 10 (fewer registers, so epilogue waves
-  // fit beside it)
+  // schedule chosen above, the default schedule 8 (the one timed alone need
+  // not be the best beside the epilogue) and schedule 10 (fewer registers, so
+  // epilogue waves fit beside it)
   if (rc == HERS_OK && scores_dev) {
     float best_o = 0.f, plain_ms = 0.f;
     int best_nch = 1, best_w = 0, best_mv = best_v;
-    const int vs[2] = {best_v, 10};
+    const int vs[3] = {best_v, 8, 10};
     bool first = true;
     for (int nch = 1; nch <= 16 && rc == HERS_OK; nch *= 2) {
       if (nch > 1 && M / nch < 16) break;
       for (int w : {0, 1, 2}) {
         if (rc != HERS_OK) break;
-        for (int vi = 0; vi < 2 && rc == HERS_OK; ++vi) {
-          if (vi == 1 && vs[1] == vs[0]) continue;
+        for (int vi = 0; vi < 3 && rc == HERS_OK; ++vi) {
+          if ((vi >= 1 && vs[vi] == vs[0]) || (vi == 2 && vs[2] == vs[1])) continue;
           ctx->overlap_chunks = nch;
           ctx->mac_wgs_per_cu = w;
           ctx->mac_variant = vs[vi];
