@@ -231,7 +231,7 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
   c->T.C = dC;
   c->T.ntt_r = 4;
   c->T.qf_ok = 1;
-  for (uint32_t i = 0; i < C.k; ++i) c->T.qf_ok &= C.q[i] < (1ull << 48);
+  for (uint32_t i = 0; i < C.k; ++i) c->T.qf_ok &= C.q[i] < (1ull << 45);
   c->T.pk_ntt = (uint64_t*)pk;
   c->T.pk_ntt_sh = (uint64_t*)pks;
   c->T.rlk_ntt = (uint64_t*)rl;

@@ -193,7 +193,8 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
     for (uint32_t j = tid; j < n; j += WG_ENC) Uf[PADX(j)] = (double)((W[j >> 6] >> (j & 63)) & 1);
     __syncthreads();
     const double* twf = T.qtw_f + (size_t)rho * n;
-    ntt_forward16(Uf, twf, twf, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
+    const ModQB mb{mf.q, mf.qinv};
+    ntt_forward_b(Uf, twf, mb, n, C.logn, tid, WG_ENC, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG_ENC) {
       const double u = Uf[PADX(j)];
       Vf[PADX(j)] = mf.mul(u, u64_to_f(pk1[j]), 0.0);
@@ -202,8 +203,8 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
     __syncthreads();
     const double* itwf = T.qitw_f + (size_t)rho * n;
     const double ninv = T.qf[2 * HC_MAXQ + rho];
-    ntt_inverse16(Uf, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
-    ntt_inverse16(Vf, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG_ENC, T.ntt_r);
+    ntt_inverse_b(Uf, itwf, ninv, mb, n, C.logn, tid, WG_ENC, T.ntt_r);
+    ntt_inverse_b(Vf, itwf, ninv, mb, n, C.logn, tid, WG_ENC, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG_ENC) {
       U[PADX(j)] = f_to_u64(Uf[PADX(j)]);
       V[PADX(j)] = f_to_u64(Vf[PADX(j)]);
@@ -651,7 +652,7 @@ k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
     for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(a[j]);
     __syncthreads();
     const double* tw = T.qtw_f + (size_t)sg * n;
-    ntt_forward16(f, tw, tw, ModQF{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
+    ntt_forward_b(f, tw, ModQB{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG) a[j] = f_to_u64(f[PADX(j)]);
   } else {
     for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
@@ -695,7 +696,7 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
     __syncthreads();
     const double* itw = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
-    ntt_inverse16(f, itw, itw, ninv, ninv, mq, n, C.logn, tid, WG, T.ntt_r);
+    ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, WG, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
     return;
   }
@@ -777,7 +778,10 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
     for (uint32_t e = 0; e < RL_PER; ++e)
       if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(dg[tid + e * nthr]);
     __syncthreads();
-    ntt_forward16(a, tw, twsh, mod, n, C.logn, tid, nthr, T.ntt_r);
+    if constexpr (QF)
+      ntt_forward_b(a, tw, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
+    else
+      ntt_forward16(a, tw, twsh, mod, n, C.logn, tid, nthr, T.ntt_r);
     const size_t k0 = (((size_t)g * 2 + 0) * k + sg) * n, k1 = (((size_t)g * 2 + 1) * k + sg) * n;
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e) {
@@ -794,7 +798,10 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
     for (uint32_t e = 0; e < RL_PER; ++e)
       if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
     __syncthreads();
-    ntt_inverse16(a, itw, itwsh, ninv, ninv_sh, mod, n, C.logn, tid, nthr, T.ntt_r);
+    if constexpr (QF)
+      ntt_inverse_b(a, itw, ninv, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
+    else
+      ntt_inverse16(a, itw, itwsh, ninv, ninv_sh, mod, n, C.logn, tid, nthr, T.ntt_r);
     uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
 #pragma unroll RL_UNROLL
     for (uint32_t e = 0; e < RL_PER; ++e) {
@@ -841,12 +848,13 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(c1[j]);
     __syncthreads();
     const double* twf = T.qtw_f + (size_t)sg * n;
-    ntt_forward16(f, twf, twf, mf, n, C.logn, tid, WG, T.ntt_r);
+    const ModQB mb{mf.q, mf.qinv};
+    ntt_forward_b(f, twf, mb, n, C.logn, tid, WG, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(S[(size_t)sg * n + j]), 0.0);
     __syncthreads();
     const double* itwf = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
-    ntt_inverse16(f, itwf, itwf, ninv, ninv, mf, n, C.logn, tid, WG, T.ntt_r);
+    ntt_inverse_b(f, itwf, ninv, mb, n, C.logn, tid, WG, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(f_to_u64(f[PADX(j)]), c0[j], q);
     return;
   }

@@ -207,6 +207,137 @@ HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M m
   HERS_SYNC();
 }
 
+// ---- balanced double-precision transforms (every q < 2^45)
+// Values are exact integers held in doubles, kept in a signed (balanced)
+// range instead of [0, 4q), so a butterfly needs no conditional corrections.
+//   mul(a, w) = a w mod q as some r with |r| < 0.7 q, for |a| <= 16 q and
+//     0 <= w < q: hi = fl(a w), lo = a w - hi (exact, one fused multiply-add),
+//     qt = rint(hi / q), within 0.63 of hi / q since |hi / q| < 2^49 and the
+//     rounding errors are below 2^-52 relative; r = (hi - qt q) + lo, both
+//     steps exact, with |lo| <= a w 2^-53 < q / 16.
+//   red(x) = x - rint(x / q) q, |red(x)| <= q/2 + 1, for |x| < 2^50.
+// A forward (Cooley-Tukey) stage maps (u, v) to (u + v w, u - v w), growing
+// magnitudes by < 0.7 q; an inverse (Gentleman-Sande) stage maps (u, v) to
+// (u + v, (u - v) w), doubling the sum.  Each pass (at most 4 stages) starts
+// from values of magnitude <= q and reduces what it stores, so no value
+// exceeds 16 q (< 2^49).
+struct ModQB {
+  double q, qinv;   // qinv = fl(1 / q)
+  HD double mul(double a, double w) const {
+#pragma clang fp contract(off)
+    const double hi = a * w;
+    const double lo = __builtin_fma(a, w, -hi);
+    return __builtin_fma(-__builtin_rint(hi * qinv), q, hi) + lo;
+  }
+  HD double red(double x) const {
+#pragma clang fp contract(off)
+    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+  }
+  HD double canon(double x) const {   // [0, q) from |x| < 2^50
+    const double r = red(x);
+    return r < 0.0 ? r + q : r;
+  }
+};
+
+template <int R>
+HD void ntt_fwd_pass_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t s0, uint32_t tid,
+                       uint32_t nthr) {
+  constexpr uint32_t E = 1u << R;
+  const uint32_t lh = 31 - __builtin_clz(n >> (s0 + R));   // log2 h
+  const uint32_t h = 1u << lh;
+  const uint32_t vts = n >> R;
+  for (uint32_t vt = tid; vt < vts; vt += nthr) {
+    const uint32_t c = vt >> lh, o = vt & (h - 1);
+    const uint32_t base = (c << (lh + R)) + o;
+    double x[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+#pragma unroll
+    for (uint32_t t = 0; t < R; ++t) {
+      const uint32_t span = E >> (t + 1);
+      const uint32_t m = 1u << (s0 + t);
+#pragma unroll
+      for (uint32_t j = 0; j < E; ++j) {
+        if (j & span) continue;
+        const double v = mod.mul(x[j + span], tw[m + (c << t) + (j / (2 * span))]);
+        const double u = x[j];
+        x[j] = u + v;
+        x[j + span] = u - v;
+      }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = mod.red(x[j]);
+  }
+  HERS_SYNC();
+}
+
+template <int R>
+HD void ntt_inv_pass_b(double* a, const double* itw, ModQB mod, uint32_t n, uint32_t lh0, uint32_t tid,
+                       uint32_t nthr) {
+  constexpr uint32_t E = 1u << R;
+  const uint32_t h = 1u << lh0;
+  const uint32_t vts = n >> R;
+  for (uint32_t vt = tid; vt < vts; vt += nthr) {
+    const uint32_t c = vt >> lh0, o = vt & (h - 1);
+    const uint32_t base = (c << (lh0 + R)) + o;
+    double x[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+#pragma unroll
+    for (uint32_t t = 0; t < R; ++t) {
+      const uint32_t span = 1u << t;
+      const uint32_t m = n >> (lh0 + t + 1);
+#pragma unroll
+      for (uint32_t j = 0; j < E; ++j) {
+        if (j & span) continue;
+        const double u = x[j], v = x[j + span];
+        x[j] = u + v;
+        x[j + span] = mod.mul(u - v, itw[m + (c << (R - 1 - t)) + (j >> (t + 1))]);
+      }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = mod.red(x[j]);
+  }
+  HERS_SYNC();
+}
+
+// Forward transform of values in [0, q) (or of magnitude <= q); output in [0, q).
+HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t logn, uint32_t tid,
+                      uint32_t nthr, uint32_t rmax = 4) {
+  uint32_t s0 = 0;
+  while (s0 < logn) {
+    const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
+    switch (r) {
+      case 4: ntt_fwd_pass_b<4>(a, tw, mod, n, s0, tid, nthr); break;
+      case 3: ntt_fwd_pass_b<3>(a, tw, mod, n, s0, tid, nthr); break;
+      case 2: ntt_fwd_pass_b<2>(a, tw, mod, n, s0, tid, nthr); break;
+      default: ntt_fwd_pass_b<1>(a, tw, mod, n, s0, tid, nthr); break;
+    }
+    s0 += r;
+  }
+  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(a[PADX(j)]);
+  HERS_SYNC();
+}
+
+// Inverse transform scaled by n^-1 (ninv in [0, q)) of values of magnitude
+// <= q; output in [0, q).
+HD void ntt_inverse_b(double* a, const double* itw, double ninv, ModQB mod, uint32_t n, uint32_t logn,
+                      uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
+  uint32_t lh0 = 0;
+  while (lh0 < logn) {
+    const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
+    switch (r) {
+      case 4: ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
+      case 3: ntt_inv_pass_b<3>(a, itw, mod, n, lh0, tid, nthr); break;
+      case 2: ntt_inv_pass_b<2>(a, itw, mod, n, lh0, tid, nthr); break;
+      default: ntt_inv_pass_b<1>(a, itw, mod, n, lh0, tid, nthr); break;
+    }
+    lh0 += r;
+  }
+  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(mod.mul(a[PADX(j)], ninv));
+  HERS_SYNC();
+}
+
 HD uint32_t bit_reverse(uint32_t x, uint32_t bits) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __brev(x) >> (32 - bits);
