@@ -186,7 +186,7 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   const uint64_t* pk1 = T.pk_ntt + ((size_t)k + rho) * n;
   const uint64_t* pk1s = T.pk_ntt_sh + ((size_t)k + rho) * n;
   if constexpr (QF) {
-    // u pk0 and u pk1 in double-precision modular arithmetic (ModQF)
+    // u pk0 and u pk1 in double precision: products by ModQF, transforms balanced (ModQB)
     double* Uf = reinterpret_cast<double*>(U);
     double* Vf = reinterpret_cast<double*>(V);
     const ModQF mf{T.qf[rho], T.qf[HC_MAXQ + rho]};
@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(WG)
 k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
   // In-place forward negacyclic NTT mod q_sigma of polynomial blockIdx.x of
   // set blockIdx.y, sigma = blockIdx.x mod k (layouts [..][k][n]); QF: in
-  // double-precision modular arithmetic (ModQF), same residues.
+  // double precision with balanced butterflies (ModQB), same residues.
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, tid = threadIdx.x;
@@ -728,8 +728,8 @@ template <bool QF>
 __global__ void __launch_bounds__(512)
 k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
               const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
-  // QF: the transforms and key products in double-precision modular
-  // arithmetic (ModQF) on elements of type E, converted at the memory edges
+  // QF: the key products (ModQF) and the transforms (balanced, ModQB) in
+  // double precision on elements of type E, converted at the memory edges
   using E = typename std::conditional<QF, double, uint64_t>::type;
   using M = typename std::conditional<QF, ModQF, ModQ>::type;
   extern __shared__ uint64_t lds64[];
@@ -842,7 +842,7 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   const uint64_t* c0 = scores + (((size_t)b * 2 + 0) * k + sg) * n;
   const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * k + sg) * n;
   if constexpr (QF) {
-    // the same product in double-precision modular arithmetic (ModQF)
+    // the same product in double precision: transforms balanced (ModQB), product by ModQF
     double* f = reinterpret_cast<double*>(lds64);
     const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
     for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(c1[j]);
