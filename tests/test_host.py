@@ -79,3 +79,54 @@ def test_table3_memory_matches_canonical_layout():
     for d, gb in zip(pv["dims"], pv["memory_gb"]):
         gib = M * d * 2 * info.k * info.n * 8 / 2**30
         assert abs(gib - gb) / gb < 0.05
+
+
+def test_double_precision_modular_arithmetic(tmp_path):
+    """The double-precision modular arithmetic of the transforms (ModQF,
+    ModQB in ntt.h), compiled for the host, against exact integers: ModQF
+    products are the residue in [0, q); ModQB products are congruent and of
+    magnitude < 0.7 q for |a| <= 16 q; ModQB reductions are congruent and of
+    magnitude <= q/2 + 1; the u64 <-> double conversions are exact below 2^52.
+    Primes just below 2^36, 2^44 and 2^45 (the largest the balanced path
+    accepts), operands random and at the extremes."""
+    import random
+    import shutil
+    import subprocess
+
+    from oracle import primes
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    src = os.path.join(os.path.dirname(__file__), "native", "f64_modarith.cpp")
+    exe = str(tmp_path / "f64_modarith")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-Wno-unknown-pragmas", "-o", exe, src], check=True)
+    rng = random.Random(2003)
+    cases = []
+    for bits in (36, 44, 45):
+        for q in primes.ntt_primes([bits, bits], 8192):
+            for _ in range(400):
+                w = rng.randrange(q)
+                cases.append(("F", q, rng.randrange(4 * q), w))
+                cases.append(("B", q, rng.randrange(-16 * q, 16 * q + 1), w))
+                cases.append(("R", q, rng.randrange(-16 * q, 16 * q + 1), 0))
+            for a in (0, 1, q - 1, 4 * q - 1):
+                cases.append(("F", q, a, q - 1))
+            for a in (-16 * q, 16 * q, -16 * q + 1, 16 * q - 1, 8 * q + q // 2):
+                cases.append(("B", q, a, q - 1))
+                cases.append(("R", q, a, 0))
+    for v in (0, 1, 2**36 - 5, 2**51 + 12345, 2**52 - 1):
+        cases.append(("C", 0, v, 0))
+    inp = "".join("%s %d %d %d\n" % c for c in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    assert len(out) == len(cases)
+    for (op, q, a, w), r in zip(cases, out):
+        r = int(r)
+        if op == "F":
+            assert r == a * w % q, (op, q, a, w, r)
+        elif op == "B":
+            assert (r - a * w) % q == 0 and 10 * abs(r) < 7 * q, (op, q, a, w, r)
+        elif op == "R":
+            assert (r - a) % q == 0 and 2 * abs(r) <= q + 2, (op, q, a, r)
+        else:
+            assert r == a, (op, a, r)
