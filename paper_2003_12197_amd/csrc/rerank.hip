@@ -133,38 +133,44 @@ k_rot_digits(DevTabs T, const uint64_t* __restrict__ in, uint64_t* __restrict__ 
              uint32_t nct, uint32_t ginv) {
   // First half of rotate-and-add for ciphertexts [nct][2][k][n]: out =
   // (c0 + tau(c0), c1) and the gadget digits of tau(c1) ([nct][L][k][n],
-  // reduced mod every q_sigma), tau: x^i -> +-x^(i g mod 2n).  One thread per
-  // destination coefficient dst (coalesced writes): with ginv = g^-1 mod 2n,
-  // i = dst ginv mod 2n is the source if i < n (sign +), else i - n is, with
-  // sign - (x^(i - n) maps to x^(dst + n) = -x^dst).
+  // reduced mod every q_sigma), tau: x^i -> +-x^(i g mod 2n).  One workgroup
+  // per (ciphertext blockIdx.x, residue r = blockIdx.y): residue r of c0 and
+  // c1 is read once, coalesced, into LDS; the digits of q_r need only that
+  // residue of tau(c1).  For destination coefficient dst, with ginv = g^-1
+  // mod 2n, i = dst ginv mod 2n is the source if i < n (sign +), else i - n
+  // is, with sign - (x^(i - n) maps to x^(dst + n) = -x^dst).
+  extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
-  const uint32_t n = C.n, k = C.k, L = C.L;
-  const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
-  if (idx >= (uint64_t)nct * n) return;
-  const uint64_t c = idx >> C.logn;
-  const uint32_t dst = (uint32_t)(idx & (n - 1));
-  const uint32_t e = (dst * ginv) & (2 * n - 1);
-  const bool neg = e >= n;
-  const uint32_t i = e & (n - 1);
-  const uint64_t* c0 = in + c * 2 * k * n;
-  const uint64_t* c1 = c0 + (size_t)k * n;
-  uint64_t* o0 = out + c * 2 * k * n;
-  uint64_t* o1 = o0 + (size_t)k * n;
-  uint64_t t1[HC_MAXQ];
-  for (uint32_t r = 0; r < k; ++r) {
-    const uint64_t q = C.q[r];
-    uint64_t v0 = c0[(size_t)r * n + i], v1 = c1[(size_t)r * n + i];
-    if (neg) { v0 = v0 ? q - v0 : 0; v1 = v1 ? q - v1 : 0; }
-    o0[(size_t)r * n + dst] = add_q(c0[(size_t)r * n + dst], v0, q);
-    o1[(size_t)r * n + dst] = c1[(size_t)r * n + dst];
-    t1[r] = v1;
+  const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
+  const uint64_t c = blockIdx.x;
+  const uint32_t r = blockIdx.y;
+  const uint64_t q = C.q[r];
+  const uint64_t* c0 = in + (c * 2 * k + r) * n;
+  const uint64_t* c1 = in + (c * 2 * k + k + r) * n;
+  uint64_t* o0 = out + (c * 2 * k + r) * n;
+  uint64_t* o1 = out + (c * 2 * k + k + r) * n;
+  uint64_t* s0 = lds64;
+  uint64_t* s1 = lds64 + n;
+  for (uint32_t j = tid; j < n; j += WG) {
+    const uint64_t v1 = c1[j];
+    s0[j] = c0[j];
+    s1[j] = v1;
+    o1[j] = v1;
   }
-  for (uint32_t gi = 0; gi < L; ++gi) {
-    const uint32_t rho = C.g_rho[gi];
-    const uint64_t y = shoup_q(t1[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
-    const uint64_t dg = C.w_bits ? (y >> C.g_shift[gi]) & ((1ULL << C.w_bits) - 1) : y;
-    for (uint32_t s = 0; s < k; ++s)
-      digits[((c * L + gi) * k + s) * n + dst] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+  __syncthreads();
+  for (uint32_t dst = tid; dst < n; dst += WG) {
+    const uint32_t e = (dst * ginv) & (2 * n - 1);
+    const uint32_t i = e & (n - 1);
+    uint64_t v0 = s0[i], v1 = s1[i];
+    if (e >= n) { v0 = v0 ? q - v0 : 0; v1 = v1 ? q - v1 : 0; }
+    o0[dst] = add_q(s0[dst], v0, q);
+    const uint64_t y = shoup_q(v1, C.q_hatinv[r], C.q_hatinv_sh[r], q);
+    for (uint32_t gi = 0; gi < L; ++gi) {
+      if (C.g_rho[gi] != r) continue;
+      const uint64_t dg = C.w_bits ? (y >> C.g_shift[gi]) & ((1ULL << C.w_bits) - 1) : y;
+      for (uint32_t s = 0; s < k; ++s)
+        digits[((c * L + gi) * k + s) * n + dst] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+    }
   }
 }
 
@@ -212,7 +218,6 @@ hipError_t launch_rotkey(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, u
 
 hipError_t launch_rot_digits(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* ct_in, uint64_t* ct_out,
                              uint64_t* digits, uint32_t nct, uint32_t g, hipStream_t s) {
-  (void)k;
   // g^-1 mod 2n (g odd): the group has order n, so g^-1 = g^(n - 1)
   const uint32_t mask = 2 * n - 1;
   uint32_t ginv = 1, b = g;
@@ -220,9 +225,8 @@ hipError_t launch_rot_digits(const DevTabs& T, uint32_t n, uint32_t k, const uin
     if (x & 1) ginv = (uint32_t)(((uint64_t)ginv * b) & mask);
     b = (uint32_t)(((uint64_t)b * b) & mask);
   }
-  const uint64_t total = (uint64_t)nct * n;
-  hipLaunchKernelGGL(k_rot_digits, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, ct_in, ct_out, digits,
-                     nct, ginv);
+  hipLaunchKernelGGL(k_rot_digits, dim3(nct, k), dim3(WG), (size_t)2 * n * 8, s, T, ct_in, ct_out, digits, nct,
+                     ginv);
   return hipGetLastError();
 }
 
