@@ -230,6 +230,7 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
     c->num_cus = cus;
   c->T.C = dC;
   c->T.ntt_r = 4;
+  c->T.nq = C.k;
   c->T.qf_ok = 1;
   for (uint32_t i = 0; i < C.k; ++i) c->T.qf_ok &= C.q[i] < (1ull << 45);
   c->T.pk_ntt = (uint64_t*)pk;

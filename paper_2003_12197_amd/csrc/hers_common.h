@@ -239,10 +239,11 @@ HD uint32_t mixed_to_p(const HersConsts& C, const uint64_t* a, bool neg, uint32_
 }
 
 // Centred representative of (a, neg) modulo t.
+template <int KQ = 0>
 HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
   const uint32_t t = C.t;
   uint32_t acc = 0;
-  for (uint32_t i = 0; i < C.k; ++i) {
+  for (uint32_t i = 0; i < (KQ ? KQ : C.k); ++i) {
     uint32_t ai = red_p(a[i], t, C.t_mu64);
     acc = add_p(acc, shoup_p(ai, C.Qw_t[i], C.Qw_t_sh[i], t), t);
   }
@@ -269,6 +270,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = FW ? FW : C.fr_words;
   uint32_t y[KP ? KP : HC_MAXP];
   double s = 0.0;
+#pragma unroll
   for (uint32_t r = 0; r < K; ++r) {
     y[r] = shoup_p(x[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
     s += (double)y[r] * C.p_inv[r];
@@ -276,9 +278,12 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   const uint64_t gamma = (uint64_t)__builtin_rint(s);
   // F in fixed point: f[0 .. W-1] fraction words, f[W] the integer part (two's complement)
   uint64_t f[(FW ? FW : HC_MAXW) + 1];
+#pragma unroll
   for (uint32_t w = 0; w <= W; ++w) f[w] = 0;
+#pragma unroll
   for (uint32_t r = 0; r < K; ++r) {
     uint64_t carry = 0;
+#pragma unroll
     for (uint32_t w = 0; w < W; ++w) {
       const u128 v = (u128)y[r] * C.fr_phi[r][w] + f[w] + carry;
       f[w] = (uint64_t)v;
@@ -288,6 +293,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   }
   {
     uint64_t carry = 0, borrow = 0;
+#pragma unroll
     for (uint32_t w = 0; w < W; ++w) {
       const u128 g = (u128)gamma * C.fr_psi[w] + carry;
       carry = (uint64_t)(g >> 64);
@@ -299,9 +305,11 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
     f[W] -= carry + borrow;
   }
   const int64_t rf = (int64_t)f[W] + (int64_t)(f[W - 1] >> 63);   // round(F)
+#pragma unroll
   for (uint32_t i = 0; i < k; ++i) {
     const uint64_t q = C.q[i];
     u128 acc = 0;                                   // sum_r y_r (I_r mod q_i) < K 2^91
+#pragma unroll
     for (uint32_t r = 0; r < K; ++r) acc += (u128)y[r] * C.fr_I[r][i];
     uint64_t v = sub_q(red128_q(C, acc, i), shoup_q(gamma, C.fr_J[i], C.fr_J_sh[i], q), q);
     const uint64_t ra = red_q(rf >= 0 ? (uint64_t)rf : (uint64_t)(-rf), q, C.q_mu64[i]);
@@ -312,11 +320,12 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
 
 // Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,
 // returns [round(t x / q)]_t in [0, t): with t x = q Y + T as above, Y = -T q^-1 mod t.
+template <int KQ = 0>
 HD uint32_t decrypt_coeff(const HersConsts& C, const uint64_t* x) {
-  uint64_t tx[HC_MAXQ], a[HC_MAXQ];
-  for (uint32_t i = 0; i < C.k; ++i) tx[i] = shoup_q(x[i], C.q_t[i], C.q_t_sh[i], C.q[i]);
-  const bool neg = garner_digits(C, tx, a);
-  uint32_t T = mixed_to_t(C, a, neg);
+  uint64_t tx[KQ ? KQ : HC_MAXQ], a[KQ ? KQ : HC_MAXQ];
+  for (uint32_t i = 0; i < (KQ ? KQ : C.k); ++i) tx[i] = shoup_q(x[i], C.q_t[i], C.q_t_sh[i], C.q[i]);
+  const bool neg = garner_digits<KQ>(C, tx, a);
+  uint32_t T = mixed_to_t<KQ>(C, a, neg);
   uint32_t y = shoup_p(T, C.qinv_t, C.qinv_t_sh, C.t);
   return y ? C.t - y : 0;
 }

@@ -251,27 +251,30 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   }
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+template <int KQ>
+__global__ void __launch_bounds__(WG)
 k_lift(DevTabs T, const uint64_t* __restrict__ canon, uint32_t nct, int32_t d, int64_t block0,
        uint32_t* __restrict__ out) {
   // Exact centred lift of canonical residues mod q to residues mod p_r
   // (the representative in (-q/2, q/2) that the tensor product needs):
   // Garner mixed-radix digits decide the sign exactly, then the digits are
   // evaluated mod p_r.  Writes the search form (coefficient domain).
+  // KQ: the number of q primes at compile time (0: read from C), so the
+  // Garner digits stay in statically indexed registers
   const HersConsts& C = *T.C;
-  const uint32_t n = C.n, k = C.k, K = C.K;
+  const uint32_t n = C.n, k = KQ ? KQ : C.k, K = C.K;
   const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
   if (idx >= (uint64_t)nct * n) return;
   const uint32_t c = (uint32_t)(idx >> C.logn), j = (uint32_t)(idx & (n - 1));
   const int64_t b = block0 + c / d;
   const uint32_t i = c % d;
   for (uint32_t poly = 0; poly < 2; ++poly) {
-    uint64_t v[HC_MAXQ], a[HC_MAXQ];
+    uint64_t v[KQ ? KQ : HC_MAXQ], a[KQ ? KQ : HC_MAXQ];
     for (uint32_t r = 0; r < k; ++r) v[r] = canon[(((size_t)c * 2 + poly) * k + r) * n + j];
-    const bool neg = garner_digits(C, v, a);
+    const bool neg = garner_digits<KQ>(C, v, a);
     for (uint32_t r = 0; r < K; ++r) {
       const size_t o = ((((size_t)b * K + r) * d + i) * 2 + poly) * n + j;
-      out[o] = mixed_to_p(C, a, neg, r);
+      out[o] = mixed_to_p<KQ>(C, a, neg, r);
     }
   }
 }
@@ -626,7 +629,8 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   // gadget digits come prime-major (all digits of q_rho, then of q_rho+1), so
   // out[rho] is indexed by the unrolled loop counter
   uint32_t g = 0;
-  for (uint32_t rho = 0; rho < k; ++rho) {
+#pragma unroll
+  for (uint32_t rho = 0; rho < (KQ ? KQ : k); ++rho) {
     const uint64_t y = shoup_q(out[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
     for (; g < L && C.g_rho[g] == rho; ++g) {
       const uint64_t dg = C.w_bits ? (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1) : y;
@@ -869,18 +873,20 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
   for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
 }
 
-extern "C" __global__ void __launch_bounds__(WG_DEC)
+template <int KQ>
+__global__ void __launch_bounds__(WG_DEC)
 k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t m, int32_t* __restrict__ out) {
   // pt = [round(t x / q)]_t coefficient-wise, then slot j = pt(psi^(2j+1))
-  // (forward NTT mod t, read at brv(j)), centred into [-t/2, t/2).
+  // (forward NTT mod t, read at brv(j)), centred into [-t/2, t/2).  KQ: the
+  // number of q primes at compile time (0: read from C).
   extern __shared__ uint32_t lds32[];
   const HersConsts& C = *T.C;
-  const uint32_t n = C.n, k = C.k, tid = threadIdx.x, t = C.t;
+  const uint32_t n = C.n, k = KQ ? KQ : C.k, tid = threadIdx.x, t = C.t;
   const int64_t bl = blockIdx.x, b = blk_lo + bl;
   for (uint32_t j = tid; j < n; j += WG_DEC) {
-    uint64_t v[HC_MAXQ];
+    uint64_t v[KQ ? KQ : HC_MAXQ];
     for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
-    lds32[PADX(j)] = decrypt_coeff(C, v);
+    lds32[PADX(j)] = decrypt_coeff<KQ>(C, v);
   }
   __syncthreads();
   ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG_DEC, T.ntt_r);
@@ -942,8 +948,14 @@ hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct
 
 hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
                        int64_t block0, uint32_t* out, hipStream_t s) {
-  uint64_t total = (uint64_t)nct * n;
-  hipLaunchKernelGGL(k_lift, dim3((uint32_t)((total + WG - 1) / WG)), dim3(WG), 0, s, T, canon, nct, d, block0, out);
+  const dim3 grid((uint32_t)(((uint64_t)nct * n + WG - 1) / WG));
+  switch (T.nq) {   // the prime counts of the parameter sets in use get unrolled bodies
+    case 1: hipLaunchKernelGGL(k_lift<1>, grid, dim3(WG), 0, s, T, canon, nct, d, block0, out); break;
+    case 2: hipLaunchKernelGGL(k_lift<2>, grid, dim3(WG), 0, s, T, canon, nct, d, block0, out); break;
+    case 3: hipLaunchKernelGGL(k_lift<3>, grid, dim3(WG), 0, s, T, canon, nct, d, block0, out); break;
+    case 5: hipLaunchKernelGGL(k_lift<5>, grid, dim3(WG), 0, s, T, canon, nct, d, block0, out); break;
+    default: hipLaunchKernelGGL(k_lift<0>, grid, dim3(WG), 0, s, T, canon, nct, d, block0, out); break;
+  }
   return hipGetLastError();
 }
 
@@ -1075,7 +1087,15 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
 
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dec_decode, dim3((uint32_t)nblk), dim3(WG_DEC), lds_bytes32(n), s, T, x, blk_lo, m, out);
+  const dim3 grid((uint32_t)nblk);
+  const size_t lds = lds_bytes32(n);
+  switch (T.nq) {
+    case 1: hipLaunchKernelGGL(k_dec_decode<1>, grid, dim3(WG_DEC), lds, s, T, x, blk_lo, m, out); break;
+    case 2: hipLaunchKernelGGL(k_dec_decode<2>, grid, dim3(WG_DEC), lds, s, T, x, blk_lo, m, out); break;
+    case 3: hipLaunchKernelGGL(k_dec_decode<3>, grid, dim3(WG_DEC), lds, s, T, x, blk_lo, m, out); break;
+    case 5: hipLaunchKernelGGL(k_dec_decode<5>, grid, dim3(WG_DEC), lds, s, T, x, blk_lo, m, out); break;
+    default: hipLaunchKernelGGL(k_dec_decode<0>, grid, dim3(WG_DEC), lds, s, T, x, blk_lo, m, out); break;
+  }
   return hipGetLastError();
 }
 
