@@ -686,22 +686,55 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
   uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
   if constexpr (QF) {
+    // RA coefficients per lane at a time, so each digit's loads for all of
+    // them are in flight together (the digit loop has a runtime bound); rings
+    // smaller than RA WG coefficients take one coefficient at a time
+    constexpr uint32_t RA = 4;
     const ModQF mq{T.qf[sg], T.qf[HC_MAXQ + sg]};
     double* f = reinterpret_cast<double*>(lds64);
-    for (uint32_t j = tid; j < n; j += WG) {
-      double acc = 0.0;
+    const bool batched = n % (RA * WG) == 0;
+    const uint32_t ra = batched ? RA : 1;
+    for (uint32_t j0 = tid; j0 < n; j0 += ra * WG) {
+      double acc[RA];
+#pragma unroll
+      for (uint32_t u = 0; u < RA; ++u) acc[u] = 0.0;
       for (uint32_t g = 0; g < L; ++g) {
-        const size_t r = (((size_t)g * 2 + comp) * k + sg) * n + j;
-        acc += mq.mul(u64_to_f(digits[((size_t)g * k + sg) * n + j]), u64_to_f(key[r]), 0.0);
-        acc = acc >= mq.q ? acc - mq.q : acc;
+        const uint64_t* dg = digits + ((size_t)g * k + sg) * n + j0;
+        const uint64_t* kg = key + (((size_t)g * 2 + comp) * k + sg) * n + j0;
+        if (batched) {
+          uint64_t dv[RA], kv[RA];
+#pragma unroll
+          for (uint32_t u = 0; u < RA; ++u) {
+            dv[u] = dg[u * WG];
+            kv[u] = kg[u * WG];
+          }
+#pragma unroll
+          for (uint32_t u = 0; u < RA; ++u) {
+            const double s = acc[u] + mq.mul(u64_to_f(dv[u]), u64_to_f(kv[u]), 0.0);
+            acc[u] = s >= mq.q ? s - mq.q : s;
+          }
+        } else {
+          const double s = acc[0] + mq.mul(u64_to_f(dg[0]), u64_to_f(kg[0]), 0.0);
+          acc[0] = s >= mq.q ? s - mq.q : s;
+        }
       }
-      f[PADX(j)] = acc;
+      for (uint32_t u = 0; u < ra; ++u) f[PADX(j0 + u * WG)] = acc[u];
     }
     __syncthreads();
     const double* itw = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
     ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, WG, T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
+    if (batched) {
+      for (uint32_t j0 = tid; j0 < n; j0 += RA * WG) {
+        uint64_t dv[RA];
+#pragma unroll
+        for (uint32_t u = 0; u < RA; ++u) dv[u] = dst[j0 + u * WG];
+#pragma unroll
+        for (uint32_t u = 0; u < RA; ++u) dst[j0 + u * WG] = add_q(dv[u], f_to_u64(f[PADX(j0 + u * WG)]), q);
+      }
+    } else {
+      for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
+    }
     return;
   }
   for (uint32_t j = tid; j < n; j += WG) {
