@@ -289,7 +289,7 @@ k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, ui
   const uint32_t n = C.n, tid = threadIdx.x;
   const uint32_t r = (blockIdx.x / inner) % C.K;
   uint32_t* a = polys + (size_t)blockIdx.y * req_stride + (size_t)blockIdx.x * n;
-  for (uint32_t j = tid; j < n; j += WG) lds32[PADX(j)] = a[j];
+  load_padded(lds32, a, n, tid, WG, [](uint32_t v) { return v; });
   __syncthreads();
   const ModP mp{C.p[r]};
   if (!inverse)
@@ -653,13 +653,13 @@ k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
   uint64_t* a = polys + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * n;
   if constexpr (QF) {
     double* f = reinterpret_cast<double*>(lds64);
-    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(a[j]);
+    load_padded(f, a, n, tid, WG, [](uint64_t v) { return u64_to_f(v); });
     __syncthreads();
     const double* tw = T.qtw_f + (size_t)sg * n;
     ntt_forward_b(f, tw, ModQB{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
     for (uint32_t j = tid; j < n; j += WG) a[j] = f_to_u64(f[PADX(j)]);
   } else {
-    for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = a[j];
+    load_padded(lds64, a, n, tid, WG, [](uint64_t v) { return v; });
     __syncthreads();
     ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG,
                   T.ntt_r);
@@ -882,7 +882,7 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     // the same product in double precision: transforms balanced (ModQB), product by ModQF
     double* f = reinterpret_cast<double*>(lds64);
     const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
-    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = u64_to_f(c1[j]);
+    load_padded(f, c1, n, tid, WG, [](uint64_t v) { return u64_to_f(v); });
     __syncthreads();
     const double* twf = T.qtw_f + (size_t)sg * n;
     const ModQB mb{mf.q, mf.qinv};
@@ -895,7 +895,7 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(f_to_u64(f[PADX(j)]), c0[j], q);
     return;
   }
-  for (uint32_t j = tid; j < n; j += WG) lds64[PADX(j)] = c1[j];
+  load_padded(lds64, c1, n, tid, WG, [](uint64_t v) { return v; });
   __syncthreads();
   ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG, T.ntt_r);
   for (uint32_t j = tid; j < n; j += WG)

@@ -93,6 +93,25 @@ HD uint64_t f_to_u64(double x) {
 #define PADX(j) ((j) + ((j) >> 4))
 HD uint32_t padded_len(uint32_t n) { return n + (n >> 4); }
 
+// Copies n words src[j] into LDS at dst[PADX(j)], converted by conv, four per
+// lane at a time so their global loads are in flight together (a loop of one
+// load per iteration waits on each in turn); n not a multiple of 4 nthr goes
+// one word at a time.
+template <class D, class S, class F>
+HD void load_padded(D* dst, const S* __restrict__ src, uint32_t n, uint32_t tid, uint32_t nthr, F conv) {
+  if (n % (4 * nthr) == 0) {
+    for (uint32_t j = tid; j < n; j += 4 * nthr) {
+      const S v0 = src[j], v1 = src[j + nthr], v2 = src[j + 2 * nthr], v3 = src[j + 3 * nthr];
+      dst[PADX(j)] = conv(v0);
+      dst[PADX(j + nthr)] = conv(v1);
+      dst[PADX(j + 2 * nthr)] = conv(v2);
+      dst[PADX(j + 3 * nthr)] = conv(v3);
+    }
+  } else {
+    for (uint32_t j = tid; j < n; j += nthr) dst[PADX(j)] = conv(src[j]);
+  }
+}
+
 // ---- radix-16 passes
 // The stages are taken in passes of R <= 4.  In a pass over stages
 // s0 .. s0+R-1 (forward, half = n >> (s+1)) the 2^R elements
