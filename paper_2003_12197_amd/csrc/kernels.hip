@@ -195,11 +195,11 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
     const double* twf = T.qtw_f + (size_t)rho * n;
     const ModQB mb{mf.q, mf.qinv};
     ntt_forward_b(Uf, twf, mb, n, C.logn, tid, WG_ENC, T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG_ENC) {
+    for_each_loaded2(pk0, pk1, n, tid, WG_ENC, [&](uint32_t j, uint64_t k0, uint64_t k1) {
       const double u = Uf[PADX(j)];
-      Vf[PADX(j)] = mf.mul(u, u64_to_f(pk1[j]), 0.0);
-      Uf[PADX(j)] = mf.mul(u, u64_to_f(pk0[j]), 0.0);
-    }
+      Vf[PADX(j)] = mf.mul(u, u64_to_f(k1), 0.0);
+      Uf[PADX(j)] = mf.mul(u, u64_to_f(k0), 0.0);
+    });
     __syncthreads();
     const double* itwf = T.qitw_f + (size_t)rho * n;
     const double ninv = T.qf[2 * HC_MAXQ + rho];
@@ -632,8 +632,14 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
 #pragma unroll
   for (uint32_t rho = 0; rho < (KQ ? KQ : k); ++rho) {
     const uint64_t y = shoup_q(out[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
+    if (!C.w_bits) {                                    // one digit per prime: digit rho is y itself
+#pragma unroll
+      for (uint32_t s = 0; s < (KQ ? KQ : k); ++s)
+        digits[(((size_t)bl * L + rho) * k + s) * n + c] = y >= C.q[s] ? red_q(y, C.q[s], C.q_mu64[s]) : y;
+      continue;
+    }
     for (; g < L && C.g_rho[g] == rho; ++g) {
-      const uint64_t dg = C.w_bits ? (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1) : y;
+      const uint64_t dg = (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1);
       for (uint32_t s = 0; s < k; ++s)
         digits[(((size_t)bl * L + g) * k + s) * n + c] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
     }
@@ -887,12 +893,14 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     const double* twf = T.qtw_f + (size_t)sg * n;
     const ModQB mb{mf.q, mf.qinv};
     ntt_forward_b(f, twf, mb, n, C.logn, tid, WG, T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG) f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(S[(size_t)sg * n + j]), 0.0);
+    for_each_loaded(S + (size_t)sg * n, n, tid, WG,
+                    [&](uint32_t j, uint64_t sv) { f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(sv), 0.0); });
     __syncthreads();
     const double* itwf = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
     ntt_inverse_b(f, itwf, ninv, mb, n, C.logn, tid, WG, T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(f_to_u64(f[PADX(j)]), c0[j], q);
+    uint64_t* xo = xout + ((size_t)bl * k + sg) * n;
+    for_each_loaded(c0, n, tid, WG, [&](uint32_t j, uint64_t v0) { xo[j] = add_q(f_to_u64(f[PADX(j)]), v0, q); });
     return;
   }
   load_padded(lds64, c1, n, tid, WG, [](uint64_t v) { return v; });
@@ -916,10 +924,23 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = KQ ? KQ : C.k, tid = threadIdx.x, t = C.t;
   const int64_t bl = blockIdx.x, b = blk_lo + bl;
-  for (uint32_t j = tid; j < n; j += WG_DEC) {
-    uint64_t v[KQ ? KQ : HC_MAXQ];
-    for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
-    lds32[PADX(j)] = decrypt_coeff<KQ>(C, v);
+  if (KQ && n % (4 * WG_DEC) == 0) {
+    // four coefficients per lane, all their residues loaded before the Garner work
+    for (uint32_t j0 = tid; j0 < n; j0 += 4 * WG_DEC) {
+      uint64_t v[4][KQ ? KQ : 1];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u)
+#pragma unroll
+        for (uint32_t i = 0; i < (KQ ? KQ : 1); ++i) v[u][i] = x[((size_t)bl * k + i) * n + j0 + u * WG_DEC];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) lds32[PADX(j0 + u * WG_DEC)] = decrypt_coeff<KQ>(C, v[u]);
+    }
+  } else {
+    for (uint32_t j = tid; j < n; j += WG_DEC) {
+      uint64_t v[KQ ? KQ : HC_MAXQ];
+      for (uint32_t i = 0; i < k; ++i) v[i] = x[((size_t)bl * k + i) * n + j];
+      lds32[PADX(j)] = decrypt_coeff<KQ>(C, v);
+    }
   }
   __syncthreads();
   ntt_forward16(lds32, T.ttw, T.ttw_sh, ModP{t}, n, C.logn, tid, WG_DEC, T.ntt_r);

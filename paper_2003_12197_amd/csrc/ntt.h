@@ -112,6 +112,39 @@ HD void load_padded(D* dst, const S* __restrict__ src, uint32_t n, uint32_t tid,
   }
 }
 
+// Calls f(j, src[j]) (f2: f(j, a[j], b[j])) for j = tid, tid + nthr, ... < n,
+// loading four words per lane before using them, as load_padded does.
+template <class S, class F>
+HD void for_each_loaded(const S* __restrict__ src, uint32_t n, uint32_t tid, uint32_t nthr, F f) {
+  if (n % (4 * nthr) == 0) {
+    for (uint32_t j = tid; j < n; j += 4 * nthr) {
+      const S v0 = src[j], v1 = src[j + nthr], v2 = src[j + 2 * nthr], v3 = src[j + 3 * nthr];
+      f(j, v0);
+      f(j + nthr, v1);
+      f(j + 2 * nthr, v2);
+      f(j + 3 * nthr, v3);
+    }
+  } else {
+    for (uint32_t j = tid; j < n; j += nthr) f(j, src[j]);
+  }
+}
+template <class S, class F>
+HD void for_each_loaded2(const S* __restrict__ a, const S* __restrict__ b, uint32_t n, uint32_t tid, uint32_t nthr,
+                         F f) {
+  if (n % (4 * nthr) == 0) {
+    for (uint32_t j = tid; j < n; j += 4 * nthr) {
+      const S a0 = a[j], a1 = a[j + nthr], a2 = a[j + 2 * nthr], a3 = a[j + 3 * nthr];
+      const S b0 = b[j], b1 = b[j + nthr], b2 = b[j + 2 * nthr], b3 = b[j + 3 * nthr];
+      f(j, a0, b0);
+      f(j + nthr, a1, b1);
+      f(j + 2 * nthr, a2, b2);
+      f(j + 3 * nthr, a3, b3);
+    }
+  } else {
+    for (uint32_t j = tid; j < n; j += nthr) f(j, a[j], b[j]);
+  }
+}
+
 // ---- radix-16 passes
 // The stages are taken in passes of R <= 4.  In a pass over stages
 // s0 .. s0+R-1 (forward, half = n >> (s+1)) the 2^R elements
