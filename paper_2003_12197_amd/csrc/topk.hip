@@ -65,11 +65,22 @@ k_topk_pass(const int32_t* __restrict__ scores, const uint64_t* __restrict__ key
     S = 2;
     while (S < count) S <<= 1;
   }
-  for (uint32_t j = tid; j < S; j += TK_WG) {
-    const uint64_t i = base + j;
-    uint64_t key = 0;
-    if (i < count) key = scores ? score_key(scores[i], i) : keys_in[i];
-    tile[j] = key;
+  if (!scores && S % (4 * TK_WG) == 0 && base + S <= count) {
+    // keys of a full tile: four per lane loaded before they are stored
+    for (uint32_t j = tid; j < S; j += 4 * TK_WG) {
+      uint64_t v[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) v[u] = keys_in[base + j + u * TK_WG];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) tile[j + u * TK_WG] = v[u];
+    }
+  } else {
+    for (uint32_t j = tid; j < S; j += TK_WG) {
+      const uint64_t i = base + j;
+      uint64_t key = 0;
+      if (i < count) key = scores ? score_key(scores[i], i) : keys_in[i];
+      tile[j] = key;
+    }
   }
   __syncthreads();
   bitonic_desc(tile, S);
@@ -119,11 +130,25 @@ k_topk_filter(const int32_t* __restrict__ scores, uint64_t m, const uint64_t* __
   const uint64_t base = tile << HERS_TOPK_TM_LOG2;
   if (tid == 0) cnt = 0;
   __syncthreads();
-  for (uint32_t j = tid; j < HERS_TOPK_TM; j += TK_WG) {
-    const uint64_t i = base + j;
-    if (i < m) {
-      const uint64_t key = score_key(scores[i], i);
-      if (key >= tau) buf[atomicAdd(&cnt, 1u)] = key;
+  if (base + HERS_TOPK_TM <= m) {
+    // full tile: four scores per lane loaded before they are compared
+    for (uint32_t j = tid; j < HERS_TOPK_TM; j += 4 * TK_WG) {
+      int32_t s[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) s[u] = scores[base + j + u * TK_WG];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        const uint64_t key = score_key(s[u], base + j + u * TK_WG);
+        if (key >= tau) buf[atomicAdd(&cnt, 1u)] = key;
+      }
+    }
+  } else {
+    for (uint32_t j = tid; j < HERS_TOPK_TM; j += TK_WG) {
+      const uint64_t i = base + j;
+      if (i < m) {
+        const uint64_t key = score_key(scores[i], i);
+        if (key >= tau) buf[atomicAdd(&cnt, 1u)] = key;
+      }
     }
   }
   __syncthreads();
