@@ -814,13 +814,33 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
   E acc0[RL_PER], acc1[RL_PER];
 #pragma unroll RL_UNROLL
   for (uint32_t e = 0; e < RL_PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
-  for (uint32_t g = 0; g < L; ++g) {
-    const uint64_t* dg = digits + ((size_t)g * k + sg) * n;
-    __syncthreads();                                    // previous digit's products read
+  // f64 form: digit g + 1 is loaded into registers while digit g is transformed
+  // (the integer form has no registers to spare for it)
+  uint64_t pre[QF ? RL_PER : 1];
+  if constexpr (QF) {
 #pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e)
-      if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(dg[tid + e * nthr]);
+    for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? digits[(size_t)sg * n + tid + e * nthr] : 0;
+  }
+  for (uint32_t g = 0; g < L; ++g) {
+    __syncthreads();                                    // previous digit's products read
+    if constexpr (QF) {
+#pragma unroll RL_UNROLL
+      for (uint32_t e = 0; e < RL_PER; ++e)
+        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(pre[e]);
+    } else {
+      const uint64_t* dg = digits + ((size_t)g * k + sg) * n;
+#pragma unroll RL_UNROLL
+      for (uint32_t e = 0; e < RL_PER; ++e)
+        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(dg[tid + e * nthr]);
+    }
     __syncthreads();
+    if constexpr (QF) {
+      if (g + 1 < L) {
+        const uint64_t* dn = digits + ((size_t)(g + 1) * k + sg) * n;
+#pragma unroll RL_UNROLL
+        for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? dn[tid + e * nthr] : 0;
+      }
+    }
     if constexpr (QF)
       ntt_forward_b(a, tw, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
     else
