@@ -229,6 +229,7 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
   c->T.C = dC;
+  c->T.C_rare = dC;
   c->T.ntt_r = 4;
   c->T.nq = C.k;
   c->T.qf_ok = 1;

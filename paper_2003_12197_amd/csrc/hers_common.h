@@ -265,17 +265,15 @@ HD uint32_t mixed_to_t(const HersConsts& C, const uint64_t* a, bool neg) {
 // every half-integer, so the rounding is exact.
 // KQ, KP, FW fix k, K and fr_words at compile time (0 = read from C), so
 // the fixed-point words stay in statically indexed registers.
-template <int KQ = 0, int KP = 0, int FW = 0>
-HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
-  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = FW ? FW : C.fr_words;
-  uint32_t y[KP ? KP : HC_MAXP];
-  double s = 0.0;
-#pragma unroll
-  for (uint32_t r = 0; r < K; ++r) {
-    y[r] = shoup_p(x[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
-    s += (double)y[r] * C.p_inv[r];
-  }
-  const uint64_t gamma = (uint64_t)__builtin_rint(s);
+//
+// Short form: the same sum over the top two fraction words only (words
+// w0 .. W-1 with w0 = W - 2) differs from the W-word F by less than
+// max(sum_r y_r, gamma) 2^-128 < 2^-93.  When its fraction is more than 2^-64
+// away from 1/2, it rounds as the W-word F does; only a fraction within 2^-64
+// of 1/2 (probability about 2^-63 per coefficient) takes the W-word sum.
+template <int FW = 0>
+HD int64_t round_F(const HersConsts& C, const uint32_t* y, uint32_t K, uint64_t gamma, uint32_t W, uint32_t w0,
+                   bool* near_half) {
   // F in fixed point: f[0 .. W-1] fraction words, f[W] the integer part (two's complement)
   uint64_t f[(FW ? FW : HC_MAXW) + 1];
 #pragma unroll
@@ -284,7 +282,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   for (uint32_t r = 0; r < K; ++r) {
     uint64_t carry = 0;
 #pragma unroll
-    for (uint32_t w = 0; w < W; ++w) {
+    for (uint32_t w = w0; w < W; ++w) {
       const u128 v = (u128)y[r] * C.fr_phi[r][w] + f[w] + carry;
       f[w] = (uint64_t)v;
       carry = (uint64_t)(v >> 64);
@@ -294,7 +292,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
   {
     uint64_t carry = 0, borrow = 0;
 #pragma unroll
-    for (uint32_t w = 0; w < W; ++w) {
+    for (uint32_t w = w0; w < W; ++w) {
       const u128 g = (u128)gamma * C.fr_psi[w] + carry;
       carry = (uint64_t)(g >> 64);
       const uint64_t gl = (uint64_t)g;
@@ -304,7 +302,27 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
     }
     f[W] -= carry + borrow;
   }
-  const int64_t rf = (int64_t)f[W] + (int64_t)(f[W - 1] >> 63);   // round(F)
+  // fraction in [1/2 - 2^-64, 1/2 + 2^-64): top word 2^63 - 1 or 2^63
+  *near_half = f[W - 1] - ((1ull << 63) - 1) < 2;
+  return (int64_t)f[W] + (int64_t)(f[W - 1] >> 63);   // round(F)
+}
+
+// ALL = false takes the two-word form and returns true when its fraction is
+// within 2^-64 of 1/2: the caller then calls again with ALL = true (W words).
+template <int KQ = 0, int KP = 0, int FW = 0, bool ALL = false>
+HD bool scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out) {
+  const uint32_t k = KQ ? KQ : C.k, K = KP ? KP : C.K, W = FW ? FW : C.fr_words;
+  uint32_t y[KP ? KP : HC_MAXP];
+  double s = 0.0;
+#pragma unroll
+  for (uint32_t r = 0; r < K; ++r) {
+    y[r] = shoup_p(x[r], C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
+    s += (double)y[r] * C.p_inv[r];
+  }
+  const uint64_t gamma = (uint64_t)__builtin_rint(s);
+  const uint32_t w0 = ALL || W <= 2 ? 0 : W - 2;
+  bool near_half = false;
+  const int64_t rf = round_F<FW>(C, y, K, gamma, W, w0, &near_half);
 #pragma unroll
   for (uint32_t i = 0; i < k; ++i) {
     const uint64_t q = C.q[i];
@@ -316,6 +334,7 @@ HD void scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
     const uint64_t rm = rf >= 0 ? ra : (ra ? q - ra : 0);
     out[i] = add_q(v, rm, q);
   }
+  return w0 != 0 && near_half;
 }
 
 // Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,

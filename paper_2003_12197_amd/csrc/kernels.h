@@ -7,6 +7,7 @@
 // Device pointers handed to every kernel by value.
 struct DevTabs {
   const HersConsts* C;
+  const HersConsts* C_rare;   // == C; read by rarely taken paths, whose constant loads then stay apart
   const uint64_t *qtw, *qtw_sh, *qitw, *qitw_sh;   // [k][n]
   const uint32_t *ptw, *ptw_sh, *pitw, *pitw_sh;   // [K][n]
   const uint32_t *ttw, *ttw_sh, *titw, *titw_sh;   // [n]

@@ -620,7 +620,14 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
   uint32_t x[KP ? KP : HC_MAXP];
   for (uint32_t r = 0; r < (KP ? KP : K); ++r) x[r] = X[(bj * K + r) * n + c];
   uint64_t out[KQ ? KQ : HC_MAXQ];
-  scale_round_coeff<KQ, KP, FW>(C, x, out);
+  if (scale_round_coeff<KQ, KP, FW, false>(C, x, out)) {
+    // two-word fraction within 2^-64 of 1/2 (rare): all W words.  The
+    // residues and constants are read again, so that nothing of the two-word
+    // pass stays live across it.
+    const volatile uint32_t* Xv = X;
+    for (uint32_t r = 0; r < (KP ? KP : K); ++r) x[r] = Xv[(bj * K + r) * n + c];
+    scale_round_coeff<KQ, KP, FW, true>(*T.C_rare, x, out);
+  }
   const int64_t b = blk_lo + bl;
   if (j < 2) {
     for (uint32_t i = 0; i < k; ++i) scores[(((size_t)b * 2 + j) * k + i) * n + c] = out[i];

@@ -130,3 +130,72 @@ def test_double_precision_modular_arithmetic(tmp_path):
             assert (r - a) % q == 0 and 2 * abs(r) <= q + 2, (op, q, a, r)
         else:
             assert r == a, (op, a, r)
+
+
+def test_rescale_two_word_rounding_matches_all_words(tmp_path):
+    """The exact rescale's round(F) (Alg. "Ciphertext Multiplication": scale by
+    t/q and round) is first formed from the top two 64-bit fraction words and
+    recomputed from all W words only when that fraction is within 2^-64 of
+    one half.  Checked with exact integers: the W-word sum's rounding, the
+    two-word sum's rounding and near-half flag, and that an unflagged
+    two-word result always equals the W-word one, on random words and on
+    carry and borrow chains built so that the two-word sum lands on the other
+    side of one half (and is flagged)."""
+    import random
+    import shutil
+    import subprocess
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    src = os.path.join(os.path.dirname(__file__), "native", "rescale_round.cpp")
+    exe = str(tmp_path / "rescale_round")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-Wno-unknown-pragmas", "-o", exe, src], check=True)
+    M = (1 << 64) - 1
+    H = 1 << 63
+    rng = random.Random(2003)
+    cases = []      # (W, y, gamma, phi[r][w], psi[w])
+    for _ in range(3000):
+        W, K = rng.randint(1, 6), rng.choice((1, 2, 3, 8, 16, 32))
+        y = [rng.randrange(1 << rng.choice((30, 32))) for _ in range(K)]
+        phi = [[rng.randrange(1 << 64) for _ in range(W)] for _ in range(K)]
+        psi = [rng.randrange(1 << 64) for _ in range(W)]
+        cases.append((W, y, rng.randrange(40), phi, psi))
+    for W in (3, 4, 5):
+        # one polynomial term, top fraction word around 1/2, random lower words
+        for top in (H - 2, H - 1, H, H + 1):
+            for _ in range(20):
+                cases.append((W, [1], 0, [[rng.randrange(1 << 64) for _ in range(W - 1)] + [top]], [0] * W))
+        # a carry from the dropped lowest word lifts the sum from just below 1/2 to exactly 1/2
+        cases.append((W, [1, 1], 0, [[M] * (W - 1) + [H - 1], [1] + [0] * (W - 1)], [0] * W))
+        # a borrow from the dropped lowest word takes 1/2 to just below it
+        cases.append((W, [1], 1, [[0] * (W - 1) + [H]], [1] + [0] * (W - 1)))
+        # the same around -1/2 and 3/2 (negative and integer parts)
+        cases.append((W, [1], 1, [[0] * W], [M] * (W - 1) + [H - 1]))
+        cases.append((W, [3, 1], 0, [[M] * (W - 1) + [H - 1], [1] + [0] * (W - 1)], [0] * W))
+        # largest operands: every word and y at their maximum
+        cases.append((W, [(1 << 32) - 1] * 32, (1 << 32) - 1, [[M] * W for _ in range(32)], [M] * W))
+    inp = "".join("%d %d %d %s %s %s\n" % (W, len(y), g, " ".join(map(str, y)),
+                                           " ".join(str(v) for row in phi for v in row), " ".join(map(str, psi)))
+                  for W, y, g, phi, psi in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.splitlines()
+    assert len(out) == len(cases)
+
+    def rounded(W, y, g, phi, psi, w0):
+        num = sum(yr * sum(row[w] << (64 * w) for w in range(w0, W)) for yr, row in zip(y, phi))
+        num -= g * sum(psi[w] << (64 * w) for w in range(w0, W))
+        num %= 1 << (64 * (W + 1))                     # the kernel's W + 1 words wrap
+        r = ((num + (1 << (64 * W - 1))) >> (64 * W)) & M
+        top = (num >> (64 * (W - 1))) & M
+        return r - (1 << 64) if r >> 63 else r, top in (H - 1, H)
+
+    flips = 0
+    for (W, y, g, phi, psi), line in zip(cases, out):
+        rs, nh, rw = (int(v) for v in line.split())
+        full, _ = rounded(W, y, g, phi, psi, 0)
+        short, near = rounded(W, y, g, phi, psi, W - 2 if W > 2 else 0)
+        assert rw == full, (W, y, g)
+        assert (rs, bool(nh)) == (short, near), (W, y, g)
+        assert nh or rs == rw, (W, y, g)             # the fallback is taken whenever it is needed
+        flips += W > 2 and short != full
+    assert flips >= 6      # the built chains do reach the W-word fallback
