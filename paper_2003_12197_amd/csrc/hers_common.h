@@ -333,6 +333,9 @@ HD bool scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
     const uint64_t ra = red_q(rf >= 0 ? (uint64_t)rf : (uint64_t)(-rf), q, C.q_mu64[i]);
     const uint64_t rm = rf >= 0 ? ra : (ra ? q - ra : 0);
     out[i] = add_q(v, rm, q);
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
   }
   return w0 != 0 && near_half;
 }
