@@ -1,0 +1,143 @@
+"""GPU parity at the batched configuration's ring: n = 8192, q = five primes of
+44, 44, 44, 43 and 43 bits (218 bits), t = 1,785,857 (21 bits), the exact-product
+base sized for d_max = 128 (K = 16 primes).
+
+App. A Alg. "Ciphertext Multiplication" and App. B Alg. "HERS Search" at the
+ring size the batched search runs at: the gallery and probe ciphertexts, the
+score ciphertexts of the single-probe search with relinearization as one fused
+kernel per (block, prime) and as two kernels, and the score ciphertexts of a
+two-probe batch (the persistent multi-probe multiply-accumulate) all equal the
+oracle's residue by residue; decrypted scores equal P^T q.  The gallery has two
+blocks, the second ragged (8192 + 77 items), and d = 3.  A wider batch (d = 9,
+five blocks: a full chunk of 8 dimensions over 4 blocks, a ragged chunk and a
+one-block tail) is checked against the oracle-checked single-probe search and
+P^T q.  Integer work: tolerance 0."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fv, hers
+from paper_2003_12197_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+C3 = dict(n=8192, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0)
+D, M_ITEMS = 3, 8192 + 77
+KEY_SEED, GAL_SEED, PROBE_SEEDS = 211, 311, (411, 412)
+
+
+def res(poly, primes):
+    return np.array(fv.to_residues(poly, primes), dtype=np.int64)
+
+
+@pytest.fixture(scope="module")
+def c3(gpu_lib):
+    print("case c3 ring: n=8192 q=44,44,44,43,43 t=21 bits K for d_max=128, d=3 m=8192+77", flush=True)
+    ctx = gpu_lib.Context(d_max=128, **C3)
+    assert ctx.K == 16 and ctx.k == 5
+    op = fv.Params(**C3)
+    P, q1 = synth.uniform_features(121, D, M_ITEMS)
+    q2 = np.random.default_rng(122).integers(-63, 64, size=D).astype(np.int32)
+    dev = ctx.device
+    sk, pk, rlk = ctx.keygen(KEY_SEED)
+    M, k, n = ctx.blocks(M_ITEMS), ctx.k, ctx.n
+    gcanon = torch.zeros(M * D * 2 * k * n, dtype=torch.int64, device=dev)
+    gal = ctx.encrypt_gallery(torch.from_numpy(P).to(dev), M_ITEMS, GAL_SEED, canon=gcanon)
+    pcanon = torch.zeros(D * 2 * k * n, dtype=torch.int64, device=dev)
+    pr1 = ctx.encrypt_probe(torch.from_numpy(q1).to(dev), PROBE_SEEDS[0], canon=pcanon)
+    pr2 = ctx.encrypt_probe(torch.from_numpy(q2).to(dev), PROBE_SEEDS[1])
+    torch.cuda.synchronize()
+    # the oracle, once per module
+    osk, opk, orlk = fv.keygen(op, KEY_SEED)
+    og = {b: hers.encrypt_gallery_block(op, opk, P, b, GAL_SEED) for b in range(M)}
+    oq1 = hers.encrypt_probe(op, opk, q1, PROBE_SEEDS[0])
+    oq2 = hers.encrypt_probe(op, opk, q2, PROBE_SEEDS[1])
+    want1 = {b: hers.search_block(op, orlk, oq1, og[b]) for b in range(M)}
+    want2 = {M - 1: hers.search_block(op, orlk, oq2, og[M - 1])}
+    print("case c3 ring: oracle done", flush=True)
+    return dict(ctx=ctx, op=op, P=P, q1=q1, q2=q2, sk=sk, pk=pk, rlk=rlk, gal=gal, pr1=pr1, pr2=pr2, M=M,
+                gcanon=gcanon.view(M, D, 2, k, n).cpu().numpy(), pcanon=pcanon.view(D, 2, k, n).cpu().numpy(),
+                osk=osk, opk=opk, orlk=orlk, og=og, oq1=oq1, want1=want1, want2=want2)
+
+
+def _assert_scores(got, want, primes):
+    got = got.cpu().numpy()
+    for b, S in want.items():
+        assert np.array_equal(got[b, 0], res(S[0], primes)), b
+        assert np.array_equal(got[b, 1], res(S[1], primes)), b
+
+
+@pytest.mark.timeout(900)
+def test_c3_keys_gallery_probe_bit_exact(c3):
+    op = c3["op"]
+    assert c3["sk"].cpu().numpy().tolist() == c3["osk"]
+    rlk = c3["rlk"].cpu().numpy()
+    for g, (b, a) in enumerate(c3["orlk"]):
+        assert np.array_equal(rlk[g, 0], res(b, op.q_primes)), g
+        assert np.array_equal(rlk[g, 1], res(a, op.q_primes)), g
+    for b, cts in c3["og"].items():
+        for i in range(D):
+            for comp in range(2):
+                assert np.array_equal(c3["gcanon"][b, i, comp], res(cts[i][comp], op.q_primes)), (b, i, comp)
+    for i, ct in enumerate(c3["oq1"]):
+        for comp in range(2):
+            assert np.array_equal(c3["pcanon"][i, comp], res(ct[comp], op.q_primes)), (i, comp)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fuse", [1, 1 << 30], ids=["fused_relin", "two_kernel_relin"])
+def test_c3_search_bit_exact(c3, fuse):
+    ctx = c3["ctx"]
+    try:
+        ctx.set_option("relin_fuse_min_wgs", fuse)
+        sc = ctx.search(c3["gal"], M_ITEMS, D, c3["pr1"])
+        _assert_scores(sc, c3["want1"], c3["op"].q_primes)
+        out = ctx.decrypt_scores(c3["sk"], sc, M_ITEMS).cpu().numpy()
+        assert np.array_equal(out, hers.plaintext_scores(c3["P"], c3["q1"]))
+    finally:
+        ctx.set_option("relin_fuse_min_wgs", 0)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fuse", [1, 0], ids=["fused_relin", "default_relin"])
+def test_c3_two_probe_batch_bit_exact(c3, fuse):
+    """Two probes on one gallery form one group of the persistent multi-probe
+    multiply-accumulate; each request's score ciphertexts are the oracle's."""
+    ctx, op = c3["ctx"], c3["op"]
+    try:
+        ctx.set_option("relin_fuse_min_wgs", fuse)
+        for ws in (None, ctx.batch_workspace([M_ITEMS] * 2, blocks_per_round=1)):
+            outs = ctx.search_batch([c3["gal"]] * 2, [M_ITEMS] * 2, [D] * 2, [c3["pr1"], c3["pr2"]], workspace=ws)
+            _assert_scores(outs[0], c3["want1"], op.q_primes)
+            _assert_scores(outs[1], c3["want2"], op.q_primes)
+            for o, qv in zip(outs, (c3["q1"], c3["q2"])):
+                dec = ctx.decrypt_scores(c3["sk"], o, M_ITEMS).cpu().numpy()
+                assert np.array_equal(dec, hers.plaintext_scores(c3["P"], qv))
+    finally:
+        ctx.set_option("relin_fuse_min_wgs", 0)
+
+
+@pytest.mark.timeout(900)
+def test_c3_wide_batch_equals_single(c3):
+    """d = 9 over 4 x 8192 + 5 items (a full chunk of 8 dimensions over 4
+    blocks, a one-dimension chunk, a ragged fifth block) with 3 probes: the
+    batch's ciphertexts equal the single-probe search's (checked against the
+    oracle at this ring above), with the relinearization fused and split."""
+    ctx = c3["ctx"]
+    d, m = 9, 4 * 8192 + 5
+    P, _ = synth.uniform_features(131, d, m)
+    gal = ctx.encrypt_gallery(torch.from_numpy(P).to(ctx.device), m, 321)
+    rng = np.random.default_rng(132)
+    qs = [rng.integers(-63, 64, size=d).astype(np.int32) for _ in range(3)]
+    prs = [ctx.encrypt_probe(torch.from_numpy(q).to(ctx.device), 500 + j) for j, q in enumerate(qs)]
+    try:
+        for fuse in (1, 1 << 30):
+            ctx.set_option("relin_fuse_min_wgs", fuse)
+            outs = ctx.search_batch([gal] * 3, [m] * 3, [d] * 3, prs)
+            for j in range(3):
+                assert torch.equal(outs[j], ctx.search(gal, m, d, prs[j])), (fuse, j)
+                dec = ctx.decrypt_scores(c3["sk"], outs[j], m).cpu().numpy()
+                assert np.array_equal(dec, hers.plaintext_scores(P, qs[j])), (fuse, j)
+    finally:
+        ctx.set_option("relin_fuse_min_wgs", 0)
