@@ -23,6 +23,13 @@
  *     the reference oracle): uint64 [2][k][n], component (ct[0], ct[1]),
  *     residue modulo q_i, coefficient j, every residue in [0, q_i).
  *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Search-form buffers are passed with their length in u32 words: a probe
+ *     must be exactly hers_probe_words(d) long, a gallery a whole number of
+ *     blocks of hers_gallery_words(n, d) words covering the m items; a buffer
+ *     of another d is rejected with HERS_EDIM.
+ *   - Calls that take features, a query or canonical ciphertexts check every
+ *     value on the GPU first (HERS_ERANGE) and synchronise `stream` to read
+ *     the result: they are not for stream capture.
  *
  * Randomness: every random polynomial is drawn from Philox4x64-10 (Salmon et
  * al., SC'11) with key (seed, domain) and counter (w / 4, obj0, obj1, obj2);
@@ -47,6 +54,9 @@ extern "C" {
 #define HERS_ESPACE (-4)   /* workspace too small                            */
 #define HERS_EDEVICE (-5)  /* HIP runtime error                              */
 #define HERS_ENOMEM (-6)   /* device allocation of library tables failed     */
+#define HERS_ERANGE (-7)   /* input value out of range: a feature or query   */
+                           /* beyond +-feature_bound, or a canonical residue */
+                           /* not below its prime                            */
 
 #define HERS_MAX_QPRIMES 8
 
@@ -83,6 +93,7 @@ typedef struct {
   uint32_t num_aux;               /* K: primes < 2^30 of the exact-product base */
   uint64_t aux[32];               /* those primes                               */
   double   log2_q, log2_aux;      /* log2 q and log2 of the product base        */
+  uint32_t d_max, feature_bound;  /* as in hers_params                           */
 } hers_info;
 
 typedef struct hers_ctx hers_ctx;
@@ -111,7 +122,7 @@ uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d);            /* u32: K 
  * items, 3 = decrypt_scores over m items, 4 = enroll_append of a batch of
  * m items, 5 = search_literal over m items, 6 = rerank_encrypt of m
  * ciphertexts, 7 = rerank of m selected ciphertexts, 8 = rerank_decrypt of m
- * ciphertexts. */
+ * ciphertexts, 9 = export of the search form of m items (a probe: m = 1). */
 uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d);
 
 /* ---- keys (App. A, Alg. "Key Generation") ------------------------------- */
@@ -133,6 +144,8 @@ int hers_load_keys(hers_ctx* ctx, const uint64_t* pk_dev, const uint64_t* rlk_de
  * (Eq. 3: row i holds dimension i of every item) and holds items
  * block0*n .. block0*n + nblocks*n - 1 (those >= m_total are read as 0), ld
  * is its row stride in items (>= nblocks*n, or >= the remaining items).
+ * Every feature of the range must lie in [-feature_bound, feature_bound]
+ * (else HERS_ERANGE and nothing is encrypted).
  * Block b, dimension i is Encrypt(BatchEncode(row i of block b)) with Philox
  * key (seed, 2) and objects (b, i, 0|1|2) for u, e1, e2.
  *   gallery_dev  search form, u32 [M][K][d][2][n]; blocks outside the range
@@ -150,7 +163,8 @@ int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, in
  * block boundaries; for every block b it touches, dimension i is
  * Encrypt(BatchEncode(the batch's values of dimension i in their slots,
  * zero elsewhere)) with Philox key (seed, 4) and objects (b, i, 0|1|2)
- * (a seed must not be reused for another batch).  Server half: CipherAdd
+ * (a seed must not be reused for another batch; features within
+ * +-feature_bound, else HERS_ERANGE).  Server half: CipherAdd
  * into block b's running ciphertext; a block that held no item starts from
  * the trivial zero ciphertext (reading of the algorithm's Encrypt(0), whose
  * rollover branch also drops the incoming ciphertext -- here the batch is
@@ -167,11 +181,41 @@ int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int6
 /* ---- query (App. B Alg. "HERS Search", client side) ---------------------
  * Dimension i is the constant plaintext [q_i]_t (Eq. 2), encrypted with the
  * public key (Philox key (seed, 3), objects (0, i, 0|1|2)).
- *   query_dev int32 [d]; probe_dev search form u32 [K][d][2][n];
+ *   query_dev int32 [d], every value within +-feature_bound (else HERS_ERANGE);
+ *   probe_dev search form u32 [K][d][2][n];
  *   canon_dev optional canonical cts [d][2][k][n]. */
 int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed,
                        uint32_t* probe_dev, uint64_t* canon_dev, void* work_dev,
                        size_t work_bytes, void* stream);
+
+/* ---- canonical ciphertexts in and out (Sec. 3.2 "Enrollment Protocol" and
+ * "Search Protocol": the client encrypts and sends ciphertexts, the server
+ * stores and searches them without any plaintext) -------------------------
+ * Import: canonical ciphertexts -> search form (exact centred lift to the
+ * product base, forward NTT); every residue must be below its prime (else
+ * HERS_ERANGE and nothing is written).
+ *   hers_import_gallery: canon_dev holds blocks block0 .. block0 + nblocks - 1
+ *     only, [nblocks][d][2][k][n] (so a large gallery is imported in chunks);
+ *     gallery_dev is the whole gallery's search form (gallery_words long),
+ *     blocks outside the range are not touched.
+ *   hers_import_probe: canon_dev [d][2][k][n] -> probe_dev [K][d][2][n].
+ * Export: search form -> canonical ciphertexts (inverse NTT, exact CRT over
+ * the product base, residues mod q_i): the inverse of import, so an imported
+ * or encrypted ciphertext comes back bit for bit.
+ *   hers_export_gallery: blocks block0 .. block0 + nblocks - 1 into canon_dev
+ *     [nblocks][d][2][k][n]; work_dev hers_workspace_bytes(ctx, 9, m, d) for
+ *     the blocks of one pass (less: blocks in chunks, at least one block).
+ *   hers_export_probe: probe_dev -> canon_dev [d][2][k][n]; work_dev
+ *     hers_workspace_bytes(ctx, 9, 1, d). */
+int hers_import_gallery(hers_ctx* ctx, const uint64_t* canon_dev, int64_t m_total, int32_t d, int64_t block0,
+                        int64_t nblocks, uint32_t* gallery_dev, uint64_t gallery_words, void* stream);
+int hers_import_probe(hers_ctx* ctx, const uint64_t* canon_dev, int32_t d, uint32_t* probe_dev,
+                      uint64_t probe_words, void* stream);
+int hers_export_gallery(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m_total,
+                        int32_t d, int64_t block0, int64_t nblocks, uint64_t* canon_dev, void* work_dev,
+                        size_t work_bytes, void* stream);
+int hers_export_probe(hers_ctx* ctx, const uint32_t* probe_dev, uint64_t probe_words, int32_t d,
+                      uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream);
 
 /* ---- search (App. B Alg. "HERS Search", server side) --------------------
  * For every block b: X_0 = sum_i P_i0 G_bi0, X_1 = sum_i (P_i0 G_bi1 + P_i1 G_bi0),
@@ -182,9 +226,9 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
  * Work is ordered on `stream`; with "overlap_chunks" it is split between
  * `stream` and the context's own stream and joined back into `stream`
  * (one context must not run two searches from different host threads). */
-int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
-                const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
-                size_t work_bytes, void* stream);
+int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m,
+                int32_t d, const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev,
+                void* work_dev, size_t work_bytes, void* stream);
 
 /* The paper-literal schedule (App. B Alg. "HERS Search" as printed): for
  * every dimension i, CipherMultiply(probe_i, gallery_i) -- tensor, rescale,
@@ -193,13 +237,13 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
  * either way) from d times the rescales and relinearizations and other
  * ciphertext bits; kept as the timed comparison for the fused schedule.
  *   work_dev  hers_workspace_bytes(ctx, 5, m, d) (or less: blocks in chunks). */
-int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d,
-                        const uint32_t* probe_dev, uint64_t* scores_dev, void* work_dev,
-                        size_t work_bytes, void* stream);
+int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words,
+                        int64_t m, int32_t d, const uint32_t* probe_dev, uint64_t probe_words,
+                        uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream);
 
 /* Batched search: nreq independent (gallery, probe) requests in one
- * submission; request r reads galleries[r] (m[r] items, d[r] dims) and
- * probes[r] and writes scores[r].  Requests on the same gallery (same
+ * submission; request r reads galleries[r] (gallery_words[r] long, m[r]
+ * items, d[r] dims) and probes[r] (probe_words[r] long) and writes scores[r].  Requests on the same gallery (same
  * pointer, m and d) are grouped, up to 16 per group: one persistent
  * multiply-accumulate launch streams each gallery block once for the whole
  * group, then every request gets its own rescale and relinearization.
@@ -207,7 +251,8 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, i
  * holds at least one block per request; with W bytes, rounds of
  * floor(W / (nreq * hers_workspace_bytes(ctx, 2, n, 1))) blocks are used. */
 int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries,
-                      const int64_t* m, const int32_t* d, const uint32_t* const* probes,
+                      const uint64_t* gallery_words, const int64_t* m, const int32_t* d,
+                      const uint32_t* const* probes, const uint64_t* probe_words,
                       uint64_t* const* scores, void* work_dev, size_t work_bytes, void* stream);
 
 /* The same batch captured once as a HIP graph and replayed by
@@ -216,9 +261,10 @@ int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galler
  * The plan keeps the context, galleries, probes, scores and workspace
  * pointers; they must stay valid until hers_plan_destroy. */
 typedef struct hers_plan hers_plan;
-int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
-                     const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores,
-                     void* work_dev, size_t work_bytes, hers_plan** out);
+int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries,
+                     const uint64_t* gallery_words, const int64_t* m, const int32_t* d,
+                     const uint32_t* const* probes, const uint64_t* probe_words,
+                     uint64_t* const* scores, void* work_dev, size_t work_bytes, hers_plan** out);
 int hers_plan_launch(hers_plan* plan, void* stream);
 void hers_plan_destroy(hers_plan* plan);
 
@@ -262,7 +308,8 @@ int hers_rotation_keygen(hers_ctx* ctx, uint64_t seed, int32_t W, uint64_t* rk_d
 /* Encrypts items (replicate = 0: feats_dev int32 [D][ld], columns 0..count-1,
  * ceil(count / S) ciphertexts, Philox key (seed, 5), objects (c, 0, 0|1|2))
  * or a probe (replicate = 1, count = 1: column 0 in every segment, one
- * ciphertext, key (seed, 6), objects (0, 0, 0|1|2)).
+ * ciphertext, key (seed, 6), objects (0, 0, 0|1|2)); every feature within
+ * +-feature_bound, else HERS_ERANGE.
  *   search_dev u32 [nct][K][2][n] (search form, d = 1); canon_dev optional
  *   canonical [nct][2][k][n]; work_dev hers_workspace_bytes(ctx, 6, nct, 0). */
 int hers_rerank_encrypt(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int64_t count, int32_t D,
@@ -293,7 +340,10 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  double-buffered load batch, non-temporal gallery loads):
  *                  0 (1,2,no) 1 (2,2,no) 2 (1,4,no) 3 (2,4,no) 4 (1,2,yes)
  *                  5 (2,2,yes) 6 (1,4,yes) 7 (2,4,yes) 8 (4,1,yes)
- *                  9 (4,2,yes) 10 (2,1,yes) 11 (1,1,yes).
+ *                  9 (4,2,yes) 10 (2,1,yes) 11 (1,1,yes); 12 (n <= 4096 only):
+ *                  one workgroup per (block, prime) over the whole ring,
+ *                  with the inverse NTT of the accumulators fused in (no
+ *                  separate transform launch or round trip through memory).
  *   "ntt_radix_log2" stages per NTT pass, 1..4 (radix 2, 4, 8, 16; default 4):
  *                  each pass keeps 2^r elements per lane in registers and
  *                  costs one barrier.
@@ -304,8 +354,9 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  multiply-accumulate.  The caller's stream waits for that
  *                  stream before hers_search returns, so stream order holds.
  *   "mac_wgs_per_cu" workgroups per compute unit of a hers_search
- *                  multiply-accumulate launch, 0..64 (0 = 8); fewer leave
- *                  room on each CU for an overlapped epilogue.
+ *                  multiply-accumulate launch, 0..64 (0 = 8, for schedule
+ *                  12 the n/4-lane workgroups that fill a CU: 2 at n = 4096);
+ *                  fewer leave room on each CU for an overlapped epilogue.
  *   "relin_fuse_min_wgs" relinearizations (and rotations) launched with at
  *                  least this many workgroups (blocks x primes x requests)
  *                  run as one fused kernel per (block, prime): digit
@@ -317,22 +368,22 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
 
-/* Autotuner: times every "mac_variant" schedule on the caller's gallery and
- * probe (reps launches each, over as many leading blocks as the search
- * workspace holds; another schedule replaces the current one only if 3%
- * faster), then the search epilogue's transforms under NTT pass
- * radix 4, 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not
- * NULL -- whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16
- * (chunks of at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule
- * found first, schedule 8 or schedule 10 (a combination other than no
+/* Autotuner: times every "mac_variant" schedule together with the inverse
+ * NTT of the accumulators (which schedule 12 does itself) on the caller's
+ * gallery and probe (reps launches each, over as many leading blocks as the
+ * search workspace holds; another schedule replaces the current one only if
+ * 3% faster), then the search epilogue's transforms under NTT pass radix 4,
+ * 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not NULL --
+ * whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16 (chunks of
+ * at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule found first,
+ * schedule 8, schedule 10 or schedule 12 (a combination other than no
  * chunks, default grid, schedule found first must be 3% faster to be
- * kept).  Keeps the
- * fastest of each in the context and returns the schedule in *chosen (may
- * be NULL).  The workspace and
- * scores_dev contents are overwritten; the call synchronizes `stream`. */
-int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                  uint64_t* scores_dev, void* work_dev, size_t work_bytes, int reps, void* stream,
-                  int64_t* chosen);
+ * kept).  Keeps the fastest of each in the context and returns the schedule
+ * in *chosen (may be NULL).  The workspace and scores_dev contents are
+ * overwritten; the call synchronizes `stream`. */
+int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
+                  const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
+                  size_t work_bytes, int reps, void* stream, int64_t* chosen);
 int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value);
 
 /* ---- nearest neighbours (App. B, Alg. "HERS Search": argmax of the decrypted scores) ----
@@ -364,12 +415,18 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
  *   of their own, so a short search never waits for a long one in its wave.
  *   Up to four waves run at once, each on its own stream.  Each result is
  *   bit-identical to the same request served alone.
- * hers_server_submit copies the query (host int32 [d] of the gallery) and
- * returns a ticket, or HERS_ENOMEM if one request alone exceeds the arena.
+ * hers_server_add_gallery takes the gallery's search form and its length in
+ * u32 words (whole blocks of d dimensions covering m items, else HERS_EDIM).
+ * hers_server_submit copies the query (host int32 [d] of the gallery, every
+ * value within +-feature_bound, else HERS_ERANGE) and returns a ticket, or
+ * HERS_ENOMEM if one request alone exceeds the arena.
  * hers_server_wait blocks until the ticket's scores are ready, optionally
  * copies the decrypted scores (host int32 [m]) and the score ciphertexts
  * (host u64 [M][2][k][n]) out, reports the latency from submission to scores
- * ready on the GPU, and releases the ticket. */
+ * ready on the GPU, and releases the ticket.  A worker short of arena
+ * memory sleeps until a result is collected or a request arrives.
+ * hers_server_destroy lets the waves on the GPU finish; requests still
+ * queued are dropped.  Every hers_server_wait must have returned first. */
 typedef struct hers_server hers_server;
 typedef struct {
   int64_t submitted, completed, deferrals, waves, max_wave, queued, in_flight;
@@ -378,8 +435,8 @@ typedef struct {
 } hers_server_stats;
 int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, size_t arena_bytes,
                        int32_t max_batch, hers_server** out);
-int hers_server_add_gallery(hers_server* srv, const uint32_t* gallery_dev, int64_t m, int32_t d,
-                            int32_t* gallery_id);
+int hers_server_add_gallery(hers_server* srv, const uint32_t* gallery_dev, uint64_t gallery_words,
+                            int64_t m, int32_t d, int32_t* gallery_id);
 int hers_server_submit(hers_server* srv, int32_t gallery_id, const int32_t* query, uint64_t seed,
                        int64_t* ticket);
 int hers_server_wait(hers_server* srv, int64_t ticket, int32_t* scores_out, uint64_t* ct_out,

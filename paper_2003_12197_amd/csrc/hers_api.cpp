@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hers.h"
+#include "internal.h"
 #include "kernels.h"
 #include "params.h"
 
@@ -19,11 +20,17 @@ static int fail(int code, const std::string& msg) {
   return code;
 }
 
+void hers::set_last_error(const std::string& msg) { g_err = msg; }
+
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \
     if (e_ != hipSuccess) return fail(HERS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// "mac_variant" of the multiply-accumulate with the inverse NTT of the
+// accumulators fused in (k_mac_intt, n <= 4096); 0 .. 11 are k_mac schedules
+#define MAC_FUSED_INTT 12
 
 struct hers_ctx {
   int num_cus = 256;
@@ -47,6 +54,9 @@ struct hers_ctx {
   // secret key in NTT form for decryptions without a key argument
   uint64_t* sk_ntt = nullptr;
   bool sk_loaded = false;
+  // input checks: a device flag word and its pinned host copy
+  uint32_t* flag_dev = nullptr;
+  uint32_t* flag_host = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_mac = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_free;
@@ -162,6 +172,40 @@ int check_d(const hers_ctx* c, int32_t d) {
   return HERS_OK;
 }
 
+// Search-form buffer lengths against (m, d): the probe must be the search form
+// of exactly d dimensions, the gallery whole blocks of d dimensions covering
+// the m items (a probe or gallery made for another d is a mismatch).
+int check_search_buffers(const hers_ctx* c, int64_t m, int32_t d, uint64_t gallery_words, uint64_t probe_words) {
+  const HersConsts& C = c->host.C;
+  const uint64_t blk = (uint64_t)C.K * d * 2 * C.n;
+  if (probe_words != blk) return fail(HERS_EDIM, "probe buffer length is not the search form of d dimensions");
+  if (gallery_words % blk || gallery_words / blk < (uint64_t)((m + C.n - 1) / C.n))
+    return fail(HERS_EDIM, "gallery buffer length is not whole blocks of d dimensions covering the m items");
+  return HERS_OK;
+}
+
+// Runs a checking kernel that may set the context's flag word, reads the flag
+// back and fails with `code` if it was set.  Synchronises the stream.
+template <class F>
+int flag_check(hers_ctx* c, hipStream_t s, F&& launch, int code, const char* msg) {
+  HIP_TRY(hipMemsetAsync(c->flag_dev, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch());
+  HIP_TRY(hipMemcpyAsync(c->flag_host, c->flag_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (*c->flag_host) return fail(code, msg);
+  return HERS_OK;
+}
+
+// Values of a [rows][ld] int32 device array (columns 0 .. cols - 1) must lie
+// in [-feature_bound, feature_bound] (Sec. 3.2, "Encoding Scheme": every
+// score then stays below t / 2 and is recovered exactly).
+int check_features(hers_ctx* c, const int32_t* v, int64_t ld, int32_t rows, int64_t cols, hipStream_t s) {
+  return flag_check(c, s, [&] {
+    return hers::launch_check_features(v, ld, rows, cols, (int32_t)c->prm.feature_bound, c->flag_dev,
+                                       (uint32_t)c->num_cus, s);
+  }, HERS_ERANGE, "a feature or query value lies outside [-feature_bound, feature_bound]");
+}
+
 }  // namespace
 
 extern "C" {
@@ -214,10 +258,16 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
       (rc = upload(c, qf_consts(C), &c->T.qf)) ||
       (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pk)) || (rc = alloc_dev(c, (size_t)2 * C.k * C.n * 8, &pks)) ||
       (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rl)) ||
-      (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rls))) {
+      (rc = alloc_dev(c, (size_t)C.L * 2 * C.k * C.n * 8, &rls)) ||
+      (rc = alloc_dev(c, 256, (void**)&c->flag_dev))) {
     std::string msg = g_err;
     hers_ctx_destroy(c);
     return fail(rc, msg);
+  }
+  if (hipHostMalloc((void**)&c->flag_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    c->flag_host = nullptr;
+    hers_ctx_destroy(c);
+    return fail(HERS_ENOMEM, "pinned host allocation failed");
   }
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_mac, hipEventDisableTiming) != hipSuccess ||
@@ -260,6 +310,7 @@ void hers_ctx_destroy(hers_ctx* ctx) {
     if (ctx->rk_ntt) (void)hipFree(ctx->rk_ntt);
     if (ctx->sk_ntt) (void)hipFree(ctx->sk_ntt);
     if (ctx->rk_ntt_sh) (void)hipFree(ctx->rk_ntt_sh);
+    if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
     for (void* p : ctx->allocs) (void)hipFree(p);
   }
   delete ctx;
@@ -344,7 +395,8 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
   if (!ctx || !key) return fail(HERS_EINVAL, "null argument");
   if (!std::strcmp(key, "mac_variant")) {
-    if (value < 0 || value > 11) return fail(HERS_EINVAL, "mac_variant must be in [0, 11]");
+    const int64_t top = ctx->host.C.n <= 4096 ? MAC_FUSED_INTT : MAC_FUSED_INTT - 1;
+    if (value < 0 || value > top) return fail(HERS_EINVAL, "mac_variant must be in [0, 11] (12 for n <= 4096)");
     ctx->mac_variant = (int)value;
     return HERS_OK;
   }
@@ -488,6 +540,7 @@ uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d)
     case 6: return (uint64_t)m * (align256((size_t)C.n * 4) + align256((size_t)2 * C.k * C.n * 8));
     case 7: return (uint64_t)m * rerank_ws_per_ct(C);
     case 8: return decrypt_ws_fixed(C) + (uint64_t)m * (decrypt_ws_per_block(C) + align256((size_t)C.n * 4));
+    case 9: return M * (uint64_t)C.K * d * 2 * C.n * 4;
     default: return 0;
   }
 }
@@ -527,6 +580,7 @@ int hers_encrypt_gallery(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, in
   if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
   const int64_t chunk = (int64_t)(work_bytes / per);
   DeviceGuard g(ctx->device);
+  if (int rc = check_features(ctx, feats_dev, ld, d, need_items, S(stream))) return rc;
   for (int64_t lo = block0; lo < block0 + nblocks; lo += chunk) {
     const int64_t nb = (lo + chunk < block0 + nblocks) ? chunk : block0 + nblocks - lo;
     uint32_t* pt = (uint32_t*)work_dev;
@@ -560,6 +614,7 @@ int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int6
   const int64_t first_empty = (k0 + n - 1) / n;               // blocks from here held no item
   DeviceGuard g(ctx->device);
   const hipStream_t s = S(stream);
+  if (int rc = check_features(ctx, feats_dev, ld, d, c, s)) return rc;
   for (int64_t lo = b_lo; lo < b_hi; lo += chunk) {
     const int64_t nb = lo + chunk < b_hi ? chunk : b_hi - lo;
     const uint32_t nct = (uint32_t)(nb * d);
@@ -577,11 +632,12 @@ int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int6
   return HERS_OK;
 }
 
-int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
-                       uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream) {
-  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
-  if (int rc = check_d(ctx, d)) return rc;
-  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+}  // extern "C"
+
+// Probe encryption after the query's range check (the serving loop checks
+// its host copy of the query at submission).
+static int encrypt_probe_impl(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
+                              uint64_t* canon_dev, void* work_dev, size_t work_bytes, hipStream_t s) {
   const HersConsts& C = ctx->host.C;
   uint64_t* canon = canon_dev;
   if (!canon) {
@@ -589,11 +645,116 @@ int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint6
     canon = (uint64_t*)work_dev;
   }
   DeviceGuard g(ctx->device);
-  TIMED(ctx, "encrypt", S(stream), hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed, HERS_DOMAIN_PROBE,
-                               canon, S(stream)));
-  TIMED(ctx, "lift", S(stream), hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, S(stream)));
-  TIMED(ctx, "ntt_fwd", S(stream), hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, S(stream)));
+  TIMED(ctx, "encrypt", s, hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed,
+                                                HERS_DOMAIN_PROBE, canon, s));
+  TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, s));
+  TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, s));
   return HERS_OK;
+}
+
+int hers::encrypt_probe_prechecked(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed,
+                                   uint32_t* probe_dev, void* work_dev, size_t work_bytes, hipStream_t s) {
+  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  return encrypt_probe_impl(ctx, query_dev, d, seed, probe_dev, nullptr, work_dev, work_bytes, s);
+}
+
+extern "C" {
+
+int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
+                       uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
+  if (!canon_dev && (!work_dev || work_bytes < (size_t)d * 2 * ctx->host.C.k * ctx->host.C.n * 8))
+    return fail(HERS_ESPACE, "workspace too small");
+  DeviceGuard g(ctx->device);
+  if (int rc = check_features(ctx, query_dev, d, 1, d, S(stream))) return rc;
+  return encrypt_probe_impl(ctx, query_dev, d, seed, probe_dev, canon_dev, work_dev, work_bytes, S(stream));
+}
+
+// ---- canonical ciphertexts in and out of the search form
+static int import_cts(hers_ctx* ctx, const uint64_t* canon_dev, int32_t d, int64_t block0, int64_t nblocks,
+                      uint32_t* out, hipStream_t s) {
+  const HersConsts& C = ctx->host.C;
+  const uint64_t nct = (uint64_t)nblocks * d;
+  if (nct > 0xffffffffull / C.n) return fail(HERS_EINVAL, "too many ciphertexts in one call");
+  DeviceGuard g(ctx->device);
+  if (int rc = flag_check(ctx, s, [&] {
+        return hers::launch_check_canon(ctx->T, canon_dev, nct * 2 * C.k * C.n, ctx->flag_dev,
+                                        (uint32_t)ctx->num_cus, s);
+      }, HERS_ERANGE, "a canonical residue is not below its prime"))
+    return rc;
+  TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, canon_dev, (uint32_t)nct, d, block0, out, s));
+  TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, out + (size_t)block0 * C.K * d * 2 * C.n,
+                                              (uint64_t)nblocks * C.K * d * 2, 2 * d, 0, s));
+  return HERS_OK;
+}
+
+int hers_import_gallery(hers_ctx* ctx, const uint64_t* canon_dev, int64_t m_total, int32_t d, int64_t block0,
+                        int64_t nblocks, uint32_t* gallery_dev, uint64_t gallery_words, void* stream) {
+  if (!ctx || !canon_dev || !gallery_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m_total);
+  if (m_total < 1 || block0 < 0 || nblocks < 1 || block0 + nblocks > M)
+    return fail(HERS_EINVAL, "block range outside the gallery");
+  if (int rc = check_search_buffers(ctx, m_total, d, gallery_words, (uint64_t)C.K * d * 2 * C.n)) return rc;
+  return import_cts(ctx, canon_dev, d, block0, nblocks, gallery_dev, S(stream));
+}
+
+int hers_import_probe(hers_ctx* ctx, const uint64_t* canon_dev, int32_t d, uint32_t* probe_dev, uint64_t probe_words,
+                      void* stream) {
+  if (!ctx || !canon_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  const HersConsts& C = ctx->host.C;
+  if (probe_words != (uint64_t)C.K * d * 2 * C.n)
+    return fail(HERS_EDIM, "probe buffer length is not the search form of d dimensions");
+  return import_cts(ctx, canon_dev, d, 0, 1, probe_dev, S(stream));
+}
+
+static int export_cts(hers_ctx* ctx, const uint32_t* search, int32_t d, int64_t nblocks, uint64_t* canon,
+                      void* work_dev, size_t work_bytes, hipStream_t s) {
+  const HersConsts& C = ctx->host.C;
+  const size_t per = (size_t)C.K * d * 2 * C.n * 4;
+  if (!work_dev || work_bytes < per) return fail(HERS_ESPACE, "workspace smaller than one block");
+  const int64_t chunk = (int64_t)(work_bytes / per);
+  DeviceGuard g(ctx->device);
+  for (int64_t lo = 0; lo < nblocks; lo += chunk) {
+    const int64_t nb = lo + chunk < nblocks ? chunk : nblocks - lo;
+    uint32_t* coef = (uint32_t*)work_dev;
+    HIP_TRY(hipMemcpyAsync(coef, search + (size_t)lo * C.K * d * 2 * C.n, (size_t)nb * per, hipMemcpyDeviceToDevice, s));
+    TIMED(ctx, "ntt_inv", s, hers::launch_ntt_p(ctx->T, C.n, coef, (uint64_t)nb * C.K * d * 2, 2 * d, 1, s));
+    TIMED(ctx, "unlift", s, hers::launch_unlift(ctx->T, C.n, coef, (uint32_t)(nb * d), d,
+                                                canon + (size_t)lo * d * 2 * C.k * C.n, s));
+  }
+  return HERS_OK;
+}
+
+int hers_export_gallery(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m_total, int32_t d,
+                        int64_t block0, int64_t nblocks, uint64_t* canon_dev, void* work_dev, size_t work_bytes,
+                        void* stream) {
+  if (!ctx || !gallery_dev || !canon_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  const HersConsts& C = ctx->host.C;
+  const int64_t M = (int64_t)hers_blocks(ctx, m_total);
+  if (m_total < 1 || block0 < 0 || nblocks < 1 || block0 + nblocks > M)
+    return fail(HERS_EINVAL, "block range outside the gallery");
+  if (int rc = check_search_buffers(ctx, m_total, d, gallery_words, (uint64_t)C.K * d * 2 * C.n)) return rc;
+  if ((uint64_t)nblocks * d > 0xffffffffull / C.n) return fail(HERS_EINVAL, "too many ciphertexts in one call");
+  return export_cts(ctx, gallery_dev + (size_t)block0 * C.K * d * 2 * C.n, d, nblocks, canon_dev, work_dev,
+                    work_bytes, S(stream));
+}
+
+int hers_export_probe(hers_ctx* ctx, const uint32_t* probe_dev, uint64_t probe_words, int32_t d, uint64_t* canon_dev,
+                      void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || !probe_dev || !canon_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  const HersConsts& C = ctx->host.C;
+  if (probe_words != (uint64_t)C.K * d * 2 * C.n)
+    return fail(HERS_EDIM, "probe buffer length is not the search form of d dimensions");
+  return export_cts(ctx, probe_dev, d, 1, canon_dev, work_dev, work_bytes, S(stream));
 }
 
 // Relinearization launches with at least this many workgroups use the fused
@@ -605,18 +766,39 @@ static uint32_t fuse_wgs(const hers_ctx* ctx) {
   return ctx->host.C.n >= 8192 ? 8u * (uint32_t)ctx->num_cus : 0xffffffffu;
 }
 
+static bool mac_fused(const hers_ctx* ctx) { return ctx->mac_variant == MAC_FUSED_INTT; }
+
 // Workgroups of a multiply-accumulate launch.
 static uint32_t mac_grid(const hers_ctx* ctx) {
   return (uint32_t)(ctx->mac_wgs_per_cu ? ctx->mac_wgs_per_cu : 8) * (uint32_t)ctx->num_cus;
 }
 
-// Per-block epilogue of blocks [lo, hi): inverse NTT of the accumulators,
-// exact rescale (with the relinearization digits), relinearization.
+// One probe's multiply-accumulate over blocks [lo, hi) (dimensions dim0 ..
+// dim0 + dcount - 1, all for dcount 0) with schedule `variant`; the fused
+// schedule leaves the accumulators in the coefficient domain.
+static hipError_t launch_mac_sched(hers_ctx* ctx, int variant, const uint32_t* gallery, const uint32_t* probe,
+                                   int32_t d, int64_t lo, int64_t hi, uint32_t* acc, hipStream_t s, int32_t dim0 = 0,
+                                   int32_t dcount = 0) {
+  const HersConsts& C = ctx->host.C;
+  if (variant == MAC_FUSED_INTT) {
+    // default: as many n/4-lane workgroups as fill a CU at 8 waves per SIMD
+    const uint32_t lanes = C.n / 4, per_cu = ctx->mac_wgs_per_cu ? (uint32_t)ctx->mac_wgs_per_cu
+                                                                  : (2048u / lanes > 0 ? 2048u / lanes : 1u);
+    return hers::launch_mac_intt(ctx->T, C.n, C.K, gallery, probe, d, lo, hi, acc, s, per_cu * (uint32_t)ctx->num_cus,
+                                 dim0, dcount);
+  }
+  return hers::launch_mac(ctx->T, C.n, C.K, gallery, probe, d, lo, hi, acc, s, variant, mac_grid(ctx), dim0, dcount);
+}
+
+// Per-block epilogue of blocks [lo, hi): inverse NTT of the accumulators
+// (unless acc_coef: the multiply-accumulate left them in the coefficient
+// domain), exact rescale (with the relinearization digits), relinearization.
 static int search_epilogue(hers_ctx* ctx, uint32_t* acc, uint64_t* digits, int64_t lo, int64_t hi,
-                           uint64_t* scores_dev, hipStream_t s) {
+                           uint64_t* scores_dev, hipStream_t s, bool acc_coef) {
   const HersConsts& C = ctx->host.C;
   const int64_t nb = hi - lo;
-  TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
+  if (!acc_coef)
+    TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
   ScorePtrs sp;
   sp.p[0] = scores_dev;
   TIMED(ctx, "rescale", s,
@@ -626,11 +808,18 @@ static int search_epilogue(hers_ctx* ctx, uint32_t* acc, uint64_t* digits, int64
   return HERS_OK;
 }
 
-int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream) {
+}  // extern "C"
+
+// The search (hers_search): blocks in chunks of the workspace; `overlap`
+// allows the chunked schedule whose epilogues run on the context's second
+// stream (it creates events on first use).
+int hers::search_impl(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
+                      const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
+                      size_t work_bytes, void* stream, bool overlap) {
   if (!ctx || !gallery_dev || !probe_dev || !scores_dev) return fail(HERS_EINVAL, "null argument");
   if (int rc = check_d(ctx, d)) return rc;
   if (m < 1) return fail(HERS_EINVAL, "empty gallery");
+  if (int rc = check_search_buffers(ctx, m, d, gallery_words, probe_words)) return rc;
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
   const HersConsts& C = ctx->host.C;
   const int64_t M = (int64_t)hers_blocks(ctx, m);
@@ -639,16 +828,15 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
   const int64_t cap = (int64_t)(work_bytes / per);
   DeviceGuard g(ctx->device);
   const hipStream_t s = S(stream);
-  int64_t nch = ctx->overlap_chunks;
+  int64_t nch = overlap ? ctx->overlap_chunks : 1;
   if (nch == 0) nch = M >= 4096 ? 8 : 1;
   if (nch <= 1 || cap < 2) {
     for (int64_t lo = 0; lo < M; lo += cap) {
       const int64_t hi = lo + cap < M ? lo + cap : M;
       uint32_t* acc = (uint32_t*)work_dev;
       uint64_t* digits = (uint64_t*)((char*)work_dev + align256((size_t)(hi - lo) * 3 * C.K * C.n * 4));
-      TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s,
-                                            ctx->mac_variant, mac_grid(ctx)));
-      if (int rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, s)) return rc;
+      TIMED(ctx, "mac", s, launch_mac_sched(ctx, ctx->mac_variant, gallery_dev, probe_dev, d, lo, hi, acc, s));
+      if (int rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, s, mac_fused(ctx))) return rc;
     }
     return HERS_OK;
   }
@@ -679,13 +867,12 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
     if (e != hipSuccess) break;
     {
       StageTimer st(ctx, "mac", s);
-      e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s, ctx->mac_variant,
-                           mac_grid(ctx));
+      e = launch_mac_sched(ctx, ctx->mac_variant, gallery_dev, probe_dev, d, lo, hi, acc, s);
     }
     if (e == hipSuccess) e = hipEventRecord(ctx->ev_mac, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->ev_mac, 0);
     if (e != hipSuccess) break;
-    rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, ctx->side);
+    rc = search_epilogue(ctx, acc, digits, lo, hi, scores_dev, ctx->side, mac_fused(ctx));
     if (rc == HERS_OK) e = hipEventRecord(ctx->ev_free[r], ctx->side);
   }
   // join even after a failure, so nothing of this call is left unordered
@@ -697,11 +884,26 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d
   return HERS_OK;
 }
 
-int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                        uint64_t* scores_dev, void* work_dev, size_t work_bytes, void* stream) {
+int hers::ctx_device(const hers_ctx* ctx) { return ctx->device; }
+
+size_t hers::search_ws_block_bytes(const hers_ctx* ctx) { return search_ws_per_block(ctx->host.C); }
+
+extern "C" {
+
+int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
+                const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
+                size_t work_bytes, void* stream) {
+  return hers::search_impl(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                           work_bytes, stream, true);
+}
+
+int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
+                        const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
+                        size_t work_bytes, void* stream) {
   if (!ctx || !gallery_dev || !probe_dev || !scores_dev) return fail(HERS_EINVAL, "null argument");
   if (int rc = check_d(ctx, d)) return rc;
   if (m < 1) return fail(HERS_EINVAL, "empty gallery");
+  if (int rc = check_search_buffers(ctx, m, d, gallery_words, probe_words)) return rc;
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
   const HersConsts& C = ctx->host.C;
   const int64_t M = (int64_t)hers_blocks(ctx, m);
@@ -721,9 +923,9 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, i
     sp.p[0] = prod;                                   // indexed from block lo (blk_lo 0 below)
     for (int32_t i = 0; i < d; ++i) {
       // CipherMultiply(probe_i, gallery_i): tensor, rescale, relinearization ...
-      TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, lo, hi, acc, s,
-                                            ctx->mac_variant, mac_grid(ctx), i, 1));
-      TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
+      TIMED(ctx, "mac", s, launch_mac_sched(ctx, ctx->mac_variant, gallery_dev, probe_dev, d, lo, hi, acc, s, i, 1));
+      if (!mac_fused(ctx))
+        TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)nb * 3 * C.K, 1, 1, s));
       TIMED(ctx, "rescale", s,
             hers::launch_rescale(ctx->T, C.n, acc, nb, 0, sp, 1, digits, 0, 0, s, C.k, C.K, C.fr_words));
       TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, digits, nb, 0, sp, 1, 0, s, nullptr, nullptr,
@@ -790,6 +992,7 @@ int hers_rerank_encrypt(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int
   const int64_t chunk = (int64_t)(work_bytes / per);
   DeviceGuard g(ctx->device);
   const hipStream_t s = S(stream);
+  if (int rc = check_features(ctx, feats_dev, ld, D, count, s)) return rc;
   const uint32_t domain = replicate ? HERS_DOMAIN_RERANK_PROBE : HERS_DOMAIN_RERANK_ITEMS;
   for (int64_t lo = 0; lo < nct; lo += chunk) {
     const int64_t nb = lo + chunk < nct ? chunk : nct - lo;
@@ -839,9 +1042,9 @@ int hers_rerank(hers_ctx* ctx, const uint32_t* items_search, int64_t nct_total, 
     TIMED(ctx, "gather", s, hers::launch_gather_cts(items_search, (uint64_t)C.K * 2 * C.n, nct_total, ids_dev + lo,
                                                    (uint32_t)nb, gath, s));
     // one ciphertext product per selected ciphertext (a search with d = 1)
-    TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, gath, probe_search, 1, 0, nb, acc, s, ctx->mac_variant,
-                                          mac_grid(ctx)));
-    if (int rc = search_epilogue(ctx, acc, digits, 0, nb, out_cts + (size_t)lo * ct_words, s)) return rc;
+    TIMED(ctx, "mac", s, launch_mac_sched(ctx, ctx->mac_variant, gath, probe_search, 1, 0, nb, acc, s));
+    if (int rc = search_epilogue(ctx, acc, digits, 0, nb, out_cts + (size_t)lo * ct_words, s, mac_fused(ctx)))
+      return rc;
     // rotate-and-add: cur -> nxt, ping-pong between out_cts and tmp
     uint64_t* cur = out_cts + (size_t)lo * ct_words;
     uint64_t* nxt = tmp;
@@ -883,10 +1086,12 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
   return HERS_OK;
 }
 
-int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t d, const uint32_t* probe_dev,
-                  uint64_t* scores_dev, void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen) {
-  if (!ctx || !gallery_dev || !probe_dev || reps < 1) return fail(HERS_EINVAL, "bad argument");
+int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
+                  const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
+                  size_t work_bytes, int reps, void* stream, int64_t* chosen) {
+  if (!ctx || !gallery_dev || !probe_dev || reps < 1 || m < 1) return fail(HERS_EINVAL, "bad argument");
   if (int rc = check_d(ctx, d)) return rc;
+  if (int rc = check_search_buffers(ctx, m, d, gallery_words, probe_words)) return rc;
   const HersConsts& C = ctx->host.C;
   const int64_t M = (int64_t)hers_blocks(ctx, m);
   const size_t per = search_ws_per_block(C);
@@ -899,11 +1104,19 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   float best = 0.f, cur_ms = 0.f;
   int best_v = ctx->mac_variant;
   int rc = HERS_OK;
-  for (int v = 0; v < 12 && rc == HERS_OK; ++v) {
-    hipError_t e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, 0, hi, (uint32_t*)work_dev, S(stream), v);
+  // each schedule with the accumulators' inverse NTT (which the fused one does itself)
+  const int nvar = C.n <= 4096 ? MAC_FUSED_INTT + 1 : MAC_FUSED_INTT;
+  auto mac_intt = [&](int v) {
+    uint32_t* acc = (uint32_t*)work_dev;
+    hipError_t e = launch_mac_sched(ctx, v, gallery_dev, probe_dev, d, 0, hi, acc, S(stream));
+    if (e == hipSuccess && v != MAC_FUSED_INTT)
+      e = hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)hi * 3 * C.K, 1, 1, S(stream));
+    return e;
+  };
+  for (int v = 0; v < nvar && rc == HERS_OK; ++v) {
+    hipError_t e = mac_intt(v);
     if (e == hipSuccess) e = hipEventRecord(e0, S(stream));
-    for (int r = 0; r < reps && e == hipSuccess; ++r)
-      e = hers::launch_mac(ctx->T, C.n, C.K, gallery_dev, probe_dev, d, 0, hi, (uint32_t*)work_dev, S(stream), v);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = mac_intt(v);
     if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -946,28 +1159,32 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, int64_t m, int32_t
   }
   if (rc == HERS_OK) ctx->mac_variant = best_v;
   // overlapped search: whole searches over chunk counts 1, 2, 4, 8, 16
-  // (chunks of at least 16 blocks) x MAC workgroups per CU (8, 1, 2) x the
-  // schedule chosen above, the default schedule 8 (the one timed alone need
-  // not be the best beside the epilogue) and schedule 10 (fewer registers, so
-  // epilogue waves fit beside it)
+  // (chunks of at least 16 blocks) x MAC workgroups per CU (default, 1, 2) x
+  // the schedule chosen above, the default schedule 8 (the one timed alone
+  // need not be the best beside the epilogue), schedule 10 (fewer registers,
+  // so epilogue waves fit beside it) and the fused schedule (n <= 4096)
   if (rc == HERS_OK && scores_dev) {
     float best_o = 0.f, plain_ms = 0.f;
     int best_nch = 1, best_w = 0, best_mv = best_v;
-    const int vs[3] = {best_v, 8, 10};
+    const int vs[4] = {best_v, 8, 10, nvar > MAC_FUSED_INTT ? MAC_FUSED_INTT : 10};
     bool first = true;
     for (int nch = 1; nch <= 16 && rc == HERS_OK; nch *= 2) {
       if (nch > 1 && M / nch < 16) break;
       for (int w : {0, 1, 2}) {
         if (rc != HERS_OK) break;
-        for (int vi = 0; vi < 3 && rc == HERS_OK; ++vi) {
-          if ((vi >= 1 && vs[vi] == vs[0]) || (vi == 2 && vs[2] == vs[1])) continue;
+        for (int vi = 0; vi < 4 && rc == HERS_OK; ++vi) {
+          bool seen = false;
+          for (int vj = 0; vj < vi; ++vj) seen |= vs[vj] == vs[vi];
+          if (seen) continue;
           ctx->overlap_chunks = nch;
           ctx->mac_wgs_per_cu = w;
           ctx->mac_variant = vs[vi];
-          rc = hers_search(ctx, gallery_dev, m, d, probe_dev, scores_dev, work_dev, work_bytes, stream);
+          rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                               work_bytes, stream);
           hipError_t e = rc == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
           for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
-            rc = hers_search(ctx, gallery_dev, m, d, probe_dev, scores_dev, work_dev, work_bytes, stream);
+            rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                               work_bytes, stream);
           if (rc != HERS_OK) break;
           if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
           if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1004,13 +1221,15 @@ struct BatchGroup {
 };
 
 // Groups requests by (gallery, m, d), at most MB_PROBES per group.
-int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m, const int32_t* d,
-                const uint32_t* const* probes, uint64_t* const* scores, std::vector<BatchGroup>* out) {
+int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const uint64_t* gallery_words,
+                const int64_t* m, const int32_t* d, const uint32_t* const* probes, const uint64_t* probe_words,
+                uint64_t* const* scores, std::vector<BatchGroup>* out) {
   out->clear();
   for (int32_t r = 0; r < nreq; ++r) {
     if (!galleries[r] || !probes[r] || !scores[r]) return fail(HERS_EINVAL, "null request pointer");
     if (int rc = check_d(ctx, d[r])) return rc;
     if (m[r] < 1) return fail(HERS_EINVAL, "empty gallery");
+    if (int rc = check_search_buffers(ctx, m[r], d[r], gallery_words[r], probe_words[r])) return rc;
     BatchGroup* g = nullptr;
     for (auto& x : *out)
       if (x.gallery == galleries[r] && x.m == m[r] && x.d == d[r] && x.reqs.size() < MB_PROBES) { g = &x; break; }
@@ -1069,8 +1288,8 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
       if (g.reqs.size() == 1) {
         // a lone probe streams its gallery with the single-probe schedule
         const int32_t r = g.reqs[0];
-        TIMED(ctx, "mac", s, hers::launch_mac(ctx->T, C.n, C.K, g.gallery, probes[r], g.d, lo, hi, acc_of[gi], s,
-                                              ctx->mac_variant));
+        TIMED(ctx, "mac", s, launch_mac_sched(ctx, ctx->mac_variant, g.gallery, probes[r], g.d, lo, hi, acc_of[gi],
+                                              s));
         continue;
       }
       MacGroup& G = A.g[A.ngroups];
@@ -1101,7 +1320,9 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         uint64_t* dig = dig_of[gi] + j0 * ds;
         ScorePtrs sp;
         for (uint32_t j = 0; j < nr; ++j) sp.p[j] = scores[g.reqs[j0 + j]];
-        TIMED(ctx, "intt_acc", s, hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
+        if (!(g.reqs.size() == 1 && mac_fused(ctx)))      // a lone probe's fused MAC left them transformed
+          TIMED(ctx, "intt_acc", s,
+                hers::launch_ntt_p(ctx->T, C.n, acc, (uint64_t)(hi - lo) * 3 * C.K, 1, 1, s, nr, as));
         TIMED(ctx, "rescale", s,
               hers::launch_rescale(ctx->T, C.n, acc, hi - lo, lo, sp, nr, dig, as, ds, s, C.k, C.K, C.fr_words));
         TIMED(ctx, "relin", s, hers::launch_relin(ctx->T, C.n, C.k, C.L, dig, hi - lo, lo, sp, nr, ds, s, nullptr,
@@ -1114,14 +1335,15 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
 
 }  // namespace
 
-int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
-                      const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores, void* work_dev,
-                      size_t work_bytes, void* stream) {
-  if (!ctx || nreq < 0 || (nreq && (!galleries || !m || !d || !probes || !scores)))
+int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const uint64_t* gallery_words,
+                      const int64_t* m, const int32_t* d, const uint32_t* const* probes, const uint64_t* probe_words,
+                      uint64_t* const* scores, void* work_dev, size_t work_bytes, void* stream) {
+  if (!ctx || nreq < 0 ||
+      (nreq && (!galleries || !gallery_words || !m || !d || !probes || !probe_words || !scores)))
     return fail(HERS_EINVAL, "null argument");
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
   std::vector<BatchGroup> groups;
-  if (int rc = plan_groups(ctx, nreq, galleries, m, d, probes, scores, &groups)) return rc;
+  if (int rc = plan_groups(ctx, nreq, galleries, gallery_words, m, d, probes, probe_words, scores, &groups)) return rc;
   DeviceGuard g(ctx->device);
   return run_batch(ctx, groups, probes, scores, work_dev, work_bytes, S(stream));
 }
@@ -1132,15 +1354,15 @@ struct hers_plan {
   hipGraphExec_t exec = nullptr;
 };
 
-int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const int64_t* m,
-                     const int32_t* d, const uint32_t* const* probes, uint64_t* const* scores, void* work_dev,
-                     size_t work_bytes, hers_plan** out) {
-  if (!ctx || !out || nreq < 1 || !galleries || !m || !d || !probes || !scores)
+int hers_plan_create(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const uint64_t* gallery_words,
+                     const int64_t* m, const int32_t* d, const uint32_t* const* probes, const uint64_t* probe_words,
+                     uint64_t* const* scores, void* work_dev, size_t work_bytes, hers_plan** out) {
+  if (!ctx || !out || nreq < 1 || !galleries || !gallery_words || !m || !d || !probes || !probe_words || !scores)
     return fail(HERS_EINVAL, "null argument");
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
   *out = nullptr;
   std::vector<BatchGroup> groups;
-  if (int rc = plan_groups(ctx, nreq, galleries, m, d, probes, scores, &groups)) return rc;
+  if (int rc = plan_groups(ctx, nreq, galleries, gallery_words, m, d, probes, probe_words, scores, &groups)) return rc;
   DeviceGuard g(ctx->device);
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

@@ -62,6 +62,8 @@ struct HersConsts {
   uint32_t Qw_p_sh[HC_MAXQ][HC_MAXP];
   uint32_t qmod_p[HC_MAXP];                          // q mod p_r
   uint32_t p_r64[HC_MAXP], p_r64_sh[HC_MAXP];        // 2^64 mod p_r
+  uint64_t phat_q[HC_MAXP][HC_MAXQ];                 // (P / p_r) mod q_i
+  uint64_t P_q[HC_MAXQ];                             // P mod q_i
 
   // ---- plaintext prime t
   uint64_t t_mu64;                                   // floor(2^64 / t)

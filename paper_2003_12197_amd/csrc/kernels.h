@@ -67,11 +67,22 @@ hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct
                           uint64_t* canon, hipStream_t s);
 hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
                        int64_t block0, uint32_t* out, hipStream_t s);
+hipError_t launch_unlift(const DevTabs& T, uint32_t n, const uint32_t* coef, uint32_t nct, int32_t d,
+                         uint64_t* canon, hipStream_t s);
+hipError_t launch_check_features(const int32_t* v, int64_t ld, int32_t rows, int64_t cols, int32_t bound,
+                                 uint32_t* flag, uint32_t num_cus, hipStream_t s);
+hipError_t launch_check_canon(const DevTabs& T, const uint64_t* canon, uint64_t words, uint32_t* flag,
+                              uint32_t num_cus, hipStream_t s);
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
                         int inverse, hipStream_t s, uint32_t nsets = 1, uint64_t set_stride = 0);
 hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
                       int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s, int variant,
                       uint32_t target_wgs = 0, int32_t dim0 = 0, int32_t dcount = 0);
+// one probe's multiply-accumulate with the inverse NTT of the accumulators
+// fused in: writes them in the coefficient domain
+hipError_t launch_mac_intt(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
+                           int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s,
+                           uint32_t target_wgs = 0, int32_t dim0 = 0, int32_t dcount = 0);
 hipError_t launch_rescale(const DevTabs& T, uint32_t n, const uint32_t* X, int64_t nblk, int64_t blk_lo,
                           const ScorePtrs& SP, uint32_t nreq, uint64_t* digits, uint64_t acc_stride,
                           uint64_t dig_stride, hipStream_t s, uint32_t k, uint32_t K, uint32_t W);

@@ -279,6 +279,67 @@ k_lift(DevTabs T, const uint64_t* __restrict__ canon, uint32_t nct, int32_t d, i
   }
 }
 
+template <int KQ>
+__global__ void __launch_bounds__(WG)
+k_unlift(DevTabs T, const uint32_t* __restrict__ coef, uint32_t nct, int32_t d, uint64_t* __restrict__ canon) {
+  // The inverse of the lift, for exporting a search form: coef holds the
+  // centred representative x of every coefficient modulo each p_r in the
+  // coefficient domain, block-local layout [nct / d][K][d][2][n].  By CRT
+  // over P, x = sum_r y_r (P/p_r) - gamma P with y_r = [x_r (P/p_r)^-1]_{p_r}
+  // and gamma = round(sum_r y_r / p_r): |x| < q/2 is a negligible fraction of
+  // P, so the double-precision sum (error below K 2^-52) rounds to the integer
+  // gamma exactly.  Writes x mod q_i, the canonical residues [nct][2][k][n].
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = KQ ? KQ : C.k, K = C.K;
+  const uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x;
+  if (idx >= (uint64_t)nct * n) return;
+  const uint32_t c = (uint32_t)(idx >> C.logn), j = (uint32_t)(idx & (n - 1));
+  const uint32_t bl = c / d, i = c % d;
+  for (uint32_t poly = 0; poly < 2; ++poly) {
+    uint32_t y[HC_MAXP];
+    double s = 0.0;
+    for (uint32_t r = 0; r < K; ++r) {
+      const uint32_t x = coef[((((size_t)bl * K + r) * d + i) * 2 + poly) * n + j];
+      y[r] = shoup_p(x, C.p_hatinv[r], C.p_hatinv_sh[r], C.p[r]);
+      s += (double)y[r] * C.p_inv[r];
+    }
+    const uint64_t gamma = (uint64_t)rint(s);
+    for (uint32_t ii = 0; ii < k; ++ii) {
+      const uint64_t q = C.q[ii];
+      uint64_t acc = 0;
+      for (uint32_t r = 0; r < K; ++r)
+        acc = add_q(acc, mul_q(red_q(y[r], q, C.q_mu64[ii]), C.phat_q[r][ii], q, C.q_bar[ii], C.q_beta[ii]), q);
+      acc = sub_q(acc, mul_q(gamma, C.P_q[ii], q, C.q_bar[ii], C.q_beta[ii]), q);
+      canon[(((size_t)c * 2 + poly) * k + ii) * n + j] = acc;
+    }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_check_features(const int32_t* __restrict__ v, int64_t ld, int64_t cols, int32_t bound,
+                 uint32_t* __restrict__ flag) {
+  // Sets *flag when a value of row blockIdx.y (columns 0 .. cols - 1 of a
+  // row-major array with row stride ld) lies outside [-bound, bound].
+  const int32_t* row = v + (int64_t)blockIdx.y * ld;
+  bool bad = false;
+  for (int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x; c < cols; c += (int64_t)gridDim.x * WG) {
+    const int32_t x = row[c];
+    bad |= x > bound || x < -bound;
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
+extern "C" __global__ void __launch_bounds__(WG)
+k_check_canon(DevTabs T, const uint64_t* __restrict__ canon, uint64_t words, uint32_t* __restrict__ flag) {
+  // Sets *flag when a residue of canonical ciphertexts [..][2][k][n] is not
+  // below its prime q_i.
+  const HersConsts& C = *T.C;
+  bool bad = false;
+  for (uint64_t w = (uint64_t)blockIdx.x * WG + threadIdx.x; w < words; w += (uint64_t)gridDim.x * WG)
+    bad |= canon[w] >= C.q[(uint32_t)(w >> C.logn) % C.k];
+  if (bad) atomicOr(flag, 1u);
+}
+
 extern "C" __global__ void __launch_bounds__(WG)
 k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, uint64_t req_stride) {
   // In-place negacyclic NTT mod p_r of polynomial blockIdx.x of set
@@ -433,6 +494,112 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
       o[comp] = u32x4{(uint32_t)a1[u][0], (uint32_t)a1[u][1], (uint32_t)a1[u][2], (uint32_t)a1[u][3]};
       o[2 * comp] = u32x4{(uint32_t)a2[u][0], (uint32_t)a2[u][1], (uint32_t)a2[u][2], (uint32_t)a2[u][3]};
     }
+  }
+}
+
+// ---------------------------------------------------------------- multiply-accumulate + inverse NTT
+// The same sums A0, A1, A2 for one probe, with the inverse transform of the
+// accumulators fused in (n <= 4096).  A work item is (block b, prime r): the
+// whole ring of that block and prime, NS groups of 4 slots per lane (n / (4 NS)
+// lanes, group s of lane l holding slots 4 (l + s lanes) .. + 3, so every
+// row load is coalesced).  With one group per lane the kernel fits 64
+// registers: two 1024-lane workgroups per CU at n = 4096 (52 KB of LDS each).  Dimensions are loaded one ahead of the products
+// (double buffering); the sums fold every 4 dimensions as in k_mac.  After
+// the d loop the three sums, reduced mod p_r, go to LDS, are transformed back
+// to the coefficient domain (inverse negacyclic NTT mod p_r, exactly as
+// k_ntt_p) and are written out: the accumulators the rescale reads, without
+// a separate transform launch and its round trip through memory.
+// Items are visited item = w + j G (G workgroups) with r = item mod K; with G
+// a multiple of lcm(K, 8) a workgroup keeps one prime, and since workgroups
+// are dealt to the 8 XCDs round-robin, an XCD's workgroups share the primes
+// r = w mod K, so the probe rows of those primes (d 2 n 4 bytes each) stay in
+// that XCD's L2.
+template <int NS, int MAXT>
+__global__ void __launch_bounds__(MAXT, 8)
+k_mac_intt(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe, int32_t d,
+           int32_t dim0, int32_t dcount, int64_t blk_lo, int64_t blk_hi, uint32_t* __restrict__ acc) {
+  extern __shared__ uint32_t lds32[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, K = C.K, tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t plen = padded_len(n);
+  const uint64_t items = (uint64_t)(blk_hi - blk_lo) * K;
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const uint32_t r = (uint32_t)(item % K);
+    const int64_t bl = (int64_t)(item / K);
+    const uint32_t p = C.p[r];
+    const uint64_t mu = C.p_mu64[r];
+    const uint32_t c34 = (uint32_t)((1ull << 34) - (uint64_t)p * (mu >> 30));   // 2^34 mod p
+    // wave-uniform bases and 32-bit lane offsets (the loads take the
+    // scalar-base form, so no 64-bit address is kept per lane)
+    const char* pr = (const char*)(probe + ((size_t)r * d + dim0) * 2 * n);
+    const char* gb = (const char*)(gallery + (((size_t)(blk_lo + bl) * K + r) * d + dim0) * 2 * n);
+    const uint32_t rowb = n * 4, lane_off = tid * 16;
+    uint64_t a0[NS][4], a1[NS][4], a2[NS][4];
+#pragma unroll
+    for (int g = 0; g < NS; ++g)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { a0[g][e] = 0; a1[g][e] = 0; a2[g][e] = 0; }
+    // the gallery rows (HBM) of dimension i + 1 are in flight while
+    // dimension i is multiplied; the probe rows (L2) are loaded when needed
+    struct Gal { u32x4 G0[NS], G1[NS]; };
+    auto load = [&](int32_t i, Gal& x) {
+      const uint32_t o0 = 2 * (uint32_t)i * rowb + lane_off, o1 = o0 + rowb;
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        x.G0[g] = __builtin_nontemporal_load((const u32x4*)(gb + (o0 + g * nthr * 16)));
+        x.G1[g] = __builtin_nontemporal_load((const u32x4*)(gb + (o1 + g * nthr * 16)));
+      }
+    };
+    Gal cur, nxt;
+    load(0, cur);
+    for (int32_t i = 0; i < dcount; ++i) {
+      if (i + 1 < dcount) load(i + 1, nxt);
+      const uint32_t o0 = 2 * (uint32_t)i * rowb + lane_off, o1 = o0 + rowb;
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        const u32x4 P0 = *(const u32x4*)(pr + (o0 + g * nthr * 16));
+        const u32x4 P1 = *(const u32x4*)(pr + (o1 + g * nthr * 16));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a0[g][e] += (uint64_t)P0[e] * cur.G0[g][e];
+          a1[g][e] += (uint64_t)P0[e] * cur.G1[g][e];
+          a1[g][e] += (uint64_t)P1[e] * cur.G0[g][e];
+          a2[g][e] += (uint64_t)P1[e] * cur.G1[g][e];
+        }
+      }
+      if (((i + 1) & 3) == 0) {      // fold: < 2^60 + 2^34, room for the next 4 dimensions' 8 products
+#pragma unroll
+        for (int g = 0; g < NS; ++g)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            a0[g][e] = fold34(a0[g][e], c34);
+            a1[g][e] = fold34(a1[g][e], c34);
+            a2[g][e] = fold34(a2[g][e], c34);
+          }
+      }
+      cur = nxt;
+    }
+#pragma unroll
+    for (int g = 0; g < NS; ++g)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t slot = 4 * (tid + g * nthr) + e;
+        lds32[PADX(slot)] = red_p(a0[g][e], p, mu);
+        lds32[plen + PADX(slot)] = red_p(a1[g][e], p, mu);
+        lds32[2 * plen + PADX(slot)] = red_p(a2[g][e], p, mu);
+      }
+    __syncthreads();
+    const ModP mp{p};
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j)
+      ntt_inverse_upto<3>(lds32 + j * plen, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r],
+                          C.p_ninv_sh[r], mp, n, C.logn, tid, nthr);
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+      uint32_t* o = acc + (((size_t)bl * 3 + j) * K + r) * n;
+      for (uint32_t c = tid; c < n; c += nthr) o[c] = lds32[j * plen + PADX(c)];
+    }
+    __syncthreads();                                       // LDS free for the next item
   }
 }
 
@@ -1040,6 +1207,36 @@ hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint
   return hipGetLastError();
 }
 
+hipError_t launch_unlift(const DevTabs& T, uint32_t n, const uint32_t* coef, uint32_t nct, int32_t d,
+                         uint64_t* canon, hipStream_t s) {
+  const dim3 grid((uint32_t)(((uint64_t)nct * n + WG - 1) / WG));
+  switch (T.nq) {
+    case 3: hipLaunchKernelGGL(k_unlift<3>, grid, dim3(WG), 0, s, T, coef, nct, d, canon); break;
+    case 5: hipLaunchKernelGGL(k_unlift<5>, grid, dim3(WG), 0, s, T, coef, nct, d, canon); break;
+    default: hipLaunchKernelGGL(k_unlift<0>, grid, dim3(WG), 0, s, T, coef, nct, d, canon); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_check_features(const int32_t* v, int64_t ld, int32_t rows, int64_t cols, int32_t bound,
+                                 uint32_t* flag, uint32_t num_cus, hipStream_t s) {
+  if (rows < 1 || cols < 1) return hipSuccess;
+  uint64_t gx = ((uint64_t)cols + WG - 1) / WG;
+  const uint64_t cap = (uint64_t)num_cus * 8 / (uint64_t)rows + 1;
+  if (gx > cap) gx = cap;
+  hipLaunchKernelGGL(k_check_features, dim3((uint32_t)gx, (uint32_t)rows), dim3(WG), 0, s, v, ld, cols, bound, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_canon(const DevTabs& T, const uint64_t* canon, uint64_t words, uint32_t* flag,
+                              uint32_t num_cus, hipStream_t s) {
+  if (!words) return hipSuccess;
+  uint64_t g = (words + WG - 1) / WG;
+  if (g > (uint64_t)num_cus * 8) g = (uint64_t)num_cus * 8;
+  hipLaunchKernelGGL(k_check_canon, dim3((uint32_t)g), dim3(WG), 0, s, T, canon, words, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_ntt_p(const DevTabs& T, uint32_t n, uint32_t* polys, uint64_t npolys, uint32_t inner,
                         int inverse, hipStream_t s, uint32_t nsets, uint64_t set_stride) {
   hipLaunchKernelGGL(k_ntt_p, dim3((uint32_t)npolys, nsets), dim3(WG), lds_bytes32(n), s, T, polys, inner, inverse,
@@ -1084,6 +1281,35 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
     default: return hipErrorInvalidValue;
   }
 #undef MAC_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_intt(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* gallery, const uint32_t* probe,
+                           int32_t d, int64_t blk_lo, int64_t blk_hi, uint32_t* acc, hipStream_t s,
+                           uint32_t target_wgs, int32_t dim0, int32_t dcount) {
+  if (dcount <= 0) dcount = d;
+  if (dim0 < 0 || dim0 + dcount > d) return hipErrorInvalidValue;
+  const uint64_t items = (uint64_t)(blk_hi - blk_lo) * K;
+  if (!items) return hipSuccess;
+  // a grid that is a multiple of lcm(K, 8), so every workgroup keeps one prime
+  uint64_t l = K;
+  while (l % 8) l += K;
+  uint64_t grid = target_wgs ? target_wgs : 512;
+  grid = grid / l * l;
+  if (grid < l) grid = l;
+  if (grid > items) grid = items;
+  const size_t lds = (size_t)3 * padded_len(n) * 4;
+  const uint32_t lanes = n / 4;                            // one group of 4 slots per lane
+  if (lanes > 1024) return hipErrorInvalidValue;           // n <= 4096
+  if (lanes > 512)
+    hipLaunchKernelGGL((k_mac_intt<1, 1024>), dim3((uint32_t)grid), dim3(lanes), lds, s, T, gallery, probe, d, dim0,
+                       dcount, blk_lo, blk_hi, acc);
+  else if (lanes > 256)
+    hipLaunchKernelGGL((k_mac_intt<1, 512>), dim3((uint32_t)grid), dim3(lanes), lds, s, T, gallery, probe, d, dim0,
+                       dcount, blk_lo, blk_hi, acc);
+  else
+    hipLaunchKernelGGL((k_mac_intt<1, 256>), dim3((uint32_t)grid), dim3(lanes), lds, s, T, gallery, probe, d, dim0,
+                       dcount, blk_lo, blk_hi, acc);
   return hipGetLastError();
 }
 

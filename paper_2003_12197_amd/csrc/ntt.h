@@ -259,6 +259,28 @@ HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M m
   HERS_SYNC();
 }
 
+// The inverse transform with passes of at most RMAX stages fixed at compile
+// time (the radix-16 pass keeps 16 elements and their twiddles in registers;
+// a kernel with a tight register budget takes radix 8).
+template <int RMAX, class M, class T>
+HD void ntt_inverse_upto(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n, uint32_t logn,
+                         uint32_t tid, uint32_t nthr) {
+  static_assert(RMAX >= 1 && RMAX <= 4, "1 to 4 stages per pass");
+  uint32_t lh0 = 0;
+  while (lh0 < logn) {
+    const uint32_t r = logn - lh0 < (uint32_t)RMAX ? logn - lh0 : (uint32_t)RMAX;
+    switch (r) {
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 3: if constexpr (RMAX >= 3) ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 2: if constexpr (RMAX >= 2) ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+    }
+    lh0 += r;
+  }
+  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
+  HERS_SYNC();
+}
+
 // ---- balanced double-precision transforms (every q < 2^45)
 // Values are exact integers held in doubles, kept in a signed (balanced)
 // range instead of [0, 4q), so a butterfly needs no conditional corrections.

@@ -260,6 +260,8 @@ std::string resolve(const hers_params& prm, hers_info* info) {
   }
   info->num_aux = K;
   info->log2_aux = have;
+  info->d_max = prm.d_max;
+  info->feature_bound = prm.feature_bound;
   return "";
 }
 
@@ -346,6 +348,16 @@ std::string precompute(const hers_params& prm, HostTables* T) {
     C.qmod_p[r] = (uint32_t)qm;
     C.p_r64[r] = (uint32_t)(((u128)1 << 64) % p);
     C.p_r64_sh[r] = sh32(C.p_r64[r], p);
+    for (uint32_t i = 0; i < k; ++i) {
+      uint64_t v = 1;
+      for (uint32_t s = 0; s < K; ++s) if (s != r) v = mulmod(v, info.aux[s] % info.q[i], info.q[i]);
+      C.phat_q[r][i] = v;
+    }
+  }
+  for (uint32_t i = 0; i < k; ++i) {
+    uint64_t v = 1;
+    for (uint32_t s = 0; s < K; ++s) v = mulmod(v, info.aux[s] % info.q[i], info.q[i]);
+    C.P_q[i] = v;
   }
   // rescale constants: t (P/p_r) / q = I_r + phi_r, t P / q = J + psi, fractions
   // in W words with 64 W > log2(K 2^30) + 1 + log2 q + 2 (exactness margin)

@@ -28,7 +28,8 @@ class HersParams(ctypes.Structure):
 
 class HersInfo(ctypes.Structure):
     _fields_ = [("n", c_u32), ("k", c_u32), ("q", c_u64 * MAX_QPRIMES), ("t", c_u64), ("num_digits", c_u32),
-                ("num_aux", c_u32), ("aux", c_u64 * 32), ("log2_q", ctypes.c_double), ("log2_aux", ctypes.c_double)]
+                ("num_aux", c_u32), ("aux", c_u64 * 32), ("log2_q", ctypes.c_double), ("log2_aux", ctypes.c_double),
+                ("d_max", c_u32), ("feature_bound", c_u32)]
 
 
 EXPORTS = {
@@ -48,7 +49,7 @@ EXPORTS = {
     "hers_load_keys": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "hers_enroll_append": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_u64, c_vp, c_vp, c_vp,
                                     ctypes.c_size_t, c_vp]),
-    "hers_search_literal": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search_literal": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_vp, c_u64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_rotation_key_words": (c_u64, [c_vp, c_i32]),
     "hers_rotation_keygen": (c_i32, [c_vp, c_u64, c_i32, c_vp, c_vp]),
     "hers_rerank_encrypt": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i32, ctypes.c_int, c_u64, c_vp, c_vp, c_vp,
@@ -59,18 +60,24 @@ EXPORTS = {
     "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                      ctypes.c_size_t, c_vp]),
     "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
-    "hers_search": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
-    "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
-                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
-    "hers_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_i32),
-                                 ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t,
-                                 ctypes.POINTER(c_vp)]),
+    "hers_import_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_u64, c_vp]),
+    "hers_import_probe": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_u64, c_vp]),
+    "hers_export_gallery": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp, ctypes.c_size_t,
+                                    c_vp]),
+    "hers_export_probe": (c_i32, [c_vp, c_vp, c_u64, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_vp, c_u64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
+                                  ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
+                                  ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
+    "hers_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
+                                 ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
+                                 ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, ctypes.POINTER(c_vp)]),
     "hers_plan_launch": (c_i32, [c_vp, c_vp]),
     "hers_plan_destroy": (None, [c_vp]),
     "hers_decrypt_scores": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_set_option": (c_i32, [c_vp, ctypes.c_char_p, c_i64]),
-    "hers_autotune": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
-                              ctypes.POINTER(c_i64)]),
+    "hers_autotune": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_vp, c_u64, c_vp, c_vp, ctypes.c_size_t,
+                              ctypes.c_int, c_vp, ctypes.POINTER(c_i64)]),
     "hers_get_option": (c_i32, [c_vp, ctypes.c_char_p, ctypes.POINTER(c_i64)]),
     "hers_topk_workspace_bytes": (c_u64, [c_i64, c_i32]),
     "hers_topk": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
@@ -87,7 +94,7 @@ class ServerStats(ctypes.Structure):
 
 EXPORTS.update({
     "hers_server_create": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_size_t, c_i32, ctypes.POINTER(c_vp)]),
-    "hers_server_add_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(c_i32)]),
+    "hers_server_add_gallery": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, ctypes.POINTER(c_i32)]),
     "hers_server_submit": (c_i32, [c_vp, c_i32, c_vp, c_u64, ctypes.POINTER(c_i64)]),
     "hers_server_wait": (c_i32, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(ctypes.c_double)]),
     "hers_server_stats_get": (c_i32, [c_vp, ctypes.POINTER(ServerStats)]),
@@ -95,7 +102,7 @@ EXPORTS.update({
 })
 
 OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT, OP_ENROLL, OP_SEARCH_LITERAL = 0, 1, 2, 3, 4, 5
-OP_RERANK_ENCRYPT, OP_RERANK, OP_RERANK_DECRYPT = 6, 7, 8
+OP_RERANK_ENCRYPT, OP_RERANK, OP_RERANK_DECRYPT, OP_EXPORT = 6, 7, 8, 9
 
 
 class HersError(RuntimeError):
@@ -147,6 +154,11 @@ def resolve(n, qbits, t_bits, w_bits=0, d_max=128, feature_bound=63):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _words(t):
+    """Length of a search-form buffer in u32 words."""
+    return t.numel() * t.element_size() // 4
 
 
 def _stream():
@@ -268,9 +280,9 @@ class Context:
             scores = self.new_scores(m)
         if workspace is None:
             workspace = self.workspace(OP_SEARCH, m, d)
-        _check(self.lib, self.lib.hers_search(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
-                                              _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
-               "hers_search")
+        _check(self.lib, self.lib.hers_search(self.handle, _ptr(gallery), _words(gallery), int(m), int(d), _ptr(probe),
+                                              _words(probe), _ptr(scores), _ptr(workspace), workspace.numel(),
+                                              _stream()), "hers_search")
         return scores
 
     def search_literal(self, gallery, m, d, probe, scores=None, workspace=None):
@@ -279,10 +291,56 @@ class Context:
             scores = self.new_scores(m)
         if workspace is None:
             workspace = self.workspace(OP_SEARCH_LITERAL, m, d)
-        _check(self.lib, self.lib.hers_search_literal(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
-                                                      _ptr(scores), _ptr(workspace), workspace.numel(), _stream()),
-               "hers_search_literal")
+        _check(self.lib, self.lib.hers_search_literal(self.handle, _ptr(gallery), _words(gallery), int(m), int(d),
+                                                      _ptr(probe), _words(probe), _ptr(scores), _ptr(workspace),
+                                                      workspace.numel(), _stream()), "hers_search_literal")
         return scores
+
+    # ---- canonical ciphertexts in and out of the search form
+    def import_gallery(self, canon, m_total, d, block0=0, nblocks=None, gallery=None):
+        """Canonical gallery ciphertexts of blocks block0 .. (int64 [nblocks][d][2][k][n] on
+        the device) into the search form; returns the gallery."""
+        if nblocks is None:
+            nblocks = self.blocks(m_total) - block0
+        if gallery is None:
+            gallery = self.new_gallery(m_total, d)
+        canon = canon.contiguous()
+        _check(self.lib, self.lib.hers_import_gallery(self.handle, _ptr(canon), int(m_total), int(d), int(block0),
+                                                      int(nblocks), _ptr(gallery), _words(gallery), _stream()),
+               "hers_import_gallery")
+        return gallery
+
+    def import_probe(self, canon, d, probe=None):
+        """Canonical probe ciphertexts (int64 [d][2][k][n]) into the search form."""
+        if probe is None:
+            probe = self._empty(self.lib.hers_probe_words(self.handle, int(d)), torch.int32)
+        _check(self.lib, self.lib.hers_import_probe(self.handle, _ptr(canon.contiguous()), int(d), _ptr(probe),
+                                                    _words(probe), _stream()), "hers_import_probe")
+        return probe
+
+    def export_gallery(self, gallery, m_total, d, block0=0, nblocks=None, out=None, workspace=None):
+        """Search-form blocks block0 .. back to canonical ciphertexts [nblocks][d][2][k][n]."""
+        if nblocks is None:
+            nblocks = self.blocks(m_total) - block0
+        if out is None:
+            out = torch.empty((nblocks, d, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        if workspace is None:
+            workspace = self.workspace(OP_EXPORT, nblocks * self.n, d)
+        _check(self.lib, self.lib.hers_export_gallery(self.handle, _ptr(gallery), _words(gallery), int(m_total),
+                                                      int(d), int(block0), int(nblocks), _ptr(out), _ptr(workspace),
+                                                      workspace.numel(), _stream()), "hers_export_gallery")
+        return out
+
+    def export_probe(self, probe, d, out=None, workspace=None):
+        """Search-form probe back to canonical ciphertexts [d][2][k][n]."""
+        if out is None:
+            out = torch.empty((d, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        if workspace is None:
+            workspace = self.workspace(OP_EXPORT, 1, d)
+        _check(self.lib, self.lib.hers_export_probe(self.handle, _ptr(probe), _words(probe), int(d), _ptr(out),
+                                                    _ptr(workspace), workspace.numel(), _stream()),
+               "hers_export_probe")
+        return out
 
     # ---- two-stage search, second stage (packed 1:1 re-ranking)
     def rotation_keygen(self, seed, W):
@@ -345,19 +403,23 @@ class Context:
         if workspace is None:
             workspace = self.batch_workspace(ms)
         arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
+        words = lambda ts: (c_u64 * nreq)(*[_words(t) for t in ts])
         _check(self.lib, self.lib.hers_search_batch(
-            self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
-            _ptr(workspace), workspace.numel(), _stream()), "hers_search_batch")
+            self.handle, nreq, arr(galleries), words(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds),
+            arr(probes), words(probes), arr(scores), _ptr(workspace), workspace.numel(), _stream()),
+            "hers_search_batch")
         return scores
 
     def plan(self, galleries, ms, ds, probes, scores, workspace):
         """Capture a batch as a HIP graph; returns a Plan whose launch() replays it."""
         nreq = len(galleries)
         arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
+        words = lambda ts: (c_u64 * nreq)(*[_words(t) for t in ts])
         h = c_vp()
         _check(self.lib, self.lib.hers_plan_create(
-            self.handle, nreq, arr(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds), arr(probes), arr(scores),
-            _ptr(workspace), workspace.numel(), ctypes.byref(h)), "hers_plan_create")
+            self.handle, nreq, arr(galleries), words(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds),
+            arr(probes), words(probes), arr(scores), _ptr(workspace), workspace.numel(), ctypes.byref(h)),
+            "hers_plan_create")
         return Plan(self, h, (galleries, probes, scores, workspace))
 
     def set_option(self, key, value):
@@ -369,7 +431,8 @@ class Context:
         if workspace is None:
             workspace = self.workspace(OP_SEARCH, m, d)
         v = c_i64()
-        _check(self.lib, self.lib.hers_autotune(self.handle, _ptr(gallery), int(m), int(d), _ptr(probe),
+        _check(self.lib, self.lib.hers_autotune(self.handle, _ptr(gallery), _words(gallery), int(m), int(d),
+                                                _ptr(probe), _words(probe),
                                                 _ptr(scores) if scores is not None else None,
                                                 _ptr(workspace), workspace.numel(), int(reps), _stream(),
                                                 ctypes.byref(v)), "hers_autotune")
@@ -463,7 +526,7 @@ class Server:
 
     def add_gallery(self, gallery, m, d):
         gid = c_i32()
-        _check(self.lib, self.lib.hers_server_add_gallery(self.handle, _ptr(gallery), int(m), int(d),
+        _check(self.lib, self.lib.hers_server_add_gallery(self.handle, _ptr(gallery), _words(gallery), int(m), int(d),
                                                           ctypes.byref(gid)), "hers_server_add_gallery")
         self.galleries[gid.value] = (gallery, int(m), int(d))
         return gid.value

@@ -1,0 +1,161 @@
+"""The C-ABI boundary on the GPU: canonical ciphertexts in and out of the
+search form, the input range guard and the dimension check.
+
+Sec. 3.2 "Enrollment Protocol" and "Search Protocol": the client holds the
+keys, encrypts and sends ciphertexts; the server stores and searches them.
+Here the client is the oracle: its keys are loaded into the context and its
+canonical gallery and probe ciphertexts are imported (in chunks), searched and
+compared with the oracle's own search bit for bit; exporting the search forms
+gives the imported ciphertexts back.  Values beyond +-feature_bound (Sec. 3.2,
+"Encoding Scheme": scores must stay below t/2) and non-canonical residues are
+rejected with HERS_ERANGE; a probe or gallery of another d with HERS_EDIM.
+Integer work: tolerance 0."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fv, hers
+from paper_2003_12197_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+R36 = dict(n=2048, qbits=(36, 36, 36), t_bits=20, w_bits=0)
+D, M_ITEMS = 5, 2 * 2048 + 37
+ERANGE, EDIM = -7, -3
+
+
+def res(poly, primes):
+    return np.array(fv.to_residues(poly, primes), dtype=np.int64)
+
+
+def cts_array(cts, primes):
+    """Oracle ciphertexts [(c0, c1), ...] -> int64 [len][2][k][n] residues."""
+    return np.stack([np.stack([res(c[0], primes), res(c[1], primes)]) for c in cts])
+
+
+@pytest.fixture(scope="module")
+def client(gpu_lib):
+    print("case boundary: n=2048 q=3x36 d=5 m=2*2048+37, oracle as the client", flush=True)
+    op = fv.Params(**R36)
+    osk, opk, orlk = fv.keygen(op, 901)
+    P, qv = synth.uniform_features(902, D, M_ITEMS)
+    M = hers.blocks(M_ITEMS, op.n)
+    og = {b: hers.encrypt_gallery_block(op, opk, P, b, 903) for b in range(M)}
+    oq = hers.encrypt_probe(op, opk, qv, 904)
+    want = {b: hers.search_block(op, orlk, oq, og[b]) for b in range(M)}
+    ctx = gpu_lib.Context(d_max=16, **R36)
+    dev = ctx.device
+    pk = torch.from_numpy(np.stack([res(opk[0], op.q_primes), res(opk[1], op.q_primes)])).to(dev)
+    rlk = torch.from_numpy(cts_array(orlk, op.q_primes)).to(dev)
+    ctx.load_keys(pk, rlk)
+    gcanon = np.stack([cts_array(og[b], op.q_primes) for b in range(M)])      # [M][d][2][k][n]
+    pcanon = cts_array(oq, op.q_primes)                                       # [d][2][k][n]
+    return dict(gpu_lib=gpu_lib, ctx=ctx, op=op, osk=osk, P=P, qv=qv, M=M, gcanon=gcanon, pcanon=pcanon,
+                want=want)
+
+
+def test_imported_client_ciphertexts_search_bit_exact(client):
+    ctx, op, M = client["ctx"], client["op"], client["M"]
+    dev = ctx.device
+    gal = ctx.new_gallery(M_ITEMS, D)
+    g = torch.from_numpy(client["gcanon"]).to(dev)
+    ctx.import_gallery(g[:1], M_ITEMS, D, block0=0, nblocks=1, gallery=gal)          # a chunk ...
+    ctx.import_gallery(g[1:], M_ITEMS, D, block0=1, nblocks=M - 1, gallery=gal)      # ... and the rest
+    pr = ctx.import_probe(torch.from_numpy(client["pcanon"]).to(dev), D)
+    sc = ctx.search(gal, M_ITEMS, D, pr).cpu().numpy()
+    for b, S in client["want"].items():
+        assert np.array_equal(sc[b, 0], res(S[0], op.q_primes)), b
+        assert np.array_equal(sc[b, 1], res(S[1], op.q_primes)), b
+    # the client decrypts the returned score ciphertexts
+    S = {b: ([int(x) for x in fv.from_residues(sc[b, 0].tolist(), op.q_primes)],
+             [int(x) for x in fv.from_residues(sc[b, 1].tolist(), op.q_primes)]) for b in range(M)}
+    assert np.array_equal(hers.decrypt_scores(op, client["osk"], S, M_ITEMS),
+                          hers.plaintext_scores(client["P"], client["qv"]))
+
+
+def test_export_returns_the_imported_ciphertexts(client):
+    ctx, M = client["ctx"], client["M"]
+    dev = ctx.device
+    gal = ctx.import_gallery(torch.from_numpy(client["gcanon"]).to(dev), M_ITEMS, D)
+    pr = ctx.import_probe(torch.from_numpy(client["pcanon"]).to(dev), D)
+    assert np.array_equal(ctx.export_gallery(gal, M_ITEMS, D).cpu().numpy(), client["gcanon"])
+    # a block range, through a one-block workspace
+    ws = ctx.workspace(9, ctx.n, D)
+    out = ctx.export_gallery(gal, M_ITEMS, D, block0=1, nblocks=M - 1, workspace=ws).cpu().numpy()
+    assert np.array_equal(out, client["gcanon"][1:])
+    assert np.array_equal(ctx.export_probe(pr, D).cpu().numpy(), client["pcanon"])
+
+
+def test_export_of_gpu_encryptions_equals_their_canonical_output(client):
+    """Encrypted on the GPU (canonical output kept), exported from the search
+    form: the same residues, at the batched configuration's five 44/43-bit
+    primes too."""
+    gpu_lib = client["gpu_lib"]
+    for cfg, d, m in ((R36, 4, 2048 + 3), (dict(n=256, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0), 6, 600)):
+        ctx = gpu_lib.Context(d_max=16, **cfg)
+        ctx.keygen(77)
+        P, qv = synth.uniform_features(78, d, m)
+        canon = ctx.new_canonical(m, d)
+        gal = ctx.encrypt_gallery(torch.from_numpy(P).to(ctx.device), m, 79, canon=canon)
+        pc = torch.empty((d, 2, ctx.k, ctx.n), dtype=torch.int64, device=ctx.device)
+        pr = ctx.encrypt_probe(torch.from_numpy(qv).to(ctx.device), 80, canon=pc)
+        assert torch.equal(ctx.export_gallery(gal, m, d), canon), cfg
+        assert torch.equal(ctx.export_probe(pr, d), pc), cfg
+
+
+def _code(e):
+    return int(str(e).split("(")[1].split(")")[0])
+
+
+def test_out_of_range_inputs_are_rejected(client):
+    gpu_lib, ctx = client["gpu_lib"], client["ctx"]
+    dev = ctx.device
+    P = client["P"].copy()
+    P[3, 2048 + 5] = 64                                           # bound + 1 in the second block
+    with pytest.raises(gpu_lib.HersError) as e:
+        ctx.encrypt_gallery(torch.from_numpy(P).to(dev), M_ITEMS, 1)
+    assert _code(e.value) == ERANGE
+    P[3, 2048 + 5] = -63                                          # the bound itself is allowed
+    ctx.encrypt_gallery(torch.from_numpy(P).to(dev), M_ITEMS, 1)
+    q = client["qv"].copy()
+    q[4] = -64
+    with pytest.raises(gpu_lib.HersError) as e:
+        ctx.encrypt_probe(torch.from_numpy(q).to(dev), 2)
+    assert _code(e.value) == ERANGE
+    gal = ctx.new_gallery(3, D)
+    with pytest.raises(gpu_lib.HersError) as e:
+        ctx.enroll_append(torch.from_numpy(np.full((D, 3), 100, np.int32)).to(dev), 0, 3, gal,
+                          ctx.new_canonical(3, D))
+    assert _code(e.value) == ERANGE
+    # a canonical residue equal to its prime
+    g = torch.from_numpy(client["gcanon"]).to(dev)
+    g[0, 1, 0, 2, 17] = int(ctx.q[2])
+    with pytest.raises(gpu_lib.HersError) as e:
+        ctx.import_gallery(g, M_ITEMS, D)
+    assert _code(e.value) == ERANGE
+    # the serving loop checks its host copy of the query at submission
+    srv = gpu_lib.Server(ctx, torch.zeros(ctx.n, dtype=torch.uint8, device=dev), 64 << 20)
+    try:
+        gid = srv.add_gallery(ctx.new_gallery(M_ITEMS, D), M_ITEMS, D)
+        with pytest.raises(gpu_lib.HersError) as e:
+            srv.submit(gid, q, 3)
+        assert _code(e.value) == ERANGE
+    finally:
+        srv.close()
+
+
+def test_dimension_mismatch_is_rejected(client):
+    gpu_lib, ctx = client["gpu_lib"], client["ctx"]
+    dev = ctx.device
+    gal = ctx.import_gallery(torch.from_numpy(client["gcanon"]).to(dev), M_ITEMS, D)
+    pr4 = ctx.import_probe(torch.from_numpy(client["pcanon"][:4].copy()).to(dev), 4)
+    with pytest.raises(gpu_lib.HersError) as e:                   # a probe of 4 dimensions for d = 5
+        ctx.search(gal, M_ITEMS, D, pr4)
+    assert _code(e.value) == EDIM
+    with pytest.raises(gpu_lib.HersError) as e:                   # a gallery of 5 dimensions read as 4
+        ctx.search(gal, M_ITEMS, 4, pr4)
+    assert _code(e.value) == EDIM
+    with pytest.raises(gpu_lib.HersError) as e:
+        ctx.search_batch([gal], [M_ITEMS], [D], [pr4])
+    assert _code(e.value) == EDIM

@@ -245,15 +245,21 @@ def test_chunked_calls_equal_single_call(case_r36):
 
 
 def test_batch_equals_single(case_r36):
-    """hers_search_batch over uneven requests equals one hers_search per request."""
+    """hers_search_batch over uneven requests equals one hers_search per
+    request (lone probes run the single-probe schedule, also the fused one)."""
     a = case_r36
     ctx = a.ctx
-    outs = ctx.search_batch([a.gallery, a.gallery], [a.m, 100], [a.d, a.d], [a.probe, a.probe])
-    assert torch.equal(outs[0], a.scores)
-    single = ctx.search(a.gallery, 100, a.d, a.probe)
-    assert torch.equal(outs[1], single)
-    # a 100-item prefix is block 0 of the full gallery
-    assert torch.equal(outs[1][0], a.scores[0])
+    try:
+        for v in (8, 12):
+            ctx.set_option("mac_variant", v)
+            outs = ctx.search_batch([a.gallery, a.gallery], [a.m, 100], [a.d, a.d], [a.probe, a.probe])
+            assert torch.equal(outs[0], a.scores), v
+            single = ctx.search(a.gallery, 100, a.d, a.probe)
+            assert torch.equal(outs[1], single), v
+            # a 100-item prefix is block 0 of the full gallery
+            assert torch.equal(outs[1][0], a.scores[0]), v
+    finally:
+        ctx.set_option("mac_variant", 8)
 
 
 @pytest.mark.timeout(600)
@@ -291,12 +297,15 @@ def test_full_size_single_probe_sampled_parity(gpu_lib):
     # blocks, so chunks reuse regions) give the same ciphertexts
     per = int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, d))
     try:
-        for oc, w, nblk in ((2, 0, None), (8, 1, None), (3, 2, 40)):
+        for v, oc, w, nblk in ((8, 2, 0, None), (8, 8, 1, None), (8, 3, 2, 40), (12, 1, 0, None), (12, 8, 1, None),
+                               (12, 3, 0, 40)):
+            ctx.set_option("mac_variant", v)                # 12: the MAC with the inverse NTT fused in
             ctx.set_option("overlap_chunks", oc)
             ctx.set_option("mac_wgs_per_cu", w)
             ws = None if nblk is None else torch.empty(per * nblk, dtype=torch.uint8, device=ctx.device)
-            assert torch.equal(ctx.search(gal, m, d, pr, workspace=ws), sc), (oc, w, nblk)
+            assert torch.equal(ctx.search(gal, m, d, pr, workspace=ws), sc), (v, oc, w, nblk)
     finally:
+        ctx.set_option("mac_variant", 8)
         ctx.set_option("overlap_chunks", 0)
         ctx.set_option("mac_wgs_per_cu", 0)
 
@@ -385,7 +394,7 @@ def test_schedules_and_radices_give_same_bits(case_r36):
             ctx.set_option("ntt_radix_log2", rl)
             g = ctx.encrypt_gallery(c.feats, c.m, c.gal_seed)
             assert torch.equal(g, base_g), rl
-            for v in range(12):
+            for v in range(13):                          # 12: the inverse NTT fused into the MAC
                 ctx.set_option("mac_variant", v)
                 assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), (rl, v)
         for fuse in (1, 1 << 30):                         # fused relinearization, then always two kernels
@@ -393,7 +402,7 @@ def test_schedules_and_radices_give_same_bits(case_r36):
             assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s), fuse
         ctx.set_option("relin_fuse_min_wgs", 0)
         chosen = ctx.autotune(c.gallery, c.m, c.d, c.probe, reps=1, scores=ctx.new_scores(c.m))
-        assert 0 <= chosen < 12 and 2 <= ctx.get_option("ntt_radix_log2") <= 4
+        assert 0 <= chosen <= 12 and 2 <= ctx.get_option("ntt_radix_log2") <= 4
         assert ctx.get_option("overlap_chunks") == 1     # 3 blocks: no chunking worth timing
         assert torch.equal(ctx.search(c.gallery, c.m, c.d, c.probe), base_s)
     finally:
@@ -485,8 +494,10 @@ def test_literal_schedule_bit_exact(case_r36):
     oq = c.oracle_probe()
     want = {b: hers.search_block_literal(c.op, c.orlk, oq, c.oracle_gallery_block(b)) for b in (0, 2)}
     one = torch.empty(int(ctx.lib.hers_workspace_bytes(ctx.handle, 5, 1, c.d)), dtype=torch.uint8, device=ctx.device)
-    for ws in (None, one):
+    for v, ws in ((8, None), (8, one), (12, one)):
+        ctx.set_option("mac_variant", v)
         sc = ctx.search_literal(c.gallery, c.m, c.d, c.probe, workspace=ws)
+        ctx.set_option("mac_variant", 8)
         got = sc.cpu().numpy()
         for b, S in want.items():
             assert np.array_equal(got[b, 0], res(S[0], c.op.q_primes)), b

@@ -67,16 +67,80 @@ def test_mixed_requests_equal_alone(serving):
         assert lat > 0
 
 
+def _align(x):
+    return (x + 255) // 256 * 256
+
+
+def _request_bytes(ctx, m, d):
+    """Arena bytes of one request: query, probe search form, score ciphertexts, scores."""
+    lib, h = ctx.lib, ctx.handle
+    return (_align(d * 4) + _align(int(lib.hers_probe_words(h, d)) * 4)
+            + _align(ctx.blocks(m) * int(lib.hers_ct_words(h)) * 8) + _align(m * 4))
+
+
+def _wave_bytes(ctx, m, d, nreq, blocks):
+    """Arena bytes of one wave's workspace: probe encryption, decryption and
+    `blocks` blocks of search per request."""
+    lib, h = ctx.lib, ctx.handle
+    enc = int(lib.hers_workspace_bytes(h, 1, 0, d))
+    dec = int(lib.hers_workspace_bytes(h, 3, min(m, 256 * ctx.n), 1))
+    per = int(lib.hers_workspace_bytes(h, 2, ctx.n, 1))
+    return _align(enc) + _align(dec) + _align(per * blocks * nreq)
+
+
+@pytest.mark.timeout(120)
 def test_memory_admission_defers_and_completes(serving):
-    """An arena with room for about two requests plus one wave's workspace:
-    later requests wait for memory, every result is still exact."""
+    """An arena with room for two requests and one wave's workspace, eight
+    requests on one gallery: every later request needs the memory of an
+    earlier, completed one, which is returned only when its result is
+    collected.  The results are collected from a second thread that starts
+    late, so the loop waits with nothing in flight and the queue full until
+    memory comes back; every result is still bit-identical."""
+    import threading
+    import time
     gpu_lib, ctx, sk, gals, reqs, alone = serving
-    per_req = 6 << 20
-    results, stats = _serve(gpu_lib, ctx, sk, gals, reqs[:8], 2 * per_req + (8 << 20), 4)
-    assert stats["completed"] == 8
-    assert stats["deferrals"] > 0
-    for j, (lat, out, ct) in enumerate(results):
+    g, m, d, _ = gals[2]
+    sub = [(j, r) for j, r in enumerate(reqs) if r[0] == 2]
+    sub = (sub * 3)[:8]
+    req_b = _request_bytes(ctx, m, d)
+    arena = 2 * req_b + _wave_bytes(ctx, m, d, 1, ctx.blocks(m)) + req_b // 2
+    srv = gpu_lib.Server(ctx, sk, arena, max_batch=4)
+    results = {}
+    try:
+        gid = srv.add_gallery(g, m, d)
+        tickets = [srv.submit(gid, qv, seed) for _, (_, qv, seed) in sub]
+
+        def collect():
+            time.sleep(0.5)                  # the first two complete, the rest wait for memory
+            for t in tickets:
+                results[t] = srv.wait(t, scores=True, ciphertexts=True)
+
+        th = threading.Thread(target=collect)
+        th.start()
+        th.join(90)
+        assert not th.is_alive(), "results were not all delivered"
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["completed"] == 8 and stats["deferrals"] > 0
+    assert stats["arena_peak"] <= arena
+    for t, (j, _) in zip(tickets, sub):
+        lat, out, ct = results[t]
         assert np.array_equal(ct, alone[j][0]), j
+        assert np.array_equal(out, alone[j][1]), j
+
+
+def test_close_with_queued_requests_returns(serving):
+    """Closing a server whose queue holds requests that cannot be admitted
+    (no result collected, arena full) returns instead of waiting forever."""
+    gpu_lib, ctx, sk, gals, reqs, alone = serving
+    g, m, d, _ = gals[2]
+    req_b = _request_bytes(ctx, m, d)
+    srv = gpu_lib.Server(ctx, sk, req_b + _wave_bytes(ctx, m, d, 1, ctx.blocks(m)) + 4096, max_batch=1)
+    gid = srv.add_gallery(g, m, d)
+    for j in range(3):
+        srv.submit(gid, reqs[2][1], 70 + j)
+    srv.close()
 
 
 def test_request_larger_than_arena_is_rejected(serving):
