@@ -11,10 +11,11 @@ The one-time enrollment (key generation, gallery encoding, encryption and
 lift) runs before the timed region and is reported on its own.
 
 Workloads (--workload):
-  single   1 probe vs 1,048,576 items x d=64, n=4096, q = 3 x 36-bit (default)
+  large    1 probe (or --probes 16) vs 100,000,000 items x d=32, n=4096,
+           q = 3 x 36-bit: the largest single-GPU instance (default)
+  single   1 probe vs 1,048,576 items x d=64, n=4096, q = 3 x 36-bit
   batched  64 probes in one captured HIP-graph submission vs 10,000,000 items
            x d=128, n=8192, q = 5 primes (218 bits), t ~ 2^21
-  large    1 probe (or --probes 16) vs 100,000,000 items x d=32, n=4096
   serving  Poisson query stream (200/s) against 8 resident galleries of sizes
            log-uniform in [1e3, 5e6] and d in {16, 32, 64}, n=4096, served by the
            continuous-batching request loop; also served one request at a time
@@ -39,10 +40,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
-# 64-bit integer multiply-add (v_mad_u64_u32) issue rate: 256 CUs x 4 SIMDs x
-# 16 lanes per clock at half rate x 2.4 GHz (a dependency-free microbenchmark
-# measures 20.6 T/s on the same part)
-MAD64_PEAK_TOPS = 256 * 4 * 16 / 2 * 2.4e9 / 1e12
+# 64-bit integer multiply-add (v_mad_u64_u32) peak: the larger of the issue
+# rate from the unit counts (256 CUs x 4 SIMDs x 16 lanes at half rate x
+# 2.4 GHz = 19.66 T/s) and the rate a dependency-free stream of the
+# instruction reaches on the part (20.56 T/s)
+MAD64_PEAK_TOPS = max(256 * 4 * 16 / 2 * 2.4e9 / 1e12, 20.56)
 
 WORKLOADS = {
     "single": dict(desc="single probe vs 1,048,576-item gallery, d=64, n=4096, q=3x36-bit primes, t=1,032,193",
@@ -89,12 +91,18 @@ MAC_SCHEDULES = {0: (1, 2, 0), 1: (2, 2, 0), 2: (1, 4, 0), 3: (2, 4, 0), 4: (1, 
                  7: (2, 4, 1), 8: (4, 1, 1), 9: (4, 2, 1), 10: (2, 1, 1), 11: (1, 1, 1)}
 
 
-def mac_kernel_name(variant):
+MAC_FUSED_INTT = 12      # the multiply-accumulate with the accumulators' inverse NTT fused in
+
+
+def mac_kernel_name(variant, n=4096):
+    if variant == MAC_FUSED_INTT:
+        lanes = n // 4
+        return "k_mac_intt<1, %d>" % (1024 if lanes > 512 else 512 if lanes > 256 else 256)
     nb, u, nt = MAC_SCHEDULES[variant]
     return "k_mac<%d, %d, %s>" % (nb, u, "true" if nt else "false")
 
 
-def measured_traffic(workload, variant=None):
+def measured_traffic(workload, variant=None, n=4096):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, or None when missing, taken on different kernel sources
     or for another multiply-accumulate schedule than `variant`."""
@@ -106,40 +114,79 @@ def measured_traffic(workload, variant=None):
     s = re.search(r"KERNEL_SOURCE_DIGEST=(\w+)", text)
     if not m or not s or s.group(1) != kernel_source_digest():
         return None
-    if variant is not None and not text.startswith("rocprofv3 counter passes for %s " % mac_kernel_name(variant)):
+    if variant is not None and not text.startswith("rocprofv3 counter passes for %s " % mac_kernel_name(variant, n)):
         return None
     return int(m.group(1))
 
 
-def cpu_baseline(cfg, P_block0, qv, m, probes):
-    """The oracle on a bounded sample: one probe's encryption and one block's
-    search + decryption (for d > 64, 8 of the d tensor products, scaled by
-    d/8), scaled to every block and probe (blocks and probes are independent)."""
+def _oracle_block_worker(cfg, keys, probe_cts, block, barrier, out):
+    """One host process of the CPU baseline: encrypts gallery block `block`
+    with the oracle (untimed), waits for the other processes, then times the
+    block's search (tensor over the sampled dimensions, rescale,
+    relinearization) and decryption, and checks the scores against P^T q."""
+    from oracle import fv, hers, philox
+    from paper_2003_12197_amd import synth
+    op = fv.Params(n=cfg["n"], qbits=cfg["qbits"], t_bits=cfg["t_bits"], w_bits=cfg["w_bits"])
+    sk, pk, rlk = keys
+    n, dims = cfg["n"], len(probe_cts)
+    P = synth.gallery_block(FEATURE_SEED, block, n, cfg["d"], cfg["m"])[:dims]
+    key = (GALLERY_SEED, philox.DOMAIN_GALLERY)       # as the oracle's batch enrollment of block `block`
+    og = [fv.encrypt(op, pk, [int(c) for c in row], key, (block, i))
+          for i, row in enumerate(hers.encode_slots(op, P))]
+    barrier.wait(timeout=600)
+    t0 = time.time()
+    S = hers.search_block(op, rlk, probe_cts, og)
+    scores = hers.decrypt_scores(op, sk, {0: S}, n)
+    t1 = time.time()
+    qv = cfg["_qv"][:dims]
+    out.put((block, t0, t1, bool(np.array_equal(scores, hers.plaintext_scores(P, qv)))))
+
+
+def cpu_baseline(cfg, qv, m, probes, log):
+    """The oracle on a bounded sample, on the host cores: the client's probe
+    encryption timed in this process, then W gallery blocks searched and
+    decrypted at once by W processes (one block each); the sample's wall
+    time scales linearly to all M blocks (blocks are independent) and every
+    probe.  For d > 64 only 8 of the d tensor products and probe ciphertexts
+    are computed, scaled by d/8."""
+    import multiprocessing as mp
     from oracle import fv, hers
     op = fv.Params(n=cfg["n"], qbits=cfg["qbits"], t_bits=cfg["t_bits"], w_bits=cfg["w_bits"])
     n, d = cfg["n"], cfg["d"]
+    host_cpus = os.cpu_count() or 1
+    workers = max(1, min(host_cpus, int(os.environ.get("OMP_NUM_THREADS") or 16), 16))
     sk, pk, rlk = fv.keygen(op, KEY_SEED)
     dims = d if d <= 64 else 8
-    og = hers.encrypt_gallery_block(op, pk, P_block0[:dims], 0, GALLERY_SEED)
     t0 = time.perf_counter()
     oq = hers.encrypt_probe(op, pk, qv[:dims], PROBE_SEED)
-    t1 = time.perf_counter()
-    X = fv.tensor(op, list(zip(oq, og)))
-    t2 = time.perf_counter()
-    c = tuple(fv.scale_round(op, x) for x in X)
-    S = fv.relinearize(op, rlk, c)
-    scores = hers.decrypt_scores(op, sk, {0: S}, n)
-    t3 = time.perf_counter()
-    assert np.array_equal(scores, hers.plaintext_scores(P_block0[:dims], qv[:dims]))
+    t_probe = (time.perf_counter() - t0) * d / dims
     M = (m + n - 1) // n
-    scale = d / dims
-    t_probe = (t1 - t0) * scale
-    t_block = (t2 - t1) * scale + (t3 - t2)
-    total = probes * (t_probe + M * t_block)
-    sample = "one %d-item block, %d of %d dimensions (tensor and probe encryption scaled x%g): probe " \
-             "encryption %.1f s, block search + decryption %.1f s per probe, scaled to %d blocks x %d probes" % (
-                 n, dims, d, scale, t_probe, t_block, M, probes)
-    return {"value": m * probes / total, "unit": "scores/s", "cores": 1, "kind": "oracle", "sample": sample}
+    blocks = sorted({int(b) for b in np.linspace(0, M - 1, workers)}) if M > workers else list(range(M))
+    ctx = mp.get_context("spawn")          # fresh interpreters: the workers never touch the GPU
+    barrier = ctx.Barrier(len(blocks))
+    out = ctx.Queue()
+    wcfg = dict(cfg, _qv=np.asarray(qv))
+    procs = [ctx.Process(target=_oracle_block_worker, args=(wcfg, (sk, pk, rlk), oq, b, barrier, out))
+             for b in blocks]
+    log("cpu baseline: oracle on %d host processes (os.cpu_count() = %d), blocks %s" % (
+        len(procs), host_cpus, blocks[:4] + (["..."] if len(blocks) > 4 else [])))
+    for p in procs:
+        p.start()
+    res = [out.get(timeout=900) for _ in procs]
+    for p in procs:
+        p.join()
+    start, end = min(r[1] for r in res), max(r[2] for r in res)
+    t_par = (end - start) * d / dims            # W blocks at once (tensor part scaled for d > 64)
+    ok = all(r[3] for r in res)
+    total = probes * (t_probe + M / len(blocks) * t_par)
+    sample = ("probe encryption (%d dims) %.1f s in one process; %d gallery blocks of %d items searched and "
+              "decrypted at once by %d processes in %.1f s%s; scaled to %d blocks x %d probe(s); scores "
+              "equal P^T q on the sample: %s" % (
+                  d, t_probe, len(blocks), n, len(blocks), t_par,
+                  "" if dims == d else " (%d of %d dimensions, scaled x%g)" % (dims, d, d / dims),
+                  M, probes, ok))
+    return {"value": m * probes / total, "unit": "scores/s", "cores": len(blocks), "host_cpu_count": host_cpus,
+            "kind": "oracle", "sample": sample}
 
 
 def run_serving(args, cfg):
@@ -391,7 +438,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--probes", type=int, default=0, help="override the workload's probes per step")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=0, help="serving: number of requests")
@@ -438,13 +485,10 @@ def main():
     gallery = ctx.new_gallery(m, d)
     chunk = max(1, min(M, (1 << 30) // (d * n * 4)))      # features of up to 1 GiB per chunk
     ws = ctx.workspace(hers_gpu.OP_ENCRYPT_GALLERY, chunk * n, d)
-    P_block0 = None
     enc_ms = 0.0
     for b0 in range(0, M, chunk):
         nb = min(chunk, M - b0)
         feats = synth.gallery_features(FEATURE_SEED, n, d, m, block0=b0, nblocks=nb)
-        if b0 == 0:
-            P_block0 = feats[:, :n].copy()
         ft = torch.from_numpy(feats).to(dev)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -628,8 +672,8 @@ def main():
         per_launch = (M * K * d * 2 * n * 4 + M * 3 * K * n * 4) / launches_per_step + K * d * 2 * n * 4
         achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, mac_variant),
-                "kernel": mac_kernel_name(mac_variant),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, mac_variant, n),
+                "kernel": mac_kernel_name(mac_variant, n),
                 "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
     else:
         # algorithmic 64-bit multiply-adds: 3 per (probe, block, dimension, base prime, slot) -- the
@@ -678,8 +722,7 @@ def main():
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a one-block sample ...")
-        result["cpu_baseline"] = cpu_baseline(cfg, P_block0, queries[0][0], m, npr)
+        result["cpu_baseline"] = cpu_baseline(cfg, queries[0][0], m, npr, log)
     print(json.dumps(result), flush=True)
     if not ok:
         sys.exit(1)

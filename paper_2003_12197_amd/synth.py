@@ -5,13 +5,16 @@ NIST SD4 probe/mate pairs, ImageNet; Sec. 4.2) and its DeepMDS++ compressed
 representations are not available.  Stand-ins with the same shapes:
 
   * features are integers in [-63, 63]; a compressed representation x in R^d
-    is drawn N(0, I_d), L2-normalised, divided by the paper's quantisation
-    step 0.004 (Sec. 3.2, "Encoding Scheme") and rounded, then clipped to the
-    feature bound;
+    is drawn N(0, I_d), L2-normalised, scaled and rounded, then clipped to the
+    feature bound.  The scale is the paper's quantisation step 0.004 (Sec. 3.2,
+    "Encoding Scheme"; x 250) where the bound allows it, else the scale that
+    puts the bound at four standard deviations of a coordinate (63 sqrt(d) / 4),
+    so that almost no coordinate clips (x 89 at d = 32, x 126 at d = 64);
   * gallery block b (items b*n .. b*n + n - 1) is generated from its own
     generator PCG64(seed + b), so any block can be regenerated on its own;
-  * a probe is a gallery item (its mate) plus N(0, 0.1^2) noise, re-normalised
-    and quantised the same way (the probe/mate structure of NIST SD4);
+  * a probe is a gallery item (its mate) plus N(0, (0.4 / sqrt(d))^2) noise per
+    coordinate (a noise vector of norm about 0.4), re-normalised and quantised
+    the same way (the probe/mate structure of NIST SD4);
   * the toy workload draws features uniformly in [-63, 63].
 """
 
@@ -23,9 +26,18 @@ QUANT_STEP = 0.004
 FEATURE_BOUND = 63
 
 
+def quant_scale(d):
+    """Integers per unit of a coordinate: 1 / 0.004, or less where 4 standard
+    deviations of a unit vector's coordinate (4 / sqrt(d)) would pass the bound."""
+    return min(1.0 / QUANT_STEP, FEATURE_BOUND * math.sqrt(d) / 4.0)
+
+
 def quantize(x):
-    """Real features -> integers at precision 0.004, clipped to the bound."""
-    return np.clip(np.rint(np.asarray(x) / QUANT_STEP), -FEATURE_BOUND, FEATURE_BOUND).astype(np.int32)
+    """Real unit-vector features [..., d] -> integers at the scale of
+    quant_scale(d), clipped to the bound."""
+    x = np.asarray(x)
+    s = quant_scale(x.shape[-1])
+    return np.clip(np.rint(x * s), -FEATURE_BOUND, FEATURE_BOUND).astype(np.int32)
 
 
 def uniform_features(seed, d, m):
@@ -60,8 +72,11 @@ def gallery_features(seed, n, d, m_total, block0=0, nblocks=None):
     return np.concatenate([gallery_block(seed, b, n, d, m_total) for b in range(block0, block0 + nblocks)], axis=1)
 
 
-def probe_for(seed, gallery_seed, n, d, m_total, noise=0.1):
-    """A probe whose mate is a seeded gallery item; returns (probe int32 [d], mate index)."""
+def probe_for(seed, gallery_seed, n, d, m_total, noise=None):
+    """A probe whose mate is a seeded gallery item; returns (probe int32 [d], mate index).
+    `noise` is the standard deviation per coordinate (default 0.4 / sqrt(d))."""
+    if noise is None:
+        noise = 0.4 / math.sqrt(d)
     rng = np.random.default_rng(seed)
     mate = int(rng.integers(0, m_total))
     b, j = divmod(mate, n)
@@ -75,7 +90,7 @@ def probe_for(seed, gallery_seed, n, d, m_total, noise=0.1):
 def clip_fraction(seed, n, d):
     """Fraction of quantised coordinates that hit the clip bound (one block)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    x = _unit_rows(rng, n, d) / QUANT_STEP
+    x = _unit_rows(rng, n, d) * quant_scale(d)
     return float(np.mean(np.abs(np.rint(x)) > FEATURE_BOUND))
 
 
