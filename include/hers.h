@@ -230,6 +230,24 @@ int hers_search(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_wor
                 int32_t d, const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev,
                 void* work_dev, size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as hers_search, bit for bit, with its workspace (accumulators and
+ * relinearization digits) in a static device array of HERS_SCRATCH_BYTES that
+ * the library holds on each GPU it runs on until the process ends.  The call
+ * allocates nothing; the blocks run in chunks that fit the array (never the
+ * overlapped schedule).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams, two threads, two contexts)
+ * race and must be serialised by the caller.  Every word the kernels read
+ * from the array is written earlier in the same call, so no state carries
+ * over between calls.  HERS_ESPACE if one block's workspace exceeds the
+ * array (no shipped parameter set does: n = 8192, five primes and K = 16
+ * need 3.2 MB). */
+#define HERS_SCRATCH_BYTES (64ull << 20)
+int hers_search_noalloc(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m,
+                        int32_t d, const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev,
+                        void* stream);
+
 /* The paper-literal schedule (App. B Alg. "HERS Search" as printed): for
  * every dimension i, CipherMultiply(probe_i, gallery_i) -- tensor, rescale,
  * relinearization -- then CipherAdd into the block's score ciphertext.  The

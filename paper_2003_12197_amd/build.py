@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhers.so")
 
-SOURCES = ["kernels.hip", "topk.hip", "rerank.hip", "hers_api.cpp", "params.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "topk.hip", "rerank.hip", "noalloc.hip", "hers_api.cpp", "params.cpp", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

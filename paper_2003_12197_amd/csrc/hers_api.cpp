@@ -275,6 +275,11 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
     hers_ctx_destroy(c);
     return fail(HERS_EDEVICE, "stream or event creation failed");
   }
+  if (int rc2 = hers::scratch_setup(device)) {
+    std::string msg = g_err;
+    hers_ctx_destroy(c);
+    return fail(rc2, msg);
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;

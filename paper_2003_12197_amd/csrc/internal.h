@@ -17,4 +17,7 @@ int search_impl(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_wor
                 size_t work_bytes, void* stream, bool overlap);
 int encrypt_probe_prechecked(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
                              void* work_dev, size_t work_bytes, hipStream_t s);
+// noalloc.hip: resolves this device's copy of the static scratch array (call
+// with `device` current)
+int scratch_setup(int device);
 }  // namespace hers

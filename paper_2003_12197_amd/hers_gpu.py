@@ -66,6 +66,7 @@ EXPORTS = {
                                     c_vp]),
     "hers_export_probe": (c_i32, [c_vp, c_vp, c_u64, c_i32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hers_search": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_vp, c_u64, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_search_noalloc": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_vp, c_u64, c_vp, c_vp]),
     "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
                                   ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
                                   ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
@@ -283,6 +284,13 @@ class Context:
         _check(self.lib, self.lib.hers_search(self.handle, _ptr(gallery), _words(gallery), int(m), int(d), _ptr(probe),
                                               _words(probe), _ptr(scores), _ptr(workspace), workspace.numel(),
                                               _stream()), "hers_search")
+        return scores
+
+    def search_noalloc(self, gallery, m, d, probe, scores):
+        """hers_search with the library's static scratch array as workspace (no allocation)."""
+        _check(self.lib, self.lib.hers_search_noalloc(self.handle, _ptr(gallery), _words(gallery), int(m), int(d),
+                                                      _ptr(probe), _words(probe), _ptr(scores), _stream()),
+               "hers_search_noalloc")
         return scores
 
     def search_literal(self, gallery, m, d, probe, scores=None, workspace=None):
