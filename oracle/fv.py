@@ -172,6 +172,22 @@ def encrypt(params, pk, m, key, obj3):
     return (ct0, ct1)
 
 
+def encrypt_sk(params, sk, m, key, obj3):
+    """Encryption under the secret key (reading of Sec. 3.2, "Search Protocol",
+    where the client encrypts its query with its private key; App. A defines
+    only the public-key form): ct = ([Delta m - a s + e]_q, a), a uniform in R_q,
+    e from chi, so that ct0 + ct1 s = Delta m + e.
+
+    `m` has coefficients in [0, t).  a, e are the Philox objects
+    (obj3[0], obj3[1], 0/1) under `key`."""
+    n, q = params.n, params.q
+    a = sample_uniform_q(params, key, (obj3[0], obj3[1], 0))
+    e = philox.sample_cbd(key, (obj3[0], obj3[1], 1), n, params.eta)
+    a_s = poly_mul_q(a, sk, q)
+    ct0 = [(params.delta * mi - x + ei) % q for mi, x, ei in zip(m, a_s, e)]
+    return (ct0, a)
+
+
 def decrypt(params, sk, ct):
     """Alg. "Decryption": pt = [round(t/q [ct0 + ct1 s]_q)]_t, returned in [0, t).
 

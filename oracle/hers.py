@@ -15,6 +15,9 @@ Readings of the paper (also listed in the design notes):
   * Gallery encryption is the batch form: one fresh Encrypt per (block, dim),
     randomness object (b, i, {0: u, 1: e1, 2: e2}) under key (seed, GALLERY).
     The probe's dimension i uses object (0, i, .) under key (seed, PROBE).
+  * The query is encrypted with the public key (the algorithm's Encrypt, the
+    only one App. A defines); the protocol text's "using the private key" is
+    kept as a second form, encrypt_probe_sk (key (seed, PROBE_SK)).
   * Search, fused form F: per block the exact tensor of the centred lifts is
     summed over the d dimensions, scaled by t/q and rounded once per
     component, then relinearized once; the score accumulator starts at the
@@ -155,6 +158,14 @@ def encrypt_probe(params, pk, qvec, seed):
     return [fv.encrypt(params, pk, probe_plaintext(params, qi), key, (0, i)) for i, qi in enumerate(qvec)]
 
 
+def encrypt_probe_sk(params, sk, qvec, seed):
+    """The query encrypted with the client's secret key (Sec. 3.2, "Search
+    Protocol"): dimension i is fv.encrypt_sk of [q_i]_t with randomness object
+    (0, i, .) under key (seed, PROBE_SK)."""
+    key = (seed, philox.DOMAIN_PROBE_SK)
+    return [fv.encrypt_sk(params, sk, probe_plaintext(params, qi), key, (0, i)) for i, qi in enumerate(qvec)]
+
+
 def search_block(params, rlk, probe_cts, gallery_cts):
     """Form F for one block: sum_i tensor(probe_i, gallery_i), t/q round, one relin."""
     X = fv.tensor(params, list(zip(probe_cts, gallery_cts)))
@@ -190,6 +201,16 @@ def decrypt_scores(params, sk, score_cts, m):
         take = min(n, m - b * n)
         out.extend(int(v) for v in z[:take])
     return np.array(out, dtype=np.int64)
+
+
+def top_k(scores, k):
+    """Alg. "HERS Search", client side, last step: the nearest neighbours are
+    the items of highest decrypted score (the argmax for k = 1); among equal
+    scores the lower item index comes first.  Returns (indices, scores) of the
+    k best, best first: the definition, a sort by (-score, index)."""
+    s = [int(v) for v in scores]
+    order = sorted(range(len(s)), key=lambda i: (-s[i], i))[:k]
+    return np.array(order, dtype=np.int64), np.array([s[i] for i in order], dtype=np.int64)
 
 
 def plaintext_scores(P, qvec):

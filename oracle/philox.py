@@ -36,6 +36,7 @@ DOMAIN_PROBE = 3
 DOMAIN_ENROLL = 4
 DOMAIN_RERANK_ITEMS = 5
 DOMAIN_RERANK_PROBE = 6
+DOMAIN_PROBE_SK = 7
 
 
 def philox4x64_10(ctr, key):

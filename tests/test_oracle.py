@@ -245,6 +245,40 @@ def test_encrypt_decrypt_and_add(toy):
     assert fv.noise(p, sk, c1, m1) <= p.eta * (2 * p.n + 1)
 
 
+def test_secret_key_encryption(toy):
+    """ct = (Delta m - a s + e, a): ct0 + ct1 s - Delta m is exactly the error e
+    (|e| <= eta, where a dropped or mis-signed a s term would leave a value
+    of the size of q), it decrypts to m and adds like a public-key ciphertext."""
+    p, sk, pk, _ = toy
+    rng = np.random.default_rng(9)
+    z = rng.integers(-500, 500, size=p.n)
+    m = [int(x) for x in hers.encode_slots(p, z[None])[0]]
+    key = (5, philox.DOMAIN_PROBE_SK)
+    c = fv.encrypt_sk(p, sk, m, key, (0, 3))
+    assert c[1] == fv.sample_uniform_q(p, key, (0, 3, 0))
+    e = philox.sample_cbd(key, (0, 3, 1), p.n, p.eta)
+    x = fv.poly_add(c[0], fv.poly_mul_q(c[1], sk, p.q), p.q)
+    assert [fv.center(v - p.delta * mi, p.q) for v, mi in zip(x, m)] == e
+    assert fv.noise(p, sk, c, m) <= p.eta
+    assert fv.decrypt(p, sk, c) == m
+    c2 = fv.encrypt(p, pk, m, (1, 2), (0, 0))
+    assert np.array_equal(hers.decode_slots(p, fv.decrypt(p, sk, fv.add(p, c, c2))), (2 * z) % p.t)
+
+
+def test_search_with_secret_key_probe_decrypts_to_inner_products(toy):
+    """The query encrypted under the secret key (Sec. 3.2, "Search
+    Protocol"), searched against public-key gallery ciphertexts: the decrypted
+    scores are P^T q (Eq. 1)."""
+    p, sk, pk, rlk = toy
+    rng = np.random.default_rng(10)
+    d, m = 3, p.n + 5
+    P = rng.integers(-63, 64, size=(d, m))
+    qv = rng.integers(-63, 64, size=d)
+    probe = hers.encrypt_probe_sk(p, sk, qv, 11)
+    S = {b: hers.search_block(p, rlk, probe, hers.encrypt_gallery_block(p, pk, P, b, 12)) for b in range(2)}
+    assert np.array_equal(hers.decrypt_scores(p, sk, S, m), hers.plaintext_scores(P, qv))
+
+
 def test_multiply_relin_is_slotwise_product(toy):
     p, sk, pk, rlk = toy
     rng = np.random.default_rng(8)
@@ -455,9 +489,54 @@ def test_single_prime_toy_config_exceeds_noise_budget():
     assert fv.noise(p, sk, c, want) > p.delta // 2
 
 
-def test_table2_operation_counts():
-    """Table 2, HERS row: ceil(m/n) d multiplications and ceil(m/n)(d-1) additions."""
-    for case in _paper()["table2_hers_counts"]["cases"]:
-        M = hers.blocks(case["m"], case["n"])
-        assert M * case["d"] == case["multiplications"]
-        assert M * (case["d"] - 1) == case["additions"]
+def test_top_k_definition():
+    """The client's last step (Alg. "HERS Search"): argmax, and the k best with
+    ties broken by lower index, on a hand-checked example and against a
+    brute-force maximum removal."""
+    idx, val = hers.top_k([3, 5, -2, 5, 1, 5], 4)
+    assert idx.tolist() == [1, 3, 5, 0] and val.tolist() == [5, 5, 5, 3]
+    rng = np.random.default_rng(13)
+    s = rng.integers(-4, 5, size=200)
+    left, want = list(range(200)), []
+    for _ in range(50):                             # repeatedly take the first maximal item
+        best = max(left, key=lambda i: (s[i], -i))
+        want.append(best)
+        left.remove(best)
+    assert hers.top_k(s, 50)[0].tolist() == want
+    assert hers.top_k(s, 1)[0][0] == int(np.argmax(s))
+
+
+def test_table2_operation_counts(toy, monkeypatch):
+    """Table 2, HERS row: ceil(m/n) d ciphertext multiplications, ceil(m/n)(d-1)
+    additions and no rotations.  Counted on the oracle's paper-literal search
+    (Alg. "HERS Search" as printed: per block, multiply each dimension's
+    ciphertexts and add the product into the running score; the first product
+    lands on the zero accumulator, so a block takes d - 1 additions)."""
+    case = _paper()["table2_hers_counts"]
+    assert case["rotations"] == 0
+    p, sk, pk, rlk = toy
+    d, m = 3, 2 * p.n + 3
+    rng = np.random.default_rng(12)
+    P = rng.integers(-63, 64, size=(d, m))
+    qv = rng.integers(-63, 64, size=d)
+    probe = hers.encrypt_probe(p, pk, qv, 13)
+    gallery = hers.encrypt_gallery(p, pk, P, 14)
+    counts = {"mul": 0, "add": 0}
+    mul, add = fv.multiply, fv.add
+
+    def counting_mul(*a):
+        counts["mul"] += 1
+        return mul(*a)
+
+    def counting_add(params, x, y):
+        if any(any(c) for c in x):                  # not the zero accumulator
+            counts["add"] += 1
+        return add(params, x, y)
+
+    monkeypatch.setattr(fv, "multiply", counting_mul)
+    monkeypatch.setattr(fv, "add", counting_add)
+    S = {b: hers.search_block_literal(p, rlk, probe, gallery[b]) for b in gallery}
+    M = -(-m // p.n)
+    assert len(gallery) == M and counts["mul"] == M * d and counts["add"] == M * (d - 1)
+    monkeypatch.undo()
+    assert np.array_equal(hers.decrypt_scores(p, sk, S, m), hers.plaintext_scores(P, qv))
