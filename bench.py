@@ -103,14 +103,15 @@ def mac_kernel_name(variant, n=4096):
 
 
 def measured_traffic(workload, variant=None, n=4096):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, or None when missing, taken on different kernel sources
-    or for another multiply-accumulate schedule than `variant`."""
+    """HBM bytes per gallery block of the dominant kernel from the committed
+    rocprofv3 counter summary (the counters of its launches divided by the
+    blocks they covered), or None when missing, taken on different kernel
+    sources or for another multiply-accumulate schedule than `variant`."""
     path = os.path.join(ROOT, "profiles", "k_mac_%s_pmc.txt" % workload)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"TRAFFIC_BYTES_PER_LAUNCH=(\d+)", text)
+    m = re.search(r"TRAFFIC_BYTES_PER_BLOCK=(\d+)", text)
     s = re.search(r"KERNEL_SOURCE_DIGEST=(\w+)", text)
     if not m or not s or s.group(1) != kernel_source_digest():
         return None
@@ -220,12 +221,18 @@ def run_serving(args, cfg):
         gals.append((g, m, d))
         log("  gallery %d: %d items x d=%d" % (gi, m, d))
     setup_s = time.perf_counter() - t0
+    sweep_rates = [float(x) for x in args.sweep.split(",")] if args.sweep else []
+    nq = max([nreq] + [args.sweep_requests] * bool(sweep_rates))
+    # the same targets at every rate (the arrival gaps only scale with it)
+    _, targets_all = synth.poisson_arrivals(601, rate, nq, len(gals))
+    queries_all = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED + 7919 * int(targets_all[j]), n,
+                                   gals[targets_all[j]][2], gals[targets_all[j]][1])[0] for j in range(nq)]
     arrivals, targets = synth.poisson_arrivals(601, rate, nreq, len(gals))
-    queries = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED + 7919 * int(targets[j]), n, gals[targets[j]][2],
-                               gals[targets[j]][1])[0] for j in range(nreq)]
+    queries = queries_all[:nreq]
     items_total = sum(gals[g][1] for g in targets)
 
-    def serve(max_batch, prof):
+    def serve(max_batch, prof, arrivals=arrivals, targets=targets, queries=queries, check_every=200):
+        nreq = len(arrivals)
         arena = 48 << 30
         if prof:
             ctx.profile_enable(True)
@@ -252,7 +259,7 @@ def run_serving(args, cfg):
         for j in range(nreq):
             while tickets[j] is None:
                 time.sleep(0.0005)
-            check = j % 200 == 0
+            check = j % check_every == 0
             lat, out, _ = srv.wait(tickets[j], scores=check)
             lats[j] = lat
             if check:
@@ -282,6 +289,23 @@ def run_serving(args, cfg):
     lat_1, el_1, st_1, _, _ = serve(1, False)
     log("one request per wave: p50 %.2f ms p99 %.2f ms, %.1f s" % (
         np.percentile(lat_1, 50), np.percentile(lat_1, 99), el_1))
+    # arrival-rate sweep: the same request stream, faster, batched and one per wave
+    sweep = []
+    for rr in sweep_rates:
+        arr, tg = synth.poisson_arrivals(601, rr, args.sweep_requests, len(gals))
+        qs = queries_all[:args.sweep_requests]
+        items = sum(gals[g][1] for g in tg)
+        row = {"rate_per_s": rr, "requests": args.sweep_requests}
+        for name, mb in (("batched", 16), ("one_per_wave", 1)):
+            lat, el, st, _, _ = serve(mb, False, arr, tg, qs, check_every=args.sweep_requests)
+            row[name] = {"requests_per_s": args.sweep_requests / el, "scores_per_s": items / el,
+                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "mean_wave": st["completed"] / max(1, st["waves"]), "max_wave": int(st["max_wave"])}
+        log("rate %g/s: batched %.0f req/s p50 %.2f p99 %.2f wave %.2f | one per wave %.0f req/s p50 %.2f p99 %.2f" % (
+            rr, row["batched"]["requests_per_s"], row["batched"]["p50_ms"], row["batched"]["p99_ms"],
+            row["batched"]["mean_wave"], row["one_per_wave"]["requests_per_s"], row["one_per_wave"]["p50_ms"],
+            row["one_per_wave"]["p99_ms"]))
+        sweep.append(row)
     mac_ms = stages["mac"][0] + stages["mac_multi"][0]
     achieved = st_b["gallery_bytes"] / (mac_ms * 1e-3) / 1e9 if mac_ms else 0.0
     result = {
@@ -305,6 +329,8 @@ def run_serving(args, cfg):
         "enrollment": {"wall_s": setup_s},
         "check": {"requests_checked_against_PTq": checked},
     }
+    if sweep:
+        result["sweep"] = sweep
     print(json.dumps(result), flush=True)
 
 
@@ -339,7 +365,7 @@ def run_two_stage(args, cfg):
     log("two-stage: %d items, stage 1 d=%d, stage 2 D=%d (W=%d, %d items per ciphertext), K=%d; enrolled in %.1f s" % (
         m, d1, D, W, S, K, setup_s))
     qv, mate = synth.probe_for(QUERY_SEED, FEATURE_SEED, n, D, m, noise=0.03)
-    q1 = torch.from_numpy(np.ascontiguousarray(qv[:d1])).to(dev)
+    q1 = np.ascontiguousarray(qv[:d1])                  # the client's query (host)
     q2 = torch.from_numpy(qv.reshape(D, 1).copy()).to(dev)
     p1 = torch.empty(int(ctx1.lib.hers_probe_words(ctx1.handle, d1)), dtype=torch.int32, device=dev)
     sc1 = ctx1.new_scores(m)
@@ -442,6 +468,8 @@ def main():
     ap.add_argument("--probes", type=int, default=0, help="override the workload's probes per step")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=0, help="serving: number of requests")
+    ap.add_argument("--sweep", default="", help="serving: comma-separated arrival rates to sweep (req/s)")
+    ap.add_argument("--sweep-requests", type=int, default=1000, help="serving: requests per sweep rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-literal", action="store_true", help="skip timing the paper-literal schedule")
     ap.add_argument("--no-autotune", action="store_true",
@@ -506,7 +534,7 @@ def main():
 
     # ---- probes, outputs, workspaces
     queries = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED, n, d, m) for j in range(npr)]
-    qdev = [torch.from_numpy(q).to(dev) for q, _ in queries]
+    qhost = [np.ascontiguousarray(q, dtype=np.int32) for q, _ in queries]   # the client's queries (host)
     probes = [torch.empty(int(ctx.lib.hers_probe_words(ctx.handle, d)), dtype=torch.int32, device=dev)
               for _ in range(npr)]
     # A batch whose score ciphertexts (npr x blocks x 2 x k x n words) do not
@@ -529,7 +557,7 @@ def main():
     ws_p = ctx.workspace(hers_gpu.OP_ENCRYPT_PROBE, 0, d)
     ws_d = ctx.workspace(hers_gpu.OP_DECRYPT, min(m, 512 * n), 1)   # decryption in rounds of 512 blocks
     for j in range(npr):
-        ctx.encrypt_probe(qdev[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
+        ctx.encrypt_probe(qhost[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
     ctx.load_secret_key(sk)          # the client keeps its key's transform
     plan = None
     if npr == 1:
@@ -562,7 +590,7 @@ def main():
 
     def step(seed, eager=False):
         for j in range(npr):
-            ctx.encrypt_probe(qdev[j], seed + j, probe=probes[j], workspace=ws_p)
+            ctx.encrypt_probe(qhost[j], seed + j, probe=probes[j], workspace=ws_p)
         if plan is None:
             search()
             for j in range(npr):
@@ -671,10 +699,13 @@ def main():
         launches_per_step = dom_n / dom_steps
         per_launch = (M * K * d * 2 * n * 4 + M * 3 * K * n * 4) / launches_per_step + K * d * 2 * n * 4
         achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
+        per_block = measured_traffic(args.workload, mac_variant, n)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, mac_variant, n),
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None if per_block is None else per_block * M / launches_per_step,
                 "kernel": mac_kernel_name(mac_variant, n),
-                "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
+                "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms,
+                "blocks_per_launch": M / launches_per_step}
     else:
         # algorithmic 64-bit multiply-adds: 3 per (probe, block, dimension, base prime, slot) -- the
         # tensor's P0 G0 and P1 G1 and, for its cross term, (P0 + P1)(G0 + G1) (Karatsuba)
@@ -682,7 +713,7 @@ def main():
         per_launch = 3.0 * npr * M * d * K * n / launches_per_step
         achieved = per_launch / (dom_avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": MAD64_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / MAD64_PEAK_TOPS, "traffic": measured_traffic(args.workload),
+                "frac": achieved / MAD64_PEAK_TOPS, "traffic": None,
                 "kernel": "k_mac_multi", "mads_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
 
     value = m * npr * args.steps / (total_ms * 1e-3)

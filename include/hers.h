@@ -27,9 +27,10 @@
  *     must be exactly hers_probe_words(d) long, a gallery a whole number of
  *     blocks of hers_gallery_words(n, d) words covering the m items; a buffer
  *     of another d is rejected with HERS_EDIM.
- *   - Calls that take features, a query or canonical ciphertexts check every
+ *   - Calls that take device features or canonical ciphertexts check every
  *     value on the GPU first (HERS_ERANGE) and synchronise `stream` to read
- *     the result: they are not for stream capture.
+ *     the result: they are not for stream capture.  A probe's query is a
+ *     host array, checked on the host.
  *
  * Randomness: every random polynomial is drawn from Philox4x64-10 (Salmon et
  * al., SC'11) with key (seed, domain) and counter (w / 4, obj0, obj1, obj2);
@@ -122,7 +123,8 @@ uint64_t hers_probe_words(const hers_ctx* ctx, int32_t d);            /* u32: K 
  * items, 3 = decrypt_scores over m items, 4 = enroll_append of a batch of
  * m items, 5 = search_literal over m items, 6 = rerank_encrypt of m
  * ciphertexts, 7 = rerank of m selected ciphertexts, 8 = rerank_decrypt of m
- * ciphertexts, 9 = export of the search form of m items (a probe: m = 1). */
+ * ciphertexts, 9 = export of the search form of m items (a probe: m = 1),
+ * 10 = encrypt_probe_sk of d dimensions. */
 uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d);
 
 /* ---- keys (App. A, Alg. "Key Generation") ------------------------------- */
@@ -181,12 +183,32 @@ int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int6
 /* ---- query (App. B Alg. "HERS Search", client side) ---------------------
  * Dimension i is the constant plaintext [q_i]_t (Eq. 2), encrypted with the
  * public key (Philox key (seed, 3), objects (0, i, 0|1|2)).
- *   query_dev int32 [d], every value within +-feature_bound (else HERS_ERANGE);
+ *   query int32 [d] in HOST memory, every value within +-feature_bound (else
+ *   HERS_ERANGE, checked on the host); the values travel in the kernel
+ *   arguments, so the call does not wait on the stream;
  *   probe_dev search form u32 [K][d][2][n];
  *   canon_dev optional canonical cts [d][2][k][n]. */
-int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed,
+int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query, int32_t d, uint64_t seed,
                        uint32_t* probe_dev, uint64_t* canon_dev, void* work_dev,
                        size_t work_bytes, void* stream);
+
+/* The query encrypted under the client's secret key instead (Sec. 3.2,
+ * "Search Protocol": the client encrypts the query "using the private key";
+ * App. A defines only public-key encryption, which hers_encrypt_probe
+ * follows): dimension i is ([Delta [q_i]_t - a s + e]_q, a), a uniform in R_q
+ * (Philox key (seed, 7), object (0, i, 0): residue rho of coefficient j from
+ * words 2(rho n + j), 2(rho n + j) + 1 as a 128-bit integer), e centred
+ * binomial (object (0, i, 1)); so ct0 + ct1 s = Delta m + e, with less noise
+ * than the public-key form.  Searched like any probe.
+ *   sk_dev uint8 [n], or NULL for the key of hers_load_secret_key;
+ *   query int32 [d] in host memory within +-feature_bound (else HERS_ERANGE);
+ *   probe_dev search form u32 [K][d][2][n] of probe_words words (else HERS_EDIM);
+ *   canon_dev optional canonical cts [d][2][k][n];
+ *   work_dev hers_workspace_bytes(ctx, 10, 0, d) (less without a canon_dev
+ *   or with sk_dev NULL: none when both are absent). */
+int hers_encrypt_probe_sk(hers_ctx* ctx, const uint8_t* sk_dev, const int32_t* query, int32_t d, uint64_t seed,
+                          uint32_t* probe_dev, uint64_t probe_words, uint64_t* canon_dev, void* work_dev,
+                          size_t work_bytes, void* stream);
 
 /* ---- canonical ciphertexts in and out (Sec. 3.2 "Enrollment Protocol" and
  * "Search Protocol": the client encrypts and sends ciphertexts, the server
@@ -422,7 +444,7 @@ int hers_topk(hers_ctx* ctx, const int32_t* scores_dev, int64_t m, int32_t k, in
  * memory) and the evaluation key stay resident.  A query submitted with
  * hers_server_submit is, on the GPU, encrypted (hers_encrypt_probe with the
  * given seed), searched against its gallery and decrypted with sk_dev.
- *   Admission: every request needs query + probe + score ciphertexts +
+ *   Admission: every request needs probe + score ciphertexts +
  *   decrypted scores, and each wave a workspace, all carved from arena_dev
  *   (arena_bytes of device memory owned by the caller) by a first-fit
  *   allocator; a request that does not fit waits (counted in deferrals) until

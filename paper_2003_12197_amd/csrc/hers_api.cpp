@@ -546,6 +546,7 @@ uint64_t hers_workspace_bytes(const hers_ctx* ctx, int op, int64_t m, int32_t d)
     case 7: return (uint64_t)m * rerank_ws_per_ct(C);
     case 8: return decrypt_ws_fixed(C) + (uint64_t)m * (decrypt_ws_per_block(C) + align256((size_t)C.n * 4));
     case 9: return M * (uint64_t)C.K * d * 2 * C.n * 4;
+    case 10: return align256((size_t)d * 2 * C.k * C.n * 8) + align256((size_t)2 * C.k * C.n * 8);
     default: return 0;
   }
 }
@@ -639,9 +640,18 @@ int hers_enroll_append(hers_ctx* ctx, const int32_t* feats_dev, int64_t ld, int6
 
 }  // extern "C"
 
-// Probe encryption after the query's range check (the serving loop checks
-// its host copy of the query at submission).
-static int encrypt_probe_impl(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
+// Query values (host) within +-feature_bound.
+static int check_query(const hers_ctx* c, const int32_t* query, int32_t d) {
+  const int64_t b = c->prm.feature_bound;
+  for (int32_t i = 0; i < d; ++i)
+    if ((int64_t)query[i] > b || (int64_t)query[i] < -b)
+      return fail(HERS_ERANGE, "a query value lies outside [-feature_bound, feature_bound]");
+  return HERS_OK;
+}
+
+// Probe encryption after the query's range check; the query (host) travels
+// in the kernel arguments.
+static int encrypt_probe_impl(hers_ctx* ctx, const int32_t* query, int32_t d, uint64_t seed, uint32_t* probe_dev,
                               uint64_t* canon_dev, void* work_dev, size_t work_bytes, hipStream_t s) {
   const HersConsts& C = ctx->host.C;
   uint64_t* canon = canon_dev;
@@ -650,33 +660,57 @@ static int encrypt_probe_impl(hers_ctx* ctx, const int32_t* query_dev, int32_t d
     canon = (uint64_t*)work_dev;
   }
   DeviceGuard g(ctx->device);
-  TIMED(ctx, "encrypt", s, hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query_dev, d, 0, seed,
+  TIMED(ctx, "encrypt", s, hers::launch_encrypt(ctx->T, C.n, C.k, (uint32_t)d, nullptr, query, d, 0, seed,
                                                 HERS_DOMAIN_PROBE, canon, s));
   TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, s));
   TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, s));
   return HERS_OK;
 }
 
-int hers::encrypt_probe_prechecked(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed,
+int hers::encrypt_probe_prechecked(hers_ctx* ctx, const int32_t* query, int32_t d, uint64_t seed,
                                    uint32_t* probe_dev, void* work_dev, size_t work_bytes, hipStream_t s) {
-  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (!ctx || !query || !probe_dev) return fail(HERS_EINVAL, "null argument");
   if (int rc = check_d(ctx, d)) return rc;
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
-  return encrypt_probe_impl(ctx, query_dev, d, seed, probe_dev, nullptr, work_dev, work_bytes, s);
+  return encrypt_probe_impl(ctx, query, d, seed, probe_dev, nullptr, work_dev, work_bytes, s);
 }
 
 extern "C" {
 
-int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query_dev, int32_t d, uint64_t seed, uint32_t* probe_dev,
+int hers_encrypt_probe(hers_ctx* ctx, const int32_t* query, int32_t d, uint64_t seed, uint32_t* probe_dev,
                        uint64_t* canon_dev, void* work_dev, size_t work_bytes, void* stream) {
-  if (!ctx || !query_dev || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (!ctx || !query || !probe_dev) return fail(HERS_EINVAL, "null argument");
   if (int rc = check_d(ctx, d)) return rc;
   if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no public key loaded");
   if (!canon_dev && (!work_dev || work_bytes < (size_t)d * 2 * ctx->host.C.k * ctx->host.C.n * 8))
     return fail(HERS_ESPACE, "workspace too small");
+  if (int rc = check_query(ctx, query, d)) return rc;
+  return encrypt_probe_impl(ctx, query, d, seed, probe_dev, canon_dev, work_dev, work_bytes, S(stream));
+}
+
+int hers_encrypt_probe_sk(hers_ctx* ctx, const uint8_t* sk_dev, const int32_t* query, int32_t d, uint64_t seed,
+                          uint32_t* probe_dev, uint64_t probe_words, uint64_t* canon_dev, void* work_dev,
+                          size_t work_bytes, void* stream) {
+  if (!ctx || !query || !probe_dev) return fail(HERS_EINVAL, "null argument");
+  if (int rc = check_d(ctx, d)) return rc;
+  if (!sk_dev && !ctx->sk_loaded) return fail(HERS_EINVAL, "no secret key given or loaded");
+  const HersConsts& C = ctx->host.C;
+  if (probe_words != (uint64_t)C.K * d * 2 * C.n)
+    return fail(HERS_EDIM, "probe buffer length is not the search form of d dimensions");
+  const size_t canon_b = canon_dev ? 0 : align256((size_t)d * 2 * C.k * C.n * 8);
+  const size_t key_b = sk_dev ? align256((size_t)2 * C.k * C.n * 8) : 0;
+  if (canon_b + key_b && (!work_dev || work_bytes < canon_b + key_b)) return fail(HERS_ESPACE, "workspace too small");
+  if (int rc = check_query(ctx, query, d)) return rc;
   DeviceGuard g(ctx->device);
-  if (int rc = check_features(ctx, query_dev, d, 1, d, S(stream))) return rc;
-  return encrypt_probe_impl(ctx, query_dev, d, seed, probe_dev, canon_dev, work_dev, work_bytes, S(stream));
+  const hipStream_t s = S(stream);
+  uint64_t* canon = canon_dev ? canon_dev : (uint64_t*)work_dev;
+  uint64_t* Sn = sk_dev ? (uint64_t*)((char*)work_dev + canon_b) : ctx->sk_ntt;
+  uint64_t* Ssh = Sn + (size_t)C.k * C.n;
+  if (sk_dev) TIMED(ctx, "sk_ntt", s, hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, s));
+  TIMED(ctx, "encrypt", s, hers::launch_encrypt_sk(ctx->T, C.n, C.k, query, d, seed, Sn, Ssh, canon, s));
+  TIMED(ctx, "lift", s, hers::launch_lift(ctx->T, C.n, canon, (uint32_t)d, d, 0, probe_dev, s));
+  TIMED(ctx, "ntt_fwd", s, hers::launch_ntt_p(ctx->T, C.n, probe_dev, (uint64_t)C.K * d * 2, 2 * d, 0, s));
+  return HERS_OK;
 }
 
 // ---- canonical ciphertexts in and out of the search form
@@ -1280,8 +1314,9 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
     std::memset(&A, 0, sizeof(A));
     auto flush = [&]() -> int {
       if (!A.ngroups) return HERS_OK;
+      // a multiple of 8 workgroups (the kernel deals its items to the XCDs)
       uint64_t grid = (uint64_t)ctx->num_cus * 2;
-      if (grid > A.total_items) grid = A.total_items;
+      if (grid > (A.total_items + 7) / 8 * 8) grid = (A.total_items + 7) / 8 * 8;
       TIMED(ctx, "mac_multi", s, hers::launch_mac_multi(ctx->T, A, (uint32_t)grid, s));
       std::memset(&A, 0, sizeof(A));
       return HERS_OK;

@@ -177,6 +177,7 @@ HD Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uin
 #define HERS_DOMAIN_ENROLL 4
 #define HERS_DOMAIN_RERANK_ITEMS 5
 #define HERS_DOMAIN_RERANK_PROBE 6
+#define HERS_DOMAIN_PROBE_SK 7
 
 // Word w of object (o0, o1, o2) under key (seed, domain).
 HD uint64_t philox_word(uint64_t seed, uint64_t domain, uint64_t o0, uint64_t o1, uint64_t o2, uint64_t w) {

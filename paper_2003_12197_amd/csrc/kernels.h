@@ -22,6 +22,13 @@ struct DevTabs {
   const double *qtw_f, *qitw_f, *qf;
 };
 
+// Query values of a probe encryption, passed by value in the kernel arguments
+// (no host-to-device copy): up to HERS_QCHUNK dimensions per launch.
+#define HERS_QCHUNK 256
+struct QueryVals {
+  int32_t v[HERS_QCHUNK];
+};
+
 // Batched multiply-accumulate: up to MB_PROBES probes of one gallery per group.
 #define MB_PROBES 16
 #define MB_WG (64 * MB_PROBES)
@@ -62,9 +69,14 @@ hipError_t launch_encode(const DevTabs& T, uint32_t n, const int32_t* feats, int
                          hipStream_t s);
 hipError_t launch_ct_add(const DevTabs& T, uint32_t n, uint32_t k, uint64_t* dst, const uint64_t* fresh, uint32_t nct,
                          int32_t d, int64_t block0, int64_t first_empty_block, hipStream_t s);
+// gallery (pt != NULL: nct plaintexts) or probe (query != NULL: host values of
+// dimensions qdim0 .. qdim0 + nct - 1, canon at the first of them)
 hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct, const uint32_t* pt,
                           const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
-                          uint64_t* canon, hipStream_t s);
+                          uint64_t* canon, hipStream_t s, int32_t qdim0 = 0);
+// probe dimensions 0 .. d - 1 from host query values
+hipError_t launch_encrypt_sk(const DevTabs& T, uint32_t n, uint32_t k, const int32_t* query, int32_t d, uint64_t seed,
+                             const uint64_t* S, const uint64_t* Ssh, uint64_t* canon, hipStream_t s);
 hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
                        int64_t block0, uint32_t* out, hipStream_t s);
 hipError_t launch_unlift(const DevTabs& T, uint32_t n, const uint32_t* coef, uint32_t nct, int32_t d,

@@ -7,6 +7,7 @@
 //   accumulators           u32 [M][3][K][n]   sum_i of the tensor, NTT then coefficient domain
 //   relin digits           u64 [M][L][k][n]   digit g of c2, reduced mod q_sigma
 // Workgroups are 256 lanes (four wave64s).
+#include <cstring>
 #include <type_traits>
 
 #include "kernels.h"
@@ -161,7 +162,7 @@ k_ct_add(DevTabs T, uint64_t* __restrict__ dst, const uint64_t* __restrict__ fre
 
 template <bool QF>
 __global__ void __launch_bounds__(WG_ENC)
-k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict__ query,
+k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, QueryVals qv, int32_t qdim0,
           int32_t d, int64_t block0, uint64_t seed, uint32_t domain, uint64_t* __restrict__ canon) {
   // Alg. "Encryption" for ciphertext c (gallery: c = b_local d + i, or probe
   // dimension c) and residue rho: ct = ([Delta m + pk0 u + e1]_q, [pk1 u + e2]_q).
@@ -171,8 +172,9 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   const uint32_t c = blockIdx.x, rho = blockIdx.y;
   const uint64_t q = C.q[rho];
   const ModQ mq{q};
+  const bool query = pt == nullptr;                     // probe dimension qdim0 + c
   const uint64_t o0 = query ? 0 : (uint64_t)(block0 + c / d);
-  const uint64_t o1 = query ? c : c % d;
+  const uint64_t o1 = query ? (uint64_t)(qdim0 + c) : c % d;
   uint64_t* U = lds64;
   uint64_t* V = lds64 + padded_len(n);
   uint64_t* W = V;                      // n/64 words of u, consumed before V is written
@@ -229,7 +231,7 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
   }
   uint32_t qconst = 0;
   if (query) {
-    int64_t z = (int64_t)query[c] % (int64_t)C.t;
+    int64_t z = (int64_t)qv.v[c] % (int64_t)C.t;
     if (z < 0) z += C.t;
     qconst = (uint32_t)z;
   }
@@ -247,6 +249,57 @@ k_encrypt(DevTabs T, const uint32_t* __restrict__ pt, const int32_t* __restrict_
       uint64_t v1 = e2 >= 0 ? add_q(V[PADX(j)], (uint64_t)e2, q) : sub_q(V[PADX(j)], (uint64_t)(-e2), q);
       o_ct0[j] = v0;
       o_ct1[j] = v1;
+    }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(WG_ENC)
+k_encrypt_sk(DevTabs T, QueryVals qv, int32_t qdim0, uint64_t seed, const uint64_t* __restrict__ S,
+             const uint64_t* __restrict__ Ssh, uint64_t* __restrict__ canon) {
+  // Probe dimension qdim0 + c, c = blockIdx.x, encrypted under the secret key (Sec. 3.2,
+  // "Search Protocol": the client encrypts its query with its private key),
+  // residue rho = blockIdx.y: ct = ([Delta m - a s + e]_q, a) with m the
+  // constant [query_c]_t, a uniform (Philox object (0, c, 0): residue rho of
+  // coefficient j from words 2(rho n + j), 2(rho n + j) + 1 as a 128-bit
+  // integer), e centred binomial (object (0, c, 1), word j).  S, Ssh: the
+  // secret key's NTT form mod each q_sigma with Shoup companions, [k][n].
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x;
+  const uint32_t c = blockIdx.x, rho = blockIdx.y, ci = (uint32_t)qdim0 + c;
+  const uint64_t q = C.q[rho];
+  const ModQ mq{q};
+  uint64_t* A = lds64;
+  uint64_t* o_ct0 = canon + (((size_t)c * 2 + 0) * k + rho) * n;
+  uint64_t* o_ct1 = canon + (((size_t)c * 2 + 1) * k + rho) * n;
+  for (uint32_t h = tid; h < n / 2; h += WG_ENC) {        // two coefficients per Philox block
+    Philox4 b = philox4x64_10(((uint64_t)rho * n) / 2 + h, 0, ci, 0, seed, HERS_DOMAIN_PROBE_SK);
+    for (int s = 0; s < 2; ++s) {
+      const uint64_t lo = b.v[2 * s], hi = b.v[2 * s + 1];
+      const uint64_t v = add_q(shoup_q(red_q(hi, q, C.q_mu64[rho]), C.q_r64[rho], C.q_r64_sh[rho], q),
+                               red_q(lo, q, C.q_mu64[rho]), q);
+      A[PADX(2 * h + s)] = v;
+      o_ct1[2 * h + s] = v;
+    }
+  }
+  __syncthreads();
+  ntt_forward16(A, T.qtw + (size_t)rho * n, T.qtw_sh + (size_t)rho * n, mq, n, C.logn, tid, WG_ENC, T.ntt_r);
+  for (uint32_t j = tid; j < n; j += WG_ENC)
+    A[PADX(j)] = shoup_q(A[PADX(j)], S[(size_t)rho * n + j], Ssh[(size_t)rho * n + j], q);   // a s
+  __syncthreads();
+  ntt_inverse16(A, T.qitw + (size_t)rho * n, T.qitw_sh + (size_t)rho * n, C.q_ninv[rho], C.q_ninv_sh[rho], mq, n,
+                C.logn, tid, WG_ENC, T.ntt_r);
+  int64_t z = (int64_t)qv.v[c] % (int64_t)C.t;
+  if (z < 0) z += C.t;
+  const uint64_t dm = shoup_q((uint64_t)z, C.q_delta[rho], C.q_delta_sh[rho], q);   // Delta m_0
+  for (uint32_t g4 = tid; g4 < n / 4; g4 += WG_ENC) {
+    Philox4 be = philox4x64_10(g4, 0, ci, 1, seed, HERS_DOMAIN_PROBE_SK);
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t j = 4 * g4 + s;
+      const int e = cbd20(be.v[s]);
+      uint64_t v = sub_q(j == 0 ? dm : 0, A[PADX(j)], q);
+      v = e >= 0 ? add_q(v, (uint64_t)e, q) : sub_q(v, (uint64_t)(-e), q);
+      o_ct0[j] = v;
     }
   }
 }
@@ -623,7 +676,7 @@ k_mac_intt(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __re
 // reduction at the end.  The residues written are the same.
 // The wave index is read as wave-uniform, so probe and staging addresses are
 // scalar bases plus the lane's offset.
-// Workgroups stride over the items (static assignment, no atomics).
+// Workgroups take the items in a fixed order (static assignment, no atomics).
 #define MB_PAIRS (MB_BLOCKS * MB_DC * 64)              // (block, dimension, slot) words per staged chunk
 #define MB_PER_THREAD (MB_PAIRS / MB_WG)
 
@@ -636,14 +689,26 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t tiles = n / 64;
-  for (uint64_t item = blockIdx.x; item < A.total_items; item += gridDim.x) {
-    int g = 0;
-    while (g + 1 < A.ngroups && item >= A.g[g + 1].item_begin) ++g;
+  // Item order: a pair (prime r, slot tile) holds the group's probe rows for
+  // that pair (nprobe d 2 64 words, 1 MB for 16 probes at d = 128), which
+  // every block of the gallery reuses.  Pairs are dealt to the XCDs by their
+  // index mod 8 (workgroups go to the XCDs round-robin), and an XCD's
+  // workgroups take the pair's block groups together, so the probe rows of
+  // the pair are read from memory about once per XCD and then hit its L2
+  // (taking items block group first would re-read them for every item).
+  const uint32_t npairs = K * tiles;
+  const uint32_t nx = gridDim.x % 8 == 0 ? 8 : 1;
+  const uint32_t xcd = blockIdx.x % nx, lw = blockIdx.x / nx, nw = gridDim.x / nx;
+  const uint64_t my_pairs = npairs > xcd ? (npairs - xcd + nx - 1) / nx : 0;   // pairs xcd, xcd + nx, ...
+  for (int g = 0; g < A.ngroups; ++g)
+  for (uint64_t t = lw; t < my_pairs * (uint64_t)((A.g[g].blk_hi - A.g[g].blk_lo + MB_BLOCKS - 1) / MB_BLOCKS);
+       t += nw) {
     const MacGroup& G = A.g[g];
-    const uint64_t local = item - G.item_begin;
-    const uint32_t tile = (uint32_t)(local % tiles);
-    const uint32_t r = (uint32_t)((local / tiles) % K);
-    const int64_t b0 = G.blk_lo + (int64_t)(local / ((uint64_t)tiles * K)) * MB_BLOCKS;
+    const uint64_t nbg = (uint64_t)((G.blk_hi - G.blk_lo + MB_BLOCKS - 1) / MB_BLOCKS);
+    const uint32_t pair = xcd + (uint32_t)(t / nbg) * nx;
+    const uint32_t tile = pair % tiles;
+    const uint32_t r = pair / tiles;
+    const int64_t b0 = G.blk_lo + (int64_t)(t % nbg) * MB_BLOCKS;
     const int nblk = (int)(G.blk_hi - b0 < MB_BLOCKS ? G.blk_hi - b0 : MB_BLOCKS);
     const int32_t d = G.d;
     const uint32_t p = C.p[r];
@@ -1183,15 +1248,25 @@ hipError_t launch_ct_add(const DevTabs& T, uint32_t n, uint32_t k, uint64_t* dst
 
 hipError_t launch_encrypt(const DevTabs& T, uint32_t n, uint32_t k, uint32_t nct, const uint32_t* pt,
                           const int32_t* query, int32_t d, int64_t block0, uint64_t seed, uint32_t domain,
-                          uint64_t* canon, hipStream_t s) {
-  size_t lds = lds_bytes(n, 2);
-  if (T.qf_ok)
-    hipLaunchKernelGGL(k_encrypt<true>, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain,
-                       canon);
-  else
-    hipLaunchKernelGGL(k_encrypt<false>, dim3(nct, k), dim3(WG_ENC), lds, s, T, pt, query, d, block0, seed, domain,
-                       canon);
-  return hipGetLastError();
+                          uint64_t* canon, hipStream_t s, int32_t qdim0) {
+  const size_t lds = lds_bytes(n, 2);
+  QueryVals qv;
+  std::memset(&qv, 0, sizeof(qv));
+  // a probe goes in launches of at most HERS_QCHUNK dimensions, its values in the arguments
+  for (uint32_t c0 = 0; c0 < nct; c0 += (query ? HERS_QCHUNK : nct)) {
+    const uint32_t cn = query ? (nct - c0 < HERS_QCHUNK ? nct - c0 : HERS_QCHUNK) : nct;
+    if (query) std::memcpy(qv.v, query + c0, cn * sizeof(int32_t));
+    uint64_t* out = canon + (size_t)c0 * 2 * k * n;
+    if (T.qf_ok)
+      hipLaunchKernelGGL(k_encrypt<true>, dim3(cn, k), dim3(WG_ENC), lds, s, T, query ? nullptr : pt, qv,
+                         qdim0 + (int32_t)c0, d, block0, seed, domain, out);
+    else
+      hipLaunchKernelGGL(k_encrypt<false>, dim3(cn, k), dim3(WG_ENC), lds, s, T, query ? nullptr : pt, qv,
+                         qdim0 + (int32_t)c0, d, block0, seed, domain, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_lift(const DevTabs& T, uint32_t n, const uint64_t* canon, uint32_t nct, int32_t d,
@@ -1373,6 +1448,21 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
     hipLaunchKernelGGL(k_relin_acc<false>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
                        key_sh);
   return hipGetLastError();
+}
+
+hipError_t launch_encrypt_sk(const DevTabs& T, uint32_t n, uint32_t k, const int32_t* query, int32_t d, uint64_t seed,
+                             const uint64_t* S, const uint64_t* Ssh, uint64_t* canon, hipStream_t s) {
+  QueryVals qv;
+  std::memset(&qv, 0, sizeof(qv));
+  for (int32_t c0 = 0; c0 < d; c0 += HERS_QCHUNK) {
+    const int32_t cn = d - c0 < HERS_QCHUNK ? d - c0 : HERS_QCHUNK;
+    std::memcpy(qv.v, query + c0, cn * sizeof(int32_t));
+    hipLaunchKernelGGL(k_encrypt_sk, dim3((uint32_t)cn, k), dim3(WG_ENC), lds_bytes(n, 1), s, T, qv, c0, seed, S, Ssh,
+                       canon + (size_t)c0 * 2 * k * n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t* sk, uint64_t* S, uint64_t* Ssh,

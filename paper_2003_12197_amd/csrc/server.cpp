@@ -6,8 +6,8 @@
 // protocol (App. B, Alg. "HERS Search"): probe encryption, the batched
 // encrypted search over its gallery, decryption of the scores.
 //
-// Admission is by memory: every request needs device memory for its query,
-// probe search form, score ciphertexts and decrypted scores, carved from a
+// Admission is by memory: every request needs device memory for its probe
+// search form, score ciphertexts and decrypted scores, carved from a
 // caller-provided arena by a first-fit allocator; a request that does not fit
 // waits in the queue (a deferral) until earlier results are collected.  A
 // worker thread forms waves: the oldest queued request and the later queued
@@ -97,8 +97,8 @@ struct Request {
   std::vector<int32_t> query;
   uint64_t seed;
   double t_arrival = 0, t_start = 0, t_done = 0;
-  size_t off = 0, bytes = 0;          // one arena range: query | probe | score cts | scores
-  size_t o_query = 0, o_probe = 0, o_ct = 0, o_out = 0;
+  size_t off = 0, bytes = 0;          // one arena range: probe | score cts | scores
+  size_t o_probe = 0, o_ct = 0, o_out = 0;
   int state = 0;                      // 0 queued, 1 on the GPU, 2 done, 3 failed
   bool in_arena = false;              // holds its arena range [off, off + bytes)
   std::string error;
@@ -159,9 +159,8 @@ struct hers_server {
 
 namespace {
 
-size_t request_bytes(const hers_server* s, const Gallery& g, size_t* oq, size_t* op, size_t* oc, size_t* oo) {
+size_t request_bytes(const hers_server* s, const Gallery& g, size_t* op, size_t* oc, size_t* oo) {
   size_t off = 0;
-  *oq = off; off += align256((size_t)g.d * 4);
   *op = off; off += align256(hers_probe_words(s->ctx, g.d) * 4);
   *oc = off; off += align256(hers_blocks(s->ctx, g.m) * hers_ct_words(s->ctx) * 8);
   *oo = off; off += align256((size_t)g.m * 4);
@@ -220,11 +219,9 @@ void launch_wave(hers_server* s, Wave& w) {
     Request* r = w.reqs[i];
     const Gallery& g = w.gals[i];
     char* rb = base + r->off;
-    if (hipMemcpyAsync(rb + r->o_query, r->query.data(), r->query.size() * 4, hipMemcpyHostToDevice, st) !=
-        hipSuccess) { fail_wave(s, w, "query upload"); return; }
-    // the query's range was checked on its host copy at submission
-    if (hers::encrypt_probe_prechecked(s->ctx, (const int32_t*)(rb + r->o_query), g.d, r->seed,
-                                       (uint32_t*)(rb + r->o_probe), ws_enc, w.enc_ws, st)) {
+    // the query (host copy) was range checked at submission
+    if (hers::encrypt_probe_prechecked(s->ctx, r->query.data(), g.d, r->seed, (uint32_t*)(rb + r->o_probe), ws_enc,
+                                       w.enc_ws, st)) {
       fail_wave(s, w, "probe encryption");
       return;
     }
@@ -445,7 +442,7 @@ int hers_server_submit(hers_server* s, int32_t gallery_id, const int32_t* query,
   r->query.assign(query, query + gal.d);
   r->seed = seed;
   r->t_arrival = now_ms();
-  r->bytes = request_bytes(s, gal, &r->o_query, &r->o_probe, &r->o_ct, &r->o_out);
+  r->bytes = request_bytes(s, gal, &r->o_probe, &r->o_ct, &r->o_out);
   if (r->bytes + wave_ws_bytes(s, s->enc_ws, s->dec_ws, 1, 1) > s->arena.size()) { delete r; return HERS_ENOMEM; }
   s->reqs[r->ticket] = r;
   s->queue.push_back(r);

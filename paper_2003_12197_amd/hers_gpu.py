@@ -60,6 +60,8 @@ EXPORTS = {
     "hers_encrypt_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i32, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                      ctypes.c_size_t, c_vp]),
     "hers_encrypt_probe": (c_i32, [c_vp, c_vp, c_i32, c_u64, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hers_encrypt_probe_sk": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_u64, c_vp, c_u64, c_vp, c_vp, ctypes.c_size_t,
+                                      c_vp]),
     "hers_import_gallery": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i64, c_i64, c_vp, c_u64, c_vp]),
     "hers_import_probe": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_u64, c_vp]),
     "hers_export_gallery": (c_i32, [c_vp, c_vp, c_u64, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp, ctypes.c_size_t,
@@ -103,7 +105,7 @@ EXPORTS.update({
 })
 
 OP_ENCRYPT_GALLERY, OP_ENCRYPT_PROBE, OP_SEARCH, OP_DECRYPT, OP_ENROLL, OP_SEARCH_LITERAL = 0, 1, 2, 3, 4, 5
-OP_RERANK_ENCRYPT, OP_RERANK, OP_RERANK_DECRYPT, OP_EXPORT = 6, 7, 8, 9
+OP_RERANK_ENCRYPT, OP_RERANK, OP_RERANK_DECRYPT, OP_EXPORT, OP_ENCRYPT_PROBE_SK = 6, 7, 8, 9, 10
 
 
 class HersError(RuntimeError):
@@ -155,6 +157,14 @@ def resolve(n, qbits, t_bits, w_bits=0, d_max=128, feature_bound=63):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _host_query(query):
+    """A query as a contiguous host int32 array (the library reads it on the host)."""
+    import numpy as np
+    if isinstance(query, torch.Tensor):
+        query = query.detach().cpu().numpy()
+    return np.ascontiguousarray(query, dtype=np.int32).reshape(-1)
 
 
 def _words(t):
@@ -261,15 +271,30 @@ class Context:
             _ptr(workspace), workspace.numel(), _stream()), "hers_enroll_append")
 
     def encrypt_probe(self, query, seed, canon=None, probe=None, workspace=None):
-        """query: int32 [d] on the device; returns the search-form probe."""
-        d = query.numel()
+        """query: int32 [d] (host array, or a tensor, copied to the host); returns the search-form probe."""
+        q = _host_query(query)
+        d = q.size
         if probe is None:
             probe = self._empty(self.lib.hers_probe_words(self.handle, d), torch.int32)
         if workspace is None and canon is None:
             workspace = self.workspace(OP_ENCRYPT_PROBE, 0, d)
         _check(self.lib, self.lib.hers_encrypt_probe(
-            self.handle, _ptr(query.contiguous()), d, seed, _ptr(probe), _ptr(canon), _ptr(workspace),
+            self.handle, q.ctypes.data_as(c_vp), d, seed, _ptr(probe), _ptr(canon), _ptr(workspace),
             0 if workspace is None else workspace.numel(), _stream()), "hers_encrypt_probe")
+        return probe
+
+    def encrypt_probe_sk(self, sk, query, seed, canon=None, probe=None, workspace=None):
+        """query int32 [d] (host array or tensor) encrypted under the secret key (sk
+        uint8 [n], or None for the loaded key); returns the search-form probe."""
+        q = _host_query(query)
+        d = q.size
+        if probe is None:
+            probe = self._empty(self.lib.hers_probe_words(self.handle, d), torch.int32)
+        if workspace is None:
+            workspace = self.workspace(OP_ENCRYPT_PROBE_SK, 0, d)
+        _check(self.lib, self.lib.hers_encrypt_probe_sk(
+            self.handle, _ptr(sk), q.ctypes.data_as(c_vp), d, int(seed), _ptr(probe), _words(probe), _ptr(canon),
+            _ptr(workspace), workspace.numel(), _stream()), "hers_encrypt_probe_sk")
         return probe
 
     def new_scores(self, m):

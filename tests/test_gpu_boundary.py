@@ -159,3 +159,21 @@ def test_dimension_mismatch_is_rejected(client):
     with pytest.raises(gpu_lib.HersError) as e:
         ctx.search_batch([gal], [M_ITEMS], [D], [pr4])
     assert _code(e.value) == EDIM
+
+
+def test_probe_of_more_dimensions_than_one_launch(gpu_lib):
+    """The query travels in the kernel arguments, 256 dimensions per launch:
+    a 300-dimension probe (public- and secret-key forms) equals the oracle's
+    ciphertexts, dimension by dimension."""
+    print("case wide probe: n=256 q=3x36 d=300 feature_bound=30", flush=True)
+    cfg = dict(n=256, qbits=(36, 36, 36), t_bits=20, w_bits=0)
+    op = fv.Params(**cfg)
+    ctx = gpu_lib.Context(d_max=300, feature_bound=30, **cfg)
+    sk, _, _ = ctx.keygen(91)
+    osk, opk, _ = fv.keygen(op, 91)
+    qv = np.random.default_rng(92).integers(-30, 31, size=300).astype(np.int32)
+    canon = torch.zeros((300, 2, ctx.k, ctx.n), dtype=torch.int64, device=ctx.device)
+    ctx.encrypt_probe(qv, 93, canon=canon)
+    assert np.array_equal(canon.cpu().numpy(), cts_array(hers.encrypt_probe(op, opk, qv, 93), op.q_primes))
+    ctx.encrypt_probe_sk(sk, qv, 94, canon=canon)
+    assert np.array_equal(canon.cpu().numpy(), cts_array(hers.encrypt_probe_sk(op, osk, qv, 94), op.q_primes))

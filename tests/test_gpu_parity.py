@@ -165,6 +165,31 @@ def test_relinearization_forms_give_same_bits(name, request):
         c.ctx.set_option("relin_fuse_min_wgs", 0)
 
 
+@pytest.mark.parametrize("name", ["case_r36", "case_c3s"])
+def test_secret_key_probe_bit_exact(name, request):
+    """The query encrypted under the secret key (Sec. 3.2, "Search Protocol"):
+    its ciphertexts equal the oracle's encrypt_probe_sk, with the key passed
+    and with the loaded key; the search with it gives the oracle's score
+    ciphertexts and decrypts to P^T q."""
+    c = request.getfixturevalue(name)
+    ctx, op, k, n = c.ctx, c.op, c.ctx.k, c.ctx.n
+    oq = hers.encrypt_probe_sk(op, c.osk, c.qv, 77)
+    canon = torch.zeros((c.d, 2, k, n), dtype=torch.int64, device=ctx.device)
+    pr = ctx.encrypt_probe_sk(c.sk, c.query, 77, canon=canon)
+    got = canon.cpu().numpy()
+    for i, ct in enumerate(oq):
+        assert np.array_equal(got[i, 0], res(ct[0], op.q_primes)), i
+        assert np.array_equal(got[i, 1], res(ct[1], op.q_primes)), i
+    ctx.load_secret_key(c.sk)
+    assert torch.equal(ctx.encrypt_probe_sk(None, c.query, 77), pr)
+    sc = ctx.search(c.gallery, c.m, c.d, pr)
+    S = hers.search_block(op, c.orlk, oq, c.oracle_gallery_block(c.M - 1))
+    last = sc[c.M - 1].cpu().numpy()
+    assert np.array_equal(last[0], res(S[0], op.q_primes)) and np.array_equal(last[1], res(S[1], op.q_primes))
+    out = ctx.decrypt_scores(c.sk, sc, c.m).cpu().numpy()
+    assert np.array_equal(out, hers.plaintext_scores(c.P, c.qv))
+
+
 def test_profile_select_times_only_named_stages(case_r36):
     """With "mac" selected only the multiply-accumulate launches carry timing
     events; with no selection every stage does."""
@@ -415,21 +440,21 @@ def test_schedules_and_radices_give_same_bits(case_r36):
 
 def test_topk_of_decrypted_scores(case_r36, gpu_lib):
     """Alg. "HERS Search" ends with the argmax of the decrypted scores: the GPU
-    top-k equals a stable sort (score descending, then index ascending)."""
+    top-k equals the oracle's top_k (score descending, then index ascending)."""
     c = case_r36
     out = c.ctx.decrypt_scores(c.sk, c.scores, c.m)
     s = out.cpu().numpy()
     for k in (1, 10, 100, 513, 4133):
         idx, val = c.ctx.topk(out, c.m, k)
-        order = np.lexsort((np.arange(c.m), -s.astype(np.int64)))[:k]
-        assert np.array_equal(idx.cpu().numpy(), order) and np.array_equal(val.cpu().numpy(), s[order])
+        oi, ov = hers.top_k(s, k)                       # the oracle's definition
+        assert np.array_equal(idx.cpu().numpy(), oi) and np.array_equal(val.cpu().numpy(), ov), k
     rng = np.random.default_rng(17)
     big = rng.integers(-300, 301, size=3_000_017).astype(np.int32)   # many ties, ragged last tile
     bt = torch.from_numpy(big).to(c.ctx.device)
-    order = np.lexsort((np.arange(big.size), -big.astype(np.int64)))
+    oi, ov = hers.top_k(big, 16384)
     for k in (512, 10000, 16384):                       # the tile path, then radix select
         idx, val = c.ctx.topk(bt, big.size, k)
-        assert np.array_equal(idx.cpu().numpy(), order[:k]) and np.array_equal(val.cpu().numpy(), big[order[:k]]), k
+        assert np.array_equal(idx.cpu().numpy(), oi[:k]) and np.array_equal(val.cpu().numpy(), ov[:k]), k
 
 
 def test_overlapped_search_gives_same_bits(case_r36):

@@ -72,9 +72,9 @@ def _align(x):
 
 
 def _request_bytes(ctx, m, d):
-    """Arena bytes of one request: query, probe search form, score ciphertexts, scores."""
+    """Arena bytes of one request: probe search form, score ciphertexts, scores."""
     lib, h = ctx.lib, ctx.handle
-    return (_align(d * 4) + _align(int(lib.hers_probe_words(h, d)) * 4)
+    return (_align(int(lib.hers_probe_words(h, d)) * 4)
             + _align(ctx.blocks(m) * int(lib.hers_ct_words(h)) * 8) + _align(m * 4))
 
 
