@@ -223,12 +223,12 @@ def run_serving(args, cfg):
     setup_s = time.perf_counter() - t0
     sweep_rates = [float(x) for x in args.sweep.split(",")] if args.sweep else []
     nq = max([nreq] + [args.sweep_requests] * bool(sweep_rates))
-    # the same targets at every rate (the arrival gaps only scale with it)
-    _, targets_all = synth.poisson_arrivals(601, rate, nq, len(gals))
+    # one request stream; at another rate the same requests arrive with their
+    # gaps scaled (a Poisson stream scaled in time is one of the scaled rate)
+    arrivals_all, targets_all = synth.poisson_arrivals(601, rate, nq, len(gals))
     queries_all = [synth.probe_for(QUERY_SEED + j, FEATURE_SEED + 7919 * int(targets_all[j]), n,
                                    gals[targets_all[j]][2], gals[targets_all[j]][1])[0] for j in range(nq)]
-    arrivals, targets = synth.poisson_arrivals(601, rate, nreq, len(gals))
-    queries = queries_all[:nreq]
+    arrivals, targets, queries = arrivals_all[:nreq], targets_all[:nreq], queries_all[:nreq]
     items_total = sum(gals[g][1] for g in targets)
 
     def serve(max_batch, prof, arrivals=arrivals, targets=targets, queries=queries, check_every=200):
@@ -242,22 +242,28 @@ def run_serving(args, cfg):
         lats = [0.0] * nreq
         start = time.perf_counter()
 
-        stop = []
+        stop, failed = [], []
 
         def submitter():
-            for j in range(nreq):
-                if stop:
-                    return
-                delay = arrivals[j] - (time.perf_counter() - start)
-                if delay > 0:
-                    time.sleep(delay)
-                tickets[j] = srv.submit(gids[targets[j]], queries[j], PROBE_SEED + j)
+            try:
+                for j in range(nreq):
+                    if stop:
+                        return
+                    delay = arrivals[j] - (time.perf_counter() - start)
+                    if delay > 0:
+                        time.sleep(delay)
+                    tickets[j] = srv.submit(gids[targets[j]], queries[j], PROBE_SEED + j)
+            except Exception as e:          # the waiting loop below reports it
+                failed.append(e)
 
         th = threading.Thread(target=submitter, daemon=True)
         th.start()
         checked = 0
         for j in range(nreq):
             while tickets[j] is None:
+                if failed:
+                    srv.close()
+                    raise SystemExit("serving: submitting request %d failed: %s" % (j, failed[0]))
                 time.sleep(0.0005)
             check = j % check_every == 0
             lat, out, _ = srv.wait(tickets[j], scores=check)
@@ -292,8 +298,8 @@ def run_serving(args, cfg):
     # arrival-rate sweep: the same request stream, faster, batched and one per wave
     sweep = []
     for rr in sweep_rates:
-        arr, tg = synth.poisson_arrivals(601, rr, args.sweep_requests, len(gals))
-        qs = queries_all[:args.sweep_requests]
+        ns = args.sweep_requests
+        arr, tg, qs = arrivals_all[:ns] * (rate / rr), targets_all[:ns], queries_all[:ns]
         items = sum(gals[g][1] for g in tg)
         row = {"rate_per_s": rr, "requests": args.sweep_requests}
         for name, mb in (("batched", 16), ("one_per_wave", 1)):
@@ -576,6 +582,13 @@ def main():
         ws_s = ctx.batch_workspace([span * n] * npr, blocks_per_round=rounds)
         mac_variant = None
         gal_of = lambda lo, hi: gallery[lo * blk_words:hi * blk_words]
+        lo0, hi0 = slices[0]
+        if args.no_autotune:
+            mb_variant = ctx.get_option("mb_variant")
+        else:
+            mb_variant = ctx.autotune_batch([gal_of(lo0, hi0)] * npr, [m_of(lo0, hi0)] * npr, [d] * npr, probes,
+                                            scores, ws_s, reps=2)
+        log("%s multi-probe schedule: %d" % ("default" if args.no_autotune else "autotuned", mb_variant))
         plans = [ctx.plan([gal_of(lo, hi)] * npr, [m_of(lo, hi)] * npr, [d] * npr, probes, scores, ws_s)
                  for lo, hi in slices]
         plan = plans[0]
@@ -668,6 +681,19 @@ def main():
     # ---- side measurements (outside the timed region): one fused search
     # alone, and the paper-literal per-dimension schedule on the same data
     side = {}
+    if npr > 1 and len(slices) == 1:
+        # the plain single-probe search on the same gallery (its own default schedule)
+        ws_1 = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 256 * n), d)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_1)
+        e0.record()
+        for _ in range(2):
+            ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_1)
+        e1.record()
+        torch.cuda.synchronize()
+        side["single_probe_search_ms"] = e0.elapsed_time(e1) / 2
+        side["single_probe_scores_per_s"] = m / (side["single_probe_search_ms"] * 1e-3)
+        del ws_1
     if npr == 1:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         search()
@@ -719,6 +745,8 @@ def main():
     value = m * npr * args.steps / (total_ms * 1e-3)
     lat = np.array(step_ms)
     search_ms = sum(stages[s][0] for s in ("mac", "mac_multi", "intt_acc", "rescale", "relin")) / kb
+    if "single_probe_scores_per_s" in side:
+        side["batched_search_over_single_probe"] = (m * npr / (search_ms * 1e-3)) / side["single_probe_scores_per_s"]
     result = {
         "metric": "encrypted scores/sec (gallery items x probes per s); p50/p99 probe latency",
         "value": value,
@@ -740,6 +768,7 @@ def main():
                    "mac_schedule": mac_variant, "ntt_radix": 1 << ctx.get_option("ntt_radix_log2"),
                    "overlap_chunks": ctx.get_option("overlap_chunks"),
                    "mac_wgs_per_cu": ctx.get_option("mac_wgs_per_cu") or 8,
+                   "multi_probe_schedule": ctx.get_option("mb_variant") if npr > 1 else None,
                    "hip_graph": plan is not None, "gallery_ranges_per_step": len(slices)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},

@@ -284,7 +284,7 @@ int hers_search_literal(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gal
 /* Batched search: nreq independent (gallery, probe) requests in one
  * submission; request r reads galleries[r] (gallery_words[r] long, m[r]
  * items, d[r] dims) and probes[r] (probe_words[r] long) and writes scores[r].  Requests on the same gallery (same
- * pointer, m and d) are grouped, up to 16 per group: one persistent
+ * pointer, m and d) are grouped, up to "mb_group" (16) per group: one persistent
  * multiply-accumulate launch streams each gallery block once for the whole
  * group, then every request gets its own rescale and relinearization.
  * Results are bit-identical to nreq calls of hers_search.  The workspace
@@ -294,6 +294,17 @@ int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galler
                       const uint64_t* gallery_words, const int64_t* m, const int32_t* d,
                       const uint32_t* const* probes, const uint64_t* probe_words,
                       uint64_t* const* scores, void* work_dev, size_t work_bytes, void* stream);
+
+/* Batched autotuner: times every multi-probe multiply-accumulate schedule
+ * ("mb_variant") on the caller's batch -- the first round of blocks of
+ * hers_search_batch with these arguments, reps launches each -- and keeps the
+ * fastest in the context (another replaces the current one only if 3%
+ * faster); the schedule in *chosen (may be NULL).  Overwrites the workspace;
+ * synchronizes `stream`.  The schedules compute the same bits. */
+int hers_autotune_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries,
+                        const uint64_t* gallery_words, const int64_t* m, const int32_t* d,
+                        const uint32_t* const* probes, const uint64_t* probe_words, uint64_t* const* scores,
+                        void* work_dev, size_t work_bytes, int reps, void* stream, int64_t* chosen);
 
 /* The same batch captured once as a HIP graph and replayed by
  * hers_plan_launch: the pointers are fixed at capture, so callers refill the
@@ -404,6 +415,15 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  transformed digits in memory; smaller ones as two kernels
  *                  with more workgroups.  0 = 8 per compute unit at
  *                  n >= 8192, never below; 1 = always.
+ *   "mb_variant"   multi-probe multiply-accumulate schedule of
+ *                  hers_search_batch, 0..3, as (probes per wave, dimensions
+ *                  per staged chunk, blocks per item): 0 (1, 8, 4) in
+ *                  1024-lane workgroups, 1 (2, 4, 2), 2 (2, 8, 2) in 512-lane
+ *                  workgroups, 3 (4, 4, 1) in 256-lane workgroups.  More
+ *                  probes per wave read each staged gallery word from LDS
+ *                  once for all of them.
+ *   "mb_group"     most probes of one gallery grouped into one multi-probe
+ *                  pass, 1..16 (default 16).
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
  * key or value. */
 int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);

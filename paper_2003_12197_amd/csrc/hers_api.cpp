@@ -47,6 +47,8 @@ struct hers_ctx {
   int overlap_chunks = 0;
   int mac_wgs_per_cu = 0;   // multiply-accumulate grid, workgroups per CU (0 = 8)
   int64_t relin_fuse_min_wgs = 0;   // fused relinearization from this many workgroups (0 = 8 per CU)
+  int mb_variant = 0;               // multi-probe multiply-accumulate schedule (launch_mac_multi)
+  int mb_group = MB_PROBES;         // probes per group of the batched search
   // rotation keys of the re-rank stage, NTT form [steps][L][2][k][n]
   uint64_t* rk_ntt = nullptr;
   uint64_t* rk_ntt_sh = nullptr;
@@ -425,6 +427,16 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     ctx->relin_fuse_min_wgs = value;
     return HERS_OK;
   }
+  if (!std::strcmp(key, "mb_variant")) {
+    if (value < 0 || value >= MB_VARIANTS) return fail(HERS_EINVAL, "mb_variant must be in [0, 3]");
+    ctx->mb_variant = (int)value;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "mb_group")) {
+    if (value < 1 || value > MB_PROBES) return fail(HERS_EINVAL, "mb_group must be in [1, 16]");
+    ctx->mb_group = (int)value;
+    return HERS_OK;
+  }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
 }
 
@@ -448,6 +460,14 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   }
   if (!std::strcmp(key, "relin_fuse_min_wgs")) {
     *value = ctx->relin_fuse_min_wgs;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "mb_variant")) {
+    *value = ctx->mb_variant;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "mb_group")) {
+    *value = ctx->mb_group;
     return HERS_OK;
   }
   return fail(HERS_EINVAL, std::string("unknown option ") + key);
@@ -1271,7 +1291,10 @@ int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, c
     if (int rc = check_search_buffers(ctx, m[r], d[r], gallery_words[r], probe_words[r])) return rc;
     BatchGroup* g = nullptr;
     for (auto& x : *out)
-      if (x.gallery == galleries[r] && x.m == m[r] && x.d == d[r] && x.reqs.size() < MB_PROBES) { g = &x; break; }
+      if (x.gallery == galleries[r] && x.m == m[r] && x.d == d[r] && x.reqs.size() < (size_t)ctx->mb_group) {
+        g = &x;
+        break;
+      }
     if (!g) {
       out->push_back({galleries[r], m[r], (int64_t)hers_blocks(ctx, m[r]), d[r], {}});
       g = &out->back();
@@ -1284,8 +1307,16 @@ int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, c
 // Enqueues a batch: rounds of at most CB blocks per group; per round one
 // persistent multiply-accumulate launch per MB_MAXG groups, then the
 // per-request epilogue (inverse NTT, rescale, relinearization).
+// Workgroups per CU of a multi-probe schedule: as many as are resident.
+uint32_t mb_wgs_per_cu(int variant) {
+  static const uint32_t per_cu[MB_VARIANTS] = {1, 2, 2, 4};
+  return variant >= 0 && variant < MB_VARIANTS ? per_cu[variant] : 1;
+}
+
+// tune_variant >= 0: only the first round's multi-probe multiply-accumulate
+// launches, with that schedule (the autotuner's timing run).
 int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32_t* const* probes,
-              uint64_t* const* scores, void* work_dev, size_t work_bytes, hipStream_t s) {
+              uint64_t* const* scores, void* work_dev, size_t work_bytes, hipStream_t s, int tune_variant = -1) {
   const HersConsts& C = ctx->host.C;
   size_t nprobe = 0;
   int64_t maxM = 0;
@@ -1314,10 +1345,11 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
     std::memset(&A, 0, sizeof(A));
     auto flush = [&]() -> int {
       if (!A.ngroups) return HERS_OK;
-      // a multiple of 8 workgroups (the kernel deals its items to the XCDs)
-      uint64_t grid = (uint64_t)ctx->num_cus * 2;
+      // the resident workgroups, a multiple of 8 (the kernel deals its items to the XCDs)
+      const int v = tune_variant >= 0 ? tune_variant : ctx->mb_variant;
+      uint64_t grid = (uint64_t)ctx->num_cus * mb_wgs_per_cu(v);
       if (grid > (A.total_items + 7) / 8 * 8) grid = (A.total_items + 7) / 8 * 8;
-      TIMED(ctx, "mac_multi", s, hers::launch_mac_multi(ctx->T, A, (uint32_t)grid, s));
+      TIMED(ctx, "mac_multi", s, hers::launch_mac_multi(ctx->T, A, (uint32_t)grid, s, v));
       std::memset(&A, 0, sizeof(A));
       return HERS_OK;
     };
@@ -1327,6 +1359,7 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
       if (lo >= hi) continue;
       if (g.reqs.size() == 1) {
         // a lone probe streams its gallery with the single-probe schedule
+        if (tune_variant >= 0) continue;
         const int32_t r = g.reqs[0];
         TIMED(ctx, "mac", s, launch_mac_sched(ctx, ctx->mac_variant, g.gallery, probes[r], g.d, lo, hi, acc_of[gi],
                                               s));
@@ -1347,6 +1380,7 @@ int run_batch(hers_ctx* ctx, const std::vector<BatchGroup>& groups, const uint32
         if (int rc = flush()) return rc;
     }
     if (int rc = flush()) return rc;
+    if (tune_variant >= 0) return HERS_OK;
     // epilogue: the requests of a group share a block range; their slabs are
     // consecutive, so one launch per kernel covers up to EP_MAXR of them
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -1386,6 +1420,54 @@ int hers_search_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galler
   if (int rc = plan_groups(ctx, nreq, galleries, gallery_words, m, d, probes, probe_words, scores, &groups)) return rc;
   DeviceGuard g(ctx->device);
   return run_batch(ctx, groups, probes, scores, work_dev, work_bytes, S(stream));
+}
+
+int hers_autotune_batch(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, const uint64_t* gallery_words,
+                        const int64_t* m, const int32_t* d, const uint32_t* const* probes, const uint64_t* probe_words,
+                        uint64_t* const* scores, void* work_dev, size_t work_bytes, int reps, void* stream,
+                        int64_t* chosen) {
+  if (!ctx || nreq < 1 || reps < 1 || !galleries || !gallery_words || !m || !d || !probes || !probe_words || !scores)
+    return fail(HERS_EINVAL, "bad argument");
+  if (!ctx->keys_loaded) return fail(HERS_EINVAL, "no evaluation key loaded");
+  std::vector<BatchGroup> groups;
+  if (int rc = plan_groups(ctx, nreq, galleries, gallery_words, m, d, probes, probe_words, scores, &groups)) return rc;
+  bool multi = false;
+  for (auto& g : groups) multi |= g.reqs.size() > 1;
+  if (!multi) {                                       // nothing runs the multi-probe kernel
+    if (chosen) *chosen = ctx->mb_variant;
+    return HERS_OK;
+  }
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = S(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 0.f, cur = 0.f;
+  int best_v = ctx->mb_variant, rc = HERS_OK;
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  for (int v = 0; v < MB_VARIANTS && rc == HERS_OK; ++v) {
+    rc = run_batch(ctx, groups, probes, scores, work_dev, work_bytes, s, v);      // warm-up
+    hipError_t e = rc == HERS_OK ? hipEventRecord(e0, s) : hipSuccess;
+    for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
+      rc = run_batch(ctx, groups, probes, scores, work_dev, work_bytes, s, v);
+    if (rc != HERS_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune_batch: ") + hipGetErrorString(e)); break; }
+    if (v == 0 || ms < best) { best = ms; best_v = v; }
+    if (v == ctx->mb_variant) cur = ms;
+  }
+  ctx->prof_on = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != HERS_OK) return rc;
+  if (best > 0.97f * cur) best_v = ctx->mb_variant;   // keep the current one unless another is clearly faster
+  ctx->mb_variant = best_v;
+  if (chosen) *chosen = best_v;
+  return HERS_OK;
 }
 
 struct hers_plan {

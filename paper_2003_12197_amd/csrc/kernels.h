@@ -31,7 +31,6 @@ struct QueryVals {
 
 // Batched multiply-accumulate: up to MB_PROBES probes of one gallery per group.
 #define MB_PROBES 16
-#define MB_WG (64 * MB_PROBES)
 #define MB_DC 8         // dimensions per register/LDS chunk
 #define MB_BLOCKS 4     // blocks per work item
 #define MB_MAXG 15      // groups per launch (kernel arguments stay below 4 KiB)
@@ -59,7 +58,11 @@ struct MacBatchArgs {
 };
 
 namespace hers {
-hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s);
+// variants as (probes per wave, dimensions per chunk, blocks per item):
+// 0 (1, 8, 4) with 1024-lane workgroups; 1 (2, 4, 2), 2 (2, 8, 2) with 512
+// lanes; 3 (4, 4, 1) with 256 lanes
+#define MB_VARIANTS 4
+hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s, int variant = 0);
 hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
                          uint64_t* pk, uint64_t* rlk, hipStream_t s);
 hipError_t launch_load_keys(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, const uint64_t* pk,

@@ -677,11 +677,20 @@ k_mac_intt(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __re
 // The wave index is read as wave-uniform, so probe and staging addresses are
 // scalar bases plus the lane's offset.
 // Workgroups take the items in a fixed order (static assignment, no atomics).
-#define MB_PAIRS (MB_BLOCKS * MB_DC * 64)              // (block, dimension, slot) words per staged chunk
-#define MB_PER_THREAD (MB_PAIRS / MB_WG)
-
-__global__ void __launch_bounds__(MB_WG)
+// PPW probes per wave: a workgroup of 64 MB_PROBES / PPW lanes.  With two,
+// every staged gallery word read from LDS feeds both probes' products (half
+// the LDS traffic per product) and the workgroup is half as wide, so two of
+// them share a CU and one's barriers overlap the other's products; the
+// probe rows are then loaded when a chunk starts instead of one chunk ahead.
+// DC dimensions and BLK blocks per staged chunk (8 and 4 with one probe per
+// wave; fewer with more probes per wave, whose registers then hold about as
+// many sums and probe values).
+template <int PPW, int DC, int BLK>
+__global__ void __launch_bounds__(64 * MB_PROBES / PPW, 4)   // 4 waves per SIMD: two 512-lane (four 256-lane) workgroups per CU
 k_mac_multi(DevTabs T, MacBatchArgs A) {
+  constexpr uint32_t WGL = 64 * MB_PROBES / PPW;         // lanes
+  constexpr uint32_t MB_PAIRS = BLK * DC * 64;            // (block, dimension, slot) words per staged chunk
+  constexpr uint32_t PER_THREAD = MB_PAIRS / WGL;         // staged pairs per lane
   __shared__ uint2 tileG[MB_PAIRS];                    // [u][v][64]: (G0, G1) of a slot
   __shared__ uint32_t tileS[MB_PAIRS];                 // [u][v][64]: G0 + G1 mod p
   const HersConsts& C = *T.C;
@@ -701,29 +710,35 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   const uint32_t xcd = blockIdx.x % nx, lw = blockIdx.x / nx, nw = gridDim.x / nx;
   const uint64_t my_pairs = npairs > xcd ? (npairs - xcd + nx - 1) / nx : 0;   // pairs xcd, xcd + nx, ...
   for (int g = 0; g < A.ngroups; ++g)
-  for (uint64_t t = lw; t < my_pairs * (uint64_t)((A.g[g].blk_hi - A.g[g].blk_lo + MB_BLOCKS - 1) / MB_BLOCKS);
+  for (uint64_t t = lw; t < my_pairs * (uint64_t)((A.g[g].blk_hi - A.g[g].blk_lo + BLK - 1) / BLK);
        t += nw) {
     const MacGroup& G = A.g[g];
-    const uint64_t nbg = (uint64_t)((G.blk_hi - G.blk_lo + MB_BLOCKS - 1) / MB_BLOCKS);
+    const uint64_t nbg = (uint64_t)((G.blk_hi - G.blk_lo + BLK - 1) / BLK);
     const uint32_t pair = xcd + (uint32_t)(t / nbg) * nx;
     const uint32_t tile = pair % tiles;
     const uint32_t r = pair / tiles;
-    const int64_t b0 = G.blk_lo + (int64_t)(t % nbg) * MB_BLOCKS;
-    const int nblk = (int)(G.blk_hi - b0 < MB_BLOCKS ? G.blk_hi - b0 : MB_BLOCKS);
+    const int64_t b0 = G.blk_lo + (int64_t)(t % nbg) * BLK;
+    const int nblk = (int)(G.blk_hi - b0 < BLK ? G.blk_hi - b0 : BLK);
     const int32_t d = G.d;
     const uint32_t p = C.p[r];
     const uint64_t mu = C.p_mu64[r];
     const uint32_t c34 = (uint32_t)((1ull << 34) - (uint64_t)p * (mu >> 30));   // 2^34 mod p (mu = floor(2^64/p))
-    const bool active = wave < (uint32_t)G.nprobe;
     const uint32_t slot = tile * 64 + lane;
-    const uint32_t* pbase = active ? G.probe[wave] + (size_t)r * d * 2 * n + tile * 64 : nullptr;
-    const uint32_t* gbase = G.gallery + tile * 64;
-    // staged pair w = tid + e MB_WG of chunk dc: block b0 + u, dimension dc + v
-    // with u, v from the wave-uniform row w / 64, slot w mod 64 = lane
-    auto fetch = [&](int32_t dc, int32_t dn, uint2 (&reg)[MB_PER_THREAD]) {
+    bool active[PPW];
+    const uint32_t* pbase[PPW];
 #pragma unroll
-      for (int e = 0; e < MB_PER_THREAD; ++e) {
-        const uint32_t uv = wave + e * (MB_WG / 64);
+    for (int q = 0; q < PPW; ++q) {
+      const uint32_t j = wave * PPW + q;                  // the group's probe j
+      active[q] = j < (uint32_t)G.nprobe;
+      pbase[q] = active[q] ? G.probe[j] + (size_t)r * d * 2 * n + tile * 64 : nullptr;
+    }
+    const uint32_t* gbase = G.gallery + tile * 64;
+    // staged pair w = tid + e WGL of chunk dc: block b0 + u, dimension dc + v
+    // with u, v from the wave-uniform row w / 64, slot w mod 64 = lane
+    auto fetch = [&](int32_t dc, int32_t dn, uint2 (&reg)[PER_THREAD]) {
+#pragma unroll
+      for (int e = 0; e < (int)PER_THREAD; ++e) {
+        const uint32_t uv = wave + e * (WGL / 64);
         const uint32_t u = uv / (uint32_t)dn, v = uv - u * (uint32_t)dn;
         if ((int)u < nblk) {
           const uint32_t* src = gbase + (((size_t)(b0 + u) * K + r) * d * 2 + 2 * (dc + v)) * n;
@@ -733,96 +748,117 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
         }
       }
     };
-    uint64_t a0[MB_BLOCKS], a2[MB_BLOCKS], as[MB_BLOCKS];
+    uint64_t a0[PPW][BLK], a2[PPW][BLK], as[PPW][BLK];
 #pragma unroll
-    for (int u = 0; u < MB_BLOCKS; ++u) { a0[u] = 0; a2[u] = 0; as[u] = 0; }
-    uint2 stage[MB_PER_THREAD];
-    uint32_t P0[MB_DC], P1[MB_DC];                     // this lane's probe values for the next chunk
+    for (int q = 0; q < PPW; ++q)
+#pragma unroll
+      for (int u = 0; u < BLK; ++u) { a0[q][u] = 0; a2[q][u] = 0; as[q][u] = 0; }
+    uint2 stage[PER_THREAD];
+    uint32_t P0[PPW][DC], P1[PPW][DC];            // this lane's probe values (PPW 1: of the next chunk)
     auto fetch_probe = [&](int32_t dc, int32_t dn) {
 #pragma unroll
-      for (int v = 0; v < MB_DC; ++v) {
-        P0[v] = active && v < dn ? pbase[(size_t)(2 * (dc + v)) * n + lane] : 0;
-        P1[v] = active && v < dn ? pbase[(size_t)(2 * (dc + v) + 1) * n + lane] : 0;
-      }
+      for (int q = 0; q < PPW; ++q)
+#pragma unroll
+        for (int v = 0; v < DC; ++v) {
+          P0[q][v] = active[q] && v < dn ? pbase[q][(size_t)(2 * (dc + v)) * n + lane] : 0;
+          P1[q][v] = active[q] && v < dn ? pbase[q][(size_t)(2 * (dc + v) + 1) * n + lane] : 0;
+        }
     };
-    fetch(0, d < MB_DC ? d : MB_DC, stage);
-    fetch_probe(0, d < MB_DC ? d : MB_DC);
-    for (int32_t dc = 0; dc < d; dc += MB_DC) {
-      const int32_t dn = d - dc < MB_DC ? d - dc : MB_DC;
+    fetch(0, d < DC ? d : DC, stage);
+    if (PPW == 1) fetch_probe(0, d < DC ? d : DC);
+    for (int32_t dc = 0; dc < d; dc += DC) {
+      const int32_t dn = d - dc < DC ? d - dc : DC;
       __syncthreads();                                 // previous chunk fully consumed
 #pragma unroll
-      for (int e = 0; e < MB_PER_THREAD; ++e) {
-        const uint32_t w = tid + e * MB_WG;
+      for (int e = 0; e < (int)PER_THREAD; ++e) {
+        const uint32_t w = tid + e * WGL;
         tileG[w] = stage[e];
         tileS[w] = add_p(stage[e].x, stage[e].y, p);
       }
       __syncthreads();
-      uint32_t Q0[MB_DC], Q1[MB_DC];
+      // PPW 1: this chunk's probe values were loaded one chunk ahead (copied
+      // out before the next chunk's load); PPW > 1: loaded now, from L2
+      uint32_t Q0[PPW][DC], Q1[PPW][DC];
+      if (PPW > 1) fetch_probe(dc, dn);
 #pragma unroll
-      for (int v = 0; v < MB_DC; ++v) { Q0[v] = P0[v]; Q1[v] = P1[v]; }
-      if (dc + MB_DC < d) {                            // next chunk in flight during the products
-        const int32_t nd = d - dc - MB_DC < MB_DC ? d - dc - MB_DC : MB_DC;
-        fetch(dc + MB_DC, nd, stage);
-        fetch_probe(dc + MB_DC, nd);
+      for (int q = 0; q < PPW; ++q)
+#pragma unroll
+        for (int v = 0; v < DC; ++v) { Q0[q][v] = P0[q][v]; Q1[q][v] = P1[q][v]; }
+      if (dc + DC < d) {                            // next chunk in flight during the products
+        const int32_t nd = d - dc - DC < DC ? d - dc - DC : DC;
+        fetch(dc + DC, nd, stage);
+        if (PPW == 1) fetch_probe(dc + DC, nd);
       }
-      if (active) {
-        static_assert(MB_DC <= 15, "a folded sum plus one chunk's products must stay below 2^64");
-        if (dn == MB_DC && nblk == MB_BLOCKS) {        // full chunk: no bounds in the product loop
+      if (active[0]) {
+        static_assert(DC <= 15, "a folded sum plus one chunk's products must stay below 2^64");
+        if (dn == DC && nblk == BLK) {        // full chunk: no bounds in the product loop
 #pragma unroll
-          for (int v = 0; v < MB_DC; ++v) {
-            const uint32_t qs = add_p(Q0[v], Q1[v], p);
+          for (int v = 0; v < DC; ++v) {
+            uint32_t qs[PPW];
 #pragma unroll
-            for (int u = 0; u < MB_BLOCKS; ++u) {
-              const uint32_t w = (uint32_t)(u * MB_DC + v) * 64 + lane;
+            for (int q = 0; q < PPW; ++q) qs[q] = add_p(Q0[q][v], Q1[q][v], p);
+#pragma unroll
+            for (int u = 0; u < BLK; ++u) {
+              const uint32_t w = (uint32_t)(u * DC + v) * 64 + lane;
               const uint2 gv = tileG[w];
               const uint32_t gs = tileS[w];
-              a0[u] += (uint64_t)Q0[v] * gv.x;
-              a2[u] += (uint64_t)Q1[v] * gv.y;
-              as[u] += (uint64_t)qs * gs;
+#pragma unroll
+              for (int q = 0; q < PPW; ++q) {
+                a0[q][u] += (uint64_t)Q0[q][v] * gv.x;
+                a2[q][u] += (uint64_t)Q1[q][v] * gv.y;
+                as[q][u] += (uint64_t)qs[q] * gs;
+              }
             }
           }
         } else {
 #pragma unroll
-          for (int v = 0; v < MB_DC; ++v) {
+          for (int v = 0; v < DC; ++v) {
             if (v >= dn) break;
-            const uint32_t qs = add_p(Q0[v], Q1[v], p);
+            uint32_t qs[PPW];
 #pragma unroll
-            for (int u = 0; u < MB_BLOCKS; ++u) {
+            for (int q = 0; q < PPW; ++q) qs[q] = add_p(Q0[q][v], Q1[q][v], p);
+#pragma unroll
+            for (int u = 0; u < BLK; ++u) {
               if (u >= nblk) break;
               const uint32_t w = ((uint32_t)u * dn + v) * 64 + lane;
               const uint2 gv = tileG[w];
               const uint32_t gs = tileS[w];
-              a0[u] += (uint64_t)Q0[v] * gv.x;
-              a2[u] += (uint64_t)Q1[v] * gv.y;
-              as[u] += (uint64_t)qs * gs;
+#pragma unroll
+              for (int q = 0; q < PPW; ++q) {
+                a0[q][u] += (uint64_t)Q0[q][v] * gv.x;
+                a2[q][u] += (uint64_t)Q1[q][v] * gv.y;
+                as[q][u] += (uint64_t)qs[q] * gs;
+              }
             }
           }
         }
 #pragma unroll
-        for (int u = 0; u < MB_BLOCKS; ++u) {
-          if (u >= nblk) break;
-          a0[u] = fold34(a0[u], c34);
-          a2[u] = fold34(a2[u], c34);
-          as[u] = fold34(as[u], c34);
-        }
+        for (int q = 0; q < PPW; ++q)
+#pragma unroll
+          for (int u = 0; u < BLK; ++u) {
+            if (u >= nblk) break;
+            a0[q][u] = fold34(a0[q][u], c34);
+            a2[q][u] = fold34(a2[q][u], c34);
+            as[q][u] = fold34(as[q][u], c34);
+          }
       }
     }
-    if (active) {
-      uint32_t* ob = G.acc + (size_t)wave * G.acc_stride;
 #pragma unroll
-      for (int u = 0; u < MB_BLOCKS; ++u) {
+    for (int q = 0; q < PPW; ++q) {
+      if (!active[q]) break;
+      uint32_t* ob = G.acc + (size_t)(wave * PPW + q) * G.acc_stride;
+#pragma unroll
+      for (int u = 0; u < BLK; ++u) {
         if (u >= nblk) break;
-        a0[u] = red_p(a0[u], p, mu);
-        a2[u] = red_p(a2[u], p, mu);
-        as[u] = red_p(as[u], p, mu);
+        const uint64_t x0 = red_p(a0[q][u], p, mu), x2 = red_p(a2[q][u], p, mu), xs = red_p(as[q][u], p, mu);
         // A1 = S - A0 - A2 mod p, all three below p
-        uint64_t a1 = as[u] + 2 * (uint64_t)p - a0[u] - a2[u];
+        uint64_t a1 = xs + 2 * (uint64_t)p - x0 - x2;
         a1 = a1 >= p ? a1 - p : a1;
         a1 = a1 >= p ? a1 - p : a1;
         uint32_t* o = ob + ((size_t)(b0 + u - G.blk_lo) * 3 * K + r) * n + slot;
-        o[0] = (uint32_t)a0[u];
+        o[0] = (uint32_t)x0;
         o[(size_t)K * n] = (uint32_t)a1;
-        o[(size_t)2 * K * n] = (uint32_t)a2[u];
+        o[(size_t)2 * K * n] = (uint32_t)x2;
       }
     }
     __syncthreads();
@@ -1388,8 +1424,13 @@ hipError_t launch_mac_intt(const DevTabs& T, uint32_t n, uint32_t K, const uint3
   return hipGetLastError();
 }
 
-hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_mac_multi, dim3(grid), dim3(MB_WG), 0, s, T, A);
+hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s, int variant) {
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_mac_multi<2, 4, 2>), dim3(grid), dim3(64 * MB_PROBES / 2), 0, s, T, A); break;
+    case 2: hipLaunchKernelGGL((k_mac_multi<2, 8, 2>), dim3(grid), dim3(64 * MB_PROBES / 2), 0, s, T, A); break;
+    case 3: hipLaunchKernelGGL((k_mac_multi<4, 4, 1>), dim3(grid), dim3(64 * MB_PROBES / 4), 0, s, T, A); break;
+    default: hipLaunchKernelGGL((k_mac_multi<1, MB_DC, MB_BLOCKS>), dim3(grid), dim3(64 * MB_PROBES), 0, s, T, A);
+  }
   return hipGetLastError();
 }
 

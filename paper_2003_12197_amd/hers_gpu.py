@@ -72,6 +72,10 @@ EXPORTS = {
     "hers_search_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
                                   ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
                                   ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, c_vp]),
+    "hers_autotune_batch": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
+                                    ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
+                                    ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, ctypes.c_int, c_vp,
+                                    ctypes.POINTER(c_i64)]),
     "hers_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_u64), ctypes.POINTER(c_i64),
                                  ctypes.POINTER(c_i32), ctypes.POINTER(c_vp), ctypes.POINTER(c_u64),
                                  ctypes.POINTER(c_vp), c_vp, ctypes.c_size_t, ctypes.POINTER(c_vp)]),
@@ -443,6 +447,18 @@ class Context:
             "hers_search_batch")
         return scores
 
+    def autotune_batch(self, galleries, ms, ds, probes, scores, workspace, reps=2):
+        """Pick the fastest multi-probe multiply-accumulate schedule for this batch; returns it."""
+        nreq = len(galleries)
+        arr = lambda ts: (c_vp * nreq)(*[t.data_ptr() for t in ts])
+        words = lambda ts: (c_u64 * nreq)(*[_words(t) for t in ts])
+        v = c_i64()
+        _check(self.lib, self.lib.hers_autotune_batch(
+            self.handle, nreq, arr(galleries), words(galleries), (c_i64 * nreq)(*ms), (c_i32 * nreq)(*ds),
+            arr(probes), words(probes), arr(scores), _ptr(workspace), workspace.numel(), int(reps), _stream(),
+            ctypes.byref(v)), "hers_autotune_batch")
+        return v.value
+
     def plan(self, galleries, ms, ds, probes, scores, workspace):
         """Capture a batch as a HIP graph; returns a Plan whose launch() replays it."""
         nreq = len(galleries)
@@ -566,6 +582,8 @@ class Server:
 
     def submit(self, gid, query, seed):
         q = self._np.ascontiguousarray(query, dtype=self._np.int32)
+        if q.ndim != 1 or q.size != self.galleries[gid][2]:
+            raise ValueError("a query of %d values for a gallery of d = %d" % (q.size, self.galleries[gid][2]))
         t = c_i64()
         rc = self.lib.hers_server_submit(self.handle, gid, q.ctypes.data_as(c_vp), int(seed), ctypes.byref(t))
         _check(self.lib, rc, "hers_server_submit")

@@ -107,15 +107,19 @@ def test_c3_two_probe_batch_bit_exact(c3, fuse):
     ctx, op = c3["ctx"], c3["op"]
     try:
         ctx.set_option("relin_fuse_min_wgs", fuse)
-        for ws in (None, ctx.batch_workspace([M_ITEMS] * 2, blocks_per_round=1)):
-            outs = ctx.search_batch([c3["gal"]] * 2, [M_ITEMS] * 2, [D] * 2, [c3["pr1"], c3["pr2"]], workspace=ws)
-            _assert_scores(outs[0], c3["want1"], op.q_primes)
-            _assert_scores(outs[1], c3["want2"], op.q_primes)
-            for o, qv in zip(outs, (c3["q1"], c3["q2"])):
-                dec = ctx.decrypt_scores(c3["sk"], o, M_ITEMS).cpu().numpy()
-                assert np.array_equal(dec, hers.plaintext_scores(c3["P"], qv))
+        for v in range(4):                                  # every multi-probe schedule
+            ctx.set_option("mb_variant", v)
+            for ws in (None, ctx.batch_workspace([M_ITEMS] * 2, blocks_per_round=1)):
+                outs = ctx.search_batch([c3["gal"]] * 2, [M_ITEMS] * 2, [D] * 2, [c3["pr1"], c3["pr2"]],
+                                        workspace=ws)
+                _assert_scores(outs[0], c3["want1"], op.q_primes)
+                _assert_scores(outs[1], c3["want2"], op.q_primes)
+        for o, qv in zip(outs, (c3["q1"], c3["q2"])):
+            dec = ctx.decrypt_scores(c3["sk"], o, M_ITEMS).cpu().numpy()
+            assert np.array_equal(dec, hers.plaintext_scores(c3["P"], qv))
     finally:
         ctx.set_option("relin_fuse_min_wgs", 0)
+        ctx.set_option("mb_variant", 0)
 
 
 @pytest.mark.timeout(900)
@@ -132,12 +136,16 @@ def test_c3_wide_batch_equals_single(c3):
     qs = [rng.integers(-63, 64, size=d).astype(np.int32) for _ in range(3)]
     prs = [ctx.encrypt_probe(torch.from_numpy(q).to(ctx.device), 500 + j) for j, q in enumerate(qs)]
     try:
-        for fuse in (1, 1 << 30):
+        single = [ctx.search(gal, m, d, prs[j]).clone() for j in range(3)]
+        for fuse, v in ((1, 0), (1 << 30, 0), (1 << 30, 1), (1 << 30, 2), (1 << 30, 3)):
             ctx.set_option("relin_fuse_min_wgs", fuse)
+            ctx.set_option("mb_variant", v)
             outs = ctx.search_batch([gal] * 3, [m] * 3, [d] * 3, prs)
             for j in range(3):
-                assert torch.equal(outs[j], ctx.search(gal, m, d, prs[j])), (fuse, j)
-                dec = ctx.decrypt_scores(c3["sk"], outs[j], m).cpu().numpy()
-                assert np.array_equal(dec, hers.plaintext_scores(P, qs[j])), (fuse, j)
+                assert torch.equal(outs[j], single[j]), (fuse, v, j)
+        for j in range(3):
+            dec = ctx.decrypt_scores(c3["sk"], outs[j], m).cpu().numpy()
+            assert np.array_equal(dec, hers.plaintext_scores(P, qs[j])), j
     finally:
         ctx.set_option("relin_fuse_min_wgs", 0)
+        ctx.set_option("mb_variant", 0)

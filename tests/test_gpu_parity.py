@@ -371,13 +371,34 @@ def batch_setup(case_r36):
 def test_batch_multi_probe_equals_single(batch_setup, case_r36):
     """Grouped requests (16 + 4 on one gallery, 3 on another, 16 + 1 on a
     third) in one submission give the same score ciphertexts as one
-    hers_search per request."""
+    hers_search per request, under every multi-probe schedule and a smaller
+    group size; a request of each group equals the oracle's score
+    ciphertext."""
     ctx, reqs = batch_setup
     gals, ms, ds, prs = [r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
-    for ws in (ctx.batch_workspace(ms), ctx.batch_workspace(ms, blocks_per_round=1)):
-        outs = ctx.search_batch(gals, ms, ds, prs, workspace=ws)
-        for j, (g, m, d, pr, P, qv) in enumerate(reqs):
-            assert torch.equal(outs[j], _single_scores(ctx, g, m, d, pr)), j
+    single = [_single_scores(ctx, g, m, d, pr) for g, m, d, pr, P, qv in reqs]
+    try:
+        for v, grp in ((0, 16), (1, 16), (2, 16), (3, 16), (1, 5)):
+            ctx.set_option("mb_variant", v)
+            ctx.set_option("mb_group", grp)
+            for ws in (ctx.batch_workspace(ms), ctx.batch_workspace(ms, blocks_per_round=1)):
+                outs = ctx.search_batch(gals, ms, ds, prs, workspace=ws)
+                for j in range(len(reqs)):
+                    assert torch.equal(outs[j], single[j]), (v, grp, j)
+    finally:
+        ctx.set_option("mb_variant", 0)
+        ctx.set_option("mb_group", 16)
+    # one request per gallery group against the oracle (the last block, ragged)
+    c = case_r36
+    for j, oseed in ((5, 1005), (21, 2001), (23, 3000)):
+        g, m, d, pr, P, qv = reqs[j]
+        b = c.ctx.blocks(m) - 1
+        gseed = {id(c.gallery): c.gal_seed}.get(id(g), 77 if d == 16 else 78)
+        og = hers.encrypt_gallery_block(c.op, c.opk, P, b, gseed)
+        S = hers.search_block(c.op, c.orlk, hers.encrypt_probe(c.op, c.opk, qv, oseed), og)
+        got = outs[j][b].cpu().numpy()
+        assert np.array_equal(got[0], res(S[0], c.op.q_primes)), j
+        assert np.array_equal(got[1], res(S[1], c.op.q_primes)), j
     dec = ctx.decrypt_scores(case_r36.sk, outs[5], ms[5]).cpu().numpy()
     assert np.array_equal(dec, hers.plaintext_scores(reqs[5][4], reqs[5][5]))
     dec = ctx.decrypt_scores(case_r36.sk, outs[21], ms[21]).cpu().numpy()
@@ -385,6 +406,14 @@ def test_batch_multi_probe_equals_single(batch_setup, case_r36):
     for j in (23, 39):
         dec = ctx.decrypt_scores(case_r36.sk, outs[j], ms[j]).cpu().numpy()
         assert np.array_equal(dec, hers.plaintext_scores(reqs[j][4], reqs[j][5])), j
+    # the batched autotuner keeps a schedule that gives the same bits
+    chosen = ctx.autotune_batch(gals, ms, ds, prs, [ctx.new_scores(m) for m in ms], ctx.batch_workspace(ms), reps=1)
+    try:
+        assert 0 <= chosen <= 3 and ctx.get_option("mb_variant") == chosen
+        outs = ctx.search_batch(gals, ms, ds, prs)
+        assert all(torch.equal(outs[j], single[j]) for j in range(len(reqs)))
+    finally:
+        ctx.set_option("mb_variant", 0)
 
 
 def test_plan_replays_match_eager(batch_setup, case_r36):
