@@ -290,11 +290,17 @@ def run_serving(args, cfg):
             ctx.profile_enable(False)
         return np.array(lats), elapsed, stats, stages, checked
 
-    lat_b, el_b, st_b, stages, checked = serve(16, True)
+    # a short untimed stream first (first launches, event pools), then the
+    # timed streams without stage events; the stage times and the roofline come
+    # from a further run of the same stream with every stage's launches timed
+    w = min(nreq, 200)
+    serve(16, False, arrivals[:w], targets[:w], queries[:w])
+    lat_b, el_b, st_b, _, checked = serve(16, False)
     log("batched: p50 %.2f ms p99 %.2f ms, %.1f s" % (np.percentile(lat_b, 50), np.percentile(lat_b, 99), el_b))
     lat_1, el_1, st_1, _, _ = serve(1, False)
     log("one request per wave: p50 %.2f ms p99 %.2f ms, %.1f s" % (
         np.percentile(lat_1, 50), np.percentile(lat_1, 99), el_1))
+    _, _, st_p, stages, _ = serve(16, True)
     # arrival-rate sweep: the same request stream, faster, batched and one per wave
     sweep = []
     for rr in sweep_rates:
@@ -313,7 +319,7 @@ def run_serving(args, cfg):
             row["one_per_wave"]["p99_ms"]))
         sweep.append(row)
     mac_ms = stages["mac"][0] + stages["mac_multi"][0]
-    achieved = st_b["gallery_bytes"] / (mac_ms * 1e-3) / 1e9 if mac_ms else 0.0
+    achieved = st_p["gallery_bytes"] / (mac_ms * 1e-3) / 1e9 if mac_ms else 0.0
     result = {
         "metric": "encrypted scores/sec (gallery items x probes per s); p50/p99 probe latency",
         "value": items_total / el_b,
@@ -331,7 +337,8 @@ def run_serving(args, cfg):
         "stage_ms": {k: v[0] for k, v in stages.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_mac + k_mac_multi",
-                     "bytes": st_b["gallery_bytes"], "mac_ms": mac_ms},
+                     "bytes": st_p["gallery_bytes"], "mac_ms": mac_ms,
+                     "from": "a run of the same stream with every stage's launches timed"},
         "enrollment": {"wall_s": setup_s},
         "check": {"requests_checked_against_PTq": checked},
     }

@@ -142,6 +142,7 @@ struct hers_server {
   bool stop = false;
   int64_t next_ticket = 1;
   hipStream_t streams[SRV_STREAMS] = {};
+  hipEvent_t events[SRV_STREAMS] = {};  // a wave's completion, on its stream (one wave per stream)
   bool stream_busy[SRV_STREAMS] = {};
   hipStream_t copy_stream = nullptr;
   hers_server_stats st;
@@ -259,7 +260,6 @@ void retire_wave(hers_server* s, Wave& w) {
   }
   s->arena.release(w.ws_off, w.ws_bytes);
   s->stream_busy[w.stream] = false;
-  if (w.ev) (void)hipEventDestroy(w.ev);
 }
 
 void worker_main(hers_server* s) {
@@ -353,15 +353,15 @@ void worker_main(hers_server* s) {
       }
       if (short_of_memory) s->st.deferrals += 1;
       if (!w.reqs.empty()) {
-        if (hipEventCreateWithFlags(&w.ev, hipEventDisableTiming) != hipSuccess) w.ev = nullptr;
         w.stream = 0;
         while (s->stream_busy[w.stream]) ++w.stream;     // fewer than SRV_STREAMS waves are in flight
         s->stream_busy[w.stream] = true;
+        w.ev = s->events[w.stream];
         s->st.waves += 1;
         s->st.max_wave = std::max<int64_t>(s->st.max_wave, (int64_t)w.reqs.size());
         s->st.arena_peak = s->arena.peak();
         lk.unlock();
-        if (w.ev) launch_wave(s, w); else fail_wave(s, w, "event create");
+        launch_wave(s, w);
         lk.lock();
         s->inflight.push_back(std::move(w));
         continue;
@@ -385,6 +385,15 @@ void worker_main(hers_server* s) {
   }
 }
 
+// Streams and events of a server (those created so far).
+void release_device(hers_server* s) {
+  for (int i = 0; i < SRV_STREAMS; ++i) {
+    if (s->events[i]) (void)hipEventDestroy(s->events[i]);
+    if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
+  }
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -397,13 +406,15 @@ int hers_server_create(hers_ctx* ctx, const uint8_t* sk_dev, void* arena_dev, si
   if (hers_ctx_info(ctx, &s->info)) { delete s; return HERS_EINVAL; }
   s->bound = s->info.feature_bound;
   (void)hipGetDevice(&s->device);
-  for (int i = 0; i < SRV_STREAMS; ++i)
-    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
-      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
-      delete s;
-      return HERS_EDEVICE;
-    }
-  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) { delete s; return HERS_EDEVICE; }
+  bool ok = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < SRV_STREAMS; ++i)
+    ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    release_device(s);
+    delete s;
+    return HERS_EDEVICE;
+  }
   s->worker = std::thread(worker_main, s);
   *out = s;
   return HERS_OK;
@@ -506,9 +517,7 @@ void hers_server_destroy(hers_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto& kv : s->reqs) delete kv.second;
-  for (int i = 0; i < SRV_STREAMS; ++i)
-    if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
-  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  release_device(s);
   delete s;
 }
 
