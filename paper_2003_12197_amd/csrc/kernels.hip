@@ -460,8 +460,7 @@ struct MacBatch {
 template <int NB, int U, bool NT>
 __global__ void __launch_bounds__(WG)
 k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restrict__ probe, int32_t d,
-      int32_t dim0, int32_t dcount, int64_t blk_lo, int64_t blk_hi, uint32_t blocks_per_group,
-      uint32_t* __restrict__ acc) {
+      int32_t dim0, int32_t dcount, int64_t blk_lo, int64_t blk_hi, uint32_t* __restrict__ acc) {
   static_assert(4 % U == 0, "U divides the fold period");
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, K = C.K;
@@ -470,13 +469,16 @@ k_mac(DevTabs T, const uint32_t* __restrict__ gallery, const uint32_t* __restric
   const uint32_t p = C.p[r];
   const uint64_t mu = C.p_mu64[r];
   const uint32_t c34 = (uint32_t)((1ull << 34) - (uint64_t)p * (mu >> 30));   // 2^34 mod p (mu = floor(2^64/p))
-  const int64_t b0 = blk_lo + (int64_t)blockIdx.z * blocks_per_group;
-  const int64_t b1 = b0 + blocks_per_group < blk_hi ? b0 + blocks_per_group : blk_hi;
   const size_t row = n / 4;                               // u32x4 between dimension rows
   // dimensions dim0 .. dim0 + dcount - 1 of the d in the layouts
   const u32x4* pr = (const u32x4*)(probe + ((size_t)r * d + dim0) * 2 * n + slot);
   const int32_t dfull = dcount / U * U;
-  for (int64_t b = b0; b < b1; b += NB) {
+  // block group z takes the steps of NB blocks z, z + G, z + 2G, ... (G groups),
+  // so the groups resident at one time read neighbouring blocks: one window of
+  // the gallery sweeps forward, rather than G windows a group's length apart
+  const int64_t stride = (int64_t)gridDim.z * NB;
+  for (int64_t b = blk_lo + (int64_t)blockIdx.z * NB; b < blk_hi; b += stride) {
+    const int64_t b1 = b + NB < blk_hi ? b + NB : blk_hi;
     const u32x4* gb[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -1365,7 +1367,8 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
   const uint64_t tiles = n / 4 / lanes;
   static const int nb_of[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 4, 2, 1};
   const int NB = variant >= 0 && variant < 12 ? nb_of[variant] : 1;
-  // about target_wgs workgroups, groups a multiple of NB blocks
+  // about target_wgs workgroups: groups of about bpg blocks, each taking its
+  // steps of NB blocks interleaved with the other groups'
   uint64_t bpg = (uint64_t)nb * tiles * K / (target_wgs ? target_wgs : 2048);
   if (bpg < (uint64_t)NB) bpg = NB;
   bpg = (bpg + NB - 1) / NB * NB;
@@ -1374,7 +1377,7 @@ hipError_t launch_mac(const DevTabs& T, uint32_t n, uint32_t K, const uint32_t* 
 #define MAC_CASE(V, NB_, U_, NT_)                                                                    \
   case V:                                                                                            \
     hipLaunchKernelGGL((k_mac<NB_, U_, NT_>), grid, dim3(lanes), 0, s, T, gallery, probe, d, dim0, dcount, \
-                       blk_lo, blk_hi, (uint32_t)bpg, acc);                                          \
+                       blk_lo, blk_hi, acc);                                                         \
     break;
   switch (variant) {
     MAC_CASE(0, 1, 2, false)
