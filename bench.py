@@ -190,6 +190,36 @@ def cpu_baseline(cfg, qv, m, probes, log):
             "kind": "oracle", "sample": sample}
 
 
+def search_traffic(ctx, M, d, mac_variant, search_ms):
+    """Bytes a single-probe search over M blocks must move through HBM, kernel
+    by kernel (each kernel's inputs read once, its outputs written once), and
+    the rate they imply at the measured search time:
+      multiply-accumulate: gallery K d 2 n 4 + accumulators 3 K n 4 per block, probe once;
+      inverse NTT of the accumulators (not with schedule 12, which writes them
+      transformed): 3 K n 4 read and written;
+      rescale: 3 K n 4 read, c0 and c1 2 k n 8 and the digits L k n 8 written;
+      relinearization: two-kernel form -- digits transformed in place (L k n 8
+      read and written), then read once more, c0 and c1 read and written
+      (2 k n 8 each way); fused form -- digits read once, c0 and c1 read and
+      written; the evaluation keys (and their Shoup companions) once per search."""
+    import torch
+    n, K, k, L = ctx.n, ctx.K, ctx.k, ctx.L
+    mac = M * (K * d * 2 * n * 4 + 3 * K * n * 4) + K * d * 2 * n * 4
+    intt = 0 if mac_variant == 12 else M * 2 * 3 * K * n * 4
+    rescale = M * (3 * K * n * 4 + 2 * k * n * 8 + L * k * n * 8)
+    chunks = max(1, ctx.get_option("overlap_chunks"))
+    opt = ctx.get_option("relin_fuse_min_wgs")
+    cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    threshold = opt if opt else (8 * cus if n >= 8192 else float("inf"))
+    fused = -(-M // chunks) * k >= threshold
+    relin = M * ((0 if fused else 2 * L * k * n * 8) + L * k * n * 8 + 2 * 2 * k * n * 8) + 2 * L * 2 * k * n * 8
+    total = mac + intt + rescale + relin
+    achieved = total / (search_ms * 1e-3) / 1e9
+    return {"bytes": total, "by_stage": {"mac": mac, "intt_acc": intt, "rescale": rescale, "relin": relin},
+            "relin_form": "fused" if fused else "two-kernel", "search_ms": search_ms,
+            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS}
+
+
 def run_serving(args, cfg):
     """Serve a Poisson query stream with the request loop; report throughput and
     latency, and the same stream served with one request per wave."""
@@ -579,9 +609,11 @@ def main():
             mac_variant = ctx.get_option("mac_variant")
         else:
             mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s, scores=scores[0])
-        log("%s k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d" % (
-            "default" if args.no_autotune else "autotuned", mac_variant, ctx.get_option("ntt_radix_log2"),
-            ctx.get_option("overlap_chunks")))
+        log("%s k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d, MAC workgroups per CU %d, "
+            "fused relinearization from %d workgroups" % (
+                "default" if args.no_autotune else "autotuned", mac_variant, ctx.get_option("ntt_radix_log2"),
+                ctx.get_option("overlap_chunks"), ctx.get_option("mac_wgs_per_cu"),
+                ctx.get_option("relin_fuse_min_wgs")))
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
@@ -749,6 +781,9 @@ def main():
                 "frac": achieved / MAD64_PEAK_TOPS, "traffic": None,
                 "kernel": "k_mac_multi", "mads_per_launch": per_launch, "avg_launch_ms": dom_avg_ms}
 
+    search_hbm = None
+    if npr == 1 and side.get("search_ms"):
+        search_hbm = search_traffic(ctx, M, d, mac_variant, side["search_ms"])
     value = m * npr * args.steps / (total_ms * 1e-3)
     lat = np.array(step_ms)
     search_ms = sum(stages[s][0] for s in ("mac", "mac_multi", "intt_acc", "rescale", "relin")) / kb
@@ -775,6 +810,7 @@ def main():
                    "mac_schedule": mac_variant, "ntt_radix": 1 << ctx.get_option("ntt_radix_log2"),
                    "overlap_chunks": ctx.get_option("overlap_chunks"),
                    "mac_wgs_per_cu": ctx.get_option("mac_wgs_per_cu") or 8,
+                   "relin_fuse_min_wgs": ctx.get_option("relin_fuse_min_wgs"),
                    "multi_probe_schedule": ctx.get_option("mb_variant") if npr > 1 else None,
                    "hip_graph": plan is not None, "gallery_ranges_per_step": len(slices)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -784,6 +820,7 @@ def main():
         "search_only_scores_per_s": m * npr / ((side.get("search_ms") or search_ms) * 1e-3),
         "side": side,
         "roofline": roof,
+        "search_hbm": search_hbm,
         "enrollment": {"gpu_encrypt_ms": enc_ms, "items_per_s": m / (enc_ms * 1e-3), "wall_s": setup_s},
         "check": {"scores_equal_PTq": ok, "argmax": top, "mate": queries[0][1]},
         "wall_s_timed": wall,
