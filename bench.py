@@ -45,6 +45,8 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 # 2.4 GHz = 19.66 T/s) and the rate a dependency-free stream of the
 # instruction reaches on the part (20.56 T/s)
 MAD64_PEAK_TOPS = max(256 * 4 * 16 / 2 * 2.4e9 / 1e12, 20.56)
+INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix peak, 5.0 POP/s
+MB_MFMA = 4               # the multi-probe schedule on the matrix cores
 
 WORKLOADS = {
     "single": dict(desc="single probe vs 1,048,576-item gallery, d=64, n=4096, q=3x36-bit primes, t=1,032,193",
@@ -617,7 +619,10 @@ def main():
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
-        rounds = max(8, min(span, (8 << 30) // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
+        # rounds of blocks as large as the free memory allows (up to 32 GiB of workspace): every round
+        # launch re-stages the probes, so fewer rounds cost less
+        budget = min(32 << 30, max(8 << 30, torch.cuda.mem_get_info()[0] - (4 << 30)))
+        rounds = max(8, min(span, budget // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
         ws_s = ctx.batch_workspace([span * n] * npr, blocks_per_round=rounds)
         mac_variant = None
         gal_of = lambda lo, hi: gallery[lo * blk_words:hi * blk_words]
@@ -771,6 +776,17 @@ def main():
                 "kernel": mac_kernel_name(mac_variant, n),
                 "bytes_per_launch": per_launch, "avg_launch_ms": dom_avg_ms,
                 "blocks_per_launch": M / launches_per_step}
+    elif ctx.get_option("mb_variant") == MB_MFMA and d <= 128:
+        # the matrix-core schedule: int8 digit products, 16 per product of two residues (four balanced
+        # base-256 digits each), 4 residue products per (probe, block, dimension, base prime, slot) --
+        # P0 G0, P0 G1, P1 G0, P1 G1 -- each a multiply and an add
+        launches_per_step = dom_n / dom_steps
+        per_launch = 2.0 * 16 * 4 * npr * M * d * K * n / launches_per_step
+        achieved = per_launch / (dom_avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": None, "kernel": "k_mac_mfma",
+                "int8_ops_per_launch": per_launch, "avg_launch_ms": dom_avg_ms,
+                "residue_products_per_s": per_launch / 32 / (dom_avg_ms * 1e-3)}
     else:
         # algorithmic 64-bit multiply-adds: 3 per (probe, block, dimension, base prime, slot) -- the
         # tensor's P0 G0 and P1 G1 and, for its cross term, (P0 + P1)(G0 + G1) (Karatsuba)

@@ -416,12 +416,16 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  with more workgroups.  0 = 8 per compute unit at
  *                  n >= 8192, never below; 1 = always.
  *   "mb_variant"   multi-probe multiply-accumulate schedule of
- *                  hers_search_batch, 0..3, as (probes per wave, dimensions
+ *                  hers_search_batch, 0..4; 0..3 as (probes per wave, dimensions
  *                  per staged chunk, blocks per item): 0 (1, 8, 4) in
  *                  1024-lane workgroups, 1 (2, 4, 2), 2 (2, 8, 2) in 512-lane
  *                  workgroups, 3 (4, 4, 1) in 256-lane workgroups.  More
  *                  probes per wave read each staged gallery word from LDS
- *                  once for all of them.
+ *                  once for all of them.  4: on the matrix cores -- the
+ *                  residues as four balanced base-256 digits, the sums over
+ *                  the dimensions as int8 matrix products per slot (MFMA),
+ *                  recombined exactly mod p; for d <= 128 (a batch with a
+ *                  larger d runs schedule 0).
  *   "mb_group"     most probes of one gallery grouped into one multi-probe
  *                  pass, 1..16 (default 16).
  * Every schedule computes the same bits.  Returns HERS_EINVAL for an unknown
@@ -436,9 +440,11 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not NULL --
  * whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16 (chunks of
  * at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule found first,
- * schedule 8, schedule 10 or schedule 12 (a combination other than no
- * chunks, default grid, schedule found first must be 3% faster to be
- * kept).  Keeps the fastest of each in the context and returns the schedule
+ * schedule 8, schedule 10 or schedule 12, and -- where the default
+ * relinearization is the two-kernel form -- over chunk counts 1, 4, 8, 16 x
+ * "mac_wgs_per_cu" 0, 1 with the relinearization fused ("relin_fuse_min_wgs"
+ * 1) and the best schedule (a combination other than no chunks, default
+ * grid, schedule found first must be 3% faster to be kept).  Keeps the fastest of each in the context and returns the schedule
  * in *chosen (may be NULL).  The workspace and scores_dev contents are
  * overwritten; the call synchronizes `stream`. */
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,

@@ -428,7 +428,7 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     return HERS_OK;
   }
   if (!std::strcmp(key, "mb_variant")) {
-    if (value < 0 || value >= MB_VARIANTS) return fail(HERS_EINVAL, "mb_variant must be in [0, 3]");
+    if (value < 0 || value >= MB_VARIANTS) return fail(HERS_EINVAL, "mb_variant must be in [0, 4]");
     ctx->mb_variant = (int)value;
     return HERS_OK;
   }
@@ -1255,12 +1255,43 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
         }
       }
     }
+    // the relinearization in one kernel per (block, prime) where the default
+    // is the two-kernel form: it moves no transformed digit through memory,
+    // which counts once the overlapped search is bound by its total traffic
+    const int64_t fuse0 = ctx->relin_fuse_min_wgs;
+    int64_t best_f = fuse0;
+    if (fuse_wgs(ctx) > 1) {
+      for (int nch : {1, 4, 8, 16}) {
+        if (rc != HERS_OK || (nch > 1 && M / nch < 16)) break;
+        for (int w : {0, 1}) {
+          ctx->overlap_chunks = nch;
+          ctx->mac_wgs_per_cu = w;
+          ctx->mac_variant = best_mv;
+          ctx->relin_fuse_min_wgs = 1;
+          rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                           work_bytes, stream);
+          hipError_t e = rc == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
+          for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
+            rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                             work_bytes, stream);
+          ctx->relin_fuse_min_wgs = fuse0;
+          if (rc != HERS_OK) break;
+          if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+          if (ms < best_o) { best_o = ms; best_nch = nch; best_w = w; best_f = 1; }
+        }
+      }
+    }
     // keep the plain schedule (no chunks, default grid) unless another wins
     // clearly: differences within timing noise would only make runs disagree
-    if (best_o > 0.97f * plain_ms) { best_nch = 1; best_w = 0; best_mv = best_v; }
+    if (best_o > 0.97f * plain_ms) { best_nch = 1; best_w = 0; best_mv = best_v; best_f = fuse0; }
     ctx->overlap_chunks = best_nch;
     ctx->mac_wgs_per_cu = best_w;
     ctx->mac_variant = best_mv;
+    ctx->relin_fuse_min_wgs = best_f;
     best_v = best_mv;
   }
   (void)hipEventDestroy(e0);
@@ -1309,7 +1340,7 @@ int plan_groups(hers_ctx* ctx, int32_t nreq, const uint32_t* const* galleries, c
 // per-request epilogue (inverse NTT, rescale, relinearization).
 // Workgroups per CU of a multi-probe schedule: as many as are resident.
 uint32_t mb_wgs_per_cu(int variant) {
-  static const uint32_t per_cu[MB_VARIANTS] = {1, 2, 2, 4};
+  static const uint32_t per_cu[MB_VARIANTS] = {1, 2, 2, 4, 1};
   return variant >= 0 && variant < MB_VARIANTS ? per_cu[variant] : 1;
 }
 

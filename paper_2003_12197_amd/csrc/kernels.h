@@ -61,7 +61,8 @@ namespace hers {
 // variants as (probes per wave, dimensions per chunk, blocks per item):
 // 0 (1, 8, 4) with 1024-lane workgroups; 1 (2, 4, 2), 2 (2, 8, 2) with 512
 // lanes; 3 (4, 4, 1) with 256 lanes
-#define MB_VARIANTS 4
+#define MB_VARIANTS 5
+#define MB_MFMA 4         // the schedule on the matrix cores (int8 digit products), d <= 128
 hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s, int variant = 0);
 hipError_t launch_keygen(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, uint64_t seed, uint8_t* sk,
                          uint64_t* pk, uint64_t* rlk, hipStream_t s);

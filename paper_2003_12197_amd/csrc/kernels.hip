@@ -867,6 +867,260 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- batched multiply-accumulate on the matrix cores
+// For one base prime p and one slot, a group's sums form three matrix
+// products over the d dimensions: A_{cc'}[probe][block] = sum_i P_c[probe][i]
+// G_c'[block][i] (c, c' the two ciphertext polynomials; A0 = A_00,
+// A1 = A_01 + A_10, A2 = A_11).  Every residue v < 2^30 is written in four
+// balanced base-256 digits, v = sum_j s_j 256^j with s_0..s_2 in [-128, 127]
+// and s_3 in [0, 64] -- the bytes of (v + 0x808080) XOR 0x808080 read as
+// signed -- so a product of residues is sum_{i,j} s_i s_j 256^(i+j) and the
+// sums over the dimensions are int8 x int8 matrix products, exact in int32
+// (|sum| <= d 2^14), on the MFMA units (v_mfma_i32_16x16x64_i8).
+// Per slot: 16-row tiles of (probe pair, polynomial, digit i) rows against 16
+// columns of (block, polynomial) for 8 blocks, one tile per digit j of the
+// gallery; a lane's four results of a tile are its (probe, c, block, c')
+// entry for i = 0..3, so with the four j tiles it holds all 16 digit
+// products of one entry and recombines them in registers:
+// X = sum_k T_k (256^k mod p), T_k = sum_{i+j=k} C_ij (|X| below 2^56), one
+// reduction mod p.  The partner entry (c, c') = (1, 0) of (0, 1) is 17 lanes
+// away (A1 = X_01 + X_10).
+// A workgroup is MF_SLOTS waves, one slot each, over a tile of MF_SLOTS
+// neighbouring slots of one prime for one group of up to 16 probes; it keeps
+// the probes' digits of its slot in registers (d <= MF_DMAX) and sweeps the
+// group's blocks 8 at a time.  The gallery words of 8 blocks x d dimensions x
+// the slot tile are staged in LDS, transposed to [slot][block][c'][dim], in two
+// buffers: while one group is multiplied, the next is written to the other
+// buffer and the one after loads into registers, so a block group costs one
+// barrier.  The results go through LDS (two buffers as well) so that every
+// row of the tile is written at once.  Work items
+// (group, prime, slot tile) are dealt so that the items reading the same
+// 128-byte gallery lines (4 tiles x the groups) run on one XCD together.
+// Exact like k_mac_multi: the same residues.
+#define MF_SLOTS 8
+#define MF_BLK 8
+#define MF_DMAX 128
+#define MF_KC (MF_DMAX / 64)
+#define MF_DS (MF_DMAX + 4)                          // staged row of dimensions, padded (LDS banks)
+#define MF_PS 68                                     // staged probe row of one 64-dimension step, padded
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bal_digits(uint32_t v) { return (v + 0x00808080u) ^ 0x00808080u; }
+
+// First of the four dimensions a lane's bytes 4 q .. 4 q + 3 of an MFMA operand
+// hold within a 64-deep K step (lane group kq = lane / 16): 16 kq + 4 q.
+__device__ __forceinline__ uint32_t mf_kbase(uint32_t kq, int q) { return 16 * kq + 4 * q; }
+
+// 4 x 4 byte transpose: out[j] holds byte j of w0, w1, w2, w3 (in that order)
+__device__ __forceinline__ void byte_transpose4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t* out) {
+  const uint32_t t0 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);   // w0.b0 w1.b0 w0.b1 w1.b1
+  const uint32_t t1 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);   // w0.b2 w1.b2 w0.b3 w1.b3
+  const uint32_t t2 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const uint32_t t3 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  out[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+  out[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+  out[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+  out[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+__global__ void __launch_bounds__(64 * MF_SLOTS, 1)
+k_mac_mfma(DevTabs T, MacBatchArgs A) {
+  constexpr uint32_t WGL = 64 * MF_SLOTS;
+  static_assert(WGL == 2 * 2 * MF_DMAX && MF_SLOTS == 8, "a lane stages one (dimension, polynomial, half-tile) row");
+  // LDS: two gallery buffers [slot][block][c'][MF_DS] (one K step of probe words [slot][probe][c][MF_PS]
+  // reuses the first), two result buffers [probe][block][comp][slot]
+  constexpr uint32_t GAL_WORDS = MF_SLOTS * MF_BLK * 2 * MF_DS, PRB_WORDS = MF_SLOTS * MB_PROBES * 2 * MF_PS;
+  constexpr uint32_t OUT_WORDS = MB_PROBES * MF_BLK * 3 * MF_SLOTS;
+  static_assert(PRB_WORDS <= 2 * GAL_WORDS, "probe staging fits the gallery buffers");
+  __shared__ __attribute__((aligned(16))) uint32_t stg[2 * GAL_WORDS];
+  __shared__ __attribute__((aligned(16))) uint32_t outb[2 * OUT_WORDS];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, K = C.K;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);     // the wave's slot in the tile
+  const uint32_t tiles = n / MF_SLOTS;
+  const uint32_t ng = (uint32_t)A.ngroups;
+  // items: line group lg = (prime, 4 neighbouring tiles) x ng groups; line groups dealt to XCDs by lg mod 8
+  const uint32_t nlg = K * tiles / 4;
+  const uint32_t nx = gridDim.x % 8 == 0 ? 8 : 1;
+  const uint32_t xcd = blockIdx.x % nx, lw = blockIdx.x / nx, nw = gridDim.x / nx;
+  const uint32_t per_lg = 4 * ng;
+  const uint64_t my_items = nlg > xcd ? (uint64_t)((nlg - xcd + nx - 1) / nx) * per_lg : 0;
+  // MFMA lane roles: A rows (l & 15) = (probe pair half, polynomial, digit), B/C columns (l & 15) =
+  // (block, polynomial), K range 16 (l >> 4) .. + 15 of a 64-dimension step; C rows 4 (l >> 4) + e
+  const uint32_t arow = lane & 15, adig = arow & 3, apc = arow >> 2;
+  const uint32_t col = lane & 15, cb = col >> 1, cc = col & 1;
+  const uint32_t kq = lane >> 4;
+  const uint32_t cpc = lane >> 4;                                     // C: (probe pair half, polynomial) of the lane
+  // staging roles: the lane's half tile (4 slots), polynomial and dimension (gallery: one row per
+  // block e; probes: probe (tid >> 8) + 2 e, polynomial, dimension of the K step)
+  const uint32_t sh = tid & 1, sc = (tid >> 1) & 1, sdim = tid >> 2;
+  const uint32_t pc_ = (tid >> 7) & 1, pdim = (tid >> 1) & 63, pj0 = tid >> 8;
+  for (uint64_t u = lw; u < my_items; u += nw) {
+    const uint32_t lg = xcd + (uint32_t)(u / per_lg) * nx;
+    const uint32_t within = (uint32_t)(u % per_lg);
+    const uint32_t g = within % ng;
+    const uint32_t pair = lg * 4 + within / ng;
+    const uint32_t tile = pair % tiles, r = pair / tiles;
+    const MacGroup& G = A.g[g];
+    const int32_t d = G.d;
+    const int kcn = (d + 63) / 64;
+    const uint32_t p = C.p[r];
+    const uint64_t mu = C.p_mu64[r];
+    const uint32_t slot0 = tile * MF_SLOTS;
+    // 256^k mod p for k = 4, 5, 6 (256^k < p below)
+    const uint32_t w4 = (uint32_t)((1ull << 32) % p), w5 = (uint32_t)(((uint64_t)w4 << 8) % p),
+                   w6 = (uint32_t)(((uint64_t)w5 << 8) % p);
+    const uint64_t off = ((1ull << 58) / p + 1) * p;                   // a multiple of p above |X|
+    // ---- the probes' digits of this slot: per K step, rows (probe, c, dim) staged as [slot][probe][c][dim]
+    mf_v4i Ad[MF_KC][8];
+#pragma unroll
+    for (int kc = 0; kc < MF_KC; ++kc) {
+      if (kc >= kcn) {
+#pragma unroll
+        for (int R = 0; R < 8; ++R) Ad[kc][R] = mf_v4i{0, 0, 0, 0};
+        continue;
+      }
+      // two passes, each issuing its loads before the first is written, so their latencies overlap
+      constexpr uint32_t PRB_PER_LANE = MB_PROBES * 2 * 64 * (MF_SLOTS / 4) / WGL, PASS = PRB_PER_LANE / 2;
+      const int32_t dim = kc * 64 + (int32_t)pdim;
+      __syncthreads();                                                // staging buffer free
+#pragma unroll
+      for (uint32_t e0 = 0; e0 < PRB_PER_LANE; e0 += PASS) {
+        u32x4 av[PASS];
+#pragma unroll
+        for (uint32_t e = 0; e < PASS; ++e) {
+          const uint32_t j = pj0 + 2 * (e0 + e);
+          av[e] = u32x4{0u, 0u, 0u, 0u};
+          if ((int32_t)j < G.nprobe && dim < d)
+            av[e] = *(const u32x4*)(G.probe[j] + (((size_t)r * d + dim) * 2 + pc_) * n + slot0 + 4 * sh);
+        }
+#pragma unroll
+        for (uint32_t e = 0; e < PASS; ++e) {
+          const uint32_t j = pj0 + 2 * (e0 + e);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) stg[(((4 * sh + s) * MB_PROBES + j) * 2 + pc_) * MF_PS + pdim] = av[e][s];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int R = 0; R < 8; ++R) {
+        const uint32_t j = 2 * R + (apc >> 1), c = apc & 1;
+        const uint32_t* src = stg + ((w * MB_PROBES + j) * 2 + c) * MF_PS;
+        uint32_t dg[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const u32x4 v = *(const u32x4*)(src + mf_kbase(kq, q4));
+          uint32_t tr[4];
+          byte_transpose4(bal_digits(v[0]), bal_digits(v[1]), bal_digits(v[2]), bal_digits(v[3]), tr);
+          dg[q4] = adig == 0 ? tr[0] : adig == 1 ? tr[1] : adig == 2 ? tr[2] : tr[3];
+        }
+        Ad[kc][R] = mf_v4i{(int)dg[0], (int)dg[1], (int)dg[2], (int)dg[3]};
+      }
+    }
+    // ---- gallery block groups of MF_BLK blocks, double-buffered in LDS; the group after next loads
+    // into registers while the next is staged and the current one multiplied
+    const int64_t nbg = (G.blk_hi - G.blk_lo + MF_BLK - 1) / MF_BLK;
+    const size_t bstride = (size_t)K * d * 2 * n;                     // words between blocks
+    const bool dim_ok = (int32_t)sdim < d;
+    const size_t lane_off = ((size_t)sdim * 2 + sc) * n + 4 * sh;
+    u32x4 pre[MF_BLK];
+    auto fetch = [&](int64_t bg) {
+      const int64_t b0 = G.blk_lo + bg * MF_BLK;
+      const uint32_t* base = G.gallery + ((size_t)b0 * K + r) * d * 2 * n + slot0 + lane_off;
+#pragma unroll
+      for (uint32_t e = 0; e < MF_BLK; ++e) {
+        pre[e] = u32x4{0u, 0u, 0u, 0u};
+        if (dim_ok && b0 + e < G.blk_hi) pre[e] = *(const u32x4*)(base + e * bstride);
+      }
+    };
+    auto stage = [&](uint32_t* buf) {
+#pragma unroll
+      for (uint32_t e = 0; e < MF_BLK; ++e)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) buf[(((4 * sh + s) * MF_BLK + e) * 2 + sc) * MF_DS + sdim] = pre[e][s];
+    };
+    fetch(0);
+    __syncthreads();                                                  // the probe staging's reads are done
+    stage(stg);
+    if (nbg > 1) fetch(1);
+    __syncthreads();
+    for (int64_t bg = 0; bg < nbg; ++bg) {
+      const int64_t b0 = G.blk_lo + bg * MF_BLK;
+      const uint32_t cur = (uint32_t)(bg & 1);
+      const uint32_t* gcur = stg + cur * GAL_WORDS;
+      uint32_t* ocur = outb + cur * OUT_WORDS;
+      // B operands of this lane: digits j of (block cb, polynomial cc) over its 16 dimensions per K step
+      mf_v4i Bd[MF_KC][4];
+#pragma unroll
+      for (int kc = 0; kc < MF_KC; ++kc) {
+        if (kc >= kcn) break;
+        const uint32_t* src = gcur + ((w * MF_BLK + cb) * 2 + cc) * MF_DS + kc * 64;
+        uint32_t tr[4][4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const u32x4 v = *(const u32x4*)(src + mf_kbase(kq, q4));
+          byte_transpose4(bal_digits(v[0]), bal_digits(v[1]), bal_digits(v[2]), bal_digits(v[3]), tr[q4]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bd[kc][j] = mf_v4i{(int)tr[0][j], (int)tr[1][j], (int)tr[2][j], (int)tr[3][j]};
+      }
+      // row tile R's products go to the matrix cores before tile R - 1 is recombined on the VALU, so the
+      // two overlap (two accumulator sets)
+      auto products = [&](int R, mf_v4i (&acc)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = mf_v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < MF_KC; ++kc) {
+          if (kc >= kcn) break;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ad[kc][R], Bd[kc][j], acc[j], 0, 0, 0);
+        }
+      };
+      auto recombine = [&](int R, const mf_v4i (&acc)[4]) {
+        // acc[j][i] = C_ij of (probe 2R + (cpc >> 1), c = cpc & 1, block cb, c' = cc)
+        const int64_t T0 = acc[0][0], T1 = (int64_t)acc[0][1] + acc[1][0];
+        const int64_t T2 = (int64_t)acc[0][2] + acc[1][1] + acc[2][0];
+        const int64_t T3 = (int64_t)acc[0][3] + acc[1][2] + acc[2][1] + acc[3][0];
+        const int32_t T4 = acc[1][3] + acc[2][2] + acc[3][1], T5 = acc[2][3] + acc[3][2], T6 = acc[3][3];
+        const int64_t S = T0 + T1 * 256 + T2 * 65536 + T3 * 16777216 + (int64_t)T4 * w4 + (int64_t)T5 * w5 +
+                          (int64_t)T6 * w6;
+        const uint32_t X = red_p((uint64_t)(S + (int64_t)off), p, mu);
+        const uint32_t Xp = (uint32_t)__shfl_xor((int)X, 17);          // (c, c') swapped
+        const uint32_t c = cpc & 1;
+        if (c == 0 || cc == 1) {                                       // (0,0) A0, (0,1) A1, (1,1) A2
+          const uint32_t comp = c + cc;
+          const uint32_t v = (c == 0 && cc == 1) ? add_p(X, Xp, p) : X;
+          ocur[(((2 * R + (cpc >> 1)) * MF_BLK + cb) * 3 + comp) * MF_SLOTS + w] = v;
+        }
+      };
+      mf_v4i accA[4], accB[4];
+      products(0, accA);
+#pragma unroll
+      for (int R = 0; R < 8; R += 2) {
+        if (R + 1 < 8) products(R + 1, accB);
+        recombine(R, accA);
+        if (R + 2 < 8) products(R + 2, accA);
+        recombine(R + 1, accB);
+      }
+      if (bg + 1 < nbg) stage(stg + (cur ^ 1) * GAL_WORDS);           // the next group, loaded meanwhile
+      __syncthreads();
+      if (bg + 2 < nbg) fetch(bg + 2);
+      // rows (probe, block, comp) of MF_SLOTS words
+#pragma unroll
+      for (uint32_t it = 0; it < (OUT_WORDS / 4 + WGL - 1) / WGL; ++it) {
+        const uint32_t e = tid + it * WGL;
+        const uint32_t half = e % (MF_SLOTS / 4), row = e / (MF_SLOTS / 4);
+        const uint32_t j = row / (MF_BLK * 3), b = (row / 3) % MF_BLK, comp = row % 3;
+        if (e >= OUT_WORDS / 4 || (int32_t)j >= G.nprobe || b0 + b >= G.blk_hi) continue;
+        const u32x4 v = *(const u32x4*)(ocur + row * MF_SLOTS + 4 * half);
+        *(u32x4*)(G.acc + (size_t)j * G.acc_stride + (((size_t)(b0 + b - G.blk_lo) * 3 + comp) * K + r) * n + slot0 +
+                  4 * half) = v;
+      }
+    }
+  }
+}
+
 template <int KQ, int KP, int FW>
 __global__ void __launch_bounds__(WG)
 k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_lo, ScorePtrs SP,
@@ -1428,6 +1682,16 @@ hipError_t launch_mac_intt(const DevTabs& T, uint32_t n, uint32_t K, const uint3
 }
 
 hipError_t launch_mac_multi(const DevTabs& T, const MacBatchArgs& A, uint32_t grid, hipStream_t s, int variant) {
+  if (variant == MB_MFMA) {
+    // the probes' digits stay in registers: d <= MF_DMAX (else the first schedule)
+    bool fits = true;
+    for (int g = 0; g < A.ngroups; ++g) fits &= A.g[g].d >= 1 && A.g[g].d <= MF_DMAX;
+    if (fits) {
+      hipLaunchKernelGGL(k_mac_mfma, dim3(grid), dim3(64 * MF_SLOTS), 0, s, T, A);
+      return hipGetLastError();
+    }
+    variant = 0;
+  }
   switch (variant) {
     case 1: hipLaunchKernelGGL((k_mac_multi<2, 4, 2>), dim3(grid), dim3(64 * MB_PROBES / 2), 0, s, T, A); break;
     case 2: hipLaunchKernelGGL((k_mac_multi<2, 8, 2>), dim3(grid), dim3(64 * MB_PROBES / 2), 0, s, T, A); break;

@@ -107,7 +107,7 @@ def test_c3_two_probe_batch_bit_exact(c3, fuse):
     ctx, op = c3["ctx"], c3["op"]
     try:
         ctx.set_option("relin_fuse_min_wgs", fuse)
-        for v in range(4):                                  # every multi-probe schedule
+        for v in range(5):                                  # every multi-probe schedule
             ctx.set_option("mb_variant", v)
             for ws in (None, ctx.batch_workspace([M_ITEMS] * 2, blocks_per_round=1)):
                 outs = ctx.search_batch([c3["gal"]] * 2, [M_ITEMS] * 2, [D] * 2, [c3["pr1"], c3["pr2"]],
@@ -137,7 +137,7 @@ def test_c3_wide_batch_equals_single(c3):
     prs = [ctx.encrypt_probe(torch.from_numpy(q).to(ctx.device), 500 + j) for j, q in enumerate(qs)]
     try:
         single = [ctx.search(gal, m, d, prs[j]).clone() for j in range(3)]
-        for fuse, v in ((1, 0), (1 << 30, 0), (1 << 30, 1), (1 << 30, 2), (1 << 30, 3)):
+        for fuse, v in ((1, 0), (1 << 30, 0), (1 << 30, 1), (1 << 30, 2), (1 << 30, 3), (1 << 30, 4), (1, 4)):
             ctx.set_option("relin_fuse_min_wgs", fuse)
             ctx.set_option("mb_variant", v)
             outs = ctx.search_batch([gal] * 3, [m] * 3, [d] * 3, prs)

@@ -371,14 +371,14 @@ def batch_setup(case_r36):
 def test_batch_multi_probe_equals_single(batch_setup, case_r36):
     """Grouped requests (16 + 4 on one gallery, 3 on another, 16 + 1 on a
     third) in one submission give the same score ciphertexts as one
-    hers_search per request, under every multi-probe schedule and a smaller
-    group size; a request of each group equals the oracle's score
-    ciphertext."""
+    hers_search per request, under every multi-probe schedule (the matrix-core
+    one included) and a smaller group size; a request of each group equals
+    the oracle's score ciphertext."""
     ctx, reqs = batch_setup
     gals, ms, ds, prs = [r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
     single = [_single_scores(ctx, g, m, d, pr) for g, m, d, pr, P, qv in reqs]
     try:
-        for v, grp in ((0, 16), (1, 16), (2, 16), (3, 16), (1, 5)):
+        for v, grp in ((0, 16), (1, 16), (2, 16), (3, 16), (1, 5), (4, 16), (4, 5)):
             ctx.set_option("mb_variant", v)
             ctx.set_option("mb_group", grp)
             for ws in (ctx.batch_workspace(ms), ctx.batch_workspace(ms, blocks_per_round=1)):
@@ -409,7 +409,7 @@ def test_batch_multi_probe_equals_single(batch_setup, case_r36):
     # the batched autotuner keeps a schedule that gives the same bits
     chosen = ctx.autotune_batch(gals, ms, ds, prs, [ctx.new_scores(m) for m in ms], ctx.batch_workspace(ms), reps=1)
     try:
-        assert 0 <= chosen <= 3 and ctx.get_option("mb_variant") == chosen
+        assert 0 <= chosen <= 4 and ctx.get_option("mb_variant") == chosen
         outs = ctx.search_batch(gals, ms, ds, prs)
         assert all(torch.equal(outs[j], single[j]) for j in range(len(reqs)))
     finally:
