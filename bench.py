@@ -519,6 +519,8 @@ def main():
     ap.add_argument("--no-literal", action="store_true", help="skip timing the paper-literal schedule")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default schedules (profiling runs: no tuning launches in the trace)")
+    ap.add_argument("--mb-variant", type=int, default=-1,
+                    help="batched workloads: use this multi-probe schedule instead of the autotuner's choice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -605,6 +607,7 @@ def main():
         ctx.encrypt_probe(qhost[j], PROBE_SEED + j, probe=probes[j], workspace=ws_p)
     ctx.load_secret_key(sk)          # the client keeps its key's transform
     plan = None
+    rounds = None
     if npr == 1:
         ws_s = ctx.workspace(hers_gpu.OP_SEARCH, min(m, 8192 * n), d)
         if args.no_autotune:
@@ -627,12 +630,16 @@ def main():
         mac_variant = None
         gal_of = lambda lo, hi: gallery[lo * blk_words:hi * blk_words]
         lo0, hi0 = slices[0]
-        if args.no_autotune:
+        if args.mb_variant >= 0:
+            ctx.set_option("mb_variant", args.mb_variant)
+            mb_variant = args.mb_variant
+        elif args.no_autotune:
             mb_variant = ctx.get_option("mb_variant")
         else:
             mb_variant = ctx.autotune_batch([gal_of(lo0, hi0)] * npr, [m_of(lo0, hi0)] * npr, [d] * npr, probes,
                                             scores, ws_s, reps=2)
-        log("%s multi-probe schedule: %d" % ("default" if args.no_autotune else "autotuned", mb_variant))
+        log("%s multi-probe schedule: %d" % ("given" if args.mb_variant >= 0 else "default" if args.no_autotune
+                                              else "autotuned", mb_variant))
         plans = [ctx.plan([gal_of(lo, hi)] * npr, [m_of(lo, hi)] * npr, [d] * npr, probes, scores, ws_s)
                  for lo, hi in slices]
         plan = plans[0]
@@ -828,7 +835,8 @@ def main():
                    "mac_wgs_per_cu": ctx.get_option("mac_wgs_per_cu") or 8,
                    "relin_fuse_min_wgs": ctx.get_option("relin_fuse_min_wgs"),
                    "multi_probe_schedule": ctx.get_option("mb_variant") if npr > 1 else None,
-                   "hip_graph": plan is not None, "gallery_ranges_per_step": len(slices)},
+                   "hip_graph": plan is not None, "gallery_ranges_per_step": len(slices),
+                   "blocks_per_round": rounds},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "per": "step of %d probe(s)" % npr},
         "stage_ms_per_step": {k: v[0] / kb for k, v in stages.items() if v[1]},
