@@ -1208,72 +1208,89 @@ template <bool QF>
 __global__ void __launch_bounds__(WG)
 k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
             const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
-  // Relinearization (or key switching), second half: for block
-  // blk_lo + blockIdx.x / 2, component comp = blockIdx.x mod 2 and residue
-  // sigma = blockIdx.y of request z, c_comp += INTT(sum_g NTT(y_g) *
-  // key_g[comp]) mod q_sigma, key [L][2][k][n] in NTT form (the evaluation
-  // keys, or a rotation key).  The two components of a (block, residue) are
-  // neighbouring workgroups, so the second reads the digits from cache.
+  // Relinearization (or key switching), second half, for residue sigma =
+  // blockIdx.y of request z: c_comp += INTT(sum_g NTT(y_g) * key_g[comp])
+  // mod q_sigma, key [L][2][k][n] in NTT form (the evaluation keys, or a
+  // rotation key).  QF: one workgroup per block does both components -- one
+  // pass over the digits (each read once) accumulates both key products, in
+  // double precision, into two LDS buffers, then the two inverse transforms.
+  // Otherwise one workgroup per (block blockIdx.x / 2, component
+  // blockIdx.x mod 2), neighbours, so the second reads the digits from cache.
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, L = C.L, tid = threadIdx.x;
-  const int64_t bl = blockIdx.x >> 1, b = blk_lo + bl;
-  const uint32_t sg = blockIdx.y, comp = blockIdx.x & 1;
+  const uint32_t sg = blockIdx.y;
   const uint64_t q = C.q[sg];
-  const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
-  uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
   if constexpr (QF) {
+    const int64_t bl = blockIdx.x, b = blk_lo + bl;
+    const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
+    uint64_t* dst0 = SP.p[blockIdx.z] + (((size_t)b * 2 + 0) * k + sg) * n;
+    uint64_t* dst1 = SP.p[blockIdx.z] + (((size_t)b * 2 + 1) * k + sg) * n;
     // RA coefficients per lane at a time, so each digit's loads for all of
     // them are in flight together (the digit loop has a runtime bound); rings
     // smaller than RA WG coefficients take one coefficient at a time
     constexpr uint32_t RA = 4;
     const ModQF mq{T.qf[sg], T.qf[HC_MAXQ + sg]};
-    double* f = reinterpret_cast<double*>(lds64);
+    double* f0 = reinterpret_cast<double*>(lds64);
+    double* f1 = f0 + padded_len(n);
     const bool batched = n % (RA * WG) == 0;
     const uint32_t ra = batched ? RA : 1;
     for (uint32_t j0 = tid; j0 < n; j0 += ra * WG) {
-      double acc[RA];
+      double a0[RA], a1[RA];
 #pragma unroll
-      for (uint32_t u = 0; u < RA; ++u) acc[u] = 0.0;
+      for (uint32_t u = 0; u < RA; ++u) { a0[u] = 0.0; a1[u] = 0.0; }
       for (uint32_t g = 0; g < L; ++g) {
         const uint64_t* dg = digits + ((size_t)g * k + sg) * n + j0;
-        const uint64_t* kg = key + (((size_t)g * 2 + comp) * k + sg) * n + j0;
-        if (batched) {
-          uint64_t dv[RA], kv[RA];
+        const uint64_t* k0 = key + (((size_t)g * 2 + 0) * k + sg) * n + j0;
+        const uint64_t* k1 = key + (((size_t)g * 2 + 1) * k + sg) * n + j0;
+        uint64_t dv[RA], kv0[RA], kv1[RA];
 #pragma unroll
-          for (uint32_t u = 0; u < RA; ++u) {
-            dv[u] = dg[u * WG];
-            kv[u] = kg[u * WG];
-          }
+        for (uint32_t u = 0; u < RA; ++u) {
+          if (u >= ra) break;
+          dv[u] = dg[u * WG];
+          kv0[u] = k0[u * WG];
+          kv1[u] = k1[u * WG];
+        }
 #pragma unroll
-          for (uint32_t u = 0; u < RA; ++u) {
-            const double s = acc[u] + mq.mul(u64_to_f(dv[u]), u64_to_f(kv[u]), 0.0);
-            acc[u] = s >= mq.q ? s - mq.q : s;
-          }
-        } else {
-          const double s = acc[0] + mq.mul(u64_to_f(dg[0]), u64_to_f(kg[0]), 0.0);
-          acc[0] = s >= mq.q ? s - mq.q : s;
+        for (uint32_t u = 0; u < RA; ++u) {
+          if (u >= ra) break;
+          const double dd = u64_to_f(dv[u]);
+          const double s0 = a0[u] + mq.mul(dd, u64_to_f(kv0[u]), 0.0);
+          const double s1 = a1[u] + mq.mul(dd, u64_to_f(kv1[u]), 0.0);
+          a0[u] = s0 >= mq.q ? s0 - mq.q : s0;
+          a1[u] = s1 >= mq.q ? s1 - mq.q : s1;
         }
       }
-      for (uint32_t u = 0; u < ra; ++u) f[PADX(j0 + u * WG)] = acc[u];
+      for (uint32_t u = 0; u < ra; ++u) {
+        f0[PADX(j0 + u * WG)] = a0[u];
+        f1[PADX(j0 + u * WG)] = a1[u];
+      }
     }
     __syncthreads();
     const double* itw = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
-    ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, WG, T.ntt_r);
-    if (batched) {
-      for (uint32_t j0 = tid; j0 < n; j0 += RA * WG) {
-        uint64_t dv[RA];
+    for (int comp = 0; comp < 2; ++comp) {
+      double* f = comp ? f1 : f0;
+      uint64_t* dst = comp ? dst1 : dst0;
+      ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, WG, T.ntt_r);
+      if (batched) {
+        for (uint32_t j0 = tid; j0 < n; j0 += RA * WG) {
+          uint64_t dv[RA];
 #pragma unroll
-        for (uint32_t u = 0; u < RA; ++u) dv[u] = dst[j0 + u * WG];
+          for (uint32_t u = 0; u < RA; ++u) dv[u] = dst[j0 + u * WG];
 #pragma unroll
-        for (uint32_t u = 0; u < RA; ++u) dst[j0 + u * WG] = add_q(dv[u], f_to_u64(f[PADX(j0 + u * WG)]), q);
+          for (uint32_t u = 0; u < RA; ++u) dst[j0 + u * WG] = add_q(dv[u], f_to_u64(f[PADX(j0 + u * WG)]), q);
+        }
+      } else {
+        for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
       }
-    } else {
-      for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
     }
     return;
   }
+  const int64_t bl = blockIdx.x >> 1, b = blk_lo + bl;
+  const uint32_t comp = blockIdx.x & 1;
+  const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
+  uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
   for (uint32_t j = tid; j < n; j += WG) {
     uint64_t acc = 0;
     for (uint32_t g = 0; g < L; ++g) {
@@ -1742,7 +1759,8 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
   // few workgroups: the digit transforms (L k per block), then key products
   // and inverse transforms (2 k per block), as separate launches with more
   // workgroups each
-  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)(2 * nblk), k, nreq);
+  // (the double-precision key products take both components of a block in one workgroup)
+  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)((T.qf_ok ? 1 : 2) * nblk), k, nreq);
   if (T.qf_ok)
     hipLaunchKernelGGL(k_ntt_q<true>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
   else
@@ -1750,7 +1768,7 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (T.qf_ok)
-    hipLaunchKernelGGL(k_relin_acc<true>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
+    hipLaunchKernelGGL(k_relin_acc<true>, g2, dim3(WG), 2 * lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
                        key_sh);
   else
     hipLaunchKernelGGL(k_relin_acc<false>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
