@@ -199,22 +199,24 @@ def search_traffic(ctx, M, d, mac_variant, search_ms):
       multiply-accumulate: gallery K d 2 n 4 + accumulators 3 K n 4 per block, probe once;
       inverse NTT of the accumulators (not with schedule 12, which writes them
       transformed): 3 K n 4 read and written;
-      rescale: 3 K n 4 read, c0 and c1 2 k n 8 and the digits L k n 8 written;
-      relinearization: two-kernel form -- digits transformed in place (L k n 8
-      read and written), then read once more, c0 and c1 read and written
-      (2 k n 8 each way); fused form -- digits read once, c0 and c1 read and
-      written; the evaluation keys (and their Shoup companions) once per search."""
+      rescale: 3 K n 4 read, c0 and c1 2 k n 8 and the digits L n 8 (each once,
+      as an integer) written;
+      relinearization: two-kernel form -- digits read (L n 8) and written
+      transformed for every residue (L k n 8), then read once more (both
+      output polynomials together), c0 and c1 read and written (2 k n 8 each
+      way); fused form -- digits read once (L n 8), c0 and c1 read and written;
+      the evaluation keys once per search."""
     import torch
     n, K, k, L = ctx.n, ctx.K, ctx.k, ctx.L
     mac = M * (K * d * 2 * n * 4 + 3 * K * n * 4) + K * d * 2 * n * 4
     intt = 0 if mac_variant == 12 else M * 2 * 3 * K * n * 4
-    rescale = M * (3 * K * n * 4 + 2 * k * n * 8 + L * k * n * 8)
+    rescale = M * (3 * K * n * 4 + 2 * k * n * 8 + L * n * 8)
     chunks = max(1, ctx.get_option("overlap_chunks"))
     opt = ctx.get_option("relin_fuse_min_wgs")
     cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
     threshold = opt if opt else (8 * cus if n >= 8192 else float("inf"))
     fused = -(-M // chunks) * k >= threshold
-    relin = M * ((0 if fused else 2 * L * k * n * 8) + L * k * n * 8 + 2 * 2 * k * n * 8) + 2 * L * 2 * k * n * 8
+    relin = M * (L * n * 8 + (0 if fused else 2 * L * k * n * 8) + 2 * 2 * k * n * 8) + L * 2 * k * n * 8
     total = mac + intt + rescale + relin
     achieved = total / (search_ms * 1e-3) / 1e9
     return {"bytes": total, "by_stage": {"mac": mac, "intt_acc": intt, "rescale": rescale, "relin": relin},

@@ -27,7 +27,8 @@ typedef unsigned __int128 u128;
 // Per-context constants, resident in device memory and read with uniform
 // indices (scalar loads).  "sh" = Shoup companion floor(w 2^W / m), W = 32 or 64.
 struct HersConsts {
-  uint32_t n, logn, k, K, L, w_bits, t, pad0;
+  uint32_t n, logn, k, K, L, w_bits, t;
+  uint32_t dig_one_sub;                // 1: every gadget digit is below 2 q_i for every i (one subtraction reduces it)
 
   // ---- ciphertext primes q_i
   uint64_t q[HC_MAXQ];

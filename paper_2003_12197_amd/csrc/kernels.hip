@@ -1158,49 +1158,53 @@ k_rescale(DevTabs T, const uint32_t* __restrict__ Xb, int64_t nblk, int64_t blk_
     return;
   }
   // gadget digits come prime-major (all digits of q_rho, then of q_rho+1), so
-  // out[rho] is indexed by the unrolled loop counter
+  // out[rho] is indexed by the unrolled loop counter.  Each digit is written
+  // once, as the integer it is (below q_rho, or 2^w_bits), in the slot of
+  // residue 0 of its [L][k][n] block: the relinearization reduces it mod
+  // every q_sigma as it reads it.
   uint32_t g = 0;
 #pragma unroll
   for (uint32_t rho = 0; rho < (KQ ? KQ : k); ++rho) {
     const uint64_t y = shoup_q(out[rho], C.q_hatinv[rho], C.q_hatinv_sh[rho], C.q[rho]);
     if (!C.w_bits) {                                    // one digit per prime: digit rho is y itself
-#pragma unroll
-      for (uint32_t s = 0; s < (KQ ? KQ : k); ++s)
-        digits[(((size_t)bl * L + rho) * k + s) * n + c] = y >= C.q[s] ? red_q(y, C.q[s], C.q_mu64[s]) : y;
+      digits[((size_t)bl * L + rho) * k * n + c] = y;
       continue;
     }
-    for (; g < L && C.g_rho[g] == rho; ++g) {
-      const uint64_t dg = (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1);
-      for (uint32_t s = 0; s < k; ++s)
-        digits[(((size_t)bl * L + g) * k + s) * n + c] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
-    }
+    for (; g < L && C.g_rho[g] == rho; ++g)
+      digits[((size_t)bl * L + g) * k * n + c] = (y >> C.g_shift[g]) & ((1ULL << C.w_bits) - 1);
   }
 }
 
 template <bool QF>
 __global__ void __launch_bounds__(WG)
-k_ntt_q(DevTabs T, uint64_t* __restrict__ polys, uint64_t set_stride) {
-  // In-place forward negacyclic NTT mod q_sigma of polynomial blockIdx.x of
-  // set blockIdx.y, sigma = blockIdx.x mod k (layouts [..][k][n]); QF: in
-  // double precision with balanced butterflies (ModQB), same residues.
+k_ntt_q(DevTabs T, uint64_t* __restrict__ digits, uint64_t set_stride) {
+  // Relinearization digits, first half: digit polynomial blockIdx.x (a
+  // block's digit g) of set blockIdx.y is an integer polynomial stored once,
+  // in the slot of residue 0 of its [k][n] row ([..][L][k][n]).  For every
+  // q_sigma, last sigma first, read it (from cache after the first time),
+  // reduce it, transform it forward (negacyclic NTT) and write residue sigma;
+  // residue 0 overwrites the integer polynomial only after its last read.
+  // QF: in double precision with balanced butterflies (ModQB), same residues.
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
-  const uint32_t n = C.n, tid = threadIdx.x;
-  const uint32_t sg = blockIdx.x % C.k;
-  uint64_t* a = polys + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * n;
-  if constexpr (QF) {
-    double* f = reinterpret_cast<double*>(lds64);
-    load_padded(f, a, n, tid, WG, [](uint64_t v) { return u64_to_f(v); });
-    __syncthreads();
-    const double* tw = T.qtw_f + (size_t)sg * n;
-    ntt_forward_b(f, tw, ModQB{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG) a[j] = f_to_u64(f[PADX(j)]);
-  } else {
-    load_padded(lds64, a, n, tid, WG, [](uint64_t v) { return v; });
-    __syncthreads();
-    ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{C.q[sg]}, n, C.logn, tid, WG,
-                  T.ntt_r);
-    for (uint32_t j = tid; j < n; j += WG) a[j] = lds64[PADX(j)];
+  const uint32_t n = C.n, k = C.k, tid = threadIdx.x;
+  uint64_t* a = digits + (size_t)blockIdx.y * set_stride + (size_t)blockIdx.x * k * n;
+  const bool one_sub = C.dig_one_sub != 0;
+  for (int32_t sg = (int32_t)k - 1; sg >= 0; --sg) {
+    const uint64_t q = C.q[sg], mu = C.q_mu64[sg];
+    __syncthreads();                                    // the previous residue's transform written back
+    if constexpr (QF) {
+      double* f = reinterpret_cast<double*>(lds64);
+      load_padded(f, a, n, tid, WG, [&](uint64_t v) { return u64_to_f(one_sub ? (v >= q ? v - q : v) : red_q(v, q, mu)); });
+      __syncthreads();
+      ntt_forward_b(f, T.qtw_f + (size_t)sg * n, ModQB{T.qf[sg], T.qf[HC_MAXQ + sg]}, n, C.logn, tid, WG, T.ntt_r);
+      for (uint32_t j = tid; j < n; j += WG) a[(size_t)sg * n + j] = f_to_u64(f[PADX(j)]);
+    } else {
+      load_padded(lds64, a, n, tid, WG, [&](uint64_t v) { return one_sub ? (v >= q ? v - q : v) : red_q(v, q, mu); });
+      __syncthreads();
+      ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, ModQ{q}, n, C.logn, tid, WG, T.ntt_r);
+      for (uint32_t j = tid; j < n; j += WG) a[(size_t)sg * n + j] = lds64[PADX(j)];
+    }
   }
 }
 
@@ -1359,6 +1363,10 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
     }
   };
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
+  // a digit is stored once, as an integer (slot of residue 0): reduced mod q_sigma here
+  const uint64_t qmu = C.q_mu64[sg];
+  const bool one_sub = C.dig_one_sub != 0;
+  auto red_dig = [&](uint64_t v) -> uint64_t { return one_sub ? (v >= q ? v - q : v) : red_q(v, q, qmu); };
   E acc0[RL_PER], acc1[RL_PER];
 #pragma unroll RL_UNROLL
   for (uint32_t e = 0; e < RL_PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
@@ -1367,24 +1375,24 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
   uint64_t pre[QF ? RL_PER : 1];
   if constexpr (QF) {
 #pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? digits[(size_t)sg * n + tid + e * nthr] : 0;
+    for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? digits[tid + e * nthr] : 0;
   }
   for (uint32_t g = 0; g < L; ++g) {
     __syncthreads();                                    // previous digit's products read
     if constexpr (QF) {
 #pragma unroll RL_UNROLL
-      for (uint32_t e = 0; e < RL_PER; ++e)
-        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(pre[e]);
+      for (uint32_t e = 0; e < RL_PER; ++e)                // reduced here, not at the load, which stays in flight
+        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(red_dig(pre[e]));
     } else {
-      const uint64_t* dg = digits + ((size_t)g * k + sg) * n;
+      const uint64_t* dg = digits + (size_t)g * k * n;
 #pragma unroll RL_UNROLL
       for (uint32_t e = 0; e < RL_PER; ++e)
-        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(dg[tid + e * nthr]);
+        if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(red_dig(dg[tid + e * nthr]));
     }
     __syncthreads();
     if constexpr (QF) {
       if (g + 1 < L) {
-        const uint64_t* dn = digits + ((size_t)(g + 1) * k + sg) * n;
+        const uint64_t* dn = digits + (size_t)(g + 1) * k * n;
 #pragma unroll RL_UNROLL
         for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? dn[tid + e * nthr] : 0;
       }
@@ -1756,11 +1764,11 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
                          digits, blk_lo, SP, dig_stride, key, key_sh);
     return hipGetLastError();
   }
-  // few workgroups: the digit transforms (L k per block), then key products
+  // few workgroups: the digit transforms (L per block, each for all k residues), then key products
   // and inverse transforms (2 k per block), as separate launches with more
   // workgroups each
   // (the double-precision key products take both components of a block in one workgroup)
-  const dim3 g1((uint32_t)(nblk * L * k), nreq), g2((uint32_t)((T.qf_ok ? 1 : 2) * nblk), k, nreq);
+  const dim3 g1((uint32_t)(nblk * L), nreq), g2((uint32_t)((T.qf_ok ? 1 : 2) * nblk), k, nreq);
   if (T.qf_ok)
     hipLaunchKernelGGL(k_ntt_q<true>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
   else

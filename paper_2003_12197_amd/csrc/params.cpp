@@ -10,6 +10,7 @@
 // representatives: |X| <= 2 d_max n ((q-1)/2)^2.
 #include "params.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -276,6 +277,14 @@ std::string precompute(const hers_params& prm, HostTables* T) {
   uint32_t logn = 0;
   while ((1u << logn) < n) ++logn;
   C.n = n; C.logn = logn; C.k = k; C.K = K; C.L = info.num_digits; C.w_bits = prm.w_bits;
+  {
+    // a digit is below 2^w_bits, or (one digit per prime) below its prime: one conditional
+    // subtraction reduces it mod q_i when that bound is below 2 q_i for every i
+    uint64_t qmin = info.q[0], qmax = info.q[0];
+    for (uint32_t i = 1; i < k; ++i) { qmin = std::min<uint64_t>(qmin, info.q[i]); qmax = std::max<uint64_t>(qmax, info.q[i]); }
+    const uint64_t dmax = prm.w_bits ? (prm.w_bits >= 63 ? ~0ull : (1ull << prm.w_bits)) : qmax;
+    C.dig_one_sub = dmax <= 2 * qmin ? 1u : 0u;
+  }
   const uint64_t t = info.t;
   C.t = (uint32_t)t;
   const uint64_t two_n = 2ULL * n;

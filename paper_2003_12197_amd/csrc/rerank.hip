@@ -133,7 +133,7 @@ k_rot_digits(DevTabs T, const uint64_t* __restrict__ in, uint64_t* __restrict__ 
              uint32_t nct, uint32_t ginv) {
   // First half of rotate-and-add for ciphertexts [nct][2][k][n]: out =
   // (c0 + tau(c0), c1) and the gadget digits of tau(c1) ([nct][L][k][n],
-  // reduced mod every q_sigma), tau: x^i -> +-x^(i g mod 2n).  One workgroup
+  // each the integer it is, in the slot of residue 0), tau: x^i -> +-x^(i g mod 2n).  One workgroup
   // per (ciphertext blockIdx.x, residue r = blockIdx.y): residue r of c0 and
   // c1 is read once, coalesced, into LDS; the digits of q_r need only that
   // residue of tau(c1).  For destination coefficient dst, with ginv = g^-1
@@ -167,9 +167,8 @@ k_rot_digits(DevTabs T, const uint64_t* __restrict__ in, uint64_t* __restrict__ 
     const uint64_t y = shoup_q(v1, C.q_hatinv[r], C.q_hatinv_sh[r], q);
     for (uint32_t gi = 0; gi < L; ++gi) {
       if (C.g_rho[gi] != r) continue;
-      const uint64_t dg = C.w_bits ? (y >> C.g_shift[gi]) & ((1ULL << C.w_bits) - 1) : y;
-      for (uint32_t s = 0; s < k; ++s)
-        digits[((c * L + gi) * k + s) * n + dst] = dg >= C.q[s] ? red_q(dg, C.q[s], C.q_mu64[s]) : dg;
+      // stored once, as an integer, in the slot of residue 0: the key switch reduces it per q_sigma
+      digits[(c * L + gi) * k * n + dst] = C.w_bits ? (y >> C.g_shift[gi]) & ((1ULL << C.w_bits) - 1) : y;
     }
   }
 }

@@ -23,6 +23,8 @@ CONFIGS = {
     "r36": dict(n=2048, qbits=(36, 36, 36), t_bits=20, w_bits=0),
     # the batched configuration's q shape (five primes of 44 and 43 bits, t of 21 bits) at a small ring
     "c3s": dict(n=256, qbits=(44, 44, 44, 43, 43), t_bits=21, w_bits=0),
+    # primes of unequal size: a relinearization digit (below 2^44) needs a full reduction mod the 32-bit prime
+    "mx": dict(n=1024, qbits=(44, 44, 32), t_bits=20, w_bits=0),
 }
 
 
@@ -93,7 +95,13 @@ def case_c3s(gpu_lib):
     return Case(gpu_lib, "c3s", 6, 2 * 256 + 17)
 
 
-CASES = ["case_c1", "case_c1b", "case_r36", "case_c3s"]
+@pytest.fixture(scope="module")
+def case_mx(gpu_lib):
+    print("case mx: n=1024 q=44,44,32 d=8 m=1024+17 (ragged)", flush=True)
+    return Case(gpu_lib, "mx", 8, 1024 + 17)
+
+
+CASES = ["case_c1", "case_c1b", "case_r36", "case_c3s", "case_mx"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -138,7 +146,7 @@ def test_score_ciphertexts_bit_exact(name, request):
         assert np.array_equal(scores[b, 1], res(S[1], c.op.q_primes)), b
 
 
-@pytest.mark.parametrize("name", ["case_c1b", "case_r36", "case_c3s"])
+@pytest.mark.parametrize("name", ["case_c1b", "case_r36", "case_c3s", "case_mx"])
 def test_decrypted_scores_equal_plaintext_inner_products(name, request):
     c = request.getfixturevalue(name)
     out = c.ctx.decrypt_scores(c.sk, c.scores, c.m).cpu().numpy()
@@ -151,11 +159,12 @@ def test_decrypted_scores_equal_plaintext_inner_products(name, request):
     assert np.array_equal(tail, out[(c.M - 1) * c.op.n:])
 
 
-@pytest.mark.parametrize("name", ["case_c1b", "case_c3s"])
+@pytest.mark.parametrize("name", ["case_c1b", "case_c3s", "case_mx"])
 def test_relinearization_forms_give_same_bits(name, request):
     """Relinearization as one fused kernel per (block, prime) and as two
     kernels give the oracle-checked score ciphertexts, with integer (54-bit
-    primes) and double-precision (44-bit primes) modular arithmetic."""
+    primes) and double-precision (44-bit primes) modular arithmetic, and with
+    primes of unequal size (digits reduced in full)."""
     c = request.getfixturevalue(name)
     try:
         for fuse in (1, 1 << 30):
