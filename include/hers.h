@@ -440,7 +440,7 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not NULL --
  * whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16 (chunks of
  * at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule found first,
- * schedule 8, schedule 10 or schedule 12, and -- where the default
+ * schedule 8, schedule 9, schedule 10 or schedule 12, and -- where the default
  * relinearization is the two-kernel form -- over chunk counts 1, 4, 8, 16 x
  * "mac_wgs_per_cu" 0, 1 with the relinearization fused ("relin_fuse_min_wgs"
  * 1) and the best schedule (a combination other than no chunks, default

@@ -1221,17 +1221,19 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
   // (chunks of at least 16 blocks) x MAC workgroups per CU (default, 1, 2) x
   // the schedule chosen above, the default schedule 8 (the one timed alone
   // need not be the best beside the epilogue), schedule 10 (fewer registers,
-  // so epilogue waves fit beside it) and the fused schedule (n <= 4096)
+  // so epilogue waves fit beside it), the fused schedule (n <= 4096) and
+  // schedule 9 (two dimensions in flight per lane: more loads outstanding
+  // from the few MAC waves a small grid leaves)
   if (rc == HERS_OK && scores_dev) {
     float best_o = 0.f, plain_ms = 0.f;
     int best_nch = 1, best_w = 0, best_mv = best_v;
-    const int vs[4] = {best_v, 8, 10, nvar > MAC_FUSED_INTT ? MAC_FUSED_INTT : 10};
+    const int vs[5] = {best_v, 8, 10, nvar > MAC_FUSED_INTT ? MAC_FUSED_INTT : 10, 9};
     bool first = true;
     for (int nch = 1; nch <= 16 && rc == HERS_OK; nch *= 2) {
       if (nch > 1 && M / nch < 16) break;
       for (int w : {0, 1, 2}) {
         if (rc != HERS_OK) break;
-        for (int vi = 0; vi < 4 && rc == HERS_OK; ++vi) {
+        for (int vi = 0; vi < 5 && rc == HERS_OK; ++vi) {
           bool seen = false;
           for (int vj = 0; vj < vi; ++vj) seen |= vs[vj] == vs[vi];
           if (seen) continue;

@@ -882,9 +882,9 @@ k_mac_multi(DevTabs T, MacBatchArgs A) {
 // gallery; a lane's four results of a tile are its (probe, c, block, c')
 // entry for i = 0..3, so with the four j tiles it holds all 16 digit
 // products of one entry and recombines them in registers:
-// X = sum_k T_k (256^k mod p), T_k = sum_{i+j=k} C_ij (|X| below 2^56), one
-// reduction mod p.  The partner entry (c, c') = (1, 0) of (0, 1) is 17 lanes
-// away (A1 = X_01 + X_10).
+// X = sum_k T_k 256^k mod p, T_k = sum_{i+j=k} C_ij, paired exactly in int32
+// before the 64-bit sum, one reduction mod p.  The partner entry
+// (c, c') = (1, 0) of (0, 1) is 17 lanes away (A1 = X_01 + X_10).
 // A workgroup is MF_SLOTS waves, one slot each, over a tile of MF_SLOTS
 // neighbouring slots of one prime for one group of up to 16 probes; it keeps
 // the probes' digits of its slot in registers (d <= MF_DMAX) and sweeps the
@@ -968,10 +968,9 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
     const uint32_t p = C.p[r];
     const uint64_t mu = C.p_mu64[r];
     const uint32_t slot0 = tile * MF_SLOTS;
-    // 256^k mod p for k = 4, 5, 6 (256^k < p below)
-    const uint32_t w4 = (uint32_t)((1ull << 32) % p), w5 = (uint32_t)(((uint64_t)w4 << 8) % p),
-                   w6 = (uint32_t)(((uint64_t)w5 << 8) % p);
-    const uint64_t off = ((1ull << 58) / p + 1) * p;                   // a multiple of p above |X|
+    // 2^32 and 2^48 mod p (lower powers of two are below p)
+    const uint32_t w4 = (uint32_t)((1ull << 32) % p), w6 = (uint32_t)(((uint64_t)w4 << 16) % p);
+    const uint64_t off = ((1ull << 62) / p + 1) * p;                   // a multiple of p above |S|
     // ---- the probes' digits of this slot: per K step, rows (probe, c, dim) staged as [slot][probe][c][dim]
     mf_v4i Ad[MF_KC][8];
 #pragma unroll
@@ -1078,13 +1077,16 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
         }
       };
       auto recombine = [&](int R, const mf_v4i (&acc)[4]) {
-        // acc[j][i] = C_ij of (probe 2R + (cpc >> 1), c = cpc & 1, block cb, c' = cc)
-        const int64_t T0 = acc[0][0], T1 = (int64_t)acc[0][1] + acc[1][0];
-        const int64_t T2 = (int64_t)acc[0][2] + acc[1][1] + acc[2][0];
-        const int64_t T3 = (int64_t)acc[0][3] + acc[1][2] + acc[2][1] + acc[3][0];
-        const int32_t T4 = acc[1][3] + acc[2][2] + acc[3][1], T5 = acc[2][3] + acc[3][2], T6 = acc[3][3];
-        const int64_t S = T0 + T1 * 256 + T2 * 65536 + T3 * 16777216 + (int64_t)T4 * w4 + (int64_t)T5 * w5 +
-                          (int64_t)T6 * w6;
+        // acc[j][i] = C_ij of (probe 2R + (cpc >> 1), c = cpc & 1, block cb, c' = cc).  The digit-column
+        // sums T_k = sum_{i+j=k} C_ij pair up exactly in int32 (d <= 128: |C_ij| <= 2^21, 2^20 with a
+        // digit 3 in [0, 64], 2^19 for C_33): U0 = T0 + 2^8 T1, U1 = T2 + 2^8 T3, U2 = T4 + 2^8 T5,
+        // U3 = T6, each below 2^31 in magnitude, and X = U0 + 2^16 U1 + 2^32 U2 + 2^48 U3, whose terms
+        // with 2^32 and 2^48 taken mod p keep |S| below 2^62
+        const int32_t U0 = acc[0][0] + 256 * (acc[0][1] + acc[1][0]);
+        const int32_t U1 = (acc[0][2] + acc[1][1] + acc[2][0]) + 256 * (acc[0][3] + acc[1][2] + acc[2][1] + acc[3][0]);
+        const int32_t U2 = (acc[1][3] + acc[2][2] + acc[3][1]) + 256 * (acc[2][3] + acc[3][2]);
+        const int32_t U3 = acc[3][3];
+        const int64_t S = (int64_t)U0 + (int64_t)U1 * 65536 + (int64_t)U2 * w4 + (int64_t)U3 * w6;
         const uint32_t X = red_p((uint64_t)(S + (int64_t)off), p, mu);
         const uint32_t Xp = (uint32_t)__shfl_xor((int)X, 17);          // (c, c') swapped
         const uint32_t c = cpc & 1;
