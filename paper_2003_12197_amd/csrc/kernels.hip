@@ -1053,7 +1053,11 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
       mf_v4i Bd[MF_KC][4];
 #pragma unroll
       for (int kc = 0; kc < MF_KC; ++kc) {
-        if (kc >= kcn) break;
+        if (kc >= kcn) {                                               // zero digits beyond d (A is zero there too)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Bd[kc][j] = mf_v4i{0, 0, 0, 0};
+          continue;
+        }
         const uint32_t* src = gcur + ((w * MF_BLK + cb) * 2 + cc) * MF_DS + kc * 64;
         uint32_t tr[4][4];
 #pragma unroll
@@ -1069,12 +1073,12 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
       auto products = [&](int R, mf_v4i (&acc)[4]) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = mf_v4i{0, 0, 0, 0};
+        // every K step, also past d (zero operands there): no branch between the MFMAs, so the
+        // scheduler can interleave them with the VALU work
 #pragma unroll
-        for (int kc = 0; kc < MF_KC; ++kc) {
-          if (kc >= kcn) break;
+        for (int kc = 0; kc < MF_KC; ++kc)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ad[kc][R], Bd[kc][j], acc[j], 0, 0, 0);
-        }
       };
       auto recombine = [&](int R, const mf_v4i (&acc)[4]) {
         // acc[j][i] = C_ij of (probe 2R + (cpc >> 1), c = cpc & 1, block cb, c' = cc).  The digit-column
@@ -1098,12 +1102,23 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
       };
       mf_v4i accA[4], accB[4];
       products(0, accA);
+      // the scheduler interleaves each tile's 8 MFMAs with the previous tile's recombination (one MFMA,
+      // then up to 6 VALU instructions), so the matrix core and the VALU work side by side
+      auto interleave = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+        }
+      };
 #pragma unroll
       for (int R = 0; R < 8; R += 2) {
         if (R + 1 < 8) products(R + 1, accB);
         recombine(R, accA);
+        if (R + 1 < 8) interleave();
         if (R + 2 < 8) products(R + 2, accA);
         recombine(R + 1, accB);
+        if (R + 2 < 8) interleave();
       }
       if (bg + 1 < nbg) stage(stg + (cur ^ 1) * GAL_WORDS);           // the next group, loaded meanwhile
       __syncthreads();
