@@ -398,7 +398,7 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *   "ntt_radix_log2" stages per NTT pass, 1..4 (radix 2, 4, 8, 16; default 4):
  *                  each pass keeps 2^r elements per lane in registers and
  *                  costs one barrier.
- *   "overlap_chunks" hers_search in this many block chunks, 0..64 (0 =
+ *   "overlap_chunks" hers_search in this many block chunks, 0..256 (0 =
  *                  automatic: 8 from 4096 blocks up, else off; 1 = off):
  *                  each chunk's rescale and relinearization run on the
  *                  context's own stream beside the next chunk's
@@ -438,10 +438,10 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * search workspace holds; another schedule replaces the current one only if
  * 3% faster), then the search epilogue's transforms under NTT pass radix 4,
  * 8 and 16, then -- when scores_dev (score cts [M][2][k][n]) is not NULL --
- * whole hers_search calls over "overlap_chunks" 1, 2, 4, 8, 16 (chunks of
+ * whole hers_search calls over "overlap_chunks" 1, 2, 4, ..., 64 (chunks of
  * at least 16 blocks) x "mac_wgs_per_cu" 0, 1, 2 x the schedule found first,
  * schedule 8, schedule 9, schedule 10 or schedule 12, and -- where the default
- * relinearization is the two-kernel form -- over chunk counts 1, 4, 8, 16 x
+ * relinearization is the two-kernel form -- over chunk counts 1, 4, 16, 64 x
  * "mac_wgs_per_cu" 0, 1 with the relinearization fused ("relin_fuse_min_wgs"
  * 1) and the best schedule (a combination other than no chunks, default
  * grid, schedule found first must be 3% faster to be kept).  Keeps the fastest of each in the context and returns the schedule

@@ -413,7 +413,7 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     return HERS_OK;
   }
   if (!std::strcmp(key, "overlap_chunks")) {
-    if (value < 0 || value > 64) return fail(HERS_EINVAL, "overlap_chunks must be in [0, 64]");
+    if (value < 0 || value > 256) return fail(HERS_EINVAL, "overlap_chunks must be in [0, 256]");
     ctx->overlap_chunks = (int)value;
     return HERS_OK;
   }
@@ -1217,7 +1217,7 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
     ctx->T.ntt_r = best_rl;
   }
   if (rc == HERS_OK) ctx->mac_variant = best_v;
-  // overlapped search: whole searches over chunk counts 1, 2, 4, 8, 16
+  // overlapped search: whole searches over chunk counts 1, 2, 4, ..., 64
   // (chunks of at least 16 blocks) x MAC workgroups per CU (default, 1, 2) x
   // the schedule chosen above, the default schedule 8 (the one timed alone
   // need not be the best beside the epilogue), schedule 10 (fewer registers,
@@ -1229,7 +1229,7 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
     int best_nch = 1, best_w = 0, best_mv = best_v;
     const int vs[5] = {best_v, 8, 10, nvar > MAC_FUSED_INTT ? MAC_FUSED_INTT : 10, 9};
     bool first = true;
-    for (int nch = 1; nch <= 16 && rc == HERS_OK; nch *= 2) {
+    for (int nch = 1; nch <= 64 && rc == HERS_OK; nch *= 2) {
       if (nch > 1 && M / nch < 16) break;
       for (int w : {0, 1, 2}) {
         if (rc != HERS_OK) break;
@@ -1263,7 +1263,7 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
     const int64_t fuse0 = ctx->relin_fuse_min_wgs;
     int64_t best_f = fuse0;
     if (fuse_wgs(ctx) > 1) {
-      for (int nch : {1, 4, 8, 16}) {
+      for (int nch : {1, 4, 16, 64}) {
         if (rc != HERS_OK || (nch > 1 && M / nch < 16)) break;
         for (int w : {0, 1}) {
           ctx->overlap_chunks = nch;
