@@ -415,6 +415,11 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  transformed digits in memory; smaller ones as two kernels
  *                  with more workgroups.  0 = 8 per compute unit at
  *                  n >= 8192, never below; 1 = always.
+ *   "relin_lane_coeffs" coefficients per lane of the fused form, 8 (default:
+ *                  n / 8 lanes, four waves per SIMD) or 16 (n / 16 lanes,
+ *                  two waves per SIMD, the next digit's loads held in
+ *                  registers); 8 applies where every q_i < 2^45 (the
+ *                  double-precision form) and n <= 8192, else 16.
  *   "mb_variant"   multi-probe multiply-accumulate schedule of
  *                  hers_search_batch, 0..4; 0..3 as (probes per wave, dimensions
  *                  per staged chunk, blocks per item): 0 (1, 8, 4) in

@@ -288,6 +288,7 @@ int hers_ctx_create(const hers_params* params, int device, hers_ctx** out) {
   c->T.C = dC;
   c->T.C_rare = dC;
   c->T.ntt_r = 4;
+  c->T.rl_per = 8;
   c->T.nq = C.k;
   c->T.qf_ok = 1;
   for (uint32_t i = 0; i < C.k; ++i) c->T.qf_ok &= C.q[i] < (1ull << 45);
@@ -412,6 +413,11 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     ctx->T.ntt_r = (uint32_t)value;
     return HERS_OK;
   }
+  if (!std::strcmp(key, "relin_lane_coeffs")) {
+    if (value != 8 && value != 16) return fail(HERS_EINVAL, "relin_lane_coeffs must be 8 or 16");
+    ctx->T.rl_per = (uint32_t)value;
+    return HERS_OK;
+  }
   if (!std::strcmp(key, "overlap_chunks")) {
     if (value < 0 || value > 256) return fail(HERS_EINVAL, "overlap_chunks must be in [0, 256]");
     ctx->overlap_chunks = (int)value;
@@ -448,6 +454,10 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   }
   if (!std::strcmp(key, "ntt_radix_log2")) {
     *value = ctx->T.ntt_r;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "relin_lane_coeffs")) {
+    *value = ctx->T.rl_per;
     return HERS_OK;
   }
   if (!std::strcmp(key, "overlap_chunks")) {

@@ -14,6 +14,7 @@ struct DevTabs {
   uint64_t *pk_ntt, *pk_ntt_sh;                    // [2][k][n] NTT domain
   uint64_t *rlk_ntt, *rlk_ntt_sh;                  // [L][2][k][n] NTT domain
   uint32_t ntt_r;                                  // stages per NTT pass (1..4: radix 2..16)
+  uint32_t rl_per;                                 // coefficients per lane of the fused relinearization (8, 16)
   uint32_t nq;                                     // k, the number of q primes (host copy for launch choices)
   // double-precision arithmetic mod q (every q_i < 2^45): twiddles as
   // doubles [k][n], and qf[i] = q_i, qf[HC_MAXQ + i] = fl(1 / q_i),

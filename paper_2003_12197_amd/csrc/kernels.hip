@@ -1327,23 +1327,23 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
 }
 
 // Fused relinearization / key switching: one workgroup per (block, residue
-// sigma, request) of n / RL_PER lanes, each owning RL_PER coefficients.  For
+// sigma, request) of n / PER lanes, each owning PER coefficients.  For
 // every gadget digit the digit polynomial mod q_sigma is transformed in LDS
 // and multiplied into both key components, accumulated in registers; then
 // the two sums are transformed back and added to c0, c1.  Same result as the
 // digit transforms of k_ntt_q followed by k_relin_acc, without writing the
-// transformed digits to memory.
-#define RL_PER 16
-#define RL_UNROLL 16  // full unroll of the per-lane loops: the accumulators stay in registers
-
-template <bool QF>
-__global__ void __launch_bounds__(512)
+// transformed digits to memory.  PER 16: 512-lane workgroups (n = 8192),
+// two waves per SIMD with room for the next digit's loads in registers;
+// PER 8: 1024-lane workgroups, four waves per SIMD, no prefetch.
+template <bool QF, int PER>
+__global__ void __launch_bounds__(PER >= 16 ? 512 : 1024)
 k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
               const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
   // QF: the key products (ModQF) and the transforms (balanced, ModQB) in
   // double precision on elements of type E, converted at the memory edges
   using E = typename std::conditional<QF, double, uint64_t>::type;
   using M = typename std::conditional<QF, ModQF, ModQ>::type;
+  constexpr int RX = PER >= 16 ? 4 : 3;                 // radix-8 passes at most with 8 per lane (registers)
   extern __shared__ uint64_t lds64[];
   E* a = reinterpret_cast<E*>(lds64);
   const HersConsts& C = *T.C;
@@ -1384,45 +1384,46 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
   const uint64_t qmu = C.q_mu64[sg];
   const bool one_sub = C.dig_one_sub != 0;
   auto red_dig = [&](uint64_t v) -> uint64_t { return one_sub ? (v >= q ? v - q : v) : red_q(v, q, qmu); };
-  E acc0[RL_PER], acc1[RL_PER];
-#pragma unroll RL_UNROLL
-  for (uint32_t e = 0; e < RL_PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
-  // f64 form: digit g + 1 is loaded into registers while digit g is transformed
-  // (the integer form has no registers to spare for it)
-  uint64_t pre[QF ? RL_PER : 1];
-  if constexpr (QF) {
-#pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? digits[tid + e * nthr] : 0;
+  E acc0[PER], acc1[PER];
+#pragma unroll PER
+  for (uint32_t e = 0; e < PER; ++e) { acc0[e] = 0; acc1[e] = 0; }
+  // f64 form with PER 16: digit g + 1 is loaded into registers while digit g
+  // is transformed (the integer form has no registers to spare for it)
+  constexpr bool PF = QF && PER >= 16;
+  uint64_t pre[PF ? PER : 1];
+  if constexpr (PF) {
+#pragma unroll PER
+    for (uint32_t e = 0; e < PER; ++e) pre[e] = tid + e * nthr < n ? digits[tid + e * nthr] : 0;
   }
   for (uint32_t g = 0; g < L; ++g) {
     __syncthreads();                                    // previous digit's products read
-    if constexpr (QF) {
-#pragma unroll RL_UNROLL
-      for (uint32_t e = 0; e < RL_PER; ++e)                // reduced here, not at the load, which stays in flight
+    if constexpr (PF) {
+#pragma unroll PER
+      for (uint32_t e = 0; e < PER; ++e)                // reduced here, not at the load, which stays in flight
         if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(red_dig(pre[e]));
     } else {
       const uint64_t* dg = digits + (size_t)g * k * n;
-#pragma unroll RL_UNROLL
-      for (uint32_t e = 0; e < RL_PER; ++e)
+#pragma unroll PER
+      for (uint32_t e = 0; e < PER; ++e)
         if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = in(red_dig(dg[tid + e * nthr]));
     }
     __syncthreads();
-    if constexpr (QF) {
+    if constexpr (PF) {
       if (g + 1 < L) {
         const uint64_t* dn = digits + (size_t)(g + 1) * k * n;
-#pragma unroll RL_UNROLL
-        for (uint32_t e = 0; e < RL_PER; ++e) pre[e] = tid + e * nthr < n ? dn[tid + e * nthr] : 0;
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) pre[e] = tid + e * nthr < n ? dn[tid + e * nthr] : 0;
       }
     }
     if constexpr (QF)
-      ntt_forward_b(a, tw, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
+      ntt_forward_b<RX>(a, tw, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
     else
-      ntt_forward16(a, tw, twsh, mod, n, C.logn, tid, nthr, T.ntt_r);
+      ntt_forward16<RX>(a, tw, twsh, mod, n, C.logn, tid, nthr, T.ntt_r);
     const size_t k0 = (((size_t)g * 2 + 0) * k + sg) * n, k1 = (((size_t)g * 2 + 1) * k + sg) * n;
-#pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e) {
+#pragma unroll PER
+    for (uint32_t e = 0; e < PER; ++e) {
       const uint32_t j = tid + e * nthr;
-      if (j >= n) break;                                // never on the GPU: n / RL_PER lanes
+      if (j >= n) break;                                // never on the GPU: n / PER lanes
       const E D = a[PADX(j)];
       acc0[e] = mac(acc0[e], D, key[k0 + j], key_sh[k0 + j]);
       acc1[e] = mac(acc1[e], D, key[k1 + j], key_sh[k1 + j]);
@@ -1430,17 +1431,17 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
   }
   for (uint32_t comp = 0; comp < 2; ++comp) {
     __syncthreads();
-#pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e)
+#pragma unroll PER
+    for (uint32_t e = 0; e < PER; ++e)
       if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
     __syncthreads();
     if constexpr (QF)
-      ntt_inverse_b(a, itw, ninv, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
+      ntt_inverse_b<RX>(a, itw, ninv, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
     else
-      ntt_inverse16(a, itw, itwsh, ninv, ninv_sh, mod, n, C.logn, tid, nthr, T.ntt_r);
+      ntt_inverse16<RX>(a, itw, itwsh, ninv, ninv_sh, mod, n, C.logn, tid, nthr, T.ntt_r);
     uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
-#pragma unroll RL_UNROLL
-    for (uint32_t e = 0; e < RL_PER; ++e) {
+#pragma unroll PER
+    for (uint32_t e = 0; e < PER; ++e) {
       const uint32_t j = tid + e * nthr;
       if (j >= n) break;
       dst[j] = add_q(dst[j], out(a[PADX(j)]), q);
@@ -1772,13 +1773,19 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
     // many workgroups: one per (block, residue, request) does the digit
     // transforms, key products and both inverse transforms (no transformed
     // digits in memory)
-    const uint32_t lanes = n / RL_PER;                 // n >= 256: at least 16 lanes
-    if (T.qf_ok)
-      hipLaunchKernelGGL(k_relin_fused<true>, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T,
-                         digits, blk_lo, SP, dig_stride, key, key_sh);
-    else
-      hipLaunchKernelGGL(k_relin_fused<false>, dim3((uint32_t)nblk, k, nreq), dim3(lanes), lds_bytes(n, 1), s, T,
-                         digits, blk_lo, SP, dig_stride, key, key_sh);
+    const dim3 grid((uint32_t)nblk, k, nreq);
+    const size_t lds = lds_bytes(n, 1);
+    if (T.rl_per == 8 && T.qf_ok && n / 8 <= 1024) {   // n >= 128: at least 16 lanes (the integer form
+      hipLaunchKernelGGL((k_relin_fused<true, 8>), grid, dim3(n / 8), lds, s, T, digits, blk_lo, SP, dig_stride,
+                         key, key_sh);                 // spills with 8 per lane: it keeps 16)
+    } else {                                           // n >= 256: at least 16 lanes
+      if (T.qf_ok)
+        hipLaunchKernelGGL((k_relin_fused<true, 16>), grid, dim3(n / 16), lds, s, T, digits, blk_lo, SP, dig_stride,
+                           key, key_sh);
+      else
+        hipLaunchKernelGGL((k_relin_fused<false, 16>), grid, dim3(n / 16), lds, s, T, digits, blk_lo, SP, dig_stride,
+                           key, key_sh);
+    }
     return hipGetLastError();
   }
   // few workgroups: the digit transforms (L per block, each for all k residues), then key products

@@ -221,14 +221,16 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
 }
 
 // Forward transform in passes of rmax (<= 4) stages; input in [0, 4m), output in [0, m).
-template <class M, class T>
+// RMAX caps rmax at compile time (fewer registers for the passes).
+template <int RMAX = 4, class M, class T>
 HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn, uint32_t tid,
                       uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
   uint32_t s0 = 0;
   while (s0 < logn) {
     const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
     switch (r) {
-      case 4: ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
       case 3: ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
       case 2: ntt_fwd_pass<2>(a, tw, twsh, mod, n, s0, tid, nthr); break;
       default: ntt_fwd_pass<1>(a, tw, twsh, mod, n, s0, tid, nthr); break;
@@ -240,15 +242,16 @@ HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint3
 }
 
 // Inverse transform in passes of rmax (<= 4) stages, scaled by n^-1; input in [0, 2m),
-// output in [0, m).
-template <class M, class T>
+// output in [0, m).  RMAX as for ntt_forward16.
+template <int RMAX = 4, class M, class T>
 HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n, uint32_t logn,
                       uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
   uint32_t lh0 = 0;
   while (lh0 < logn) {
     const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
     switch (r) {
-      case 4: ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
       case 3: ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
       case 2: ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
       default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
@@ -376,13 +379,15 @@ HD void ntt_inv_pass_b(double* a, const double* itw, ModQB mod, uint32_t n, uint
 }
 
 // Forward transform of values in [0, q) (or of magnitude <= q); output in [0, q).
+template <int RMAX = 4>
 HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t logn, uint32_t tid,
                       uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
   uint32_t s0 = 0;
   while (s0 < logn) {
     const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
     switch (r) {
-      case 4: ntt_fwd_pass_b<4>(a, tw, mod, n, s0, tid, nthr); break;
+      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_b<4>(a, tw, mod, n, s0, tid, nthr); break;
       case 3: ntt_fwd_pass_b<3>(a, tw, mod, n, s0, tid, nthr); break;
       case 2: ntt_fwd_pass_b<2>(a, tw, mod, n, s0, tid, nthr); break;
       default: ntt_fwd_pass_b<1>(a, tw, mod, n, s0, tid, nthr); break;
@@ -395,13 +400,15 @@ HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32
 
 // Inverse transform scaled by n^-1 (ninv in [0, q)) of values of magnitude
 // <= q; output in [0, q).
+template <int RMAX = 4>
 HD void ntt_inverse_b(double* a, const double* itw, double ninv, ModQB mod, uint32_t n, uint32_t logn,
                       uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
   uint32_t lh0 = 0;
   while (lh0 < logn) {
     const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
     switch (r) {
-      case 4: ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
       case 3: ntt_inv_pass_b<3>(a, itw, mod, n, lh0, tid, nthr); break;
       case 2: ntt_inv_pass_b<2>(a, itw, mod, n, lh0, tid, nthr); break;
       default: ntt_inv_pass_b<1>(a, itw, mod, n, lh0, tid, nthr); break;

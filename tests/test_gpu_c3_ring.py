@@ -5,7 +5,8 @@ base sized for d_max = 128 (K = 16 primes).
 App. A Alg. "Ciphertext Multiplication" and App. B Alg. "HERS Search" at the
 ring size the batched search runs at: the gallery and probe ciphertexts, the
 score ciphertexts of the single-probe search with relinearization as one fused
-kernel per (block, prime) and as two kernels, and the score ciphertexts of a
+kernel per (block, prime) -- 1024 lanes of 8 coefficients and 512 lanes of
+16 -- and as two kernels, and the score ciphertexts of a
 two-probe batch (the persistent multi-probe multiply-accumulate) all equal the
 oracle's residue by residue; decrypted scores equal P^T q.  The gallery has two
 blocks, the second ragged (8192 + 77 items), and d = 3.  A wider batch (d = 9,
@@ -86,17 +87,20 @@ def test_c3_keys_gallery_probe_bit_exact(c3):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("fuse", [1, 1 << 30], ids=["fused_relin", "two_kernel_relin"])
-def test_c3_search_bit_exact(c3, fuse):
+@pytest.mark.parametrize("fuse,per", [(1, 8), (1, 16), (1 << 30, 8)],
+                         ids=["fused_relin_1024_lanes", "fused_relin_512_lanes", "two_kernel_relin"])
+def test_c3_search_bit_exact(c3, fuse, per):
     ctx = c3["ctx"]
     try:
         ctx.set_option("relin_fuse_min_wgs", fuse)
+        ctx.set_option("relin_lane_coeffs", per)
         sc = ctx.search(c3["gal"], M_ITEMS, D, c3["pr1"])
         _assert_scores(sc, c3["want1"], c3["op"].q_primes)
         out = ctx.decrypt_scores(c3["sk"], sc, M_ITEMS).cpu().numpy()
         assert np.array_equal(out, hers.plaintext_scores(c3["P"], c3["q1"]))
     finally:
         ctx.set_option("relin_fuse_min_wgs", 0)
+        ctx.set_option("relin_lane_coeffs", 8)
 
 
 @pytest.mark.timeout(900)

@@ -161,17 +161,20 @@ def test_decrypted_scores_equal_plaintext_inner_products(name, request):
 
 @pytest.mark.parametrize("name", ["case_c1b", "case_c3s", "case_mx"])
 def test_relinearization_forms_give_same_bits(name, request):
-    """Relinearization as one fused kernel per (block, prime) and as two
-    kernels give the oracle-checked score ciphertexts, with integer (54-bit
-    primes) and double-precision (44-bit primes) modular arithmetic, and with
-    primes of unequal size (digits reduced in full)."""
+    """Relinearization as one fused kernel per (block, prime) -- 8 and 16
+    coefficients per lane -- and as two kernels give the oracle-checked score
+    ciphertexts, with integer (54-bit primes) and double-precision (44-bit
+    primes) modular arithmetic, and with primes of unequal size (digits
+    reduced in full)."""
     c = request.getfixturevalue(name)
     try:
-        for fuse in (1, 1 << 30):
+        for fuse, per in ((1, 8), (1, 16), (1 << 30, 8)):
             c.ctx.set_option("relin_fuse_min_wgs", fuse)
-            assert torch.equal(c.ctx.search(c.gallery, c.m, c.d, c.probe), c.scores), fuse
+            c.ctx.set_option("relin_lane_coeffs", per)
+            assert torch.equal(c.ctx.search(c.gallery, c.m, c.d, c.probe), c.scores), (fuse, per)
     finally:
         c.ctx.set_option("relin_fuse_min_wgs", 0)
+        c.ctx.set_option("relin_lane_coeffs", 8)
 
 
 @pytest.mark.parametrize("name", ["case_r36", "case_c3s"])
