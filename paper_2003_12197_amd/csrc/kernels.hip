@@ -1225,8 +1225,8 @@ k_ntt_q(DevTabs T, uint64_t* __restrict__ digits, uint64_t set_stride) {
   }
 }
 
-template <bool QF>
-__global__ void __launch_bounds__(WG)
+template <bool QF, int NT>
+__global__ void __launch_bounds__(NT)
 k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, ScorePtrs SP, uint64_t dig_stride,
             const uint64_t* __restrict__ key, const uint64_t* __restrict__ key_sh) {
   // Relinearization (or key switching), second half, for residue sigma =
@@ -1249,14 +1249,14 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
     uint64_t* dst1 = SP.p[blockIdx.z] + (((size_t)b * 2 + 1) * k + sg) * n;
     // RA coefficients per lane at a time, so each digit's loads for all of
     // them are in flight together (the digit loop has a runtime bound); rings
-    // smaller than RA WG coefficients take one coefficient at a time
+    // smaller than RA NT coefficients take one coefficient at a time
     constexpr uint32_t RA = 4;
     const ModQF mq{T.qf[sg], T.qf[HC_MAXQ + sg]};
     double* f0 = reinterpret_cast<double*>(lds64);
     double* f1 = f0 + padded_len(n);
-    const bool batched = n % (RA * WG) == 0;
+    const bool batched = n % (RA * NT) == 0;
     const uint32_t ra = batched ? RA : 1;
-    for (uint32_t j0 = tid; j0 < n; j0 += ra * WG) {
+    for (uint32_t j0 = tid; j0 < n; j0 += ra * NT) {
       double a0[RA], a1[RA];
 #pragma unroll
       for (uint32_t u = 0; u < RA; ++u) { a0[u] = 0.0; a1[u] = 0.0; }
@@ -1268,9 +1268,9 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
 #pragma unroll
         for (uint32_t u = 0; u < RA; ++u) {
           if (u >= ra) break;
-          dv[u] = dg[u * WG];
-          kv0[u] = k0[u * WG];
-          kv1[u] = k1[u * WG];
+          dv[u] = dg[u * NT];
+          kv0[u] = k0[u * NT];
+          kv1[u] = k1[u * NT];
         }
 #pragma unroll
         for (uint32_t u = 0; u < RA; ++u) {
@@ -1283,8 +1283,8 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
         }
       }
       for (uint32_t u = 0; u < ra; ++u) {
-        f0[PADX(j0 + u * WG)] = a0[u];
-        f1[PADX(j0 + u * WG)] = a1[u];
+        f0[PADX(j0 + u * NT)] = a0[u];
+        f1[PADX(j0 + u * NT)] = a1[u];
       }
     }
     __syncthreads();
@@ -1293,17 +1293,17 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
     for (int comp = 0; comp < 2; ++comp) {
       double* f = comp ? f1 : f0;
       uint64_t* dst = comp ? dst1 : dst0;
-      ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, WG, T.ntt_r);
+      ntt_inverse_b(f, itw, ninv, ModQB{mq.q, mq.qinv}, n, C.logn, tid, NT, T.ntt_r);
       if (batched) {
-        for (uint32_t j0 = tid; j0 < n; j0 += RA * WG) {
+        for (uint32_t j0 = tid; j0 < n; j0 += RA * NT) {
           uint64_t dv[RA];
 #pragma unroll
-          for (uint32_t u = 0; u < RA; ++u) dv[u] = dst[j0 + u * WG];
+          for (uint32_t u = 0; u < RA; ++u) dv[u] = dst[j0 + u * NT];
 #pragma unroll
-          for (uint32_t u = 0; u < RA; ++u) dst[j0 + u * WG] = add_q(dv[u], f_to_u64(f[PADX(j0 + u * WG)]), q);
+          for (uint32_t u = 0; u < RA; ++u) dst[j0 + u * NT] = add_q(dv[u], f_to_u64(f[PADX(j0 + u * NT)]), q);
         }
       } else {
-        for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
+        for (uint32_t j = tid; j < n; j += NT) dst[j] = add_q(dst[j], f_to_u64(f[PADX(j)]), q);
       }
     }
     return;
@@ -1312,7 +1312,7 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   const uint32_t comp = blockIdx.x & 1;
   const uint64_t* digits = digits_b + (size_t)blockIdx.z * dig_stride + (size_t)bl * L * k * n;
   uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
-  for (uint32_t j = tid; j < n; j += WG) {
+  for (uint32_t j = tid; j < n; j += NT) {
     uint64_t acc = 0;
     for (uint32_t g = 0; g < L; ++g) {
       const size_t r = (((size_t)g * 2 + comp) * k + sg) * n + j;
@@ -1322,8 +1322,8 @@ k_relin_acc(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, Sc
   }
   __syncthreads();
   ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg],
-                ModQ{q}, n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t j = tid; j < n; j += WG) dst[j] = add_q(dst[j], lds64[PADX(j)], q);
+                ModQ{q}, n, C.logn, tid, NT, T.ntt_r);
+  for (uint32_t j = tid; j < n; j += NT) dst[j] = add_q(dst[j], lds64[PADX(j)], q);
 }
 
 // Fused relinearization / key switching: one workgroup per (block, residue
@@ -1465,11 +1465,13 @@ k_sk_ntt(DevTabs T, const uint8_t* __restrict__ sk, uint64_t* __restrict__ S, ui
   }
 }
 
-template <bool QF>
-__global__ void __launch_bounds__(WG)
+template <bool QF, int NT>
+__global__ void __launch_bounds__(NT)
 k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const uint64_t* __restrict__ S,
           const uint64_t* __restrict__ Ssh, uint64_t* __restrict__ xout) {
-  // x = [c0 + c1 s]_q for block blk_lo + blockIdx.x, residue sigma.
+  // x = [c0 + c1 s]_q for block blk_lo + blockIdx.x, residue sigma; NT lanes
+  // (512 at n = 8192, where a 256-lane workgroup's LDS share would leave two
+  // waves per SIMD).
   extern __shared__ uint64_t lds64[];
   const HersConsts& C = *T.C;
   const uint32_t n = C.n, k = C.k, tid = threadIdx.x, sg = blockIdx.y;
@@ -1482,30 +1484,30 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     // the same product in double precision: transforms balanced (ModQB), product by ModQF
     double* f = reinterpret_cast<double*>(lds64);
     const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
-    load_padded(f, c1, n, tid, WG, [](uint64_t v) { return u64_to_f(v); });
+    load_padded(f, c1, n, tid, NT, [](uint64_t v) { return u64_to_f(v); });
     __syncthreads();
     const double* twf = T.qtw_f + (size_t)sg * n;
     const ModQB mb{mf.q, mf.qinv};
-    ntt_forward_b(f, twf, mb, n, C.logn, tid, WG, T.ntt_r);
-    for_each_loaded(S + (size_t)sg * n, n, tid, WG,
+    ntt_forward_b(f, twf, mb, n, C.logn, tid, NT, T.ntt_r);
+    for_each_loaded(S + (size_t)sg * n, n, tid, NT,
                     [&](uint32_t j, uint64_t sv) { f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(sv), 0.0); });
     __syncthreads();
     const double* itwf = T.qitw_f + (size_t)sg * n;
     const double ninv = T.qf[2 * HC_MAXQ + sg];
-    ntt_inverse_b(f, itwf, ninv, mb, n, C.logn, tid, WG, T.ntt_r);
+    ntt_inverse_b(f, itwf, ninv, mb, n, C.logn, tid, NT, T.ntt_r);
     uint64_t* xo = xout + ((size_t)bl * k + sg) * n;
-    for_each_loaded(c0, n, tid, WG, [&](uint32_t j, uint64_t v0) { xo[j] = add_q(f_to_u64(f[PADX(j)]), v0, q); });
+    for_each_loaded(c0, n, tid, NT, [&](uint32_t j, uint64_t v0) { xo[j] = add_q(f_to_u64(f[PADX(j)]), v0, q); });
     return;
   }
-  load_padded(lds64, c1, n, tid, WG, [](uint64_t v) { return v; });
+  load_padded(lds64, c1, n, tid, NT, [](uint64_t v) { return v; });
   __syncthreads();
-  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t j = tid; j < n; j += WG)
+  ntt_forward16(lds64, T.qtw + (size_t)sg * n, T.qtw_sh + (size_t)sg * n, mq, n, C.logn, tid, NT, T.ntt_r);
+  for (uint32_t j = tid; j < n; j += NT)
     lds64[PADX(j)] = shoup_q(lds64[PADX(j)], S[(size_t)sg * n + j], Ssh[(size_t)sg * n + j], q);
   __syncthreads();
   ntt_inverse16(lds64, T.qitw + (size_t)sg * n, T.qitw_sh + (size_t)sg * n, C.q_ninv[sg], C.q_ninv_sh[sg], mq,
-              n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t j = tid; j < n; j += WG) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
+              n, C.logn, tid, NT, T.ntt_r);
+  for (uint32_t j = tid; j < n; j += NT) xout[((size_t)bl * k + sg) * n + j] = add_q(lds64[PADX(j)], c0[j], q);
 }
 
 template <int KQ>
@@ -1799,12 +1801,14 @@ hipError_t launch_relin(const DevTabs& T, uint32_t n, uint32_t k, uint32_t L, ui
     hipLaunchKernelGGL(k_ntt_q<false>, g1, dim3(WG), lds_bytes(n, 1), s, T, digits, dig_stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // (512 lanes in double precision: its two LDS buffers leave room for two
+  // workgroups per CU at n = 4096, one at 8192)
   if (T.qf_ok)
-    hipLaunchKernelGGL(k_relin_acc<true>, g2, dim3(WG), 2 * lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
-                       key_sh);
+    hipLaunchKernelGGL((k_relin_acc<true, 512>), g2, dim3(512), 2 * lds_bytes(n, 1), s, T, digits, blk_lo, SP,
+                       dig_stride, key, key_sh);
   else
-    hipLaunchKernelGGL(k_relin_acc<false>, g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride, key,
-                       key_sh);
+    hipLaunchKernelGGL((k_relin_acc<false, WG>), g2, dim3(WG), lds_bytes(n, 1), s, T, digits, blk_lo, SP, dig_stride,
+                       key, key_sh);
   return hipGetLastError();
 }
 
@@ -1831,12 +1835,13 @@ hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t
 
 hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,
                           int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s) {
-  if (T.qf_ok)
-    hipLaunchKernelGGL(k_dec_mul<true>, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S,
-                       Ssh, x);
+  const dim3 grid((uint32_t)nblk, k);
+  if (T.qf_ok && n >= 8192)
+    hipLaunchKernelGGL((k_dec_mul<true, 512>), grid, dim3(512), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
+  else if (T.qf_ok)
+    hipLaunchKernelGGL((k_dec_mul<true, WG>), grid, dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
   else
-    hipLaunchKernelGGL(k_dec_mul<false>, dim3((uint32_t)nblk, k), dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S,
-                       Ssh, x);
+    hipLaunchKernelGGL((k_dec_mul<false, WG>), grid, dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
   return hipGetLastError();
 }
 
