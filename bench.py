@@ -624,10 +624,11 @@ def main():
         search = lambda: ctx.search(gallery, m, d, probes[0], scores=scores[0], workspace=ws_s)
         dominant = "mac"
     else:
-        # rounds of blocks as large as the free memory allows (up to 32 GiB of workspace): every round
-        # launch re-stages the probes, so fewer rounds cost less
-        budget = min(32 << 30, max(8 << 30, torch.cuda.mem_get_info()[0] - (4 << 30)))
-        rounds = max(8, min(span, budget // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
+        # rounds of blocks as large as the free memory allows (up to 96 GiB of workspace, 8 GiB left
+        # free), of even size: every round launch re-stages the probes, so fewer rounds cost less
+        budget = min(96 << 30, max(8 << 30, torch.cuda.mem_get_info()[0] - (8 << 30)))
+        cap = max(8, min(span, budget // (npr * int(ctx.lib.hers_workspace_bytes(ctx.handle, 2, n, 1)))))
+        rounds = -(-span // -(-span // cap))
         ws_s = ctx.batch_workspace([span * n] * npr, blocks_per_round=rounds)
         mac_variant = None
         gal_of = lambda lo, hi: gallery[lo * blk_words:hi * blk_words]
