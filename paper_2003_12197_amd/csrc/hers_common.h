@@ -71,6 +71,11 @@ struct HersConsts {
   uint32_t t_ninv, t_ninv_sh;
   uint32_t Qw_t[HC_MAXQ], Qw_t_sh[HC_MAXQ];          // (q_0 ... q_{i-1}) mod t
   uint32_t qmod_t, qinv_t, qinv_t_sh, pad1;
+  // decryption by fractions: dec_c[i] = floor(t 2^64 / q_i); the rounded
+  // fixed-point sum is taken while its low word is below dec_lo_max =
+  // 2^64 - sum_i q_i (0: never)
+  uint64_t dec_c[HC_MAXQ];
+  uint64_t dec_lo_max;
 
   // ---- gadget (relinearization digits), key order
   uint32_t g_rho[HC_MAXL], g_shift[HC_MAXL];
@@ -346,12 +351,41 @@ HD bool scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
 
 // Decryption scale (Alg. "Decryption"): given x mod q_i of x = [c0 + c1 s]_q,
 // returns [round(t x / q)]_t in [0, t): with t x = q Y + T as above, Y = -T q^-1 mod t.
+// Exact CRT form (Garner digits of t x, its centred representative).
 template <int KQ = 0>
-HD uint32_t decrypt_coeff(const HersConsts& C, const uint64_t* x) {
+HD uint32_t decrypt_coeff_exact(const HersConsts& C, const uint64_t* x) {
   uint64_t tx[KQ ? KQ : HC_MAXQ], a[KQ ? KQ : HC_MAXQ];
   for (uint32_t i = 0; i < (KQ ? KQ : C.k); ++i) tx[i] = shoup_q(x[i], C.q_t[i], C.q_t_sh[i], C.q[i]);
   const bool neg = garner_digits<KQ>(C, tx, a);
   uint32_t T = mixed_to_t<KQ>(C, a, neg);
   uint32_t y = shoup_p(T, C.qinv_t, C.qinv_t_sh, C.t);
   return y ? C.t - y : 0;
+}
+
+// The same value from fractions.  With y_i = [x_i (q/q_i)^-1]_{q_i},
+// x = sum_i y_i q/q_i - a q for an integer 0 <= a < k, so
+// t x / q = sum_i y_i t / q_i - a t and round(t x / q) = round(S) mod t,
+// S = sum_i y_i t / q_i (each term below t).  With c_i = floor(t 2^64 / q_i),
+// A = sum_i y_i c_i (exact in 128 bits) lies below 2^64 S by less than
+// sum_i y_i < sum_i q_i, so for B = A + 2^63 the value floor(B / 2^64) is
+// round(S) whenever B mod 2^64 < 2^64 - sum_i q_i (no carry can be missing).
+// Returns false, leaving *v unset, when that low word is too close to the
+// carry (never for the small noise of a valid ciphertext: t x / q is then
+// close to an integer, so B mod 2^64 is close to 1/2).
+template <int KQ = 0>
+HD bool decrypt_coeff_frac(const HersConsts& C, const uint64_t* x, uint32_t* v) {
+  u128 B = (u128)1 << 63;
+#pragma unroll
+  for (uint32_t i = 0; i < (KQ ? KQ : C.k); ++i)
+    B += (u128)shoup_q(x[i], C.q_hatinv[i], C.q_hatinv_sh[i], C.q[i]) * C.dec_c[i];
+  if ((uint64_t)B >= C.dec_lo_max) return false;
+  *v = red_p((uint64_t)(B >> 64), C.t, C.t_mu64);
+  return true;
+}
+
+template <int KQ = 0>
+HD uint32_t decrypt_coeff(const HersConsts& C, const uint64_t* x) {
+  uint32_t v;
+  if (decrypt_coeff_frac<KQ>(C, x, &v)) return v;
+  return decrypt_coeff_exact<KQ>(C, x);
 }

@@ -409,6 +409,17 @@ std::string precompute(const hers_params& prm, HostTables* T) {
     C.qinv_t = (uint32_t)invmod(qm, t);
     C.qinv_t_sh = sh32(C.qinv_t, (uint32_t)t);
   }
+  {
+    // decryption by fractions (hers_common.h: decrypt_coeff_frac)
+    u128 qs = 0;
+    bool ok = true;
+    for (uint32_t i = 0; i < k; ++i) {
+      ok &= t < info.q[i];
+      C.dec_c[i] = ok ? (uint64_t)(((u128)t << 64) / info.q[i]) : 0;
+      qs += info.q[i];
+    }
+    C.dec_lo_max = ok && qs < ((u128)1 << 64) ? (uint64_t)(((u128)1 << 64) - qs) : 0;
+  }
 
   // ---- gadget: digit (rho, l) has value (q/q_rho) 2^(l w) mod q, which is 0 mod q_i for i != rho
   {

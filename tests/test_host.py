@@ -199,3 +199,73 @@ def test_rescale_two_word_rounding_matches_all_words(tmp_path):
         assert nh or rs == rw, (W, y, g)             # the fallback is taken whenever it is needed
         flips += W > 2 and short != full
     assert flips >= 6      # the built chains do reach the W-word fallback
+
+
+@pytest.mark.parametrize("n,t_bits,qbits", [
+    (4096, 20, (36, 36, 36)),            # the 10^8 x 32 ring
+    (8192, 21, (44, 44, 44, 43, 43)),    # the batched ring
+    (1024, 20, (44, 44, 32)),            # primes of unequal size
+    (256, 20, (60, 60, 60, 60)),         # wide primes, fraction form still on
+    (256, 20, (61,) * 6),                # the widest primes: a window of 3/4 beside each carry
+])
+def test_decryption_scale_fraction_form(tmp_path, n, t_bits, qbits):
+    """Alg. "Decryption" scales [c0 + c1 s]_q by t/q and rounds.  The kernel
+    first forms round(t x / q) mod t from 64-bit fixed-point fractions
+    t / q_i and falls back to the exact CRT form when the rounded sum's low
+    word is within sum_i q_i of a carry.  Checked on the host with the
+    resolved constants against round(t x / q) mod t computed with exact
+    integers: random x, x just beside the half-integer points of t x / q
+    (where the fraction form must step aside), x near the integer points (a
+    valid ciphertext's small noise) and the ends of [0, q)."""
+    import random
+    import shutil
+    import subprocess
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    csrc = os.path.join(ROOT, "paper_2003_12197_amd", "csrc")
+    exe = str(tmp_path / "decrypt_scale")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-Wno-unknown-pragmas", "-o", exe,
+                    os.path.join(os.path.dirname(__file__), "native", "decrypt_scale.cpp"),
+                    os.path.join(csrc, "params.cpp")], check=True)
+    k = len(qbits)
+    # the harness prints the resolved t and q_i first; read them with an empty input
+    head = subprocess.run([exe], input="%d %d %d %s\n" % (n, t_bits, k, " ".join(map(str, qbits))),
+                          capture_output=True, text=True, check=True).stdout.split()
+    t, qs = int(head[1]), [int(v) for v in head[2:2 + k]]
+    q = 1
+    for qi in qs:
+        q *= qi
+    rng = random.Random(12197 + n + k)
+    xs = [rng.randrange(q) for _ in range(1500)] + [0, 1, q - 1]
+    near_half, near_int = [q // 2, (q + 1) // 2], []            # t x / q within t / 2q of t / 2 (t odd)
+    for _ in range(300):
+        j = rng.randrange(t)
+        c = (2 * j + 1) * q // (2 * t)                 # t c / q just below j + 1/2
+        near_half += [(c + dlt) % q for dlt in range(-2, 4)]
+        c = j * q // t
+        near_int += [(c + dlt) % q for dlt in (-(1 << 20), -5, 0, 5, 1 << 20)]
+    xs += near_half + near_int
+    lines = "".join(" ".join(str(x % qi) for qi in qs) + "\n" for x in xs)
+    out = subprocess.run([exe], input="%d %d %d %s\n" % (n, t_bits, k, " ".join(map(str, qbits))) + lines,
+                         capture_output=True, text=True, check=True).stdout.splitlines()[1:]
+    assert len(out) == len(xs)
+    fast_n = 0
+    for x, line in zip(xs, out):
+        fast, v, exact = (int(w) for w in line.split())
+        want = (2 * t * x + q) // (2 * q) % t          # round(t x / q) mod t (no ties: q is odd, x < q)
+        assert exact == want, (x, exact, want)
+        if fast:
+            assert v == want, (x, v, want)
+        fast_n += fast
+    if sum(qs) < (1 << 54):
+        # a window of sum_i q_i / 2^64 < 2^-10 beside each carry: the fraction form decides all but
+        # the near-half points, and steps aside beside some of them
+        assert fast_n >= len(xs) - len(near_half)
+        hs = set(near_half)
+        assert any(x in hs and line.startswith("0 ") for x, line in zip(xs, out))
+    elif sum(qs) < (1 << 64):
+        assert fast_n > 0                               # wide primes: a wide window, some decided
+    else:
+        assert fast_n == 0                              # (no parameter set reaches a sum of 2^64)
