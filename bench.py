@@ -615,7 +615,12 @@ def main():
         if args.no_autotune:
             mac_variant = ctx.get_option("mac_variant")
         else:
+            # tuned as the timed steps run: with timing events around the multiply-accumulate launches
+            # (they shift which chunking is fastest by a few percent)
+            ctx.profile_select(["mac"])
+            ctx.profile_enable(True)
             mac_variant = ctx.autotune(gallery, m, d, probes[0], reps=3, workspace=ws_s, scores=scores[0])
+            ctx.profile_enable(False)
         log("%s k_mac schedule: %d, NTT pass radix 2^%d, overlap chunks %d, MAC workgroups per CU %d, "
             "fused relinearization from %d workgroups" % (
                 "default" if args.no_autotune else "autotuned", mac_variant, ctx.get_option("ntt_radix_log2"),

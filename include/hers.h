@@ -448,10 +448,13 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value);
  * schedule 8, schedule 9, schedule 10 or schedule 12, and -- where the default
  * relinearization is the two-kernel form -- over chunk counts 1, 4, 16, 64 x
  * "mac_wgs_per_cu" 0, 1 with the relinearization fused ("relin_fuse_min_wgs"
- * 1) and the best schedule (a combination other than no chunks, default
- * grid, schedule found first must be 3% faster to be kept).  Keeps the fastest of each in the context and returns the schedule
- * in *chosen (may be NULL).  The workspace and scores_dev contents are
- * overwritten; the call synchronizes `stream`. */
+ * 1) and the best schedule; the plain combination (no chunks, default grid,
+ * schedule found first) and the four fastest others are then timed again in
+ * turn, one search each over 2 reps rounds, and another than the plain one
+ * must be 3% faster by those sums to be kept.  Keeps the fastest of each in
+ * the context and returns the schedule in *chosen (may be NULL).  The
+ * workspace and scores_dev contents are overwritten; the call synchronizes
+ * `stream`. */
 int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_words, int64_t m, int32_t d,
                   const uint32_t* probe_dev, uint64_t probe_words, uint64_t* scores_dev, void* work_dev,
                   size_t work_bytes, int reps, void* stream, int64_t* chosen);

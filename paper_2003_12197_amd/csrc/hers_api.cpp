@@ -1233,78 +1233,100 @@ int hers_autotune(hers_ctx* ctx, const uint32_t* gallery_dev, uint64_t gallery_w
   // need not be the best beside the epilogue), schedule 10 (fewer registers,
   // so epilogue waves fit beside it), the fused schedule (n <= 4096) and
   // schedule 9 (two dimensions in flight per lane: more loads outstanding
-  // from the few MAC waves a small grid leaves)
+  // from the few MAC waves a small grid leaves); then the fused
+  // relinearization where the default is the two-kernel form.  The sweep
+  // times each combination once (reps searches); the four fastest and the
+  // plain one (no chunks, default grid, schedule found first) are then timed
+  // again one search at a time in turn, 2 reps rounds, so that drift over
+  // the sweep favours none of them, and the sums decide.
   if (rc == HERS_OK && scores_dev) {
-    float best_o = 0.f, plain_ms = 0.f;
-    int best_nch = 1, best_w = 0, best_mv = best_v;
+    struct Cand { float ms; int nch, w, v; int64_t f; };
+    std::vector<Cand> cands;
+    const int64_t fuse0 = ctx->relin_fuse_min_wgs;
+    auto apply = [&](const Cand& c) {
+      ctx->overlap_chunks = c.nch;
+      ctx->mac_wgs_per_cu = c.w;
+      ctx->mac_variant = c.v;
+      ctx->relin_fuse_min_wgs = c.f;
+    };
+    // one timed pass of `count` searches under c (after one untimed one when warm)
+    auto time_searches = [&](const Cand& c, int count, bool warm, float* ms) -> int {
+      apply(c);
+      int r2 = warm ? hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev,
+                                  work_dev, work_bytes, stream)
+                    : HERS_OK;
+      hipError_t e = r2 == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
+      for (int r = 0; r < count && r2 == HERS_OK && e == hipSuccess; ++r)
+        r2 = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
+                         work_bytes, stream);
+      if (r2 != HERS_OK) return r2;
+      if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+      if (e != hipSuccess) return fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+      return HERS_OK;
+    };
     const int vs[5] = {best_v, 8, 10, nvar > MAC_FUSED_INTT ? MAC_FUSED_INTT : 10, 9};
-    bool first = true;
     for (int nch = 1; nch <= 64 && rc == HERS_OK; nch *= 2) {
       if (nch > 1 && M / nch < 16) break;
       for (int w : {0, 1, 2}) {
-        if (rc != HERS_OK) break;
         for (int vi = 0; vi < 5 && rc == HERS_OK; ++vi) {
           bool seen = false;
           for (int vj = 0; vj < vi; ++vj) seen |= vs[vj] == vs[vi];
           if (seen) continue;
-          ctx->overlap_chunks = nch;
-          ctx->mac_wgs_per_cu = w;
-          ctx->mac_variant = vs[vi];
-          rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
-                               work_bytes, stream);
-          hipError_t e = rc == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
-          for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
-            rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
-                               work_bytes, stream);
-          if (rc != HERS_OK) break;
-          if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
-          if (first) plain_ms = ms;                        // nch 1, default grid, schedule found first
-          if (first || ms < best_o) { best_o = ms; best_nch = nch; best_w = w; best_mv = vs[vi]; first = false; }
+          Cand c{0.f, nch, w, vs[vi], fuse0};
+          rc = time_searches(c, reps, true, &c.ms);
+          if (rc == HERS_OK) cands.push_back(c);
         }
       }
     }
     // the relinearization in one kernel per (block, prime) where the default
     // is the two-kernel form: it moves no transformed digit through memory,
     // which counts once the overlapped search is bound by its total traffic
-    const int64_t fuse0 = ctx->relin_fuse_min_wgs;
-    int64_t best_f = fuse0;
-    if (fuse_wgs(ctx) > 1) {
+    if (rc == HERS_OK && fuse_wgs(ctx) > 1 && !cands.empty()) {
+      int mv = cands[0].v;
+      float mb = cands[0].ms;
+      for (const Cand& c : cands)
+        if (c.ms < mb) { mb = c.ms; mv = c.v; }
       for (int nch : {1, 4, 16, 64}) {
         if (rc != HERS_OK || (nch > 1 && M / nch < 16)) break;
         for (int w : {0, 1}) {
-          ctx->overlap_chunks = nch;
-          ctx->mac_wgs_per_cu = w;
-          ctx->mac_variant = best_mv;
-          ctx->relin_fuse_min_wgs = 1;
-          rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
-                           work_bytes, stream);
-          hipError_t e = rc == HERS_OK ? hipEventRecord(e0, S(stream)) : hipSuccess;
-          for (int r = 0; r < reps && rc == HERS_OK && e == hipSuccess; ++r)
-            rc = hers_search(ctx, gallery_dev, gallery_words, m, d, probe_dev, probe_words, scores_dev, work_dev,
-                             work_bytes, stream);
-          ctx->relin_fuse_min_wgs = fuse0;
-          if (rc != HERS_OK) break;
-          if (e == hipSuccess) e = hipEventRecord(e1, S(stream));
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e != hipSuccess) { rc = fail(HERS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
-          if (ms < best_o) { best_o = ms; best_nch = nch; best_w = w; best_f = 1; }
+          Cand c{0.f, nch, w, mv, 1};
+          rc = time_searches(c, reps, true, &c.ms);
+          if (rc == HERS_OK) cands.push_back(c);
         }
       }
     }
-    // keep the plain schedule (no chunks, default grid) unless another wins
-    // clearly: differences within timing noise would only make runs disagree
-    if (best_o > 0.97f * plain_ms) { best_nch = 1; best_w = 0; best_mv = best_v; best_f = fuse0; }
-    ctx->overlap_chunks = best_nch;
-    ctx->mac_wgs_per_cu = best_w;
-    ctx->mac_variant = best_mv;
-    ctx->relin_fuse_min_wgs = best_f;
-    best_v = best_mv;
+    if (rc == HERS_OK && !cands.empty()) {
+      // cands[0] is the plain combination; the four fastest others join it
+      std::vector<Cand> fin{cands[0]};
+      std::vector<Cand> rest(cands.begin() + 1, cands.end());
+      std::sort(rest.begin(), rest.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+      for (size_t i = 0; i < rest.size() && fin.size() < 5; ++i) fin.push_back(rest[i]);
+      std::vector<float> tot(fin.size(), 0.f);
+      for (int round = 0; round < 2 * reps && rc == HERS_OK; ++round)
+        for (size_t i = 0; i < fin.size() && rc == HERS_OK; ++i) {
+          float ms = 0.f;
+          rc = time_searches(fin[i], 1, round == 0, &ms);
+          tot[i] += ms;
+        }
+      if (rc == HERS_OK) {
+        size_t bi = 0;
+        for (size_t i = 1; i < fin.size(); ++i)
+          if (tot[i] < tot[bi]) bi = i;
+        // keep the plain combination unless another wins clearly: differences
+        // within timing noise would only make runs disagree
+        if (tot[bi] > 0.97f * tot[0]) bi = 0;
+        apply(fin[bi]);
+        best_v = fin[bi].v;
+      }
+    }
+    if (rc != HERS_OK) {
+      ctx->overlap_chunks = 1;
+      ctx->mac_wgs_per_cu = 0;
+      ctx->mac_variant = best_v;
+      ctx->relin_fuse_min_wgs = fuse0;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
