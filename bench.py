@@ -456,8 +456,8 @@ def run_two_stage(args, cfg):
     ctx1.profile_enable(False)
     # stage breakdown (untimed): a few more steps with every stage timed
     kb = min(args.steps, 10)
-    names = ("mac", "intt_acc", "rescale", "relin", "encrypt", "lift", "ntt_fwd", "sk_ntt", "dec_mul", "dec_decode",
-             "topk", "encode", "gather", "rotate")
+    names = ("mac", "intt_acc", "rescale", "relin", "encrypt", "lift", "ntt_fwd", "sk_ntt", "decrypt", "dec_mul",
+             "dec_decode", "topk", "encode", "gather", "rotate")
     ctx1.profile_select(None)
     for c in (ctx1, ctx2):
         c.profile_enable(True)
@@ -714,7 +714,7 @@ def main():
         step(PROBE_SEED, eager=True)
     torch.cuda.synchronize()
     stage_names = ("mac", "mac_multi", "intt_acc", "rescale", "relin", "encrypt", "lift", "ntt_fwd", "sk_ntt",
-                   "dec_mul", "dec_decode", "topk")
+                   "decrypt", "dec_mul", "dec_decode", "topk")
     stages = {st: ctx.profile_read(st) for st in stage_names}
     ctx.profile_enable(False)
     if plan is not None:

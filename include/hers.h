@@ -415,6 +415,11 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  transformed digits in memory; smaller ones as two kernels
  *                  with more workgroups.  0 = 8 per compute unit at
  *                  n >= 8192, never below; 1 = always.
+ *   "dec_fused"    1 (default): hers_decrypt_scores in one kernel per block
+ *                  where it fits (double-precision arithmetic, n = 4096,
+ *                  three q primes), [c0 + c1 s]_q kept in registers; 0: the
+ *                  product and the decoding as two kernels through the
+ *                  workspace.  The same scores either way.
  *   "relin_lane_coeffs" coefficients per lane of the fused form, 8 (default:
  *                  n / 8 lanes, four waves per SIMD) or 16 (n / 16 lanes,
  *                  two waves per SIMD, the next digit's loads held in

@@ -45,6 +45,7 @@ struct hers_ctx {
   // per-block epilogue runs on, and its events (MAC done, join, one per
   // workspace region)
   int overlap_chunks = 0;
+  int dec_fused = 1;                // decryption and decoding in one kernel where it fits
   int mac_wgs_per_cu = 0;   // multiply-accumulate grid, workgroups per CU (0 = 8)
   int64_t relin_fuse_min_wgs = 0;   // fused relinearization from this many workgroups (0 = 8 per CU)
   int mb_variant = 0;               // multi-probe multiply-accumulate schedule (launch_mac_multi)
@@ -413,6 +414,11 @@ int hers_set_option(hers_ctx* ctx, const char* key, int64_t value) {
     ctx->T.ntt_r = (uint32_t)value;
     return HERS_OK;
   }
+  if (!std::strcmp(key, "dec_fused")) {
+    if (value != 0 && value != 1) return fail(HERS_EINVAL, "dec_fused must be 0 or 1");
+    ctx->dec_fused = (int)value;
+    return HERS_OK;
+  }
   if (!std::strcmp(key, "relin_lane_coeffs")) {
     if (value != 8 && value != 16) return fail(HERS_EINVAL, "relin_lane_coeffs must be 8 or 16");
     ctx->T.rl_per = (uint32_t)value;
@@ -458,6 +464,10 @@ int hers_get_option(const hers_ctx* ctx, const char* key, int64_t* value) {
   }
   if (!std::strcmp(key, "relin_lane_coeffs")) {
     *value = ctx->T.rl_per;
+    return HERS_OK;
+  }
+  if (!std::strcmp(key, "dec_fused")) {
+    *value = ctx->dec_fused;
     return HERS_OK;
   }
   if (!std::strcmp(key, "overlap_chunks")) {
@@ -1616,6 +1626,12 @@ int hers_decrypt_scores(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* sc
   uint64_t* x = (uint64_t*)((char*)work_dev + fixed);
   DeviceGuard g(ctx->device);
   if (sk_dev) TIMED(ctx, "sk_ntt", S(stream), hers::launch_sk_ntt(ctx->T, C.n, C.k, sk_dev, Sn, Ssh, S(stream)));
+  if (hers::dec_fused_fits(ctx->T, C.n) && ctx->dec_fused) {
+    // one kernel per block: x stays in registers (the workspace's x area is unused)
+    TIMED(ctx, "decrypt", S(stream), hers::launch_dec_fused(ctx->T, C.n, scores_dev, M, 0, Sn, m, scores_out_dev,
+                                                             S(stream)));
+    return HERS_OK;
+  }
   for (int64_t lo = 0; lo < M; lo += chunk) {
     const int64_t nb = lo + chunk < M ? chunk : M - lo;
     TIMED(ctx, "dec_mul", S(stream), hers::launch_dec_mul(ctx->T, C.n, C.k, scores_dev, nb, lo, Sn, Ssh, x, S(stream)));

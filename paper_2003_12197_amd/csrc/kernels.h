@@ -122,6 +122,12 @@ hipError_t launch_sk_ntt(const DevTabs& T, uint32_t n, uint32_t k, const uint8_t
                          hipStream_t s);
 hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64_t* scores, int64_t nblk,
                           int64_t blk_lo, const uint64_t* S, const uint64_t* Ssh, uint64_t* x, hipStream_t s);
+// Decryption and decoding in one kernel per block (the double-precision
+// form at n = 4096 with three q primes); false / hipErrorInvalidValue
+// elsewhere.
+bool dec_fused_fits(const DevTabs& T, uint32_t n);
+hipError_t launch_dec_fused(const DevTabs& T, uint32_t n, const uint64_t* scores, int64_t nblk, int64_t blk_lo,
+                            const uint64_t* S, int64_t m, int32_t* out, hipStream_t s);
 hipError_t launch_dec_decode(const DevTabs& T, uint32_t n, const uint64_t* x, int64_t nblk, int64_t blk_lo,
                              int64_t m, int32_t* out, hipStream_t s);
 // top-k of decrypted scores (topk.hip): generic passes over tiles of

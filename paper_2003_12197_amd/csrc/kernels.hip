@@ -1548,6 +1548,60 @@ k_dec_decode(DevTabs T, const uint64_t* __restrict__ x, int64_t blk_lo, int64_t 
   }
 }
 
+// Decryption and slot decoding of one block in one workgroup (App. A Alg.
+// "Decryption", then the slot decode): for each q_sigma in turn,
+// x_sigma = [c0 + c1 s]_{q_sigma} goes through LDS as in k_dec_mul's double-
+// precision form (forward transform of c1, product by the key's transform,
+// inverse transform, plus c0) and stays in registers, PER coefficients per
+// lane; then each coefficient's scale as in k_dec_decode (decrypt_coeff), the
+// forward transform mod t and the centred slots.  The same values as the two
+// kernels, without x in memory.  Transform passes of at most RX stages (every
+// lane busy at n = NT PER with PER = 8 and RX = 3).
+template <int KQ, int NT, int PER, int RX>
+__global__ void __launch_bounds__(NT)
+k_dec_fused(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const uint64_t* __restrict__ S,
+            int64_t m, int32_t* __restrict__ out) {
+  extern __shared__ uint64_t lds64[];
+  const HersConsts& C = *T.C;
+  const uint32_t n = C.n, tid = threadIdx.x;              // n == NT PER (checked at launch)
+  const int64_t bl = blockIdx.x, b = blk_lo + bl;
+  double* f = reinterpret_cast<double*>(lds64);
+  uint32_t* l32 = reinterpret_cast<uint32_t*>(f + padded_len(n));
+  uint64_t x[PER][KQ];
+#pragma unroll
+  for (int sg = 0; sg < KQ; ++sg) {
+    const uint64_t q = C.q[sg];
+    const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
+    const ModQB mb{mf.q, mf.qinv};
+    const uint64_t* c0 = scores + (((size_t)b * 2 + 0) * KQ + sg) * n;
+    const uint64_t* c1 = scores + (((size_t)b * 2 + 1) * KQ + sg) * n;
+    if (sg) __syncthreads();                                 // the previous prime's reads of f are done
+    load_padded(f, c1, n, tid, NT, [](uint64_t v) { return u64_to_f(v); });
+    __syncthreads();
+    ntt_forward_b<RX>(f, T.qtw_f + (size_t)sg * n, mb, n, C.logn, tid, NT, T.ntt_r);
+    for_each_loaded(S + (size_t)sg * n, n, tid, NT,
+                    [&](uint32_t j, uint64_t sv) { f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(sv), 0.0); });
+    __syncthreads();
+    ntt_inverse_b<RX>(f, T.qitw_f + (size_t)sg * n, T.qf[2 * HC_MAXQ + sg], mb, n, C.logn, tid, NT, T.ntt_r);
+    uint64_t cv[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) cv[e] = c0[tid + e * NT];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) x[e][sg] = add_q(f_to_u64(f[PADX(tid + e * NT)]), cv[e], q);
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) l32[PADX(tid + e * NT)] = decrypt_coeff<KQ>(C, x[e]);
+  __syncthreads();
+  ntt_forward16<RX>(l32, T.ttw, T.ttw_sh, ModP{C.t}, n, C.logn, tid, NT, T.ntt_r);
+  const uint32_t t = C.t;
+  for (uint32_t sl = tid; sl < n; sl += NT) {
+    const int64_t item = b * n + sl;
+    if (item >= m) continue;
+    const uint32_t z = l32[PADX(bit_reverse(sl, C.logn))];
+    out[item] = z >= (t + 1) / 2 ? (int32_t)z - (int32_t)t : (int32_t)z;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 namespace hers {
@@ -1842,6 +1896,21 @@ hipError_t launch_dec_mul(const DevTabs& T, uint32_t n, uint32_t k, const uint64
     hipLaunchKernelGGL((k_dec_mul<true, WG>), grid, dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
   else
     hipLaunchKernelGGL((k_dec_mul<false, WG>), grid, dim3(WG), lds_bytes(n, 1), s, T, scores, blk_lo, S, Ssh, x);
+  return hipGetLastError();
+}
+
+bool dec_fused_fits(const DevTabs& T, uint32_t n) {
+  // (five primes at n = 8192 would hold 80 registers of x per lane in 1024-lane
+  // workgroups and spill: they keep the two kernels)
+  return T.qf_ok && T.nq == 3 && n == 4096;
+}
+
+hipError_t launch_dec_fused(const DevTabs& T, uint32_t n, const uint64_t* scores, int64_t nblk, int64_t blk_lo,
+                            const uint64_t* S, int64_t m, int32_t* out, hipStream_t s) {
+  if (!dec_fused_fits(T, n)) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)nblk);
+  const size_t lds = lds_bytes(n, 1) + lds_bytes32(n);
+  hipLaunchKernelGGL((k_dec_fused<3, 512, 8, 3>), grid, dim3(512), lds, s, T, scores, blk_lo, S, m, out);
   return hipGetLastError();
 }
 

@@ -7,7 +7,8 @@ carry.  A valid ciphertext never gets there (t x / q sits near an integer), so
 these score ciphertexts are built to: c1 = 0 and c0 = x with t x / q just
 below and just above a half-integer, beside integers, and at random, one value
 per coefficient.  The decoded slots equal the oracle's decryption of the same
-ciphertexts.  Integer work: tolerance 0.
+ciphertexts, from the one-kernel decryption (n = 4096, three primes) and the
+two-kernel one.  Integer work: tolerance 0.
 """
 
 import random
@@ -59,10 +60,15 @@ def test_decoding_next_to_half_integer(gpu_lib, cfg):
     for b, (c0, _) in blocks.items():
         sc[b, 0] = np.array(fv.to_residues(c0, op.q_primes), dtype=np.int64)
     m = 2 * n - 7                                      # a ragged second block
-    got = ctx.decrypt_scores(sk, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
     want = hers.decrypt_scores(op, osk, blocks, m)
-    assert np.array_equal(got, want)
-    # the loaded-key form too
-    ctx.load_secret_key(sk)
-    got = ctx.decrypt_scores(None, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
-    assert np.array_equal(got, want)
+    try:
+        for fused in (1, 0):                           # one kernel per block (where it fits), then two
+            ctx.set_option("dec_fused", fused)
+            got = ctx.decrypt_scores(sk, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
+            assert np.array_equal(got, want), fused
+            # the loaded-key form too
+            ctx.load_secret_key(sk)
+            got = ctx.decrypt_scores(None, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
+            assert np.array_equal(got, want), fused
+    finally:
+        ctx.set_option("dec_fused", 1)
