@@ -59,16 +59,16 @@ def test_decoding_next_to_half_integer(gpu_lib, cfg):
     sc = np.zeros((2, 2, k, n), dtype=np.int64)
     for b, (c0, _) in blocks.items():
         sc[b, 0] = np.array(fv.to_residues(c0, op.q_primes), dtype=np.int64)
-    m = 2 * n - 7                                      # a ragged second block
-    want = hers.decrypt_scores(op, osk, blocks, m)
     try:
-        for fused in (1, 0):                           # one kernel per block (where it fits), then two
-            ctx.set_option("dec_fused", fused)
-            got = ctx.decrypt_scores(sk, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
-            assert np.array_equal(got, want), fused
-            # the loaded-key form too
-            ctx.load_secret_key(sk)
-            got = ctx.decrypt_scores(None, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
-            assert np.array_equal(got, want), fused
+        for m in (2 * n - 7, 1):                       # a ragged second block; a single item
+            want = hers.decrypt_scores(op, osk, {b: blocks[b] for b in range(ctx.blocks(m))}, m)
+            for fused in (1, 0):                       # one kernel per block (where it fits), then two
+                ctx.set_option("dec_fused", fused)
+                got = ctx.decrypt_scores(sk, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
+                assert np.array_equal(got, want), (m, fused)
+                # the loaded-key form too
+                ctx.load_secret_key(sk)
+                got = ctx.decrypt_scores(None, torch.from_numpy(sc).to(ctx.device), m).cpu().numpy()
+                assert np.array_equal(got, want), (m, fused)
     finally:
         ctx.set_option("dec_fused", 1)
