@@ -966,11 +966,23 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
     const int32_t d = G.d;
     const int kcn = (d + 63) / 64;
     const uint32_t p = C.p[r];
-    const uint64_t mu = C.p_mu64[r];
     const uint32_t slot0 = tile * MF_SLOTS;
-    // 2^32 and 2^48 mod p (lower powers of two are below p)
-    const uint32_t w4 = (uint32_t)((1ull << 32) % p), w6 = (uint32_t)(((uint64_t)w4 << 16) % p);
-    const uint64_t off = ((1ull << 62) / p + 1) * p;                   // a multiple of p above |S|
+    // the recombination's constants: 2^(32 + 16 k) mod p for k = 0..3, balanced (|c_k| <= p/2), and
+    // -p^-1 mod 2^32 for one Montgomery reduction by 2^32 (p^-1 by Newton's iteration: p p = 1 mod 8
+    // for odd p, and each step doubles the correct low bits)
+    int32_t cbal[4];
+    {
+      uint64_t v = (1ull << 32) % p;
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        cbal[k4] = v > p / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
+        v = (v << 16) % p;
+      }
+    }
+    uint32_t pinv = p;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) pinv *= 2u - p * pinv;
+    const uint32_t npinv = 0u - pinv;
     // ---- the probes' digits of this slot: per K step, rows (probe, c, dim) staged as [slot][probe][c][dim]
     mf_v4i Ad[MF_KC][8];
 #pragma unroll
@@ -1084,14 +1096,20 @@ k_mac_mfma(DevTabs T, MacBatchArgs A) {
         // acc[j][i] = C_ij of (probe 2R + (cpc >> 1), c = cpc & 1, block cb, c' = cc).  The digit-column
         // sums T_k = sum_{i+j=k} C_ij pair up exactly in int32 (d <= 128: |C_ij| <= 2^21, 2^20 with a
         // digit 3 in [0, 64], 2^19 for C_33): U0 = T0 + 2^8 T1, U1 = T2 + 2^8 T3, U2 = T4 + 2^8 T5,
-        // U3 = T6, each below 2^31 in magnitude, and X = U0 + 2^16 U1 + 2^32 U2 + 2^48 U3, whose terms
-        // with 2^32 and 2^48 taken mod p keep |S| below 2^62
+        // U3 = T6, each below 2^31 in magnitude, and X = U0 + 2^16 U1 + 2^32 U2 + 2^48 U3 mod p.
+        // S = sum_k U_k c_k (c_k = 2^(32 + 16 k) mod p, balanced) is X 2^32 mod p with |S| < 2^32 p;
+        // with m = -S p^-1 mod 2^32, S + m p is divisible by 2^32, and (S + m p) / 2^32, congruent
+        // to X, lies in (-p, 2p): one conditional add and one conditional subtract of p remain
         const int32_t U0 = acc[0][0] + 256 * (acc[0][1] + acc[1][0]);
         const int32_t U1 = (acc[0][2] + acc[1][1] + acc[2][0]) + 256 * (acc[0][3] + acc[1][2] + acc[2][1] + acc[3][0]);
         const int32_t U2 = (acc[1][3] + acc[2][2] + acc[3][1]) + 256 * (acc[2][3] + acc[3][2]);
         const int32_t U3 = acc[3][3];
-        const int64_t S = (int64_t)U0 + (int64_t)U1 * 65536 + (int64_t)U2 * w4 + (int64_t)U3 * w6;
-        const uint32_t X = red_p((uint64_t)(S + (int64_t)off), p, mu);
+        const int64_t S = (int64_t)U0 * cbal[0] + (int64_t)U1 * cbal[1] + (int64_t)U2 * cbal[2] +
+                          (int64_t)U3 * cbal[3];
+        const uint32_t mq = (uint32_t)S * npinv;
+        int32_t xt = (int32_t)(uint32_t)(((uint64_t)S + (uint64_t)mq * p) >> 32);
+        xt += xt < 0 ? (int32_t)p : 0;
+        const uint32_t X = (uint32_t)xt >= p ? (uint32_t)xt - p : (uint32_t)xt;
         const uint32_t Xp = (uint32_t)__shfl_xor((int)X, 17);          // (c, c') swapped
         const uint32_t c = cpc & 1;
         if (c == 0 || cc == 1) {                                       // (0,0) A0, (0,1) A1, (1,1) A2
