@@ -335,13 +335,13 @@ HD bool scale_round_coeff(const HersConsts& C, const uint32_t* x, uint64_t* out)
 #pragma unroll
   for (uint32_t i = 0; i < k; ++i) {
     const uint64_t q = C.q[i];
-    u128 acc = 0;                                   // sum_r y_r (I_r mod q_i) < K 2^91
+    // sum_r y_r (I_r mod q_i) - gamma (J mod q_i) + round(F), offset by 2^8 q_i and reduced once:
+    // gamma <= K <= 32 and |round(F)| < K 2^30 <= 2^35 < 224 q_i (q_i > 2^29), so the sum is
+    // positive, and below 2^8 2^61 + K 2^91 + 2^35 < 2^97
+    u128 acc = ((u128)q << 8) - (u128)gamma * C.fr_J[i] + (u128)(__int128)rf;
 #pragma unroll
     for (uint32_t r = 0; r < K; ++r) acc += (u128)y[r] * C.fr_I[r][i];
-    uint64_t v = sub_q(red128_q(C, acc, i), shoup_q(gamma, C.fr_J[i], C.fr_J_sh[i], q), q);
-    const uint64_t ra = red_q(rf >= 0 ? (uint64_t)rf : (uint64_t)(-rf), q, C.q_mu64[i]);
-    const uint64_t rm = rf >= 0 ? ra : (ra ? q - ra : 0);
-    out[i] = add_q(v, rm, q);
+    out[i] = red128_q(C, acc, i);
 #if defined(__HIP_DEVICE_COMPILE__)
     __builtin_amdgcn_sched_barrier(0);
 #endif
