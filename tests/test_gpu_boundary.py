@@ -177,3 +177,50 @@ def test_probe_of_more_dimensions_than_one_launch(gpu_lib):
     assert np.array_equal(canon.cpu().numpy(), cts_array(hers.encrypt_probe(op, opk, qv, 93), op.q_primes))
     ctx.encrypt_probe_sk(sk, qv, 94, canon=canon)
     assert np.array_equal(canon.cpu().numpy(), cts_array(hers.encrypt_probe_sk(op, osk, qv, 94), op.q_primes))
+
+
+def test_degenerate_calls_are_rejected_and_leave_the_context_usable(gpu_lib):
+    """Degenerate calls fail on the host, before any launch, with their error
+    codes: a search before an evaluation key is loaded, an empty gallery
+    (m = 0) for the search, the no-allocation search, the paper-literal
+    schedule and decryption, workspaces smaller than one block, top-k with
+    k = 0, k > m or m = 0.  The context stays usable: a search afterwards
+    gives the same score ciphertexts as one before, and they decrypt to P^T q."""
+    print("case degenerate calls: n=256 q=3x36 d=3 m=300", flush=True)
+    EINVAL, ESPACE = -1, -4
+    cfg = dict(n=256, qbits=(36, 36, 36), t_bits=20, w_bits=0)
+    d, m = 3, 300
+    ctx = gpu_lib.Context(d_max=8, **cfg)
+    dev = ctx.device
+    gal = torch.zeros(int(ctx.lib.hers_gallery_words(ctx.handle, m, d)), dtype=torch.int32, device=dev)
+    pr = torch.zeros(int(ctx.lib.hers_probe_words(ctx.handle, d)), dtype=torch.int32, device=dev)
+    sc = ctx.new_scores(m)
+    ws = ctx.workspace(gpu_lib.OP_SEARCH, m, d)
+
+    def code_of(call):
+        with pytest.raises(gpu_lib.HersError) as e:
+            call()
+        return _code(e.value)
+
+    assert code_of(lambda: ctx.search(gal, m, d, pr, scores=sc, workspace=ws)) == EINVAL      # no key yet
+    sk, _, _ = ctx.keygen(906)
+    P, qv = synth.uniform_features(907, d, m)
+    gal = ctx.encrypt_gallery(torch.from_numpy(P).to(dev), m, 908)
+    pr = ctx.encrypt_probe(torch.from_numpy(qv).to(dev), 909)
+    before = ctx.search(gal, m, d, pr, workspace=ws).clone()
+    tiny = torch.empty(256, dtype=torch.uint8, device=dev)
+    wsd = ctx.workspace(gpu_lib.OP_DECRYPT, m, 1)
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    assert code_of(lambda: ctx.search(gal, 0, d, pr, scores=sc, workspace=ws)) == EINVAL
+    assert code_of(lambda: ctx.search_noalloc(gal, 0, d, pr, sc)) == EINVAL
+    assert code_of(lambda: ctx.search_literal(gal, 0, d, pr, scores=sc, workspace=ws)) == EINVAL
+    assert code_of(lambda: ctx.decrypt_scores(sk, sc, 0, out=out, workspace=wsd)) == EINVAL
+    assert code_of(lambda: ctx.search(gal, m, d, pr, scores=sc, workspace=tiny)) == ESPACE
+    assert code_of(lambda: ctx.decrypt_scores(sk, sc, m, out=out, workspace=tiny)) == ESPACE
+    dec = ctx.decrypt_scores(sk, before, m, out=out, workspace=wsd)
+    assert code_of(lambda: ctx.topk(dec, m, 0)) == EINVAL
+    assert code_of(lambda: ctx.topk(dec, m, m + 1)) == EINVAL
+    assert code_of(lambda: ctx.topk(dec, 0, 1)) == EINVAL
+    after = ctx.search(gal, m, d, pr, scores=sc, workspace=ws)
+    assert torch.equal(after, before)
+    assert np.array_equal(ctx.decrypt_scores(sk, after, m).cpu().numpy(), hers.plaintext_scores(P, qv))
