@@ -154,7 +154,9 @@ HD void for_each_loaded2(const S* __restrict__ a, const S* __restrict__ b, uint3
 // them back.  Virtual threads of a pass touch disjoint elements, so one
 // barrier per pass suffices (and a single host thread can run them in turn).
 
-template <int R, class M, class T>
+// FIN (the last pass of a transform): each value is reduced to [0, m) before it
+// is stored, which saves the transform a further pass over LDS and a barrier.
+template <int R, bool FIN = false, class M, class T>
 HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t s0, uint32_t tid, uint32_t nthr) {
   constexpr uint32_t E = 1u << R;
   const uint32_t lh = 31 - __builtin_clz(n >> (s0 + R));   // log2 h
@@ -182,14 +184,16 @@ HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = x[j];
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = FIN ? mod.full(x[j]) : x[j];
   }
   HERS_SYNC();
 }
 
-template <int R, class M, class T>
+// FIN (the last pass): each value is scaled by ninv (a full product, [0, m))
+// before it is stored.
+template <int R, bool FIN = false, class M, class T>
 HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint32_t lh0, uint32_t tid,
-                     uint32_t nthr) {
+                     uint32_t nthr, T ninv = T(0), T ninv_sh = T(0)) {
   // stages with half = 2^lh0 .. 2^(lh0+R-1); elements idx = c 2^(lh0+R) + j 2^lh0 + o
   constexpr uint32_t E = 1u << R;
   const uint32_t h = 1u << lh0;
@@ -215,7 +219,7 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = x[j];
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = FIN ? mod.mul(x[j], ninv, ninv_sh) : x[j];
   }
   HERS_SYNC();
 }
@@ -229,16 +233,27 @@ HD void ntt_forward16(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint3
   uint32_t s0 = 0;
   while (s0 < logn) {
     const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
-    switch (r) {
-      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
-      case 3: ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
-      case 2: ntt_fwd_pass<2>(a, tw, twsh, mod, n, s0, tid, nthr); break;
-      default: ntt_fwd_pass<1>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+    if (s0 + r < logn) {
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        case 3: ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        case 2: ntt_fwd_pass<2>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        default: ntt_fwd_pass<1>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      }
+    } else {                                          // the last pass stores reduced values
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4, true>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        case 3: ntt_fwd_pass<3, true>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        case 2: ntt_fwd_pass<2, true>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+        default: ntt_fwd_pass<1, true>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      }
     }
     s0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.full(a[PADX(j)]);
-  HERS_SYNC();
+  if (logn == 0) {
+    for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.full(a[PADX(j)]);
+    HERS_SYNC();
+  }
 }
 
 // Inverse transform in passes of rmax (<= 4) stages, scaled by n^-1; input in [0, 2m),
@@ -250,16 +265,27 @@ HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M m
   uint32_t lh0 = 0;
   while (lh0 < logn) {
     const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
-    switch (r) {
-      case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      case 3: ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      case 2: ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+    if (lh0 + r < logn) {
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        case 3: ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        case 2: ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      }
+    } else {                                          // the last pass stores scaled values
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        case 3: ntt_inv_pass<3, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        case 2: ntt_inv_pass<2, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        default: ntt_inv_pass<1, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+      }
     }
     lh0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
-  HERS_SYNC();
+  if (logn == 0) {
+    for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
+    HERS_SYNC();
+  }
 }
 
 // The inverse transform with passes of at most RMAX stages fixed at compile
@@ -272,16 +298,27 @@ HD void ntt_inverse_upto(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, 
   uint32_t lh0 = 0;
   while (lh0 < logn) {
     const uint32_t r = logn - lh0 < (uint32_t)RMAX ? logn - lh0 : (uint32_t)RMAX;
-    switch (r) {
-      case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      case 3: if constexpr (RMAX >= 3) ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      case 2: if constexpr (RMAX >= 2) ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
-      default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+    if (lh0 + r < logn) {
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        case 3: if constexpr (RMAX >= 3) ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        case 2: if constexpr (RMAX >= 2) ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+        default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      }
+    } else {                                          // the last pass stores scaled values
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        case 3: if constexpr (RMAX >= 3) ntt_inv_pass<3, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        case 2: if constexpr (RMAX >= 2) ntt_inv_pass<2, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+        default: ntt_inv_pass<1, true>(a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh); break;
+      }
     }
     lh0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
-  HERS_SYNC();
+  if (logn == 0) {
+    for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
+    HERS_SYNC();
+  }
 }
 
 // ---- balanced double-precision transforms (every q < 2^45)
@@ -316,7 +353,8 @@ struct ModQB {
   }
 };
 
-template <int R>
+// FIN (the last pass): stored values are brought to [0, q).
+template <int R, bool FIN = false>
 HD void ntt_fwd_pass_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t s0, uint32_t tid,
                        uint32_t nthr) {
   constexpr uint32_t E = 1u << R;
@@ -343,14 +381,15 @@ HD void ntt_fwd_pass_b(double* a, const double* tw, ModQB mod, uint32_t n, uint3
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = mod.red(x[j]);
+    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = FIN ? mod.canon(mod.red(x[j])) : mod.red(x[j]);
   }
   HERS_SYNC();
 }
 
-template <int R>
+// FIN (the last pass): stored values are scaled by ninv and brought to [0, q).
+template <int R, bool FIN = false>
 HD void ntt_inv_pass_b(double* a, const double* itw, ModQB mod, uint32_t n, uint32_t lh0, uint32_t tid,
-                       uint32_t nthr) {
+                       uint32_t nthr, double ninv = 0.0) {
   constexpr uint32_t E = 1u << R;
   const uint32_t h = 1u << lh0;
   const uint32_t vts = n >> R;
@@ -373,7 +412,8 @@ HD void ntt_inv_pass_b(double* a, const double* itw, ModQB mod, uint32_t n, uint
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = mod.red(x[j]);
+    for (uint32_t j = 0; j < E; ++j)
+      a[PADX(base + j * h)] = FIN ? mod.canon(mod.mul(mod.red(x[j]), ninv)) : mod.red(x[j]);
   }
   HERS_SYNC();
 }
@@ -386,16 +426,27 @@ HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32
   uint32_t s0 = 0;
   while (s0 < logn) {
     const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
-    switch (r) {
-      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_b<4>(a, tw, mod, n, s0, tid, nthr); break;
-      case 3: ntt_fwd_pass_b<3>(a, tw, mod, n, s0, tid, nthr); break;
-      case 2: ntt_fwd_pass_b<2>(a, tw, mod, n, s0, tid, nthr); break;
-      default: ntt_fwd_pass_b<1>(a, tw, mod, n, s0, tid, nthr); break;
+    if (s0 + r < logn) {
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_b<4>(a, tw, mod, n, s0, tid, nthr); break;
+        case 3: ntt_fwd_pass_b<3>(a, tw, mod, n, s0, tid, nthr); break;
+        case 2: ntt_fwd_pass_b<2>(a, tw, mod, n, s0, tid, nthr); break;
+        default: ntt_fwd_pass_b<1>(a, tw, mod, n, s0, tid, nthr); break;
+      }
+    } else {                                          // the last pass stores values in [0, q)
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_b<4, true>(a, tw, mod, n, s0, tid, nthr); break;
+        case 3: ntt_fwd_pass_b<3, true>(a, tw, mod, n, s0, tid, nthr); break;
+        case 2: ntt_fwd_pass_b<2, true>(a, tw, mod, n, s0, tid, nthr); break;
+        default: ntt_fwd_pass_b<1, true>(a, tw, mod, n, s0, tid, nthr); break;
+      }
     }
     s0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(a[PADX(j)]);
-  HERS_SYNC();
+  if (logn == 0) {
+    for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(a[PADX(j)]);
+    HERS_SYNC();
+  }
 }
 
 // Inverse transform scaled by n^-1 (ninv in [0, q)) of values of magnitude
@@ -407,16 +458,27 @@ HD void ntt_inverse_b(double* a, const double* itw, double ninv, ModQB mod, uint
   uint32_t lh0 = 0;
   while (lh0 < logn) {
     const uint32_t r = logn - lh0 < rmax ? logn - lh0 : rmax;
-    switch (r) {
-      case 4: if constexpr (RMAX >= 4) ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
-      case 3: ntt_inv_pass_b<3>(a, itw, mod, n, lh0, tid, nthr); break;
-      case 2: ntt_inv_pass_b<2>(a, itw, mod, n, lh0, tid, nthr); break;
-      default: ntt_inv_pass_b<1>(a, itw, mod, n, lh0, tid, nthr); break;
+    if (lh0 + r < logn) {
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
+        case 3: ntt_inv_pass_b<3>(a, itw, mod, n, lh0, tid, nthr); break;
+        case 2: ntt_inv_pass_b<2>(a, itw, mod, n, lh0, tid, nthr); break;
+        default: ntt_inv_pass_b<1>(a, itw, mod, n, lh0, tid, nthr); break;
+      }
+    } else {                                          // the last pass stores scaled values in [0, q)
+      switch (r) {
+        case 4: if constexpr (RMAX >= 4) ntt_inv_pass_b<4, true>(a, itw, mod, n, lh0, tid, nthr, ninv); break;
+        case 3: ntt_inv_pass_b<3, true>(a, itw, mod, n, lh0, tid, nthr, ninv); break;
+        case 2: ntt_inv_pass_b<2, true>(a, itw, mod, n, lh0, tid, nthr, ninv); break;
+        default: ntt_inv_pass_b<1, true>(a, itw, mod, n, lh0, tid, nthr, ninv); break;
+      }
     }
     lh0 += r;
   }
-  for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(mod.mul(a[PADX(j)], ninv));
-  HERS_SYNC();
+  if (logn == 0) {
+    for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(mod.mul(a[PADX(j)], ninv));
+    HERS_SYNC();
+  }
 }
 
 HD uint32_t bit_reverse(uint32_t x, uint32_t bits) {
