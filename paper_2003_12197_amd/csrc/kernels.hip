@@ -1413,7 +1413,38 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
 #pragma unroll PER
     for (uint32_t e = 0; e < PER; ++e) pre[e] = tid + e * nthr < n ? digits[tid + e * nthr] : 0;
   }
+  // double-precision form with the transforms' edge passes in registers: the
+  // first forward pass on the digit as loaded, the last inverse pass on the
+  // way out (a lane's PER coefficients tid + e n / PER are those passes'
+  // elements when the workgroup has n / PER lanes and the passes may span
+  // log2 PER stages)
+  constexpr int LP = PER >= 16 ? 4 : 3;
+  const bool edge_regs = QF && !PF && (nthr << LP) == n && C.logn > (uint32_t)LP && T.ntt_r >= (uint32_t)LP;
   for (uint32_t g = 0; g < L; ++g) {
+    if constexpr (QF && !PF) {
+      if (edge_regs) {
+        const uint64_t* dg = digits + (size_t)g * k * n;
+        double x[PER];
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) x[e] = in(red_dig(dg[tid + e * nthr]));
+        const ModQB mb{mod.q, mod.qinv};
+        ntt_fwd_first_regs_b<LP>(x, tw, mb);
+        __syncthreads();                                // previous digit's products read
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) a[PADX(tid + e * nthr)] = x[e];
+        __syncthreads();
+        ntt_forward_b_from<RX>(a, tw, mb, n, C.logn, LP, tid, nthr, T.ntt_r);
+        const size_t k0 = (((size_t)g * 2 + 0) * k + sg) * n, k1 = (((size_t)g * 2 + 1) * k + sg) * n;
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) {
+          const uint32_t j = tid + e * nthr;
+          const E D = a[PADX(j)];
+          acc0[e] = mac(acc0[e], D, key[k0 + j], key_sh[k0 + j]);
+          acc1[e] = mac(acc1[e], D, key[k1 + j], key_sh[k1 + j]);
+        }
+        continue;
+      }
+    }
     __syncthreads();                                    // previous digit's products read
     if constexpr (PF) {
 #pragma unroll PER
@@ -1453,6 +1484,23 @@ k_relin_fused(DevTabs T, const uint64_t* __restrict__ digits_b, int64_t blk_lo, 
     for (uint32_t e = 0; e < PER; ++e)
       if (tid + e * nthr < n) a[PADX(tid + e * nthr)] = comp ? acc1[e] : acc0[e];
     __syncthreads();
+    if constexpr (QF && !PF) {
+      if (edge_regs) {
+        const ModQB mb{mod.q, mod.qinv};
+        ntt_inverse_b_upto<RX>(a, itw, mb, n, C.logn - LP, tid, nthr, T.ntt_r);
+        double x[PER];
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) x[e] = a[PADX(tid + e * nthr)];
+        ntt_inv_last_regs_b<LP>(x, itw, ninv, mb);
+        uint64_t* dst = SP.p[blockIdx.z] + (((size_t)b * 2 + comp) * k + sg) * n;
+#pragma unroll PER
+        for (uint32_t e = 0; e < PER; ++e) {
+          const uint32_t j = tid + e * nthr;
+          dst[j] = add_q(dst[j], out(x[e]), q);
+        }
+        continue;
+      }
+    }
     if constexpr (QF)
       ntt_inverse_b<RX>(a, itw, ninv, ModQB{mod.q, mod.qinv}, n, C.logn, tid, nthr, T.ntt_r);
     else

@@ -418,12 +418,13 @@ HD void ntt_inv_pass_b(double* a, const double* itw, ModQB mod, uint32_t n, uint
   HERS_SYNC();
 }
 
-// Forward transform of values in [0, q) (or of magnitude <= q); output in [0, q).
+// Stages s_begin .. logn - 1 of the forward transform below, on the values its
+// earlier passes stored; output in [0, q).
 template <int RMAX = 4>
-HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t logn, uint32_t tid,
-                      uint32_t nthr, uint32_t rmax = 4) {
+HD void ntt_forward_b_from(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t logn, uint32_t s_begin,
+                           uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
   if (rmax > (uint32_t)RMAX) rmax = RMAX;
-  uint32_t s0 = 0;
+  uint32_t s0 = s_begin;
   while (s0 < logn) {
     const uint32_t r = logn - s0 < rmax ? logn - s0 : rmax;
     if (s0 + r < logn) {
@@ -443,10 +444,17 @@ HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32
     }
     s0 += r;
   }
-  if (logn == 0) {
+  if (s_begin >= logn) {
     for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(a[PADX(j)]);
     HERS_SYNC();
   }
+}
+
+// Forward transform of values in [0, q) (or of magnitude <= q); output in [0, q).
+template <int RMAX = 4>
+HD void ntt_forward_b(double* a, const double* tw, ModQB mod, uint32_t n, uint32_t logn, uint32_t tid,
+                      uint32_t nthr, uint32_t rmax = 4) {
+  ntt_forward_b_from<RMAX>(a, tw, mod, n, logn, 0, tid, nthr, rmax);
 }
 
 // Inverse transform scaled by n^-1 (ninv in [0, q)) of values of magnitude
@@ -479,6 +487,71 @@ HD void ntt_inverse_b(double* a, const double* itw, double ninv, ModQB mod, uint
     for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.canon(mod.mul(a[PADX(j)], ninv));
     HERS_SYNC();
   }
+}
+
+// The inverse transform's stages of half 2^0 .. 2^(lh_end - 1), without the
+// scaling: the passes before a last pass that the caller runs itself.
+template <int RMAX = 4>
+HD void ntt_inverse_b_upto(double* a, const double* itw, ModQB mod, uint32_t n, uint32_t lh_end, uint32_t tid,
+                           uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
+  uint32_t lh0 = 0;
+  while (lh0 < lh_end) {
+    const uint32_t r = lh_end - lh0 < rmax ? lh_end - lh0 : rmax;
+    switch (r) {
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass_b<4>(a, itw, mod, n, lh0, tid, nthr); break;
+      case 3: ntt_inv_pass_b<3>(a, itw, mod, n, lh0, tid, nthr); break;
+      case 2: ntt_inv_pass_b<2>(a, itw, mod, n, lh0, tid, nthr); break;
+      default: ntt_inv_pass_b<1>(a, itw, mod, n, lh0, tid, nthr); break;
+    }
+    lh0 += r;
+  }
+}
+
+// ---- balanced passes in registers, at the edges of a transform
+// With n / 2^R lanes, the elements tid + j n / 2^R (j < 2^R) of lane tid are
+// exactly those of one virtual thread of the first forward pass (stages
+// 0 .. R-1) and of the last inverse pass (halves n / 2^R .. n / 2).  A kernel
+// holding them in registers runs those passes there, which saves a round trip
+// through LDS and a barrier; the butterflies and reductions are those of
+// ntt_fwd_pass_b / ntt_inv_pass_b, so the values are the same.
+template <int R>
+HD void ntt_fwd_first_regs_b(double (&x)[1 << R], const double* tw, ModQB mod) {
+  constexpr uint32_t E = 1u << R;
+#pragma unroll
+  for (uint32_t t = 0; t < R; ++t) {
+    const uint32_t span = E >> (t + 1);
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+      if (j & span) continue;
+      const double v = mod.mul(x[j + span], tw[(1u << t) + j / (2 * span)]);
+      const double u = x[j];
+      x[j] = u + v;
+      x[j + span] = u - v;
+    }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < E; ++j) x[j] = mod.red(x[j]);
+}
+
+// The last inverse pass on values stored by the earlier passes, scaled by
+// ninv: output in [0, q).
+template <int R>
+HD void ntt_inv_last_regs_b(double (&x)[1 << R], const double* itw, double ninv, ModQB mod) {
+  constexpr uint32_t E = 1u << R;
+#pragma unroll
+  for (uint32_t t = 0; t < R; ++t) {
+    const uint32_t span = 1u << t;
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+      if (j & span) continue;
+      const double u = x[j], v = x[j + span];
+      x[j] = u + v;
+      x[j + span] = mod.mul(u - v, itw[(E >> (t + 1)) + (j >> (t + 1))]);
+    }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < E; ++j) x[j] = mod.canon(mod.mul(mod.red(x[j]), ninv));
 }
 
 HD uint32_t bit_reverse(uint32_t x, uint32_t bits) {
