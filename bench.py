@@ -214,7 +214,11 @@ def search_traffic(ctx, M, d, mac_variant, search_ms):
     chunks = max(1, ctx.get_option("overlap_chunks"))
     opt = ctx.get_option("relin_fuse_min_wgs")
     cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
-    threshold = opt if opt else (8 * cus if n >= 8192 else float("inf"))
+    # the library's default: 8 workgroups per CU at n >= 8192; below, always
+    # where the fused kernel's double-precision 8-per-lane form applies
+    edge = (max(int(x) for x in ctx.q) < (1 << 45) and ctx.get_option("relin_lane_coeffs") == 8
+            and ctx.get_option("ntt_radix_log2") >= 3 and n >= 128)
+    threshold = opt if opt else (8 * cus if n >= 8192 else (1 if edge else float("inf")))
     fused = -(-M // chunks) * k >= threshold
     relin = M * (L * n * 8 + (0 if fused else 2 * L * k * n * 8) + 2 * 2 * k * n * 8) + L * 2 * k * n * 8
     total = mac + intt + rescale + relin

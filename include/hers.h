@@ -414,7 +414,9 @@ int hers_rerank_decrypt(hers_ctx* ctx, const uint8_t* sk_dev, const uint64_t* ct
  *                  transforms, key products, inverse transforms without the
  *                  transformed digits in memory; smaller ones as two kernels
  *                  with more workgroups.  0 = 8 per compute unit at
- *                  n >= 8192, never below; 1 = always.
+ *                  n >= 8192; below n = 8192 always where every q_i <
+ *                  2^45, "relin_lane_coeffs" is 8 and "ntt_radix_log2" is at
+ *                  least 3, else never; 1 = always.
  *   "dec_fused"    1 (default): hers_decrypt_scores in one kernel per block
  *                  where it fits (double-precision arithmetic, n = 4096,
  *                  three q primes), [c0 + c1 s]_q kept in registers; 0: the

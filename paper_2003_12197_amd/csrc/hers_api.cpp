@@ -838,11 +838,17 @@ int hers_export_probe(hers_ctx* ctx, const uint32_t* probe_dev, uint64_t probe_w
 
 // Relinearization launches with at least this many workgroups use the fused
 // kernel.  Default: 8 per CU at n >= 8192 (measured faster there: each
-// transformed digit saved is 64 KB); at smaller n the two-kernel form, whose
-// launches keep more waves per CU, measured faster at every size.
+// transformed digit saved is 64 KB).  Below n = 8192, the double-precision
+// form of 8 coefficients per lane, whose transforms run their first and last
+// passes in registers, measured 15-27% faster than the two-kernel form at
+// every launch size at n = 4096 (16 to 4096 blocks), so it is always used
+// where it applies (primes below 2^45, passes of at least 3 stages); other
+// parameter sets below n = 8192 keep the two-kernel form.
 static uint32_t fuse_wgs(const hers_ctx* ctx) {
   if (ctx->relin_fuse_min_wgs) return (uint32_t)ctx->relin_fuse_min_wgs;
-  return ctx->host.C.n >= 8192 ? 8u * (uint32_t)ctx->num_cus : 0xffffffffu;
+  if (ctx->host.C.n >= 8192) return 8u * (uint32_t)ctx->num_cus;
+  const bool edge_form = ctx->T.qf_ok && ctx->T.rl_per == 8 && ctx->T.ntt_r >= 3 && ctx->host.C.n >= 128;
+  return edge_form ? 1u : 0xffffffffu;
 }
 
 static bool mac_fused(const hers_ctx* ctx) { return ctx->mac_variant == MAC_FUSED_INTT; }
