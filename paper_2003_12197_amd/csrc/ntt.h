@@ -189,11 +189,12 @@ HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32
   HERS_SYNC();
 }
 
-// FIN (the last pass): each value is scaled by ninv (a full product, [0, m))
-// before it is stored.
-template <int R, bool FIN = false, class M, class T>
-HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint32_t lh0, uint32_t tid,
-                     uint32_t nthr, T ninv = T(0), T ninv_sh = T(0)) {
+// One inverse pass from src to dst, each in LDS (padded index) or, with
+// SRC_G / DST_G, in global memory (plain index).  FIN (the last pass): each
+// value is scaled by ninv (a full product, [0, m)) before it is stored.
+template <int R, bool SRC_G, bool DST_G, bool FIN, class M, class T>
+HD void ntt_inv_pass_io(const T* src, T* dst, const T* itw, const T* itwsh, M mod, uint32_t n, uint32_t lh0,
+                        uint32_t tid, uint32_t nthr, T ninv, T ninv_sh) {
   // stages with half = 2^lh0 .. 2^(lh0+R-1); elements idx = c 2^(lh0+R) + j 2^lh0 + o
   constexpr uint32_t E = 1u << R;
   const uint32_t h = 1u << lh0;
@@ -203,7 +204,7 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
     const uint32_t base = (c << (lh0 + R)) + o;
     T x[E];
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+    for (uint32_t j = 0; j < E; ++j) x[j] = SRC_G ? src[base + j * h] : src[PADX(base + j * h)];
 #pragma unroll
     for (uint32_t t = 0; t < R; ++t) {                // half = 2^(lh0+t): pairs (j, j + 2^t)
       const uint32_t span = 1u << t;
@@ -219,9 +220,19 @@ HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = FIN ? mod.mul(x[j], ninv, ninv_sh) : x[j];
+    for (uint32_t j = 0; j < E; ++j) {
+      const T v = FIN ? mod.mul(x[j], ninv, ninv_sh) : x[j];
+      if constexpr (DST_G) dst[base + j * h] = v;
+      else dst[PADX(base + j * h)] = v;
+    }
   }
   HERS_SYNC();
+}
+
+template <int R, bool FIN = false, class M, class T>
+HD void ntt_inv_pass(T* a, const T* itw, const T* itwsh, M mod, uint32_t n, uint32_t lh0, uint32_t tid,
+                     uint32_t nthr, T ninv = T(0), T ninv_sh = T(0)) {
+  ntt_inv_pass_io<R, false, false, FIN>(a, a, itw, itwsh, mod, n, lh0, tid, nthr, ninv, ninv_sh);
 }
 
 // Forward transform in passes of rmax (<= 4) stages; input in [0, 4m), output in [0, m).
@@ -285,6 +296,58 @@ HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M m
   if (logn == 0) {
     for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
     HERS_SYNC();
+  }
+}
+
+// The inverse transform (as ntt_inverse16, input in [0, 2m), output in
+// [0, m)) of the n words at g in global memory, in place, with the LDS buffer
+// a: the first pass reads g and the last pass writes g (scaled by ninv), so
+// the polynomial makes two fewer trips through LDS than a load into LDS,
+// ntt_inverse16 and a store would.  With more stages than one pass holds, the
+// last pass takes as many stages as it can and the middle passes the rest.
+template <int RMAX = 4, class M, class T>
+HD void ntt_inverse16_g(T* g, T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M mod, uint32_t n,
+                        uint32_t logn, uint32_t tid, uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
+  if (rmax < 1) rmax = 1;
+  if (logn <= rmax) {                                   // one pass, global to global
+    switch (logn) {
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass_io<4, true, true, true>(g, g, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+      case 3: if constexpr (RMAX >= 3) ntt_inv_pass_io<3, true, true, true>(g, g, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+      case 2: if constexpr (RMAX >= 2) ntt_inv_pass_io<2, true, true, true>(g, g, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+      case 1: ntt_inv_pass_io<1, true, true, true>(g, g, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+      default:
+        for (uint32_t j = tid; j < n; j += nthr) g[j] = mod.mul(g[j], ninv, ninv_sh);
+        HERS_SYNC();
+        break;
+    }
+    return;
+  }
+  const uint32_t r0 = rmax;
+  const uint32_t rl = logn - r0 < rmax ? logn - r0 : rmax;
+  switch (r0) {                                         // first pass: global to LDS
+    case 4: if constexpr (RMAX >= 4) ntt_inv_pass_io<4, true, false, false>(g, a, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+    case 3: if constexpr (RMAX >= 3) ntt_inv_pass_io<3, true, false, false>(g, a, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+    case 2: if constexpr (RMAX >= 2) ntt_inv_pass_io<2, true, false, false>(g, a, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+    default: ntt_inv_pass_io<1, true, false, false>(g, a, itw, itwsh, mod, n, 0, tid, nthr, ninv, ninv_sh); break;
+  }
+  const uint32_t lh_last = logn - rl;
+  uint32_t lh0 = r0;
+  while (lh0 < lh_last) {                               // middle passes in LDS
+    const uint32_t r = lh_last - lh0 < rmax ? lh_last - lh0 : rmax;
+    switch (r) {
+      case 4: if constexpr (RMAX >= 4) ntt_inv_pass<4>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 3: if constexpr (RMAX >= 3) ntt_inv_pass<3>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      case 2: if constexpr (RMAX >= 2) ntt_inv_pass<2>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+      default: ntt_inv_pass<1>(a, itw, itwsh, mod, n, lh0, tid, nthr); break;
+    }
+    lh0 += r;
+  }
+  switch (rl) {                                         // last pass: LDS to global, scaled
+    case 4: if constexpr (RMAX >= 4) ntt_inv_pass_io<4, false, true, true>(a, g, itw, itwsh, mod, n, lh_last, tid, nthr, ninv, ninv_sh); break;
+    case 3: if constexpr (RMAX >= 3) ntt_inv_pass_io<3, false, true, true>(a, g, itw, itwsh, mod, n, lh_last, tid, nthr, ninv, ninv_sh); break;
+    case 2: if constexpr (RMAX >= 2) ntt_inv_pass_io<2, false, true, true>(a, g, itw, itwsh, mod, n, lh_last, tid, nthr, ninv, ninv_sh); break;
+    default: ntt_inv_pass_io<1, false, true, true>(a, g, itw, itwsh, mod, n, lh_last, tid, nthr, ninv, ninv_sh); break;
   }
 }
 
