@@ -162,7 +162,8 @@ def cpu_baseline(cfg, qv, m, probes, log):
     dims = d if d <= 64 else 8
     t0 = time.perf_counter()
     oq = hers.encrypt_probe(op, pk, qv[:dims], PROBE_SEED)
-    t_probe = (time.perf_counter() - t0) * d / dims
+    t_probe_meas = time.perf_counter() - t0
+    t_probe = t_probe_meas * d / dims
     M = (m + n - 1) // n
     blocks = sorted({int(b) for b in np.linspace(0, M - 1, workers)}) if M > workers else list(range(M))
     ctx = mp.get_context("spawn")          # fresh interpreters: the workers never touch the GPU
@@ -179,15 +180,20 @@ def cpu_baseline(cfg, qv, m, probes, log):
     for p in procs:
         p.join()
     start, end = min(r[1] for r in res), max(r[2] for r in res)
-    t_par = (end - start) * d / dims            # W blocks at once (tensor part scaled for d > 64)
+    t_par_meas = end - start
+    t_par = t_par_meas * d / dims               # W blocks at once (tensor part scaled for d > 64)
     ok = all(r[3] for r in res)
     total = probes * (t_probe + M / len(blocks) * t_par)
-    sample = ("probe encryption (%d dims) %.1f s in one process; %d gallery blocks of %d items searched and "
-              "decrypted at once by %d processes in %.1f s%s; scaled to %d blocks x %d probe(s); scores "
-              "equal P^T q on the sample: %s" % (
-                  d, t_probe, len(blocks), n, len(blocks), t_par,
-                  "" if dims == d else " (%d of %d dimensions, scaled x%g)" % (dims, d, d / dims),
-                  M, probes, ok))
+    if dims == d:
+        sample = ("probe encryption (%d dims) %.1f s in one process; %d gallery blocks of %d items searched and "
+                  "decrypted at once by %d processes in %.1f s; scaled to %d blocks x %d probe(s); scores "
+                  "equal P^T q on the sample: %s" % (d, t_probe, len(blocks), n, len(blocks), t_par, M, probes, ok))
+    else:
+        sample = ("probe encryption of %d of %d dims %.1f s in one process (x%g: %.1f s); %d gallery blocks of %d "
+                  "items searched over %d of %d dimensions and decrypted at once by %d processes in %.1f s (x%g: "
+                  "%.1f s); scaled to %d blocks x %d probe(s); scores equal P^T q on the sample's dimensions: %s" % (
+                      dims, d, t_probe_meas, d / dims, t_probe, len(blocks), n, dims, d, len(blocks), t_par_meas,
+                      d / dims, t_par, M, probes, ok))
     return {"value": m * probes / total, "unit": "scores/s", "cores": len(blocks), "host_cpu_count": host_cpus,
             "kind": "oracle", "sample": sample}
 
