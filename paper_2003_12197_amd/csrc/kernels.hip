@@ -1553,10 +1553,35 @@ k_dec_mul(DevTabs T, const uint64_t* __restrict__ scores, int64_t blk_lo, const 
     // the same product in double precision: transforms balanced (ModQB), product by ModQF
     double* f = reinterpret_cast<double*>(lds64);
     const ModQF mf{T.qf[sg], T.qf[HC_MAXQ + sg]};
-    load_padded(f, c1, n, tid, NT, [](uint64_t v) { return u64_to_f(v); });
-    __syncthreads();
     const double* twf = T.qtw_f + (size_t)sg * n;
     const ModQB mb{mf.q, mf.qinv};
+    if (n == 16u * NT && C.logn > 4 && T.ntt_r >= 4) {
+      // 16 coefficients per lane, tid + e NT: the elements of the first
+      // forward pass and of the last inverse pass, which run in registers on
+      // c1 as loaded and on the way out (as in k_relin_fused)
+      const double* itwf = T.qitw_f + (size_t)sg * n;
+      double xr[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xr[e] = u64_to_f(c1[tid + e * NT]);
+      ntt_fwd_first_regs_b<4>(xr, twf, mb);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) f[PADX(tid + e * NT)] = xr[e];
+      __syncthreads();
+      ntt_forward_b_from<4>(f, twf, mb, n, C.logn, 4, tid, NT, T.ntt_r);
+      for_each_loaded(S + (size_t)sg * n, n, tid, NT,
+                      [&](uint32_t j, uint64_t sv) { f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(sv), 0.0); });
+      __syncthreads();
+      ntt_inverse_b_upto<4>(f, itwf, mb, n, C.logn - 4, tid, NT, T.ntt_r);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xr[e] = f[PADX(tid + e * NT)];
+      ntt_inv_last_regs_b<4>(xr, itwf, T.qf[2 * HC_MAXQ + sg], mb);
+      uint64_t* xo = xout + ((size_t)bl * k + sg) * n;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xo[tid + e * NT] = add_q(f_to_u64(xr[e]), c0[tid + e * NT], q);
+      return;
+    }
+    load_padded(f, c1, n, tid, NT, [](uint64_t v) { return u64_to_f(v); });
+    __syncthreads();
     ntt_forward_b(f, twf, mb, n, C.logn, tid, NT, T.ntt_r);
     for_each_loaded(S + (size_t)sg * n, n, tid, NT,
                     [&](uint32_t j, uint64_t sv) { f[PADX(j)] = mf.mul(f[PADX(j)], u64_to_f(sv), 0.0); });
