@@ -393,7 +393,8 @@ k_check_canon(DevTabs T, const uint64_t* __restrict__ canon, uint64_t words, uin
   if (bad) atomicOr(flag, 1u);
 }
 
-extern "C" __global__ void __launch_bounds__(WG)
+// (at least 5 waves per SIMD: the register budget the inverse direction fits)
+extern "C" __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5)))
 k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, uint64_t req_stride) {
   // In-place negacyclic NTT mod p_r of polynomial blockIdx.x of set
   // blockIdx.y (at polys + blockIdx.y * req_stride words), where
@@ -404,17 +405,13 @@ k_ntt_p(DevTabs T, uint32_t* __restrict__ polys, uint32_t inner, int inverse, ui
   const uint32_t r = (blockIdx.x / inner) % C.K;
   uint32_t* a = polys + (size_t)blockIdx.y * req_stride + (size_t)blockIdx.x * n;
   const ModP mp{C.p[r]};
-  if (inverse) {
-    // the first pass reads the polynomial from memory and the last one writes
-    // it back, so it crosses LDS two times fewer than a load, transform and store
+  // the first pass reads the polynomial from memory and the last one writes
+  // it back, so it crosses LDS two times fewer than a load, transform and store
+  if (inverse)
     ntt_inverse16_g(a, lds32, T.pitw + (size_t)r * n, T.pitw_sh + (size_t)r * n, C.p_ninv[r], C.p_ninv_sh[r], mp,
                     n, C.logn, tid, WG, T.ntt_r);
-    return;
-  }
-  load_padded(lds32, a, n, tid, WG, [](uint32_t v) { return v; });
-  __syncthreads();
-  ntt_forward16(lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG, T.ntt_r);
-  for (uint32_t j = tid; j < n; j += WG) a[j] = lds32[PADX(j)];
+  else
+    ntt_forward16_g(a, lds32, T.ptw + (size_t)r * n, T.ptw_sh + (size_t)r * n, mp, n, C.logn, tid, WG, T.ntt_r);
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));

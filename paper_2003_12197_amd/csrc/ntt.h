@@ -154,10 +154,13 @@ HD void for_each_loaded2(const S* __restrict__ a, const S* __restrict__ b, uint3
 // them back.  Virtual threads of a pass touch disjoint elements, so one
 // barrier per pass suffices (and a single host thread can run them in turn).
 
-// FIN (the last pass of a transform): each value is reduced to [0, m) before it
-// is stored, which saves the transform a further pass over LDS and a barrier.
-template <int R, bool FIN = false, class M, class T>
-HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t s0, uint32_t tid, uint32_t nthr) {
+// One forward pass from src to dst, each in LDS (padded index) or, with
+// SRC_G / DST_G, in global memory (plain index).  FIN (the last pass of a
+// transform): each value is reduced to [0, m) before it is stored, which saves
+// the transform a further pass over LDS and a barrier.
+template <int R, bool SRC_G, bool DST_G, bool FIN, class M, class T>
+HD void ntt_fwd_pass_io(const T* src, T* dst, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t s0,
+                        uint32_t tid, uint32_t nthr) {
   constexpr uint32_t E = 1u << R;
   const uint32_t lh = 31 - __builtin_clz(n >> (s0 + R));   // log2 h
   const uint32_t h = 1u << lh;
@@ -167,7 +170,7 @@ HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32
     const uint32_t base = (c << (lh + R)) + o;
     T x[E];
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) x[j] = a[PADX(base + j * h)];
+    for (uint32_t j = 0; j < E; ++j) x[j] = SRC_G ? src[base + j * h] : src[PADX(base + j * h)];
 #pragma unroll
     for (uint32_t t = 0; t < R; ++t) {                // stage s0 + t: pairs (j, j + E/2^(t+1))
       const uint32_t span = E >> (t + 1);
@@ -184,9 +187,18 @@ HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < E; ++j) a[PADX(base + j * h)] = FIN ? mod.full(x[j]) : x[j];
+    for (uint32_t j = 0; j < E; ++j) {
+      const T v = FIN ? mod.full(x[j]) : x[j];
+      if constexpr (DST_G) dst[base + j * h] = v;
+      else dst[PADX(base + j * h)] = v;
+    }
   }
   HERS_SYNC();
+}
+
+template <int R, bool FIN = false, class M, class T>
+HD void ntt_fwd_pass(T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t s0, uint32_t tid, uint32_t nthr) {
+  ntt_fwd_pass_io<R, false, false, FIN>(a, a, tw, twsh, mod, n, s0, tid, nthr);
 }
 
 // One inverse pass from src to dst, each in LDS (padded index) or, with
@@ -297,6 +309,61 @@ HD void ntt_inverse16(T* a, const T* itw, const T* itwsh, T ninv, T ninv_sh, M m
     for (uint32_t j = tid; j < n; j += nthr) a[PADX(j)] = mod.mul(a[PADX(j)], ninv, ninv_sh);
     HERS_SYNC();
   }
+}
+
+// The forward transform (as ntt_forward16, input in [0, 4m), output in
+// [0, m)) of the n words at g in global memory, in place, with the LDS buffer
+// a: the first pass reads g (consecutive words across the lanes), and the
+// result goes back to g from LDS (the last pass's own elements are
+// consecutive words per lane, which would make every store instruction
+// strided): one trip through LDS fewer than a load into LDS, ntt_forward16
+// and a store.  With more stages than one pass holds, the last pass takes as
+// many stages as it can and the middle passes the rest.
+template <int RMAX = 4, class M, class T>
+HD void ntt_forward16_g(T* g, T* a, const T* tw, const T* twsh, M mod, uint32_t n, uint32_t logn, uint32_t tid,
+                        uint32_t nthr, uint32_t rmax = 4) {
+  if (rmax > (uint32_t)RMAX) rmax = RMAX;
+  if (rmax < 1) rmax = 1;
+  if (logn <= rmax) {                                   // one pass, global to global
+    switch (logn) {
+      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_io<4, true, true, true>(g, g, tw, twsh, mod, n, 0, tid, nthr); break;
+      case 3: if constexpr (RMAX >= 3) ntt_fwd_pass_io<3, true, true, true>(g, g, tw, twsh, mod, n, 0, tid, nthr); break;
+      case 2: if constexpr (RMAX >= 2) ntt_fwd_pass_io<2, true, true, true>(g, g, tw, twsh, mod, n, 0, tid, nthr); break;
+      case 1: ntt_fwd_pass_io<1, true, true, true>(g, g, tw, twsh, mod, n, 0, tid, nthr); break;
+      default:
+        for (uint32_t j = tid; j < n; j += nthr) g[j] = mod.full(g[j]);
+        HERS_SYNC();
+        break;
+    }
+    return;
+  }
+  const uint32_t r0 = rmax;
+  const uint32_t rl = logn - r0 < rmax ? logn - r0 : rmax;
+  switch (r0) {                                         // first pass: global to LDS
+    case 4: if constexpr (RMAX >= 4) ntt_fwd_pass_io<4, true, false, false>(g, a, tw, twsh, mod, n, 0, tid, nthr); break;
+    case 3: if constexpr (RMAX >= 3) ntt_fwd_pass_io<3, true, false, false>(g, a, tw, twsh, mod, n, 0, tid, nthr); break;
+    case 2: if constexpr (RMAX >= 2) ntt_fwd_pass_io<2, true, false, false>(g, a, tw, twsh, mod, n, 0, tid, nthr); break;
+    default: ntt_fwd_pass_io<1, true, false, false>(g, a, tw, twsh, mod, n, 0, tid, nthr); break;
+  }
+  const uint32_t s_last = logn - rl;
+  uint32_t s0 = r0;
+  while (s0 < s_last) {                                 // middle passes in LDS
+    const uint32_t r = s_last - s0 < rmax ? s_last - s0 : rmax;
+    switch (r) {
+      case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      case 3: if constexpr (RMAX >= 3) ntt_fwd_pass<3>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      case 2: if constexpr (RMAX >= 2) ntt_fwd_pass<2>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+      default: ntt_fwd_pass<1>(a, tw, twsh, mod, n, s0, tid, nthr); break;
+    }
+    s0 += r;
+  }
+  switch (rl) {                                         // last pass in LDS, reduced
+    case 4: if constexpr (RMAX >= 4) ntt_fwd_pass<4, true>(a, tw, twsh, mod, n, s_last, tid, nthr); break;
+    case 3: if constexpr (RMAX >= 3) ntt_fwd_pass<3, true>(a, tw, twsh, mod, n, s_last, tid, nthr); break;
+    case 2: if constexpr (RMAX >= 2) ntt_fwd_pass<2, true>(a, tw, twsh, mod, n, s_last, tid, nthr); break;
+    default: ntt_fwd_pass<1, true>(a, tw, twsh, mod, n, s_last, tid, nthr); break;
+  }
+  for (uint32_t j = tid; j < n; j += nthr) g[j] = a[PADX(j)];
 }
 
 // The inverse transform (as ntt_inverse16, input in [0, 2m), output in
